@@ -1,0 +1,283 @@
+#!/usr/bin/env python3
+"""Benchmark of the non-separable 2-D CDF 5/3 DWT on one MI355X.
+
+Timed step: on one resident 8192 x 8192 float32 image (6 levels), the whole
+hot path once: forward transform, inverse transform, and adjoint (W^T g) of a
+coefficient-shaped gradient.  Inputs are generated on the device before the
+timed region; two buffer sets alternate between steps so that the 256 MB
+Infinity Cache cannot hold a step's input from the previous step.
+
+value = pixels transformed per second over the step, in Gpixel/s (each of the
+three passes counts the image's 8192^2 pixels once, whatever the number of
+levels).
+
+Side measurements reported in "detail": per-direction times and effective
+bandwidth, the integer 16384^2 forward/inverse, the ragged 256-image batch
+(one persistent launch vs 256 plain launches), the 32 x 3 x 1024^2 autograd
+forward/backward, and a device-to-device copy ceiling.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+METRIC = "Gpixel/s and % HBM roofline, 2-D CDF 5/3 fwd/adjoint; batched vs plain"
+HBM_PEAK_GBPS = 8000.0
+
+
+def level_sizes(w, h, levels):
+    out = [(w, h)]
+    for _ in range(levels):
+        w, h = (w + 1) // 2, (h + 1) // 2
+        out.append((w, h))
+    return out
+
+
+def alg_bytes(w, h, levels, elem=4):
+    """Each level reads its input region once and writes as many coefficients."""
+    return sum(2 * elem * a * b for (a, b) in level_sizes(w, h, levels)[:-1])
+
+
+def kernel_sources_digest():
+    h = hashlib.sha256()
+    for name in ("kernels.hip", "dwt2_internal.h"):
+        with open(os.path.join(ROOT, "paper_1708_07853_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(kernel_key):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.txt")
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("#") or ":" not in line:
+                continue
+            k, v = (t.strip() for t in line.split(":", 1))
+            rec[k] = v
+    if rec.get("kernel_sources_sha256_16") != kernel_sources_digest():
+        return None
+    v = rec.get(f"{kernel_key}_bytes_per_launch")
+    return float(v) if v else None
+
+
+class Timer:
+    def __init__(self, torch):
+        self.torch = torch
+
+    def __call__(self, fn, reps):
+        t = self.torch
+        ev = [(t.cuda.Event(enable_timing=True), t.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for a, b in ev:
+            a.record()
+            fn()
+            b.record()
+        t.cuda.synchronize()
+        return [a.elapsed_time(b) for a, b in ev]
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-detail", action="store_true", help="skip the side measurements")
+    ap.add_argument("--only", choices=["step", "fwd", "inv", "bwd", "copy"], default=None,
+                    help="profiling aid: run only this part, untimed JSON omitted")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} (WORLD_SIZE {world}) is not supported: "
+              "this build has no multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1708_07853_amd as dwt
+    from paper_1708_07853_amd import synth, _lib
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a ROCm GPU", file=sys.stderr)
+        sys.exit(1)
+    lib = _lib.load()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    timer = Timer(torch)
+
+    W = H = 8192
+    L = 6
+    npx = W * H
+    sets = []
+    for s in range(2):
+        x = synth.image_device(W, H, 2 + 100 * s, device=dev)
+        g = torch.randn((H, W), generator=torch.Generator(device=dev).manual_seed(6 + s), device=dev) * 16
+        sets.append(dict(x=x, c=torch.empty_like(x), r=torch.empty_like(x), g=g, gx=torch.empty_like(x)))
+    wsb = dwt.workspace_size(W, H, L)
+    ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+
+    def fwd(s):
+        dwt.fwd(s["x"], L, out=s["c"], workspace=ws)
+
+    def inv(s):
+        dwt.inv(s["c"], L, out=s["r"], workspace=ws)
+
+    def bwd(s):
+        dwt.bwd(s["g"], L, out=s["gx"], workspace=ws)
+
+    if args.only:
+        reps = max(1, args.steps)
+        for i in range(reps):
+            s = sets[i & 1]
+            if args.only in ("step", "fwd"):
+                fwd(s)
+            if args.only in ("step", "inv"):
+                inv(s)
+            if args.only in ("step", "bwd"):
+                bwd(s)
+            if args.only == "copy":
+                s["c"].copy_(s["x"])
+        torch.cuda.synchronize()
+        print(json.dumps({"only": args.only, "reps": reps}))
+        return
+
+    # ---- warmup + timed steps -------------------------------------------
+    for i in range(args.warmup):
+        s = sets[i & 1]
+        fwd(s); inv(s); bwd(s)
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        s = sets[i & 1]
+        e = ev[i]
+        e[0].record(); fwd(s); e[1].record(); inv(s); e[2].record(); bwd(s); e[3].record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    per_dir = {k: float(np.median([e[j].elapsed_time(e[j + 1]) for e in ev]))
+               for j, k in enumerate(("fwd", "inv", "bwd"))}
+    value = 3 * npx / (ms_step * 1e-3) / 1e9
+
+    # ---- dominant kernel: the level-1 forward kernel of the 6-level call --
+    # (a 1-level call launches exactly that kernel with the same grid; only
+    # its LL destination differs)
+    s0 = sets[0]
+    l1 = timer(lambda: dwt.fwd(s0["x"], 1, out=s0["c"]), max(args.steps, 20))
+    l1_ms = float(np.mean(l1))
+    l1_bytes = 2 * 4 * npx
+    achieved = l1_bytes / (l1_ms * 1e-3) / 1e9
+    traffic = read_traffic("fwd_level1_8192")
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
+                "kernel": "level_kernel<fwd, float> level 1, 8192x8192",
+                "bytes_per_launch": l1_bytes, "avg_launch_ms": round(l1_ms, 5)}
+
+    detail = {"ms_per_direction": {k: round(v, 4) for k, v in per_dir.items()},
+              "direction_GBps_alg": {k: round(alg_bytes(W, H, L) / (v * 1e-3) / 1e9, 1) for k, v in per_dir.items()},
+              "direction_frac_of_8TBps": {k: round(alg_bytes(W, H, L) / (v * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)
+                                          for k, v in per_dir.items()},
+              "alg_bytes_per_direction": alg_bytes(W, H, L)}
+
+    if not args.no_detail:
+        # copy ceiling: read + write of 1 GiB
+        a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        cp = timer(lambda: b.copy_(a), 20)
+        detail["copy_ceiling_GBps"] = round(2 * a.numel() * 4 / (float(np.median(cp)) * 1e-3) / 1e9, 1)
+        del a, b
+        # integer 16384^2, 6 levels, forward + inverse
+        xi = synth.image_device(16384, 16384, 3, dtype=torch.int32, device=dev)
+        ci, ri = torch.empty_like(xi), torch.empty_like(xi)
+        wsi = torch.empty(dwt.workspace_size(16384, 16384, 6, mode=1), dtype=torch.uint8, device=dev)
+        for _ in range(2):
+            dwt.fwd(xi, 6, out=ci, workspace=wsi); dwt.inv(ci, 6, out=ri, workspace=wsi)
+        tf = timer(lambda: dwt.fwd(xi, 6, out=ci, workspace=wsi), 10)
+        ti = timer(lambda: dwt.inv(ci, 6, out=ri, workspace=wsi), 10)
+        detail["int32_16384_L6"] = {
+            "fwd_ms": round(float(np.median(tf)), 4), "inv_ms": round(float(np.median(ti)), 4),
+            "fwd_Gpx_s": round(16384 ** 2 / (np.median(tf) * 1e-3) / 1e9, 1),
+            "inv_Gpx_s": round(16384 ** 2 / (np.median(ti) * 1e-3) / 1e9, 1),
+            "fwd_frac_of_8TBps": round(alg_bytes(16384, 16384, 6) / (np.median(tf) * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+            "roundtrip_exact": bool(torch.equal(ri, xi))}
+        del xi, ci, ri, wsi
+        # ragged batch: 256 images, (64..4096)^2, 3 levels
+        sizes = synth.ragged_sizes(256, 4)
+        imgs = [synth.image_device(w, h, 4000 + i, device=dev) for i, (w, h) in enumerate(sizes)]
+        outs = [torch.empty_like(t) for t in imgs]
+        wss = [torch.empty(max(1, dwt.workspace_size(w, h, 3)), dtype=torch.uint8, device=dev) for (w, h) in sizes]
+
+        def plain():
+            for im, o, w_ in zip(imgs, outs, wss):
+                dwt.fwd(im, 3, out=o, workspace=w_)
+
+        t_build = time.perf_counter()
+        dwt.fwd_batched(imgs, 3, outs=outs)
+        torch.cuda.synchronize()
+        t_build = time.perf_counter() - t_build
+        plain()
+        tp = timer(plain, 5)
+        tb = timer(lambda: dwt.fwd_batched(imgs, 3, outs=outs), 5)
+        gpx = sum(w * h for w, h in sizes)
+        detail["ragged_256_L3"] = {
+            "plain_ms": round(float(np.median(tp)), 3), "batched_ms": round(float(np.median(tb)), 3),
+            "plain_images_per_s": round(256 / (np.median(tp) * 1e-3), 1),
+            "batched_images_per_s": round(256 / (np.median(tb) * 1e-3), 1),
+            "batched_Gpx_s": round(gpx / (np.median(tb) * 1e-3) / 1e9, 1),
+            "first_call_s": round(t_build, 3), "Gpx": round(gpx / 1e9, 3)}
+        del imgs, outs, wss
+        # autograd: 32 x 3 x 1024^2, 4 levels, forward + loss + backward
+        xb = torch.stack([synth.image_device(1024, 1024, 5000 + k, device=dev) for k in range(96)]).reshape(32, 3, 1024, 1024)
+        xb.requires_grad_()
+
+        def fb():
+            y = dwt.DWT2Function.apply(xb, 4)
+            y.abs().sum().backward()
+
+        fb()
+        ta = timer(fb, 5)
+        detail["autograd_32x3x1024_L4"] = {"fwd_loss_bwd_ms": round(float(np.median(ta)), 3)}
+        del xb
+        torch.cuda.empty_cache()
+
+    # ---- CPU baseline: the oracle on a bounded sample --------------------
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        side = 4096
+        crop = sets[0]["x"][:side, :side].double().cpu().numpy()
+        g = sets[0]["g"][:side, :side].double().cpu().numpy()
+        t = time.perf_counter()
+        c = oracle.fwd(crop, L)
+        oracle.inv(c, L)
+        oracle.adj(g, L)
+        dt = time.perf_counter() - t
+        cpu = {"value": round(3 * side * side / dt / 1e9, 5), "unit": "Gpixel/s", "cores": 1, "kind": "oracle",
+               "sample": f"{side}x{side} top-left crop of the 8192x8192 image, {L} levels, float64 "
+                         f"forward + inverse + adjoint, numpy (single thread), {dt:.2f} s"}
+
+    out = {"metric": METRIC, "value": round(value, 3), "unit": "Gpixel/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "8192x8192 float32 image, 6 levels: forward + inverse + adjoint per step "
+                                  "(non-separable CDF 5/3, symmetric extension)",
+                      "width": W, "height": H, "levels": L, "parallelism": "none (1 GPU)"},
+           "roofline": roofline, "cpu_baseline": cpu, "detail": detail}
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

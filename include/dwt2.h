@@ -1,0 +1,167 @@
+/*
+ * dwt2.h -- multi-level 2-D CDF 5/3 discrete wavelet transform on AMD
+ * Instinct MI355X (gfx950), computed with the non-separable lifting scheme of
+ * Barina et al., "The Parallel Algorithm for the 2-D Discrete Wavelet
+ * Transform" (§3, eq. (5)).
+ *
+ * Mathematical definition (what every entry point computes)
+ * ---------------------------------------------------------
+ * One level splits a w x h region X into the quadruple (LL, HL, LH, HH) of
+ * §2 by sample parity: a = X[2i][2j], b = X[2i][2j+1], c = X[2i+1][2j],
+ * d = X[2i+1][2j+1].  The CDF 5/3 lifting pair of §2, eq. (2) (K = 1) uses
+ * predict P(z) = -1/2 (1 + z) and update U(z) = 1/4 (1 + z^-1), without
+ * scaling.  The level applies the spatial predict and then the spatial
+ * update of §3, eq. (5); in exact arithmetic this equals the separable
+ * sequence of §2, eq. (3) (horizontal predict, vertical predict, horizontal
+ * update, vertical update).  Samples outside the region are taken from its
+ * whole-sample symmetric extension (x[-i] = x[i], x[N-1+i] = x[N-1-i]).
+ * Even 0-based indices are L: a length-N axis keeps ceil(N/2) L and
+ * floor(N/2) H coefficients.  Levels recurse on LL (Mallat).
+ *
+ * Modes
+ *   DWT2_F32      float32 samples; results within 2e-4 absolute of the
+ *                 float64 definition for 8-bit-range inputs.
+ *   DWT2_I32_REV  int32 samples, reversible integer 5/3: predict
+ *                 d -= floor((l + r) / 2), update s += floor((l + r + 2) / 4),
+ *                 rounded separable steps composed in the eq. (3) order
+ *                 inside each spatial step.  Bit-exact and exactly
+ *                 invertible.  Inputs must keep every intermediate sum in
+ *                 int32 range (|x| <= 2^24 is always safe).
+ *
+ * Output layout ("Mallat-packed", same w x h shape as the image), with
+ * w_0 = w, w_k = ceil(w_{k-1} / 2) (likewise h):
+ *   LL_L   rows [0, h_L),          cols [0, w_L)
+ *   HL_k   rows [0, h_k),          cols [w_k, w_{k-1})
+ *   LH_k   rows [h_k, h_{k-1}),    cols [0, w_k)
+ *   HH_k   rows [h_k, h_{k-1}),    cols [w_k, w_{k-1})
+ *
+ * Conventions for every call
+ *   - Image, coefficient and workspace pointers are DEVICE pointers of the
+ *     current HIP device; strides are in ELEMENTS (4-byte samples).
+ *   - stream is a hipStream_t passed as void* (NULL = the null stream).
+ *     Calls are asynchronous and stream-ordered; the return value covers
+ *     argument validation and launch only, execution errors surface at the
+ *     caller's next synchronisation.
+ *   - Ownership: the caller owns src, dst and workspace; the library never
+ *     frees or retains them beyond the call's stream work.  The library owns
+ *     only its batched-plan cache (released by dwt2_clear_plan_cache).
+ *   - Errors are negative status codes; validation happens before any HIP
+ *     call, so a failing call has no side effects.  No C++ exception crosses
+ *     this interface.  dwt2_last_error() gives a thread-local detail string.
+ *   - The transforms are out of place: src and dst must not overlap, and the
+ *     workspace must overlap neither.
+ *   - Calls on different streams need distinct workspaces.
+ */
+#ifndef DWT2_H
+#define DWT2_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* modes */
+enum { DWT2_F32 = 0, DWT2_I32_REV = 1 };
+/* boundary extension: whole-sample symmetric is the only one */
+enum { DWT2_EXT_SYMMETRIC = 0 };
+/* status codes */
+enum {
+  DWT2_OK = 0,
+  DWT2_ERR_ARG = -1,       /* null pointer, width/height < 2, stride < width,
+                              batch < 1, batch stride too small, bad boundary */
+  DWT2_ERR_SIZE = -2,      /* levels < 1, a level input below 2 x 2, or a
+                              dimension above DWT2_MAX_DIM */
+  DWT2_ERR_MODE = -3,      /* unknown mode, or integer mode in dwt2_bwd */
+  DWT2_ERR_WORKSPACE = -4, /* workspace smaller than the queried size */
+  DWT2_ERR_ALIAS = -5,     /* src == dst */
+  DWT2_ERR_HIP = -6,       /* HIP runtime / launch failure (detail in last_error) */
+  DWT2_ERR_NOMEM = -7      /* host or plan-cache allocation failed */
+};
+
+#define DWT2_MAX_DIM (1 << 28)
+#define DWT2_MAX_LEVELS 24
+
+/* Bytes of device workspace that dwt2_fwd / dwt2_inv / dwt2_bwd need for
+ * `batch` images of width x height with `levels` levels (0 when one level
+ * suffices, since no intermediate LL is stored).  Returns 0 as well for
+ * invalid arguments; the transform call then reports the error. */
+size_t dwt2_workspace_size(int32_t width, int32_t height, int32_t batch,
+                           int32_t levels, int32_t mode);
+
+/* Forward transform (§3, eq. (5), per level; levels chained on LL).
+ *   src   image(s): width x height samples, row stride src_stride, image b
+ *         at src + b * src_batch_stride (elements).  Read only.
+ *   dst   Mallat-packed coefficients, same geometry convention.  Written.
+ *   mode  DWT2_F32 (float*) or DWT2_I32_REV (int32_t*).
+ *   boundary must be DWT2_EXT_SYMMETRIC.
+ *   workspace / workspace_bytes: device scratch of at least
+ *         dwt2_workspace_size(...) bytes (may be NULL when that is 0). */
+int dwt2_fwd(const void* src, int64_t src_stride, int64_t src_batch_stride,
+             void* dst, int64_t dst_stride, int64_t dst_batch_stride,
+             int32_t width, int32_t height, int32_t batch, int32_t levels,
+             int32_t mode, int32_t boundary, void* workspace,
+             size_t workspace_bytes, void* stream);
+
+/* Inverse transform: src holds Mallat-packed coefficients, dst receives the
+ * image.  Per level, coarsest first, the eq. (5) steps are undone (update
+ * first); the integer mode undoes the composed rounded steps exactly. */
+int dwt2_inv(const void* src, int64_t src_stride, int64_t src_batch_stride,
+             void* dst, int64_t dst_stride, int64_t dst_batch_stride,
+             int32_t width, int32_t height, int32_t batch, int32_t levels,
+             int32_t mode, int32_t boundary, void* workspace,
+             size_t workspace_bytes, void* stream);
+
+/* Adjoint (transpose) of the float forward transform: src holds a gradient
+ * with respect to the packed coefficients, dst receives W^T src, the
+ * gradient with respect to the image.  Per level, coarsest first, the
+ * transposed spatial update and then the transposed spatial predict are
+ * applied with the boundary weights that transpose the symmetric extension.
+ * mode must be DWT2_F32 (DWT2_ERR_MODE otherwise). */
+int dwt2_bwd(const void* src, int64_t src_stride, int64_t src_batch_stride,
+             void* dst, int64_t dst_stride, int64_t dst_batch_stride,
+             int32_t width, int32_t height, int32_t batch, int32_t levels,
+             int32_t mode, int32_t boundary, void* workspace,
+             size_t workspace_bytes, void* stream);
+
+/* One image of a ragged batch (all pointers device pointers). */
+typedef struct {
+  const void* src;
+  void* dst;
+  int64_t src_stride;
+  int64_t dst_stride;
+  int32_t width;
+  int32_t height;
+} dwt2_image_t;
+
+/* Workspace bytes for dwt2_fwd_batched over this list of images. */
+size_t dwt2_batched_workspace_size(const dwt2_image_t* images, int32_t n,
+                                   int32_t levels, int32_t mode);
+
+/* Forward transform of n images of unequal sizes in one persistent kernel
+ * launch, replayed from a HIP graph that is cached per shape set.
+ *   images  HOST array of n descriptors; every image is validated like a
+ *           dwt2_fwd call (the detail string names the failing image).
+ * Results are bit-identical to n separate dwt2_fwd calls.  The first call
+ * for a new shape set builds the plan (tile choice, schedule, graph) and is
+ * therefore not capture-safe; later calls only update the descriptor table
+ * and launch the graph on `stream`.  Calls sharing a workspace must be
+ * stream-ordered. */
+int dwt2_fwd_batched(const dwt2_image_t* images, int32_t n, int32_t levels,
+                     int32_t mode, int32_t boundary, void* workspace,
+                     size_t workspace_bytes, void* stream);
+
+/* Static description of a status code. */
+const char* dwt2_status_string(int status);
+/* Thread-local detail of the last failing call on this thread ("" if none). */
+const char* dwt2_last_error(void);
+/* Releases every cached batched plan (graphs, device tables, pinned staging).
+ * Must not race with dwt2_fwd_batched calls. */
+void dwt2_clear_plan_cache(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DWT2_H */

@@ -1,0 +1,159 @@
+"""Python front end of libdwt2: tensors in, tensors out.
+
+Every call marshals device pointers, strides and the current HIP stream into
+the C ABI; all arithmetic runs in the library's HIP kernels.  Tensors must
+live on a ROCm device, be float32 (DWT2_F32) or int32 (DWT2_I32_REV), and have
+unit stride along the last (width) axis.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import List, Sequence
+
+import torch
+
+from . import _lib
+from ._lib import DWT2_EXT_SYMMETRIC, DWT2_F32, DWT2_I32_REV
+
+__all__ = ["fwd", "inv", "bwd", "fwd_batched", "DWT2Function", "workspace_size", "level_sizes",
+           "DWT2_F32", "DWT2_I32_REV"]
+
+
+def level_sizes(w: int, h: int, levels: int):
+    out = [(w, h)]
+    for _ in range(levels):
+        w, h = (w + 1) // 2, (h + 1) // 2
+        out.append((w, h))
+    return out
+
+
+def _mode_of(t: torch.Tensor, mode) -> int:
+    if mode is None:
+        if t.dtype == torch.float32:
+            return DWT2_F32
+        if t.dtype == torch.int32:
+            return DWT2_I32_REV
+        raise TypeError(f"unsupported dtype {t.dtype}: float32 or int32 expected")
+    want = torch.float32 if mode == DWT2_F32 else torch.int32
+    if t.dtype != want:
+        raise TypeError(f"mode {mode} needs {want}, got {t.dtype}")
+    return mode
+
+
+def _as_batch(t: torch.Tensor):
+    """View (..., H, W) as (B, H, W) with uniform strides, copying if needed."""
+    if not t.is_cuda:
+        raise ValueError("the DWT runs on the GPU: move the tensor to a ROCm device first")
+    if t.dim() < 2:
+        raise ValueError("need at least (H, W)")
+    h, w = t.shape[-2], t.shape[-1]
+    b = t.reshape(-1, h, w) if t.dim() > 2 else t.unsqueeze(0)
+    if b.stride(-1) != 1 or b.stride(-2) < w:
+        b = b.contiguous()
+    if b.shape[0] > 1 and b.stride(0) < b.stride(-2) * h:
+        b = b.contiguous()
+    return b
+
+
+def workspace_size(w: int, h: int, levels: int, batch: int = 1, mode: int = DWT2_F32) -> int:
+    return int(_lib.load().dwt2_workspace_size(w, h, batch, levels, mode))
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _run(name: str, x: torch.Tensor, levels: int, mode, out: torch.Tensor | None,
+         workspace: torch.Tensor | None = None) -> torch.Tensor:
+    lib = _lib.load()
+    mode = _mode_of(x, mode)
+    xb = _as_batch(x)
+    batch, h, w = xb.shape
+    if out is None:
+        out = torch.empty(x.shape, dtype=x.dtype, device=x.device)
+    ob = _as_batch(out)
+    if ob.shape != xb.shape or ob.dtype != xb.dtype:
+        raise ValueError("out must match the input's shape and dtype")
+    if ob.data_ptr() != out.data_ptr() or (out.dim() > 2 and not out.is_contiguous()):
+        raise ValueError("out must be a contiguous tensor")
+    nbytes = int(lib.dwt2_workspace_size(w, h, batch, levels, mode))
+    ws = None
+    if nbytes:
+        if workspace is not None and workspace.numel() * workspace.element_size() >= nbytes:
+            ws = workspace
+        else:
+            ws = torch.empty(nbytes, dtype=torch.uint8, device=x.device)
+    with torch.cuda.device(x.device):
+        status = getattr(lib, name)(
+            xb.data_ptr(), xb.stride(1), xb.stride(0) if batch > 1 else 0,
+            ob.data_ptr(), ob.stride(1), ob.stride(0) if batch > 1 else 0,
+            w, h, batch, levels, mode, DWT2_EXT_SYMMETRIC,
+            ws.data_ptr() if ws is not None else None, nbytes, _stream())
+    _lib.check(status)
+    return out
+
+
+def fwd(x: torch.Tensor, levels: int, mode=None, out=None, workspace=None) -> torch.Tensor:
+    """Forward multi-level transform of (..., H, W); returns Mallat-packed
+    coefficients of the same shape.  `workspace` (a device byte tensor of at
+    least workspace_size(...) bytes) avoids a per-call allocation."""
+    return _run("dwt2_fwd", x, levels, mode, out, workspace)
+
+
+def inv(c: torch.Tensor, levels: int, mode=None, out=None, workspace=None) -> torch.Tensor:
+    """Inverse of fwd."""
+    return _run("dwt2_inv", c, levels, mode, out, workspace)
+
+
+def bwd(g: torch.Tensor, levels: int, out=None, workspace=None) -> torch.Tensor:
+    """Adjoint of the float forward transform: W^T g."""
+    return _run("dwt2_bwd", g, levels, DWT2_F32, out, workspace)
+
+
+def _image_table(srcs: Sequence[torch.Tensor], dsts: Sequence[torch.Tensor]):
+    arr = (_lib.Dwt2Image * len(srcs))()
+    for i, (s, d) in enumerate(zip(srcs, dsts)):
+        if s.dim() != 2 or s.stride(1) != 1 or d.stride(1) != 1:
+            raise ValueError(f"image {i}: need a 2-D tensor with unit column stride")
+        arr[i].src, arr[i].dst = s.data_ptr(), d.data_ptr()
+        arr[i].src_stride, arr[i].dst_stride = s.stride(0), d.stride(0)
+        arr[i].height, arr[i].width = s.shape
+    return arr
+
+
+def fwd_batched(images: Sequence[torch.Tensor], levels: int, mode=None,
+                outs: Sequence[torch.Tensor] | None = None) -> List[torch.Tensor]:
+    """Forward transform of a ragged list of 2-D images in one persistent
+    launch (see dwt2_fwd_batched)."""
+    lib = _lib.load()
+    if not images:
+        return []
+    mode = _mode_of(images[0], mode)
+    for t in images:
+        _mode_of(t, mode)
+        if not t.is_cuda:
+            raise ValueError("images must be on the GPU")
+    if outs is None:
+        outs = [torch.empty_like(t) for t in images]
+    arr = _image_table(images, outs)
+    n = len(images)
+    nbytes = int(lib.dwt2_batched_workspace_size(arr, n, levels, mode))
+    ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=images[0].device)
+    with torch.cuda.device(images[0].device):
+        status = lib.dwt2_fwd_batched(arr, n, levels, mode, DWT2_EXT_SYMMETRIC, ws.data_ptr(), nbytes, _stream())
+    _lib.check(status)
+    return list(outs)
+
+
+class DWT2Function(torch.autograd.Function):
+    """y = W x (float32, multi-level); the backward applies the hand-written
+    adjoint kernel, W^T g.  Linear, so nothing is saved for backward."""
+
+    @staticmethod
+    def forward(ctx, x: torch.Tensor, levels: int):
+        ctx.levels = levels
+        return fwd(x.contiguous(), levels, DWT2_F32)
+
+    @staticmethod
+    def backward(ctx, g: torch.Tensor):
+        return bwd(g.contiguous(), ctx.levels), None

@@ -1,0 +1,75 @@
+// Internal types shared by the host API (api.cpp) and the HIP kernels
+// (kernels.hip).  Not part of the public interface.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/dwt2.h"
+
+namespace dwt2 {
+
+// A wave (64 lanes) owns a vertical strip of quadruple columns; each lane owns
+// two adjacent quadruples (four pixel columns, one 16-byte vector per pixel
+// row).  Of the 128 quadruple columns a wave loads, the first one and the last
+// one only feed their neighbours, so a strip writes 126 columns and strip s
+// writes quadruple columns [126 s - 1, 126 s + 125).
+constexpr int kWave = 64;
+constexpr int kStripLoaded = 128;
+constexpr int kStripOut = 126;
+constexpr int kWavesPerBlock = 4;
+constexpr int kBlock = kWave * kWavesPerBlock;
+
+enum Dir : int32_t { kFwd = 0, kInv = 1, kBwd = 2 };
+
+// One level of one image.  "Pixels" is the level input region X_{k-1}
+// (w_{k-1} x h_{k-1}); "ll" is LL_k; "band" is the origin of the packed
+// coefficient array, whose [0, h_{k-1}) x [0, w_{k-1}) corner holds this
+// level's quadruple (LL_k at the origin unless ll points elsewhere).
+//   forward : reads pixels, writes ll and the three H bands into band
+//   inverse : reads ll and the H bands, writes pixels
+//   adjoint : like inverse (gradients)
+struct LevelDesc {
+  const void* pix_in;   // forward input pixels
+  void* pix_out;        // inverse/adjoint output pixels
+  const void* ll_in;    // inverse/adjoint LL_k input
+  void* ll_out;         // forward LL_k output
+  const void* band_in;  // inverse/adjoint H-band source (packed array origin)
+  void* band_out;       // forward H-band destination (packed array origin)
+  int64_t pix_stride;
+  int64_t ll_stride;
+  int64_t band_stride;
+  int32_t W, H;         // level input size
+  int32_t seg;          // quadruple rows per work item
+  int32_t nstrips;
+  int32_t nsegs;
+  int32_t pad_;
+};
+
+// Plain (uniform-geometry) launch of one level over a batch of images.
+struct LevelLaunch {
+  LevelDesc d;
+  int64_t pix_bstride;   // element strides between consecutive images
+  int64_t ll_bstride;
+  int64_t band_bstride;
+  int64_t items;         // batch * nsegs * nstrips
+  int32_t items_per_image;
+  int32_t pad_;
+};
+
+inline int ceil_half(int n) { return (n + 1) >> 1; }
+
+inline int num_strips(int W) {
+  // strip s writes quadruple columns [126 s - 1, 126 s + 125) of ceil(W/2)
+  const int ns = ceil_half(W);
+  return (ns + 1 + kStripOut - 1) / kStripOut;
+}
+
+inline int64_t ll_pitch(int w) {  // padded row pitch (elements) of an LL buffer
+  return ((int64_t)w + 63) & ~(int64_t)63;
+}
+
+// Kernel launchers (kernels.hip).  Return hipError_t as int.
+int launch_level(int dir, int mode, int chunk, const LevelLaunch& a, void* stream);
+
+}  // namespace dwt2

@@ -1,0 +1,38 @@
+// Host-side helpers shared by the plain entry points (api.cpp) and the
+// batched entry point (batched.cpp).
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "dwt2_internal.h"
+
+namespace dwt2 {
+
+struct Geo {
+  int L;
+  int w[DWT2_MAX_LEVELS + 1];
+  int h[DWT2_MAX_LEVELS + 1];
+};
+
+// One uniform-geometry call (a batch of equally sized images).
+struct Call {
+  const char* src;
+  int64_t src_stride, src_bs;
+  char* dst;
+  int64_t dst_stride, dst_bs;
+  int32_t batch;
+  int32_t mode;
+  char* ws;
+};
+
+int fail(int code, const char* fmt, ...);
+void clear_error();
+int check_geometry(int32_t width, int32_t height, int32_t levels, Geo& g);
+void ws_layout(const Geo& g, size_t& a_bytes, size_t& b_bytes);
+size_t ws_per_image(const Geo& g);
+int choose_seg(int ns_h, int64_t strips_times_batch);
+void fill_level(LevelDesc& d, int W, int H, int seg);
+int run_levels(int dir, const Call& c, const Geo& g, void* stream);
+
+}  // namespace dwt2

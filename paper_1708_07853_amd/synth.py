@@ -72,3 +72,32 @@ def channel_batch(b: int, c: int, w: int, h: int, seed_base: int = 5000,
         for ch in range(c):
             out[i, ch] = image(w, h, seed_base + c * i + ch, dtype)
     return out
+
+
+def image_device(w: int, h: int, seed: int, dtype=None, device="cuda"):
+    """The same recipe built on the device (for large benchmark inputs): the
+    blob parameters come from the same PCG64 draws as `image`, the noise from
+    torch's device generator seeded with `seed`, so the pixels follow the same
+    distribution but are not identical to `image(w, h, seed)`."""
+    import torch
+
+    dtype = torch.float32 if dtype is None else dtype
+    rng = np.random.Generator(np.random.PCG64(seed))
+    blobs = []
+    for _ in range(N_BLOBS):
+        cx = rng.uniform(0.0, w)
+        cy = rng.uniform(0.0, h)
+        amp = rng.uniform(-64.0, 64.0)
+        u = rng.uniform(0.05, 0.20)
+        blobs.append((cx, cy, amp, u * w))
+    xs = torch.arange(w, dtype=torch.float64, device=device)
+    ys = torch.arange(h, dtype=torch.float64, device=device)
+    acc = torch.full((h, w), 128.0, dtype=torch.float64, device=device)
+    for (cx, cy, amp, s) in blobs:
+        gx = torch.exp(-((xs - cx) ** 2) / (2.0 * s * s))
+        gy = amp * torch.exp(-((ys - cy) ** 2) / (2.0 * s * s))
+        acc += gy[:, None] * gx[None, :]
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed)
+    acc += NOISE_SIGMA * torch.randn((h, w), generator=gen, dtype=torch.float64, device=device)
+    return torch.clamp(torch.round(acc), 0.0, 255.0).to(dtype)

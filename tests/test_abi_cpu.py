@@ -1,0 +1,116 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, sizes workspaces, and rejects every invalid argument before
+any HIP call (all pointers below are never dereferenced)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1708_07853_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+FAKE_A, FAKE_B, FAKE_WS = 0x10000, 0x20000, 0x30000
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_1708_07853_amd import build
+        build.build()
+    return _lib.load()
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "dwt2.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dwt2_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(lib):
+    names = header_functions()
+    assert len(names) >= 9
+    assert sorted(names) == sorted(_lib.EXPORTS)
+    for n in names:
+        assert getattr(lib, n) is not None
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    saved = _lib._lib
+    try:
+        _lib._lib = None
+        with pytest.raises(RuntimeError, match="not built"):
+            _lib.load(str(tmp_path / "nope.so"))
+    finally:
+        _lib._lib = saved
+
+
+def test_workspace_sizes(lib):
+    assert lib.dwt2_workspace_size(512, 512, 1, 1, 0) == 0          # one level: no LL buffer
+    # two levels: LL_1 (256 x 256, pitch 256) only
+    assert lib.dwt2_workspace_size(512, 512, 1, 2, 0) == 256 * 256 * 4
+    # three levels: LL_1 and LL_2
+    assert lib.dwt2_workspace_size(512, 512, 1, 3, 0) == (256 * 256 + 128 * 128) * 4
+    assert lib.dwt2_workspace_size(512, 512, 3, 3, 1) == 3 * (256 * 256 + 128 * 128) * 4
+    # pitch padded to 64 elements: 101 -> ceil 51 -> 64
+    assert lib.dwt2_workspace_size(101, 40, 1, 2, 0) == ((64 * 20 * 4 + 255) // 256) * 256
+    assert lib.dwt2_workspace_size(4, 4, 1, 3, 0) == 0               # invalid: level 3 input 1 x 1
+    assert lib.dwt2_workspace_size(4, 4, 1, 2, 5) == 0               # invalid mode
+
+
+def call(lib, fn, **kw):
+    a = dict(src=FAKE_A, ss=64, sb=0, dst=FAKE_B, ds=64, db=0, w=64, h=64, batch=1, levels=2,
+             mode=0, boundary=0, ws=FAKE_WS, wsb=1 << 30, stream=None)
+    a.update(kw)
+    return getattr(lib, fn)(a["src"], a["ss"], a["sb"], a["dst"], a["ds"], a["db"], a["w"], a["h"],
+                            a["batch"], a["levels"], a["mode"], a["boundary"], a["ws"], a["wsb"], a["stream"])
+
+
+BAD = [
+    (dict(src=None), -1), (dict(dst=None), -1), (dict(w=1), -1), (dict(h=1), -1),
+    (dict(ss=63), -1), (dict(ds=10), -1), (dict(batch=0), -1), (dict(batch=2, sb=64 * 63), -1),
+    (dict(boundary=1), -1), (dict(levels=0), -2), (dict(levels=7), -2), (dict(levels=99), -2),
+    (dict(w=1 << 29, ss=1 << 29, ds=1 << 29), -2), (dict(mode=2), -3), (dict(dst=FAKE_A), -5),
+    (dict(ws=None), -4), (dict(wsb=100), -4),
+]
+
+
+@pytest.mark.parametrize("fn", ["dwt2_fwd", "dwt2_inv", "dwt2_bwd"])
+@pytest.mark.parametrize("kw,code", BAD, ids=[str(b[0]) for b in BAD])
+def test_validation_errors(lib, fn, kw, code):
+    assert call(lib, fn, **kw) == code
+    assert lib.dwt2_last_error().decode() != ""
+
+
+def test_adjoint_rejects_integer_mode(lib):
+    assert call(lib, "dwt2_bwd", mode=1) == -3
+    assert "F32" in lib.dwt2_last_error().decode()
+
+
+def test_status_strings(lib):
+    for code in range(-7, 1):
+        assert lib.dwt2_status_string(code)
+    assert lib.dwt2_status_string(-100) == b"unknown status"
+
+
+def _images(specs):
+    arr = (_lib.Dwt2Image * len(specs))()
+    for i, (w, h, s) in enumerate(specs):
+        arr[i].src, arr[i].dst = FAKE_A + i * 0x1000000, FAKE_B + i * 0x1000000
+        arr[i].src_stride = arr[i].dst_stride = s
+        arr[i].width, arr[i].height = w, h
+    return arr
+
+
+def test_batched_validation(lib):
+    ok = _images([(64, 64, 64), (33, 17, 40)])
+    assert lib.dwt2_batched_workspace_size(ok, 2, 2, 0) > 0
+    bad = _images([(64, 64, 64), (33, 17, 20)])           # image 1: stride < width
+    assert lib.dwt2_fwd_batched(bad, 2, 2, 0, 0, FAKE_WS, 1 << 30, None) == -1
+    assert "image 1" in lib.dwt2_last_error().decode()
+    tiny = _images([(64, 64, 64), (3, 3, 3)])             # image 1: level 2 input 2 x 2 ok, level 3 not
+    assert lib.dwt2_fwd_batched(tiny, 2, 3, 0, 0, FAKE_WS, 1 << 30, None) == -2
+    assert lib.dwt2_fwd_batched(ok, 2, 2, 0, 0, FAKE_WS, 10, None) == -4
+    assert lib.dwt2_fwd_batched(ok, 0, 2, 0, 0, FAKE_WS, 1 << 30, None) == -1
+    assert lib.dwt2_fwd_batched(ok, 2, 2, 9, 0, FAKE_WS, 1 << 30, None) == -3
+    assert lib.dwt2_fwd_batched(ok, 2, 2, 0, 3, FAKE_WS, 1 << 30, None) == -1

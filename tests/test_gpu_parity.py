@@ -1,0 +1,229 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Bars: integer mode bit-exact; float32 within 2e-4 absolute of the float64
+oracle on 8-bit-range data (the adjoint on gradients of the loss's size).
+"""
+import itertools
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import FLOAT, INT
+import crops
+from paper_1708_07853_amd import synth
+
+pytestmark = pytest.mark.gpu
+TOL = 2e-4
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def D():
+    import paper_1708_07853_amd as d
+    return d
+
+
+def to_gpu(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def max_levels(w, h, cap=6):
+    lv = 1
+    while lv < cap and -(-w // (1 << lv)) >= 2 and -(-h // (1 << lv)) >= 2:
+        lv += 1
+    return lv
+
+
+def maxdiff(a, b):
+    return float(np.abs(np.asarray(a, dtype=np.float64) - np.asarray(b, dtype=np.float64)).max())
+
+
+SWEEP_H = [2, 3, 4, 5, 7, 8, 13, 16, 33, 64, 67]
+SWEEP_W = [2, 3, 5, 6, 17, 64, 66, 127, 130, 253, 256, 257, 515]
+SWEEP = list(itertools.product(SWEEP_H, SWEEP_W))
+
+
+def _img(h, w, seed, dtype=np.int64):
+    return np.random.default_rng(seed).integers(0, 256, size=(h, w)).astype(dtype)
+
+
+@pytest.mark.parametrize("mode", ["f32", "int"])
+def test_forward_size_sweep(mode):
+    d = D()
+    for idx, (h, w) in enumerate(SWEEP):
+        x = _img(h, w, idx)
+        for levels in sorted({1, max_levels(w, h, 4)}):
+            if mode == "int":
+                got = d.fwd(to_gpu(x.astype(np.int32)), levels).cpu().numpy()
+                ref = oracle.fwd(x, levels, INT)
+                assert np.array_equal(got, ref), (h, w, levels)
+            else:
+                got = d.fwd(to_gpu(x.astype(np.float32)), levels).cpu().numpy()
+                assert maxdiff(got, oracle.fwd(x, levels)) <= TOL, (h, w, levels)
+
+
+@pytest.mark.parametrize("mode", ["f32", "int"])
+def test_inverse_size_sweep(mode):
+    d = D()
+    for idx, (h, w) in enumerate(SWEEP):
+        x = _img(h, w, 1000 + idx)
+        for levels in sorted({1, max_levels(w, h, 4)}):
+            if mode == "int":
+                c = oracle.fwd(x, levels, INT)
+                got = d.inv(to_gpu(c.astype(np.int32)), levels).cpu().numpy()
+                assert np.array_equal(got, x), (h, w, levels)
+            else:
+                c = oracle.fwd(x, levels).astype(np.float32)
+                got = d.inv(to_gpu(c), levels).cpu().numpy()
+                assert maxdiff(got, oracle.inv(c.astype(np.float64), levels)) <= TOL, (h, w, levels)
+
+
+def test_adjoint_size_sweep():
+    d = D()
+    for idx, (h, w) in enumerate(SWEEP):
+        g = np.random.default_rng(2000 + idx).normal(size=(h, w)).astype(np.float32) * 16
+        for levels in sorted({1, max_levels(w, h, 4)}):
+            got = d.bwd(to_gpu(g), levels).cpu().numpy()
+            assert maxdiff(got, oracle.adj(g.astype(np.float64), levels)) <= TOL, (h, w, levels)
+
+
+MULTI = [(300, 517, 3), (1000, 771, 5), (129, 2049, 4), (2050, 130, 5), (777, 1031, 6), (4, 8200, 2)]
+
+
+@pytest.mark.parametrize("h,w,levels", MULTI)
+def test_multi_tile_all_directions(h, w, levels):
+    """Several strips and segments with ragged tails, every direction, both modes."""
+    d = D()
+    x = synth.image(w, h, seed=h * 7 + w, dtype=np.int32)
+    # float forward / inverse / adjoint
+    cf = d.fwd(to_gpu(x.astype(np.float32)), levels).cpu().numpy()
+    ref = oracle.fwd(x.astype(np.float64), levels)
+    assert maxdiff(cf, ref) <= TOL
+    xr = d.inv(to_gpu(ref.astype(np.float32)), levels).cpu().numpy()
+    assert maxdiff(xr, oracle.inv(ref.astype(np.float32).astype(np.float64), levels)) <= TOL
+    g = np.random.default_rng(h).normal(size=(h, w)).astype(np.float32) * 8
+    ga = d.bwd(to_gpu(g), levels).cpu().numpy()
+    assert maxdiff(ga, oracle.adj(g.astype(np.float64), levels)) <= TOL
+    # integer forward / inverse
+    ci = d.fwd(to_gpu(x), levels).cpu().numpy()
+    refi = oracle.fwd(x.astype(np.int64), levels, INT)
+    assert np.array_equal(ci, refi)
+    assert np.array_equal(d.inv(to_gpu(ci), levels).cpu().numpy(), x)
+
+
+def test_batch_dimension_and_strided_input():
+    d = D()
+    b = np.stack([synth.image(45, 70, s) for s in range(6)]).reshape(3, 2, 70, 45)
+    got = d.fwd(to_gpu(b), 3).cpu().numpy()
+    for i in range(3):
+        for j in range(2):
+            assert maxdiff(got[i, j], oracle.fwd(b[i, j].astype(np.float64), 3)) <= TOL
+    # a strided, misaligned view (row stride 101, offset 3 elements)
+    big = synth.image(101, 60, 5)
+    view = to_gpu(big)[:, 3:3 + 90]
+    assert view.stride(0) == 101 and not view.is_contiguous()
+    got = d.fwd(view, 3).cpu().numpy()
+    assert maxdiff(got, oracle.fwd(big[:, 3:93].astype(np.float64), 3)) <= TOL
+    gi = d.fwd(to_gpu(big.astype(np.int32))[:, 1:88], 2).cpu().numpy()
+    assert np.array_equal(gi, oracle.fwd(big[:, 1:88].astype(np.int64), 2, INT))
+
+
+def test_config1_512_single_level():
+    d = D()
+    x = synth.image(512, 512, 1)
+    got = d.fwd(to_gpu(x), 1).cpu().numpy()
+    assert maxdiff(got, oracle.fwd(x.astype(np.float64), 1)) <= TOL
+    xi = x.astype(np.int32)
+    assert np.array_equal(d.fwd(to_gpu(xi), 1).cpu().numpy(), oracle.fwd(xi.astype(np.int64), 1, INT))
+
+
+def test_repeatable_bit_for_bit():
+    d = D()
+    x = to_gpu(synth.image(1500, 997, 11))
+    a = d.fwd(x, 5)
+    for _ in range(3):
+        assert torch.equal(a, d.fwd(x, 5))
+    g = torch.randn(997, 1500, device="cuda")
+    b = d.bwd(g, 5)
+    assert torch.equal(b, d.bwd(g, 5))
+
+
+def test_ragged_batched_equals_plain():
+    d = D()
+    sizes = [(2, 2), (3, 5), (64, 64), (65, 33), (300, 17), (129, 257), (1000, 999), (640, 480)]
+    for mode, dt in (("f32", np.float32), ("int", np.int32)):
+        imgs = [to_gpu(synth.image(w, h, 40 + i, dt)) for i, (w, h) in enumerate(sizes)]
+        outs = d.fwd_batched(imgs, 1)
+        for im, o in zip(imgs, outs):
+            assert torch.equal(o, d.fwd(im, 1))
+    imgs = [to_gpu(synth.image(w, h, 60 + i)) for i, (w, h) in enumerate(sizes) if min(w, h) >= 4]
+    outs = d.fwd_batched(imgs, 2)
+    for im, o in zip(imgs, outs):
+        assert torch.equal(o, d.fwd(im, 2))
+
+
+# ------------------------------------------------------------- full sizes
+
+def _check_crops_fwd(packed, img, levels, mode):
+    h, w = img.shape
+    total = 0
+    fn = (lambda c, L: oracle.fwd(c.astype(np.float64), L)) if mode == "f32" else \
+        (lambda c, L: oracle.fwd(c.astype(np.int64), L, INT))
+    for (y0, x0, sz) in crops.standard_crops(h, w, 768, levels):
+        worst, n = crops.compare_fwd_crop(packed, img, y0, x0, sz, levels, fn)
+        total += n
+        if mode == "int":
+            assert worst == 0, (y0, x0, sz)
+        else:
+            assert worst <= TOL, (y0, x0, sz, worst)
+    return total
+
+
+def test_config2_8192_float_forward_inverse():
+    d = D()
+    levels = 6
+    x = synth.image(8192, 8192, 2)
+    xg = to_gpu(x)
+    c = d.fwd(xg, levels)
+    packed = c.cpu().numpy()
+    assert _check_crops_fwd(packed, x, levels, "f32") > 100000
+    # inverse: oracle inverse on crops of the same coefficients, and roundtrip
+    r = d.inv(c, levels)
+    rn = r.cpu().numpy()
+    assert maxdiff(rn, x) <= TOL
+    for (y0, x0, sz) in crops.standard_crops(8192, 8192, 1024, levels)[:3]:
+        worst, n = crops.compare_pixels_crop(rn, packed, y0, x0, sz, levels,
+                                             lambda p, L: oracle.inv(p.astype(np.float64), L))
+        assert n > 0 and worst <= TOL
+
+
+def test_config3_16384_integer_forward_inverse():
+    d = D()
+    levels = 6
+    x = synth.image(16384, 16384, 3, np.int32)
+    xg = to_gpu(x)
+    c = d.fwd(xg, levels)
+    packed = c.cpu().numpy()
+    assert _check_crops_fwd(packed, x, levels, "int") > 100000
+    r = d.inv(c, levels)
+    assert torch.equal(r, xg)
+    del c, r, xg
+    torch.cuda.empty_cache()
+
+
+def test_config5_adjoint_against_oracle():
+    """The batch of the autograd workload: W^T g for the same g as the oracle."""
+    d = D()
+    levels = 4
+    x = synth.channel_batch(2, 3, 1024, 1024)
+    g = np.random.default_rng(6).normal(size=x.shape).astype(np.float32) * 16
+    got = d.bwd(to_gpu(g), levels).cpu().numpy()
+    for b in range(2):
+        for ch in range(3):
+            assert maxdiff(got[b, ch], oracle.adj(g[b, ch].astype(np.float64), levels)) <= TOL
