@@ -152,6 +152,13 @@ int dwt2_fwd_batched(const dwt2_image_t* images, int32_t n, int32_t levels,
                      int32_t mode, int32_t boundary, void* workspace,
                      size_t workspace_bytes, void* stream);
 
+/* Process-wide tiling override, for tuning sweeps and tests: seg = quadruple
+ * rows per work item (0 = automatic), chunk = quadruple rows per prefetch
+ * chunk (1, 2 or 4; 0 = automatic).  Results are bit-identical for every
+ * setting; only speed changes.  Must not race with running calls.
+ * Returns DWT2_OK, or DWT2_ERR_ARG for values outside those ranges. */
+int dwt2_set_tiling(int32_t seg, int32_t chunk);
+
 /* Static description of a status code. */
 const char* dwt2_status_string(int status);
 /* Thread-local detail of the last failing call on this thread ("" if none). */

@@ -15,7 +15,7 @@ import torch
 from . import _lib
 from ._lib import DWT2_EXT_SYMMETRIC, DWT2_F32, DWT2_I32_REV
 
-__all__ = ["fwd", "inv", "bwd", "fwd_batched", "DWT2Function", "workspace_size", "level_sizes",
+__all__ = ["fwd", "inv", "bwd", "fwd_batched", "DWT2Function", "workspace_size", "level_sizes", "set_tiling",
            "DWT2_F32", "DWT2_I32_REV"]
 
 
@@ -53,6 +53,11 @@ def _as_batch(t: torch.Tensor):
     if b.shape[0] > 1 and b.stride(0) < b.stride(-2) * h:
         b = b.contiguous()
     return b
+
+
+def set_tiling(seg: int = 0, chunk: int = 0) -> None:
+    """Process-wide tiling override (0 = automatic); results do not change."""
+    _lib.check(_lib.load().dwt2_set_tiling(seg, chunk))
 
 
 def workspace_size(w: int, h: int, levels: int, batch: int = 1, mode: int = DWT2_F32) -> int:

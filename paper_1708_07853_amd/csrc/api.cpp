@@ -2,10 +2,12 @@
 // workspace layout and the per-level launch sequence.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "dwt2_internal.h"
@@ -60,15 +62,62 @@ size_t ws_per_image(const Geo& g) {
   return a + b;
 }
 
-int choose_seg(int ns_h, int64_t strips_times_batch) {
-  static const int forced = [] {
-    const char* e = getenv("DWT2_SEG");
-    return e ? atoi(e) : 0;
-  }();
-  if (forced > 0) return forced;
-  int seg = 64;
-  while (seg > 1 && strips_times_batch * ((ns_h + seg - 1) / seg) < 4096) seg >>= 1;
-  return seg;
+static int env_int(const char* name) {
+  const char* e = getenv(name);
+  return e ? atoi(e) : 0;
+}
+
+// Compute units of the current device (cached per device).
+static int device_cus() {
+  static std::mutex mu;
+  static int cache[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!cache[dev]) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+    cache[dev] = n;
+  }
+  return cache[dev];
+}
+
+// Resident waves of the level kernel over the whole device (cached).
+static int64_t resident_waves(int dir, int mode, int ch) {
+  static std::mutex mu;
+  static int cache[3][2][3] = {};
+  const int ci = ch >= 4 ? 2 : (ch >= 2 ? 1 : 0);
+  int blocks;
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    int& c = cache[dir][mode][ci];
+    if (!c) {
+      c = level_blocks_per_cu(dir, mode, ch);
+      if (c <= 0) c = 2;
+    }
+    blocks = c;
+  }
+  return (int64_t)blocks * kWavesPerBlock * device_cus();
+}
+
+// Segment height (quadruple rows per work item) and chunk size: enough
+// segments for one round of resident waves, each a whole number of chunk
+// pairs where possible.
+static std::atomic<int> g_forced_seg{-1}, g_forced_ch{-1};
+
+Tiling choose_tiling(int dir, int mode, int ns_h, int64_t strips_times_batch) {
+  if (g_forced_seg.load() < 0) g_forced_seg.store(env_int("DWT2_SEG") > 0 ? env_int("DWT2_SEG") : 0);
+  if (g_forced_ch.load() < 0) g_forced_ch.store(env_int("DWT2_CH") > 0 ? env_int("DWT2_CH") : 0);
+  const int forced_seg = g_forced_seg.load(), forced_ch = g_forced_ch.load();
+  Tiling t;
+  t.ch = forced_ch > 0 ? (forced_ch >= 4 ? 4 : (forced_ch >= 2 ? 2 : 1)) : 2;
+  const int64_t slots = resident_waves(dir, mode, t.ch);
+  const int64_t per_strip = slots / strips_times_batch > 1 ? slots / strips_times_batch : 1;
+  int seg = (int)((ns_h + per_strip - 1) / per_strip);
+  if (forced_ch <= 0 && seg < 2 * t.ch) t.ch = 1;
+  seg = (seg + 2 * t.ch - 1) / (2 * t.ch) * (2 * t.ch);
+  t.seg = forced_seg > 0 ? forced_seg : seg;
+  return t;
 }
 
 void fill_level(LevelDesc& d, int W, int H, int seg) {
@@ -77,6 +126,22 @@ void fill_level(LevelDesc& d, int W, int H, int seg) {
   d.seg = seg;
   d.nstrips = num_strips(W);
   d.nsegs = (ceil_half(H) + seg - 1) / seg;
+}
+
+static bool al(const void* p, unsigned bytes) { return ((uintptr_t)p & (bytes - 1)) == 0; }
+
+// Whether the vector path's alignment assumptions hold for this level:
+// 16-byte pixel rows and 8-byte band rows (even band origins).
+int fast_layout(int dir, const LevelLaunch& a, int batch, int W) {
+  const LevelDesc& d = a.d;
+  const bool many = batch > 1;
+  const bool px_ok = al(dir == kFwd ? d.pix_in : d.pix_out, 16) && d.pix_stride % 4 == 0 &&
+                     (!many || a.pix_bstride % 4 == 0);
+  const bool ll_ok = al(dir == kFwd ? d.ll_out : d.ll_in, 8) && d.ll_stride % 2 == 0 &&
+                     (!many || a.ll_bstride % 2 == 0);
+  const bool band_ok = al(dir == kFwd ? d.band_out : d.band_in, 8) && d.band_stride % 2 == 0 &&
+                       (!many || a.band_bstride % 2 == 0) && ceil_half(W) % 2 == 0;
+  return px_ok && ll_ok && band_ok;
 }
 
 // LL_m lives in buffer A (m odd) or B (m even) of each image's workspace slice.
@@ -95,7 +160,8 @@ int run_levels(int dir, const Call& c, const Geo& g, void* stream) {
     memset(&a, 0, sizeof a);
     const int W = g.w[k - 1], H = g.h[k - 1];
     const int64_t strips_batch = (int64_t)num_strips(W) * c.batch;
-    fill_level(a.d, W, H, choose_seg(ceil_half(H), strips_batch));
+    const Tiling t = choose_tiling(dir, c.mode, ceil_half(H), strips_batch);
+    fill_level(a.d, W, H, t.seg);
     // pixels of the level input: the image (k = 1) or LL_{k-1}
     const bool px_is_image = (k == 1);
     char* px = px_is_image ? (dir == kFwd ? const_cast<char*>(c.src) : c.dst) : ll_buf(c, g, k - 1);
@@ -121,7 +187,8 @@ int run_levels(int dir, const Call& c, const Geo& g, void* stream) {
     }
     a.items_per_image = a.d.nstrips * a.d.nsegs;
     a.items = (int64_t)a.items_per_image * c.batch;
-    const int err = launch_level(dir, c.mode, 4, a, stream);
+    a.d.fast_ok = fast_layout(dir, a, c.batch, W);
+    const int err = launch_level(dir, c.mode, t.ch, a, stream);
     if (err != hipSuccess)
       return fail(DWT2_ERR_HIP, "level %d launch failed: %s", k, hipGetErrorString((hipError_t)err));
   }
@@ -203,5 +270,14 @@ const char* dwt2_status_string(int status) {
 }
 
 const char* dwt2_last_error(void) { return g_last_error.c_str(); }
+
+int dwt2_set_tiling(int32_t seg, int32_t chunk) {
+  clear_error();
+  if (seg < 0 || seg > (1 << 20) || !(chunk == 0 || chunk == 1 || chunk == 2 || chunk == 4))
+    return fail(DWT2_ERR_ARG, "seg must be >= 0 and chunk one of 0, 1, 2, 4");
+  g_forced_seg.store(seg);
+  g_forced_ch.store(chunk);
+  return DWT2_OK;
+}
 
 }  // extern "C"

@@ -9,14 +9,11 @@
 
 namespace dwt2 {
 
-// A wave (64 lanes) owns a vertical strip of quadruple columns; each lane owns
-// two adjacent quadruples (four pixel columns, one 16-byte vector per pixel
-// row).  Of the 128 quadruple columns a wave loads, the first one and the last
-// one only feed their neighbours, so a strip writes 126 columns and strip s
-// writes quadruple columns [126 s - 1, 126 s + 125).
+// A wave (64 lanes) owns a vertical strip of 128 quadruple columns; each lane
+// owns two adjacent quadruples (four pixel columns, one 16-byte vector per
+// pixel row), so strip s covers quadruple columns [128 s, 128 s + 128).
 constexpr int kWave = 64;
-constexpr int kStripLoaded = 128;
-constexpr int kStripOut = 126;
+constexpr int kStripQuads = 128;
 constexpr int kWavesPerBlock = 4;
 constexpr int kBlock = kWave * kWavesPerBlock;
 
@@ -43,7 +40,7 @@ struct LevelDesc {
   int32_t seg;          // quadruple rows per work item
   int32_t nstrips;
   int32_t nsegs;
-  int32_t pad_;
+  int32_t fast_ok;      // pointers/strides aligned for the vector path
 };
 
 // Plain (uniform-geometry) launch of one level over a batch of images.
@@ -59,11 +56,7 @@ struct LevelLaunch {
 
 inline int ceil_half(int n) { return (n + 1) >> 1; }
 
-inline int num_strips(int W) {
-  // strip s writes quadruple columns [126 s - 1, 126 s + 125) of ceil(W/2)
-  const int ns = ceil_half(W);
-  return (ns + 1 + kStripOut - 1) / kStripOut;
-}
+inline int num_strips(int W) { return (ceil_half(W) + kStripQuads - 1) / kStripQuads; }
 
 inline int64_t ll_pitch(int w) {  // padded row pitch (elements) of an LL buffer
   return ((int64_t)w + 63) & ~(int64_t)63;
@@ -71,5 +64,7 @@ inline int64_t ll_pitch(int w) {  // padded row pitch (elements) of an LL buffer
 
 // Kernel launchers (kernels.hip).  Return hipError_t as int.
 int launch_level(int dir, int mode, int chunk, const LevelLaunch& a, void* stream);
+// Resident 256-thread blocks per CU of the level kernel (0 if unknown).
+int level_blocks_per_cu(int dir, int mode, int chunk);
 
 }  // namespace dwt2

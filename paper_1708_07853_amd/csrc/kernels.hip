@@ -1,15 +1,24 @@
 // HIP kernels for gfx950: one level of the 2-D CDF 5/3 transform with the
 // non-separable lifting scheme (§3, eq. (5)) -- forward, inverse, adjoint.
 //
-// Mapping.  A wave owns a vertical strip of 128 quadruple columns (lane l
-// holds quadruple columns 2l and 2l+1, i.e. one 16-byte vector of each pixel
-// row) and walks down a segment of quadruple rows.  Vertical neighbours stay
-// in registers from one row to the next; horizontal neighbours cross lanes
-// with one shuffle per exchanged value.  Each level therefore reads its input
-// once and writes its output once; the only synchronisation points of the
-// lifting (the "|" of eq. (5)) become lane shuffles: one exchange of the
-// right neighbour's L samples for the spatial predict and one of the left
-// neighbour's predicted values for the spatial update.
+// Mapping.  A wave owns a strip of 128 quadruple columns (lane l holds the
+// quadruples 2l and 2l+1, i.e. one 16-byte vector of each pixel row) and walks
+// down a segment of quadruple rows.  Vertical neighbours stay in registers
+// from one row to the next; horizontal neighbours cross lanes with full-wave
+// DPP shifts.  The first and last lanes also load the few samples just
+// outside the strip (per-lane halo loads), so every lane writes its two
+// quadruples and the strip's output rows are whole, aligned 512-byte runs.
+// Each level therefore reads its input once and writes its output once; the
+// synchronisation points of the lifting (the "|" of eq. (5)) become one
+// exchange of the right neighbour's L samples for the spatial predict and one
+// exchange of the left neighbour's predicted values for the spatial update.
+//
+// Memory pipeline.  Rows are fetched in chunks of CH quadruple rows; while
+// one chunk is computed the next one is already in flight (two register
+// buffers).  Interior work items (all columns inside the image, aligned, a
+// whole number of chunk pairs) run a branch-free loop so the compiler's
+// wait counts stay exact; items at the image edges take a general path with
+// folded gathers, masked stores and row guards.
 //
 // Boundaries.  Forward and inverse read the whole-sample symmetric extension
 // of their input (the interleaved coefficient array for the inverse), so the
@@ -24,6 +33,8 @@
 
 namespace dwt2 {
 namespace {
+
+constexpr int kStripQ = 128;  // quadruple columns per wave
 
 template <typename T>
 struct V4 {
@@ -43,102 +54,53 @@ __device__ __forceinline__ int fold_idx(int p, int n) {
   return p >= n ? m - p : p;
 }
 
-// Row of band coefficients for interleaved index p of parity `par` (0: L, 1: H)
-// of an axis of length n, following the symmetric extension.
-__device__ __forceinline__ int band_idx(int q, int n, int par) {
-  return (fold_idx(2 * q + par, n) - par) >> 1;
-}
+// Band column of quadruple column q for parity `par` (0: L, 1: H) on an axis
+// of length n, following the symmetric extension of the interleaved array.
+__device__ __forceinline__ int band_idx(int q, int n, int par) { return (fold_idx(2 * q + par, n) - par) >> 1; }
 
-__device__ __forceinline__ bool aligned(const void* p, unsigned bytes) {
-  return ((uintptr_t)p & (bytes - 1)) == 0;
-}
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
+// Lane exchange by full-wave DPP shifts: from_next gives lane i the value of
+// lane i+1 (wave_shl:1), from_prev the value of lane i-1 (wave_shr:1); the
+// lane without a source receives 0.  A lane reads its neighbour's register
+// only if the neighbour is active, so every exchange runs in wave-uniform
+// control flow (nxt / prv below), and lanes 0 and 63 substitute their halo
+// values afterwards with a select.
+__device__ __forceinline__ int dpp_next(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, false); }
+__device__ __forceinline__ int dpp_prev(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, false); }
+__device__ __forceinline__ int from_next(int v) { return dpp_next(v); }
+__device__ __forceinline__ int from_prev(int v) { return dpp_prev(v); }
+__device__ __forceinline__ float from_next(float v) { return __int_as_float(dpp_next(__float_as_int(v))); }
+__device__ __forceinline__ float from_prev(float v) { return __int_as_float(dpp_prev(__float_as_int(v))); }
+// sel ? alt : neighbour value, with the exchange done by every lane
 template <typename T>
-__device__ __forceinline__ T shfl_dn(T v) {
-  return __shfl_down(v, 1, kWave);
+__device__ __forceinline__ T nxt(bool sel, T alt, T v) {
+  const T n = from_next(v);
+  return sel ? alt : n;
 }
 template <typename T>
-__device__ __forceinline__ T shfl_up(T v) {
-  return __shfl_up(v, 1, kWave);
-}
-
-// Four consecutive pixels c0..c0+3 of (folded) row r.
-template <typename T>
-__device__ __forceinline__ V4<T> load_px4(const T* base, int64_t stride, int r, int H, int c0, int W) {
-  const T* row = base + (int64_t)fold_idx(r, H) * stride;
-  V4<T> v;
-  if (c0 >= 0 && c0 + 3 < W && aligned(row + c0, 16)) {
-    const Ext4<T> t = *reinterpret_cast<const Ext4<T>*>(row + c0);
-    v.x = t.x; v.y = t.y; v.z = t.z; v.w = t.w;
-  } else {
-    v.x = row[fold_idx(c0, W)];
-    v.y = row[fold_idx(c0 + 1, W)];
-    v.z = row[fold_idx(c0 + 2, W)];
-    v.w = row[fold_idx(c0 + 3, W)];
-  }
-  return v;
-}
-
-// Two consecutive band coefficients q, q+1 of a band row with n entries
-// (n = count of that parity on an axis of length Wl), mirrored outside.
-template <typename T>
-__device__ __forceinline__ void load_band2(const T* row, int q, int n, int Wl, int par, T& vL, T& vR) {
-  if (q >= 0 && q + 1 < n && aligned(row + q, 8)) {
-    const Ext2<T> t = *reinterpret_cast<const Ext2<T>*>(row + q);
-    vL = t.x; vR = t.y;
-  } else {
-    vL = row[band_idx(q, Wl, par)];
-    vR = row[band_idx(q + 1, Wl, par)];
-  }
-}
-
-// Same, but zero outside [0, n) (adjoint: no extension).
-template <typename T>
-__device__ __forceinline__ void load_band2_zero(const T* row, int q, int n, T& vL, T& vR) {
-  if (q >= 0 && q + 1 < n && aligned(row + q, 8)) {
-    const Ext2<T> t = *reinterpret_cast<const Ext2<T>*>(row + q);
-    vL = t.x; vR = t.y;
-  } else {
-    vL = (q >= 0 && q < n) ? row[q] : T(0);
-    vR = (q + 1 >= 0 && q + 1 < n) ? row[q + 1] : T(0);
-  }
+__device__ __forceinline__ T prv(bool sel, T alt, T v) {
+  const T p = from_prev(v);
+  return sel ? alt : p;
 }
 
 template <typename T>
-__device__ __forceinline__ void store2(T* row, int q, T vL, T vR, bool okL, bool okR) {
-  if (okL && okR && aligned(row + q, 8)) {
-    Ext2<T> t;
-    t.x = vL; t.y = vR;
-    *reinterpret_cast<Ext2<T>*>(row + q) = t;
-  } else {
-    if (okL) row[q] = vL;
-    if (okR) row[q + 1] = vR;
-  }
+__device__ __forceinline__ void st2(T* p, T a, T b) {
+  Ext2<T> t;
+  t.x = a;
+  t.y = b;
+  *reinterpret_cast<Ext2<T>*>(p) = t;
 }
-
-// Pixels c0..c0+3 of one output row; quadruple L covers c0, c0+1 and R covers
-// c0+2, c0+3.
 template <typename T>
-__device__ __forceinline__ void store_px4(T* row, int c0, int W, V4<T> v, bool okL, bool okR) {
-  if (okL && okR && c0 >= 0 && c0 + 3 < W && aligned(row + c0, 16)) {
-    Ext4<T> t;
-    t.x = v.x; t.y = v.y; t.z = v.z; t.w = v.w;
-    *reinterpret_cast<Ext4<T>*>(row + c0) = t;
-  } else {
-    if (okL) {
-      if (c0 >= 0 && c0 < W) row[c0] = v.x;
-      if (c0 + 1 >= 0 && c0 + 1 < W) row[c0 + 1] = v.y;
-    }
-    if (okR) {
-      if (c0 + 2 >= 0 && c0 + 2 < W) row[c0 + 2] = v.z;
-      if (c0 + 3 >= 0 && c0 + 3 < W) row[c0 + 3] = v.w;
-    }
-  }
+__device__ __forceinline__ void st4(T* p, const V4<T>& v) {
+  Ext4<T> t;
+  t.x = v.x; t.y = v.y; t.z = v.z; t.w = v.w;
+  *reinterpret_cast<Ext4<T>*>(p) = t;
 }
 
 // ---------------------------------------------------------------------------
 // Per-quadruple arithmetic.  Every kernel variant evaluates exactly these
-// expressions, so results do not depend on tiling or scheduling.
+// expressions, so results do not depend on tiling, paths or scheduling.
 // Neighbour suffixes: R = next column, D = next row, L = previous column,
 // U = previous row.
 // ---------------------------------------------------------------------------
@@ -201,8 +163,8 @@ __device__ __forceinline__ void f32_inv_predict(float a, float aR, float aD, flo
   d = __fmaf_rn(0.25f, sh + (aD + aDR), __fmaf_rn(0.5f, bp + bpD, __fmaf_rn(0.5f, cp + cpR, dp)));
 }
 
-// Integer inverse, first half (undo vertical then horizontal update):
-// a1 = a2 - floor((c2U + c2 + 2)/4), b1 = b2 - floor((d2U + d2 + 2)/4),
+// Integer inverse, first half (undo the vertical then the horizontal update):
+// b1 = b2 - floor((d2U + d2 + 2)/4); a1 = a2 - floor((c2U + c2 + 2)/4),
 // a = a1 - floor((b1L + b1 + 2)/4), c1 = c2 - floor((d2L + d2 + 2)/4).
 __device__ __forceinline__ int i32_inv_b1(int b2, int d2U, int d2) { return b2 - ((d2U + d2 + 2) >> 2); }
 __device__ __forceinline__ void i32_inv_update(int a2, int c2U, int c2, int b1L, int b1, int d2L, int d2, int& a,
@@ -211,7 +173,7 @@ __device__ __forceinline__ void i32_inv_update(int a2, int c2U, int c2, int b1L,
   a = a1 - ((b1L + b1 + 2) >> 2);
   c1 = c2 - ((d2L + d2 + 2) >> 2);
 }
-// Second half (undo vertical then horizontal predict).
+// Second half (undo the vertical then the horizontal predict).
 __device__ __forceinline__ int i32_inv_c(int c1, int a, int aD) { return c1 + ((a + aD) >> 1); }
 __device__ __forceinline__ void i32_inv_predict(int a, int aR, int b1, int b1D, int c, int cR, int d2, int& b,
                                                 int& d) {
@@ -250,7 +212,7 @@ __device__ __forceinline__ AxisW axis_weights(int m, int n) {
 __device__ __forceinline__ void f32_adj_a(float ga, float gaR, float gaD, float gaDR, float gb, float gbD,
                                           float gc, float gcR, float gd, AxisW h, AxisW v, float& gb1, float& gc1,
                                           float& gd1) {
-  const float th = h.alpha * ga + h.beta * gaR;      // U^T_h ga (x4)
+  const float th = h.alpha * ga + h.beta * gaR;  // U^T_h ga (x4)
   const float thD = h.alpha * gaD + h.beta * gaDR;
   gb1 = __fmaf_rn(0.25f, th, gb);
   gc1 = __fmaf_rn(0.25f, v.alpha * ga + v.beta * gaD, gc);
@@ -271,13 +233,14 @@ __device__ __forceinline__ void f32_adj_b(float ga, float gb1L, float gb1, float
 }
 
 // ---------------------------------------------------------------------------
-// Work item = (image, segment of quadruple rows, strip); one wave each.
+// Work items
 // ---------------------------------------------------------------------------
 struct Item {
   int W, H, ns_w, nd_w, ns_h, nd_h;
-  int qL;        // global quadruple column of this lane's first quadruple
-  int I0, I1;    // quadruple rows written
-  bool outL, outR;
+  int lane;
+  int qL;       // global quadruple column of this lane's first quadruple
+  int I0, I1;   // quadruple rows written
+  bool first, last;
 };
 
 __device__ __forceinline__ Item make_item(const LevelDesc& d, int strip, int seg, int lane) {
@@ -285,343 +248,595 @@ __device__ __forceinline__ Item make_item(const LevelDesc& d, int strip, int seg
   it.W = d.W; it.H = d.H;
   it.ns_w = (d.W + 1) >> 1; it.nd_w = d.W >> 1;
   it.ns_h = (d.H + 1) >> 1; it.nd_h = d.H >> 1;
-  it.qL = kStripOut * strip - 2 + 2 * lane;
+  it.lane = lane;
+  it.qL = kStripQ * strip + 2 * lane;
   it.I0 = seg * d.seg;
   it.I1 = min(it.I0 + d.seg, it.ns_h);
-  it.outL = lane != 0;
-  it.outR = lane != kWave - 1 && it.qL + 1 >= 0;
+  it.first = lane == 0;
+  it.last = lane == kWave - 1;
   return it;
 }
 
-// ----------------------------------------------------------------- forward
-template <int CH>
-__device__ void fwd_f32(const LevelDesc& d, const float* __restrict__ px, float* __restrict__ ll,
-                        float* __restrict__ band, const Item& it) {
-  const int W = it.W, H = it.H, c0 = 2 * it.qL;
-  const int64_t ps = d.pix_stride, ls = d.ll_stride, bs = d.band_stride;
-  const int qL = it.qL, qR = qL + 1;
-  const bool llL = it.outL && qL < it.ns_w, llR = it.outR && qR < it.ns_w;
-  const bool hlL = it.outL && qL < it.nd_w, hlR = it.outR && qR < it.nd_w;
-
-  // prologue: predicted values of quadruple row I0 - 1
-  V4<float> E = load_px4(px, ps, 2 * it.I0 - 2, H, c0, W);
-  V4<float> O = load_px4(px, ps, 2 * it.I0 - 1, H, c0, W);
-  V4<float> E1 = load_px4(px, ps, 2 * it.I0, H, c0, W);
-  float aN = shfl_dn(E.x), aDN = shfl_dn(E1.x), cN = shfl_dn(O.x);
-  float cpU_L, cpU_R, dpU_L, dpU_R, dpUL_L;
-  {
-    float bpL, bpR;
-    f32_predict(E.x, E.z, E1.x, E1.z, E.y, E1.y, O.x, O.z, O.y, bpL, cpU_L, dpU_L);
-    f32_predict(E.z, aN, E1.z, aDN, E.w, E1.w, O.z, cN, O.w, bpR, cpU_R, dpU_R);
-    dpUL_L = shfl_up(dpU_R);
-  }
-  E = E1;
-  aN = aDN;
-
-  for (int i0 = it.I0; i0 < it.I1; i0 += CH) {
-    V4<float> Ob[CH], Eb[CH];
+// Double-buffered row pipeline.  The caller has issued the loads of chunk A
+// (rows I0 .. I0+CH-1) before its prologue.  Fast items have a positive
+// multiple of 2*CH rows and run without guards; the others are guarded.
+template <int CH, bool FAST, typename Buf, typename LoadF, typename RowF>
+__device__ __forceinline__ void run_rows(int I0, int I1, Buf& A, Buf& B, LoadF&& load_chunk, RowF&& row) {
+  int i0 = I0;
+  if constexpr (FAST) {
+    const int npairs = (I1 - I0) / (2 * CH);
+    for (int p = 1; p < npairs; ++p) {
+      load_chunk(B, i0 + CH);
 #pragma unroll
-    for (int m = 0; m < CH; ++m) {
-      Ob[m] = load_px4(px, ps, 2 * (i0 + m) + 1, H, c0, W);
-      Eb[m] = load_px4(px, ps, 2 * (i0 + m) + 2, H, c0, W);
+      for (int m = 0; m < CH; ++m) row(A, m, i0 + m);
+      load_chunk(A, i0 + 2 * CH);
+#pragma unroll
+      for (int m = 0; m < CH; ++m) row(B, m, i0 + CH + m);
+      i0 += 2 * CH;
     }
+    load_chunk(B, i0 + CH);
 #pragma unroll
-    for (int m = 0; m < CH; ++m) {
-      const int i = i0 + m;
-      if (i < it.I1) {
-        const V4<float> o = Ob[m], e1 = Eb[m];
-        const float aDN1 = shfl_dn(e1.x), cN1 = shfl_dn(o.x);
-        float bpL, cpL, dpL, bpR, cpR, dpR;
-        f32_predict(E.x, E.z, e1.x, e1.z, E.y, e1.y, o.x, o.z, o.y, bpL, cpL, dpL);
-        f32_predict(E.z, aN, e1.z, aDN1, E.w, e1.w, o.z, cN1, o.w, bpR, cpR, dpR);
-        const float bpP = shfl_up(bpR), dpP = shfl_up(dpR);
-        float llv_L, hlv_L, lhv_L, llv_R, hlv_R, lhv_R;
-        f32_update(E.x, bpP, bpL, cpU_L, cpL, dpUL_L, dpU_L, dpP, dpL, llv_L, hlv_L, lhv_L);
-        f32_update(E.z, bpL, bpR, cpU_R, cpR, dpU_L, dpU_R, dpL, dpR, llv_R, hlv_R, lhv_R);
-        store2(ll + (int64_t)i * ls, qL, llv_L, llv_R, llL, llR);
-        store2(band + (int64_t)i * bs + it.ns_w, qL, hlv_L, hlv_R, hlL, hlR);
-        if (i < it.nd_h) {
-          float* r = band + (int64_t)(it.ns_h + i) * bs;
-          store2(r, qL, lhv_L, lhv_R, llL, llR);
-          store2(r + it.ns_w, qL, dpL, dpR, hlL, hlR);
-        }
-        cpU_L = cpL; cpU_R = cpR; dpU_L = dpL; dpU_R = dpR; dpUL_L = dpP;
-        E = e1;
-        aN = aDN1;
-      }
+    for (int m = 0; m < CH; ++m) row(A, m, i0 + m);
+#pragma unroll
+    for (int m = 0; m < CH; ++m) row(B, m, i0 + CH + m);
+  } else {
+    for (;;) {
+#pragma unroll
+      for (int m = 0; m < CH; ++m)
+        if (i0 + m < I1) row(A, m, i0 + m);
+      i0 += CH;
+      if (i0 >= I1) break;
+      load_chunk(A, i0);
     }
   }
 }
 
-template <int CH>
+// ---------------------------------------------------------------- forward
+// Pixel rows: four pixels per lane plus two halo pixels (lane 0: the two
+// columns left of the strip; lane 63: the column right of it).
+template <typename T, bool FAST>
+struct PxLoader {
+  const T* base;
+  int64_t stride;
+  int H;
+  int c0;
+  int col[4];
+  int hc0, hc1;
+  __device__ __forceinline__ void load(int r, V4<T>& m, T& h0, T& h1) const {
+    const T* row = base + (int64_t)fold_idx(r, H) * stride;
+    if constexpr (FAST) {
+      const Ext4<T> t = *reinterpret_cast<const Ext4<T>*>(row + c0);
+      m.x = t.x; m.y = t.y; m.z = t.z; m.w = t.w;
+    } else {
+      m.x = row[col[0]]; m.y = row[col[1]]; m.z = row[col[2]]; m.w = row[col[3]];
+    }
+    h0 = row[hc0];
+    h1 = row[hc1];
+  }
+};
+
+template <typename T, bool FAST>
+__device__ __forceinline__ PxLoader<T, FAST> px_loader(const T* base, int64_t stride, const Item& it) {
+  PxLoader<T, FAST> L;
+  L.base = base; L.stride = stride; L.H = it.H;
+  L.c0 = 2 * it.qL;
+  for (int k = 0; k < 4; ++k) L.col[k] = fold_idx(L.c0 + k, it.W);
+  if (it.first) {
+    L.hc0 = fold_idx(L.c0 - 2, it.W);
+    L.hc1 = fold_idx(L.c0 - 1, it.W);
+  } else if (it.last) {
+    L.hc0 = L.hc1 = fold_idx(L.c0 + 4, it.W);
+  } else {
+    L.hc0 = L.hc1 = L.col[0];
+  }
+  return L;
+}
+
+template <typename T, int CH>
+struct PxBuf {
+  V4<T> o[CH], e[CH];
+  T ho0[CH], ho1[CH], he0[CH], he1[CH];
+};
+
+// Stores of one row of the four bands (forward).
+template <typename T, bool FAST>
+struct BandStore {
+  T* ll;
+  int64_t ls;
+  T* band;
+  int64_t bs;
+  int ns_w, nd_w, ns_h, nd_h, qL;
+  bool okL_s, okR_s, okL_d, okR_d;  // general path: quadruple column valid for L / H parity
+  __device__ __forceinline__ void put(int i, T llL, T llR, T hlL, T hlR, T lhL, T lhR, T hhL, T hhR) const {
+    T* rl = ll + (int64_t)i * ls + qL;
+    T* rh = band + (int64_t)i * bs + ns_w + qL;
+    if constexpr (FAST) {
+      st2(rl, llL, llR);
+      st2(rh, hlL, hlR);
+      T* r2 = band + (int64_t)(ns_h + i) * bs + qL;
+      st2(r2, lhL, lhR);
+      st2(r2 + ns_w, hhL, hhR);
+    } else {
+      if (okL_s) rl[0] = llL;
+      if (okR_s) rl[1] = llR;
+      if (okL_d) rh[0] = hlL;
+      if (okR_d) rh[1] = hlR;
+      if (i < nd_h) {
+        T* r2 = band + (int64_t)(ns_h + i) * bs + qL;
+        if (okL_s) r2[0] = lhL;
+        if (okR_s) r2[1] = lhR;
+        if (okL_d) r2[ns_w] = hhL;
+        if (okR_d) r2[ns_w + 1] = hhR;
+      }
+    }
+  }
+};
+
+template <typename T, bool FAST>
+__device__ __forceinline__ BandStore<T, FAST> band_store(T* ll, int64_t ls, T* band, int64_t bs, const Item& it) {
+  BandStore<T, FAST> S;
+  S.ll = ll; S.ls = ls; S.band = band; S.bs = bs;
+  S.ns_w = it.ns_w; S.nd_w = it.nd_w; S.ns_h = it.ns_h; S.nd_h = it.nd_h; S.qL = it.qL;
+  S.okL_s = it.qL < it.ns_w; S.okR_s = it.qL + 1 < it.ns_w;
+  S.okL_d = it.qL < it.nd_w; S.okR_d = it.qL + 1 < it.nd_w;
+  return S;
+}
+
+template <int CH, bool FAST>
+__device__ void fwd_f32(const LevelDesc& d, const float* __restrict__ px, float* __restrict__ ll,
+                        float* __restrict__ band, const Item& it) {
+  const PxLoader<float, FAST> L = px_loader<float, FAST>(px, d.pix_stride, it);
+  const BandStore<float, FAST> S = band_store<float, FAST>(ll, d.ll_stride, band, d.band_stride, it);
+  const bool first = it.first, last = it.last;
+  using Buf = PxBuf<float, CH>;
+  auto load_chunk = [&](Buf& b, int i0) {
+#pragma unroll
+    for (int m = 0; m < CH; ++m) {
+      L.load(2 * (i0 + m) + 1, b.o[m], b.ho0[m], b.ho1[m]);
+      L.load(2 * (i0 + m) + 2, b.e[m], b.he0[m], b.he1[m]);
+    }
+  };
+  V4<float> E, O, E1;
+  float hE0, hE1, hO0, hO1, hN0, hN1;
+  L.load(2 * it.I0 - 2, E, hE0, hE1);
+  L.load(2 * it.I0 - 1, O, hO0, hO1);
+  L.load(2 * it.I0, E1, hN0, hN1);
+  Buf A, B;
+  load_chunk(A, it.I0);
+
+  // prologue: predicted values of quadruple row I0 - 1
+  float cpU_L, cpU_R, dpU_L, dpU_R, dpUL_L;
+  {
+    const float aN = nxt(last, hE0, E.x), aDN = nxt(last, hN0, E1.x);
+    const float cN = nxt(last, hO0, O.x);
+    float bpL, bpR, bpH, cpH, dpH;
+    f32_predict(E.x, E.z, E1.x, E1.z, E.y, E1.y, O.x, O.z, O.y, bpL, cpU_L, dpU_L);
+    f32_predict(E.z, aN, E1.z, aDN, E.w, E1.w, O.z, cN, O.w, bpR, cpU_R, dpU_R);
+    f32_predict(hE0, E.x, hN0, E1.x, hE1, hN1, hO0, O.x, hO1, bpH, cpH, dpH);
+    dpUL_L = prv(first, dpH, dpU_R);
+  }
+  E = E1;
+  hE0 = hN0;
+  hE1 = hN1;
+  float aN = nxt(last, hE0, E.x);
+
+  auto row = [&](const Buf& b, int m, int i) {
+    const V4<float>& o = b.o[m];
+    const V4<float>& e1 = b.e[m];
+    const float aDN = nxt(last, b.he0[m], e1.x);
+    const float cN = nxt(last, b.ho0[m], o.x);
+    float bpL, cpL, dpL, bpR, cpR, dpR, bpH, cpH, dpH;
+    f32_predict(E.x, E.z, e1.x, e1.z, E.y, e1.y, o.x, o.z, o.y, bpL, cpL, dpL);
+    f32_predict(E.z, aN, e1.z, aDN, E.w, e1.w, o.z, cN, o.w, bpR, cpR, dpR);
+    f32_predict(hE0, E.x, b.he0[m], e1.x, hE1, b.he1[m], b.ho0[m], o.x, b.ho1[m], bpH, cpH, dpH);
+    const float bpP = prv(first, bpH, bpR);
+    const float dpP = prv(first, dpH, dpR);
+    float llL, hlL, lhL, llR, hlR, lhR;
+    f32_update(E.x, bpP, bpL, cpU_L, cpL, dpUL_L, dpU_L, dpP, dpL, llL, hlL, lhL);
+    f32_update(E.z, bpL, bpR, cpU_R, cpR, dpU_L, dpU_R, dpL, dpR, llR, hlR, lhR);
+    S.put(i, llL, llR, hlL, hlR, lhL, lhR, dpL, dpR);
+    cpU_L = cpL; cpU_R = cpR; dpU_L = dpL; dpU_R = dpR; dpUL_L = dpP;
+    E = e1;
+    hE0 = b.he0[m];
+    hE1 = b.he1[m];
+    aN = aDN;
+  };
+  run_rows<CH, FAST>(it.I0, it.I1, A, B, load_chunk, row);
+}
+
+template <int CH, bool FAST>
 __device__ void fwd_i32(const LevelDesc& d, const int* __restrict__ px, int* __restrict__ ll,
                         int* __restrict__ band, const Item& it) {
-  const int W = it.W, H = it.H, c0 = 2 * it.qL;
-  const int64_t ps = d.pix_stride, ls = d.ll_stride, bs = d.band_stride;
-  const int qL = it.qL, qR = qL + 1;
-  const bool llL = it.outL && qL < it.ns_w, llR = it.outR && qR < it.ns_w;
-  const bool hlL = it.outL && qL < it.nd_w, hlR = it.outR && qR < it.nd_w;
+  const PxLoader<int, FAST> L = px_loader<int, FAST>(px, d.pix_stride, it);
+  const BandStore<int, FAST> S = band_store<int, FAST>(ll, d.ll_stride, band, d.band_stride, it);
+  const bool first = it.first, last = it.last;
+  using Buf = PxBuf<int, CH>;
+  auto load_chunk = [&](Buf& b, int i0) {
+#pragma unroll
+    for (int m = 0; m < CH; ++m) {
+      L.load(2 * (i0 + m) + 1, b.o[m], b.ho0[m], b.ho1[m]);
+      L.load(2 * (i0 + m) + 2, b.e[m], b.he0[m], b.he1[m]);
+    }
+  };
+  V4<int> E, O, E1;
+  int hE0, hE1, hO0, hO1, hN0, hN1;
+  L.load(2 * it.I0 - 2, E, hE0, hE1);
+  L.load(2 * it.I0 - 1, O, hO0, hO1);
+  L.load(2 * it.I0, E1, hN0, hN1);
+  Buf A, B;
+  load_chunk(A, it.I0);
 
-  V4<int> E = load_px4(px, ps, 2 * it.I0 - 2, H, c0, W);
-  V4<int> O = load_px4(px, ps, 2 * it.I0 - 1, H, c0, W);
-  V4<int> E1 = load_px4(px, ps, 2 * it.I0, H, c0, W);
-  int aN = shfl_dn(E.x), aDN = shfl_dn(E1.x), cN = shfl_dn(O.x);
   int c2U_L, c2U_R, d2U_L, d2U_R;
   {
-    int b1L, c1L, b1R, c1R;
+    const int aN = nxt(last, hE0, E.x), aDN = nxt(last, hN0, E1.x);
+    const int cN = nxt(last, hO0, O.x);
+    int b1L, c1L, b1R, c1R, b1H, c1H, d2H;
     i32_predict(E.x, E.z, E1.x, E1.z, E.y, E1.y, O.x, O.z, O.y, b1L, c1L, d2U_L);
     i32_predict(E.z, aN, E1.z, aDN, E.w, E1.w, O.z, cN, O.w, b1R, c1R, d2U_R);
-    const int d2P = shfl_up(d2U_R);
+    i32_predict(hE0, E.x, hN0, E1.x, hE1, hN1, hO0, O.x, hO1, b1H, c1H, d2H);
+    const int d2P = prv(first, d2H, d2U_R);
     c2U_L = i32_c2(c1L, d2P, d2U_L);
     c2U_R = i32_c2(c1R, d2U_L, d2U_R);
   }
   E = E1;
-  aN = aDN;
+  hE0 = hN0;
+  hE1 = hN1;
+  int aN = nxt(last, hE0, E.x);
 
-  for (int i0 = it.I0; i0 < it.I1; i0 += CH) {
-    V4<int> Ob[CH], Eb[CH];
-#pragma unroll
-    for (int m = 0; m < CH; ++m) {
-      Ob[m] = load_px4(px, ps, 2 * (i0 + m) + 1, H, c0, W);
-      Eb[m] = load_px4(px, ps, 2 * (i0 + m) + 2, H, c0, W);
-    }
-#pragma unroll
-    for (int m = 0; m < CH; ++m) {
-      const int i = i0 + m;
-      if (i < it.I1) {
-        const V4<int> o = Ob[m], e1 = Eb[m];
-        const int aDN1 = shfl_dn(e1.x), cN1 = shfl_dn(o.x);
-        int b1L, c1L, d2L, b1R, c1R, d2R;
-        i32_predict(E.x, E.z, e1.x, e1.z, E.y, e1.y, o.x, o.z, o.y, b1L, c1L, d2L);
-        i32_predict(E.z, aN, e1.z, aDN1, E.w, e1.w, o.z, cN1, o.w, b1R, c1R, d2R);
-        const int b1P = shfl_up(b1R), d2P = shfl_up(d2R);
-        const int c2L = i32_c2(c1L, d2P, d2L), c2R = i32_c2(c1R, d2L, d2R);
-        int llv_L, hlv_L, llv_R, hlv_R;
-        i32_update(E.x, b1P, b1L, c2U_L, c2L, d2U_L, d2L, llv_L, hlv_L);
-        i32_update(E.z, b1L, b1R, c2U_R, c2R, d2U_R, d2R, llv_R, hlv_R);
-        store2(ll + (int64_t)i * ls, qL, llv_L, llv_R, llL, llR);
-        store2(band + (int64_t)i * bs + it.ns_w, qL, hlv_L, hlv_R, hlL, hlR);
-        if (i < it.nd_h) {
-          int* r = band + (int64_t)(it.ns_h + i) * bs;
-          store2(r, qL, c2L, c2R, llL, llR);
-          store2(r + it.ns_w, qL, d2L, d2R, hlL, hlR);
-        }
-        c2U_L = c2L; c2U_R = c2R; d2U_L = d2L; d2U_R = d2R;
-        E = e1;
-        aN = aDN1;
+  auto row = [&](const Buf& b, int m, int i) {
+    const V4<int>& o = b.o[m];
+    const V4<int>& e1 = b.e[m];
+    const int aDN = nxt(last, b.he0[m], e1.x);
+    const int cN = nxt(last, b.ho0[m], o.x);
+    int b1L, c1L, d2L, b1R, c1R, d2R, b1H, c1H, d2H;
+    i32_predict(E.x, E.z, e1.x, e1.z, E.y, e1.y, o.x, o.z, o.y, b1L, c1L, d2L);
+    i32_predict(E.z, aN, e1.z, aDN, E.w, e1.w, o.z, cN, o.w, b1R, c1R, d2R);
+    i32_predict(hE0, E.x, b.he0[m], e1.x, hE1, b.he1[m], b.ho0[m], o.x, b.ho1[m], b1H, c1H, d2H);
+    const int b1P = prv(first, b1H, b1R);
+    const int d2P = prv(first, d2H, d2R);
+    const int c2L = i32_c2(c1L, d2P, d2L), c2R = i32_c2(c1R, d2L, d2R);
+    int llL, hlL, llR, hlR;
+    i32_update(E.x, b1P, b1L, c2U_L, c2L, d2U_L, d2L, llL, hlL);
+    i32_update(E.z, b1L, b1R, c2U_R, c2R, d2U_R, d2R, llR, hlR);
+    S.put(i, llL, llR, hlL, hlR, c2L, c2R, d2L, d2R);
+    c2U_L = c2L; c2U_R = c2R; d2U_L = d2L; d2U_R = d2R;
+    E = e1;
+    hE0 = b.he0[m];
+    hE1 = b.he1[m];
+    aN = aDN;
+  };
+  run_rows<CH, FAST>(it.I0, it.I1, A, B, load_chunk, row);
+}
+
+// ------------------------------------------------------- inverse / adjoint
+// Band rows for this lane's two quadruples plus two halo values per part
+// (even part: LL and HL rows; odd part: LH and HH rows).  MIRROR reads the
+// symmetric extension of the interleaved coefficients (inverse); otherwise
+// values outside the bands are zero (adjoint).
+template <typename T, bool FAST, bool MIRROR>
+struct BandLoader {
+  const T* ll;
+  int64_t ls;
+  const T* band;
+  int64_t bs;
+  int H, ns_h, nd_h, ns_w, qL;
+  int cl0, cl1, ch0, ch1;  // general path: columns of quads qL, qL+1 (L / H parity bands)
+  bool zl0, zl1, zh0, zh1; // general path, zero fill: column inside its band
+  int hp0, hp1;            // halo band parity
+  int hc0, hc1;            // halo columns (inside the band)
+  bool hv0, hv1;           // zero fill: halo inside the band
+
+  __device__ __forceinline__ void pair(const T* rl, const T* rh, T& lL, T& lR, T& hL, T& hR) const {
+    if constexpr (FAST) {
+      const Ext2<T> a = *reinterpret_cast<const Ext2<T>*>(rl + qL);
+      const Ext2<T> b = *reinterpret_cast<const Ext2<T>*>(rh + qL);
+      lL = a.x; lR = a.y; hL = b.x; hR = b.y;
+    } else {
+      lL = rl[cl0]; lR = rl[cl1]; hL = rh[ch0]; hR = rh[ch1];
+      if constexpr (!MIRROR) {
+        lL = zl0 ? lL : T(0); lR = zl1 ? lR : T(0);
+        hL = zh0 ? hL : T(0); hR = zh1 ? hR : T(0);
       }
     }
   }
-}
-
-// ----------------------------------------------------------------- inverse
-// Coefficient row r of the four bands for this lane's two quadruples,
-// mirrored through the interleaved symmetric extension.
-template <typename T>
-struct Quad2 {
-  T llL, llR, hlL, hlR, lhL, lhR, hhL, hhR;
+  __device__ __forceinline__ void halos(const T* rl, const T* rh, T& h0, T& h1) const {
+    h0 = (hp0 ? rh : rl)[hc0];
+    h1 = (hp1 ? rh : rl)[hc1];
+    if constexpr (!MIRROR) {
+      h0 = hv0 ? h0 : T(0);
+      h1 = hv1 ? h1 : T(0);
+    }
+  }
+  // row r of LL and HL
+  __device__ __forceinline__ void even(int r, T& lL, T& lR, T& hL, T& hR, T& h0, T& h1) const {
+    if constexpr (!MIRROR && !FAST) {
+      if (r < 0 || r >= ns_h) {
+        lL = lR = hL = hR = h0 = h1 = T(0);
+        return;
+      }
+    }
+    const int re = MIRROR ? (fold_idx(2 * r, H) >> 1) : r;
+    const T* rl = ll + (int64_t)re * ls;
+    const T* rh = band + (int64_t)re * bs + ns_w;
+    pair(rl, rh, lL, lR, hL, hR);
+    halos(rl, rh, h0, h1);
+  }
+  // row r of LH and HH
+  __device__ __forceinline__ void odd(int r, T& lL, T& lR, T& hL, T& hR, T& h0, T& h1) const {
+    if constexpr (!MIRROR && !FAST) {
+      if (r < 0 || r >= nd_h) {
+        lL = lR = hL = hR = h0 = h1 = T(0);
+        return;
+      }
+    }
+    const int ro = MIRROR ? ((fold_idx(2 * r + 1, H) - 1) >> 1) : r;
+    const T* rl = band + (int64_t)(ns_h + ro) * bs;
+    const T* rh = rl + ns_w;
+    pair(rl, rh, lL, lR, hL, hR);
+    halos(rl, rh, h0, h1);
+  }
 };
 
-template <typename T>
-__device__ __forceinline__ void load_even(const T* ll, int64_t ls, const T* band, int64_t bs, const Item& it, int r,
-                                          Quad2<T>& q) {
-  const int re = fold_idx(2 * r, it.H) >> 1;
-  load_band2(ll + (int64_t)re * ls, it.qL, it.ns_w, it.W, 0, q.llL, q.llR);
-  load_band2(band + (int64_t)re * bs + it.ns_w, it.qL, it.nd_w, it.W, 1, q.hlL, q.hlR);
-}
-template <typename T>
-__device__ __forceinline__ void load_odd(const T* band, int64_t bs, const Item& it, int r, Quad2<T>& q) {
-  const int ro = (fold_idx(2 * r + 1, it.H) - 1) >> 1;
-  const T* row = band + (int64_t)(it.ns_h + ro) * bs;
-  load_band2(row, it.qL, it.ns_w, it.W, 0, q.lhL, q.lhR);
-  load_band2(row + it.ns_w, it.qL, it.nd_w, it.W, 1, q.hhL, q.hhR);
+// Halo assignment: (parity, quadruple column) of the two halo values of
+// lanes 0 and 63; other lanes read their own first quadruple (unused).
+template <typename T, bool FAST, bool MIRROR>
+__device__ __forceinline__ BandLoader<T, FAST, MIRROR> band_loader(const T* ll, int64_t ls, const T* band,
+                                                                   int64_t bs, const Item& it, int p0_first,
+                                                                   int p1_first, int p0_last, int p1_last) {
+  BandLoader<T, FAST, MIRROR> L;
+  L.ll = ll; L.ls = ls; L.band = band; L.bs = bs;
+  L.H = it.H; L.ns_h = it.ns_h; L.nd_h = it.nd_h; L.ns_w = it.ns_w; L.qL = it.qL;
+  const int W = it.W, ns = it.ns_w, nd = it.nd_w, q = it.qL;
+  auto col = [&](int qq, int par, bool& valid) {
+    const int n = par ? nd : ns;
+    valid = qq >= 0 && qq < n;
+    return MIRROR ? band_idx(qq, W, par) : clampi(qq, 0, n - 1);
+  };
+  L.cl0 = col(q, 0, L.zl0); L.cl1 = col(q + 1, 0, L.zl1);
+  L.ch0 = col(q, 1, L.zh0); L.ch1 = col(q + 1, 1, L.zh1);
+  int qq0 = q, qq1 = q;
+  L.hp0 = 0; L.hp1 = 0;
+  if (it.first) {
+    qq0 = q - 1; qq1 = q - 1; L.hp0 = p0_first; L.hp1 = p1_first;
+  } else if (it.last) {
+    qq0 = q + 2; qq1 = q + 2; L.hp0 = p0_last; L.hp1 = p1_last;
+  }
+  L.hc0 = col(qq0, L.hp0, L.hv0);
+  L.hc1 = col(qq1, L.hp1, L.hv1);
+  return L;
 }
 
-template <int CH>
+template <typename T, int CH>
+struct QBuf {
+  T llL[CH], llR[CH], hlL[CH], hlR[CH], he0[CH], he1[CH];
+  T lhL[CH], lhR[CH], hhL[CH], hhR[CH], ho0[CH], ho1[CH];
+};
+
+// Stores of two pixel rows (inverse / adjoint): four pixels per lane.
+template <typename T, bool FAST>
+struct PxStore {
+  T* base;
+  int64_t stride;
+  int W, H, c0;
+  __device__ __forceinline__ void row(int r, const V4<T>& v) const {
+    T* p = base + (int64_t)r * stride + c0;
+    if constexpr (FAST) {
+      st4(p, v);
+    } else {
+      if (r < H) {
+        if (c0 < W) p[0] = v.x;
+        if (c0 + 1 < W) p[1] = v.y;
+        if (c0 + 2 < W) p[2] = v.z;
+        if (c0 + 3 < W) p[3] = v.w;
+      }
+    }
+  }
+};
+
+template <int CH, bool FAST>
 __device__ void inv_f32(const LevelDesc& d, const float* __restrict__ ll, const float* __restrict__ band,
                         float* __restrict__ px, const Item& it) {
-  const int W = it.W, c0 = 2 * it.qL;
-  const int64_t ps = d.pix_stride, ls = d.ll_stride, bs = d.band_stride;
-
-  // prologue: odd part of row I0 - 1, full row I0, undo-update of row I0
-  Quad2<float> q0, q1;
-  load_odd(band, bs, it, it.I0 - 1, q0);
-  load_even(ll, ls, band, bs, it, it.I0, q1);
-  load_odd(band, bs, it, it.I0, q1);
-  float hhUL_L = shfl_up(q0.hhR);
-  float a_L, a_R, bp_L, bp_R, cp_L, cp_R;
-  float lhU_L = q0.lhL, lhU_R = q0.lhR, hhU_L = q0.hhL, hhU_R = q0.hhR;
-  {
-    const float hlP = shfl_up(q1.hlR), hhP = shfl_up(q1.hhR);
-    f32_inv_update(q1.llL, hlP, q1.hlL, lhU_L, q1.lhL, hhUL_L, hhU_L, hhP, q1.hhL, a_L, bp_L, cp_L);
-    f32_inv_update(q1.llR, q1.hlL, q1.hlR, lhU_R, q1.lhR, hhU_L, hhU_R, q1.hhL, q1.hhR, a_R, bp_R, cp_R);
-    hhUL_L = hhP;
-  }
-  float hh_L = q1.hhL, hh_R = q1.hhR;
-  lhU_L = q1.lhL; lhU_R = q1.lhR; hhU_L = q1.hhL; hhU_R = q1.hhR;
-  float aN = shfl_dn(a_L), cpN = shfl_dn(cp_L);
-
-  for (int i0 = it.I0; i0 < it.I1; i0 += CH) {
-    Quad2<float> qb[CH];
+  // halos: lane 0 -> HL / HH of quad qL-1 (parity 1); lane 63 -> quad qL+2:
+  // h0 = LL / LH (parity 0), h1 = HL / HH (parity 1)
+  const BandLoader<float, FAST, true> L = band_loader<float, FAST, true>(ll, d.ll_stride, band, d.band_stride, it,
+                                                                         1, 1, 0, 1);
+  const PxStore<float, FAST> S{px, d.pix_stride, it.W, it.H, 2 * it.qL};
+  const bool first = it.first, last = it.last;
+  using Buf = QBuf<float, CH>;
+  auto load_chunk = [&](Buf& b, int i0) {
 #pragma unroll
     for (int m = 0; m < CH; ++m) {
-      load_even(ll, ls, band, bs, it, i0 + m + 1, qb[m]);
-      load_odd(band, bs, it, i0 + m + 1, qb[m]);
+      L.even(i0 + m + 1, b.llL[m], b.llR[m], b.hlL[m], b.hlR[m], b.he0[m], b.he1[m]);
+      L.odd(i0 + m + 1, b.lhL[m], b.lhR[m], b.hhL[m], b.hhR[m], b.ho0[m], b.ho1[m]);
     }
-#pragma unroll
-    for (int m = 0; m < CH; ++m) {
-      const int i = i0 + m;
-      if (i < it.I1) {
-        const Quad2<float> n = qb[m];
-        // undo the update for row i + 1
-        const float hlP = shfl_up(n.hlR), hhP = shfl_up(n.hhR);
-        float a1_L, a1_R, bp1_L, bp1_R, cp1_L, cp1_R;
-        f32_inv_update(n.llL, hlP, n.hlL, lhU_L, n.lhL, hhUL_L, hhU_L, hhP, n.hhL, a1_L, bp1_L, cp1_L);
-        f32_inv_update(n.llR, n.hlL, n.hlR, lhU_R, n.lhR, hhU_L, hhU_R, n.hhL, n.hhR, a1_R, bp1_R, cp1_R);
-        const float aN1 = shfl_dn(a1_L), cpN1 = shfl_dn(cp1_L);
-        // undo the predict for row i
-        V4<float> e, o;
-        e.x = a_L; e.z = a_R;
-        f32_inv_predict(a_L, a_R, a1_L, a1_R, bp_L, bp1_L, cp_L, cp_R, hh_L, e.y, o.x, o.y);
-        f32_inv_predict(a_R, aN, a1_R, aN1, bp_R, bp1_R, cp_R, cpN, hh_R, e.w, o.z, o.w);
-        store_px4(px + (int64_t)(2 * i) * ps, c0, W, e, it.outL, it.outR);
-        if (2 * i + 1 < it.H) store_px4(px + (int64_t)(2 * i + 1) * ps, c0, W, o, it.outL, it.outR);
-        // advance
-        a_L = a1_L; a_R = a1_R; bp_L = bp1_L; bp_R = bp1_R; cp_L = cp1_L; cp_R = cp1_R;
-        hh_L = n.hhL; hh_R = n.hhR;
-        lhU_L = n.lhL; lhU_R = n.lhR; hhU_L = n.hhL; hhU_R = n.hhR; hhUL_L = hhP;
-        aN = aN1; cpN = cpN1;
-      }
-    }
-  }
+  };
+  float lhU_L, lhU_R, hhU_L, hhU_R, hoU0, hoU1;
+  L.odd(it.I0 - 1, lhU_L, lhU_R, hhU_L, hhU_R, hoU0, hoU1);
+  float q_llL, q_llR, q_hlL, q_hlR, q_he0, q_he1, q_lhL, q_lhR, q_hhL, q_hhR, q_ho0, q_ho1;
+  L.even(it.I0, q_llL, q_llR, q_hlL, q_hlR, q_he0, q_he1);
+  L.odd(it.I0, q_lhL, q_lhR, q_hhL, q_hhR, q_ho0, q_ho1);
+  Buf A, B;
+  load_chunk(A, it.I0);
+
+  float hhUL_L = prv(first, hoU0, hhU_R);
+  float a_L, a_R, bp_L, bp_R, cp_L, cp_R, aN, cpN, hh_L, hh_R;
+  // undo the update of one coefficient row (L, R and the right halo quad X)
+  auto undo_update = [&](float llL, float llR, float hlL, float hlR, float he0, float he1, float lhL, float lhR,
+                         float hhL, float hhR, float ho0, float ho1, float& oaL, float& oaR, float& obL,
+                         float& obR, float& ocL, float& ocR, float& oaN, float& ocN) {
+    const float hlP = prv(first, he0, hlR);
+    const float hhP = prv(first, ho0, hhR);
+    f32_inv_update(llL, hlP, hlL, lhU_L, lhL, hhUL_L, hhU_L, hhP, hhL, oaL, obL, ocL);
+    f32_inv_update(llR, hlL, hlR, lhU_R, lhR, hhU_L, hhU_R, hhL, hhR, oaR, obR, ocR);
+    float aX, bX, cX;
+    f32_inv_update(he0, hlR, he1, hoU0, ho0, hhU_R, hoU1, hhR, ho1, aX, bX, cX);
+    oaN = nxt(last, aX, oaL);
+    ocN = nxt(last, cX, ocL);
+    lhU_L = lhL; lhU_R = lhR; hhU_L = hhL; hhU_R = hhR; hhUL_L = hhP; hoU0 = ho0; hoU1 = ho1;
+  };
+  undo_update(q_llL, q_llR, q_hlL, q_hlR, q_he0, q_he1, q_lhL, q_lhR, q_hhL, q_hhR, q_ho0, q_ho1, a_L, a_R, bp_L,
+              bp_R, cp_L, cp_R, aN, cpN);
+  hh_L = q_hhL;
+  hh_R = q_hhR;
+
+  auto row = [&](const Buf& b, int m, int i) {
+    float a1_L, a1_R, bp1_L, bp1_R, cp1_L, cp1_R, aN1, cpN1;
+    undo_update(b.llL[m], b.llR[m], b.hlL[m], b.hlR[m], b.he0[m], b.he1[m], b.lhL[m], b.lhR[m], b.hhL[m],
+                b.hhR[m], b.ho0[m], b.ho1[m], a1_L, a1_R, bp1_L, bp1_R, cp1_L, cp1_R, aN1, cpN1);
+    V4<float> e, o;
+    e.x = a_L;
+    e.z = a_R;
+    f32_inv_predict(a_L, a_R, a1_L, a1_R, bp_L, bp1_L, cp_L, cp_R, hh_L, e.y, o.x, o.y);
+    f32_inv_predict(a_R, aN, a1_R, aN1, bp_R, bp1_R, cp_R, cpN, hh_R, e.w, o.z, o.w);
+    S.row(2 * i, e);
+    S.row(2 * i + 1, o);
+    a_L = a1_L; a_R = a1_R; bp_L = bp1_L; bp_R = bp1_R; cp_L = cp1_L; cp_R = cp1_R;
+    aN = aN1; cpN = cpN1;
+    hh_L = b.hhL[m];
+    hh_R = b.hhR[m];
+  };
+  run_rows<CH, FAST>(it.I0, it.I1, A, B, load_chunk, row);
 }
 
-template <int CH>
+template <int CH, bool FAST>
 __device__ void inv_i32(const LevelDesc& d, const int* __restrict__ ll, const int* __restrict__ band,
                         int* __restrict__ px, const Item& it) {
-  const int W = it.W, c0 = 2 * it.qL;
-  const int64_t ps = d.pix_stride, ls = d.ll_stride, bs = d.band_stride;
-
-  Quad2<int> q0, q1;
-  load_odd(band, bs, it, it.I0 - 1, q0);
-  load_even(ll, ls, band, bs, it, it.I0, q1);
-  load_odd(band, bs, it, it.I0, q1);
-  // row I0: b1 (needs HH of row I0-1), then a and c1
-  int b1_L = i32_inv_b1(q1.hlL, q0.hhL, q1.hhL), b1_R = i32_inv_b1(q1.hlR, q0.hhR, q1.hhR);
-  int a_L, a_R, c1_L, c1_R;
-  {
-    const int b1P = shfl_up(b1_R), hhP = shfl_up(q1.hhR);
-    i32_inv_update(q1.llL, q0.lhL, q1.lhL, b1P, b1_L, hhP, q1.hhL, a_L, c1_L);
-    i32_inv_update(q1.llR, q0.lhR, q1.lhR, b1_L, b1_R, q1.hhL, q1.hhR, a_R, c1_R);
-  }
-  int hh_L = q1.hhL, hh_R = q1.hhR, lh_L = q1.lhL, lh_R = q1.lhR;
-  int aN = shfl_dn(a_L);
-
-  for (int i0 = it.I0; i0 < it.I1; i0 += CH) {
-    Quad2<int> qb[CH];
+  const BandLoader<int, FAST, true> L = band_loader<int, FAST, true>(ll, d.ll_stride, band, d.band_stride, it,
+                                                                     1, 1, 0, 1);
+  const PxStore<int, FAST> S{px, d.pix_stride, it.W, it.H, 2 * it.qL};
+  const bool first = it.first, last = it.last;
+  using Buf = QBuf<int, CH>;
+  auto load_chunk = [&](Buf& b, int i0) {
 #pragma unroll
     for (int m = 0; m < CH; ++m) {
-      load_even(ll, ls, band, bs, it, i0 + m + 1, qb[m]);
-      load_odd(band, bs, it, i0 + m + 1, qb[m]);
+      L.even(i0 + m + 1, b.llL[m], b.llR[m], b.hlL[m], b.hlR[m], b.he0[m], b.he1[m]);
+      L.odd(i0 + m + 1, b.lhL[m], b.lhR[m], b.hhL[m], b.hhR[m], b.ho0[m], b.ho1[m]);
     }
-#pragma unroll
-    for (int m = 0; m < CH; ++m) {
-      const int i = i0 + m;
-      if (i < it.I1) {
-        const Quad2<int> n = qb[m];
-        // first half for row i + 1
-        const int b1n_L = i32_inv_b1(n.hlL, hh_L, n.hhL), b1n_R = i32_inv_b1(n.hlR, hh_R, n.hhR);
-        const int b1P = shfl_up(b1n_R), hhP = shfl_up(n.hhR);
-        int an_L, an_R, c1n_L, c1n_R;
-        i32_inv_update(n.llL, lh_L, n.lhL, b1P, b1n_L, hhP, n.hhL, an_L, c1n_L);
-        i32_inv_update(n.llR, lh_R, n.lhR, b1n_L, b1n_R, n.hhL, n.hhR, an_R, c1n_R);
-        const int aN1 = shfl_dn(an_L);
-        // second half for row i
-        const int c_L = i32_inv_c(c1_L, a_L, an_L), c_R = i32_inv_c(c1_R, a_R, an_R);
-        const int cN = shfl_dn(c_L);
-        V4<int> e, o;
-        e.x = a_L; e.z = a_R;
-        o.x = c_L; o.z = c_R;
-        i32_inv_predict(a_L, a_R, b1_L, b1n_L, c_L, c_R, hh_L, e.y, o.y);
-        i32_inv_predict(a_R, aN, b1_R, b1n_R, c_R, cN, hh_R, e.w, o.w);
-        store_px4(px + (int64_t)(2 * i) * ps, c0, W, e, it.outL, it.outR);
-        if (2 * i + 1 < it.H) store_px4(px + (int64_t)(2 * i + 1) * ps, c0, W, o, it.outL, it.outR);
-        a_L = an_L; a_R = an_R; b1_L = b1n_L; b1_R = b1n_R; c1_L = c1n_L; c1_R = c1n_R;
-        hh_L = n.hhL; hh_R = n.hhR; lh_L = n.lhL; lh_R = n.lhR;
-        aN = aN1;
-      }
-    }
-  }
+  };
+  // state of the previous coefficient row: LH (c2U) and HH (d2U) of L, R;
+  // odd halos (lane 0: HH of quad qL-1; lane 63: LH / HH of quad qL+2)
+  int lhU_L, lhU_R, hhU_L, hhU_R, hoU0, hoU1;
+  L.odd(it.I0 - 1, lhU_L, lhU_R, hhU_L, hhU_R, hoU0, hoU1);
+  int q_llL, q_llR, q_hlL, q_hlR, q_he0, q_he1, q_lhL, q_lhR, q_hhL, q_hhR, q_ho0, q_ho1;
+  L.even(it.I0, q_llL, q_llR, q_hlL, q_hlR, q_he0, q_he1);
+  L.odd(it.I0, q_lhL, q_lhR, q_hhL, q_hhR, q_ho0, q_ho1);
+  Buf A, B;
+  load_chunk(A, it.I0);
+
+  // first half of one coefficient row: b1, a, c1 for L, R and the right halo
+  // quad X; lane 0 forms b1 of quad qL-1 from its halo.
+  auto first_half = [&](int llL, int llR, int hlL, int hlR, int he0, int he1, int lhL, int lhR, int hhL, int hhR,
+                        int ho0, int ho1, int& b1L, int& b1R, int& aL, int& aR, int& aX, int& c1L, int& c1R,
+                        int& c1X) {
+    b1L = i32_inv_b1(hlL, hhU_L, hhL);
+    b1R = i32_inv_b1(hlR, hhU_R, hhR);
+    const int b1X = i32_inv_b1(he1, hoU1, ho1);
+    const int b1H = i32_inv_b1(he0, hoU0, ho0);
+    const int b1P = prv(first, b1H, b1R);
+    const int hhP = prv(first, ho0, hhR);
+    i32_inv_update(llL, lhU_L, lhL, b1P, b1L, hhP, hhL, aL, c1L);
+    i32_inv_update(llR, lhU_R, lhR, b1L, b1R, hhL, hhR, aR, c1R);
+    i32_inv_update(he0, hoU0, ho0, b1R, b1X, hhR, ho1, aX, c1X);
+    lhU_L = lhL; lhU_R = lhR; hhU_L = hhL; hhU_R = hhR; hoU0 = ho0; hoU1 = ho1;
+  };
+  int b1_L, b1_R, a_L, a_R, a_X, c1_L, c1_R, c1_X;
+  const int hh0_L = q_hhL, hh0_R = q_hhR;
+  first_half(q_llL, q_llR, q_hlL, q_hlR, q_he0, q_he1, q_lhL, q_lhR, q_hhL, q_hhR, q_ho0, q_ho1, b1_L, b1_R, a_L,
+             a_R, a_X, c1_L, c1_R, c1_X);
+  int hh_L = hh0_L, hh_R = hh0_R;
+
+  auto row = [&](const Buf& b, int m, int i) {
+    int b1n_L, b1n_R, an_L, an_R, an_X, c1n_L, c1n_R, c1n_X;
+    first_half(b.llL[m], b.llR[m], b.hlL[m], b.hlR[m], b.he0[m], b.he1[m], b.lhL[m], b.lhR[m], b.hhL[m],
+               b.hhR[m], b.ho0[m], b.ho1[m], b1n_L, b1n_R, an_L, an_R, an_X, c1n_L, c1n_R, c1n_X);
+    const int c_L = i32_inv_c(c1_L, a_L, an_L), c_R = i32_inv_c(c1_R, a_R, an_R);
+    const int c_X = i32_inv_c(c1_X, a_X, an_X);
+    const int aN = nxt(last, a_X, a_L);
+    const int cN = nxt(last, c_X, c_L);
+    V4<int> e, o;
+    e.x = a_L;
+    e.z = a_R;
+    o.x = c_L;
+    o.z = c_R;
+    i32_inv_predict(a_L, a_R, b1_L, b1n_L, c_L, c_R, hh_L, e.y, o.y);
+    i32_inv_predict(a_R, aN, b1_R, b1n_R, c_R, cN, hh_R, e.w, o.w);
+    S.row(2 * i, e);
+    S.row(2 * i + 1, o);
+    a_L = an_L; a_R = an_R; a_X = an_X; b1_L = b1n_L; b1_R = b1n_R; c1_L = c1n_L; c1_R = c1n_R; c1_X = c1n_X;
+    hh_L = b.hhL[m];
+    hh_R = b.hhR[m];
+  };
+  run_rows<CH, FAST>(it.I0, it.I1, A, B, load_chunk, row);
 }
 
-// ----------------------------------------------------------------- adjoint
-__device__ __forceinline__ void load_adj(const float* ll, int64_t ls, const float* band, int64_t bs, const Item& it,
-                                         int r, Quad2<float>& q) {
-  if (r >= 0 && r < it.ns_h) {
-    load_band2_zero(ll + (int64_t)r * ls, it.qL, it.ns_w, q.llL, q.llR);
-    load_band2_zero(band + (int64_t)r * bs + it.ns_w, it.qL, it.nd_w, q.hlL, q.hlR);
-  } else {
-    q.llL = q.llR = q.hlL = q.hlR = 0.f;
-  }
-  if (r >= 0 && r < it.nd_h) {
-    const float* row = band + (int64_t)(it.ns_h + r) * bs;
-    load_band2_zero(row, it.qL, it.ns_w, q.lhL, q.lhR);
-    load_band2_zero(row + it.ns_w, it.qL, it.nd_w, q.hhL, q.hhR);
-  } else {
-    q.lhL = q.lhR = q.hhL = q.hhR = 0.f;
-  }
-}
-
-template <int CH>
+template <int CH, bool FAST>
 __device__ void bwd_f32(const LevelDesc& d, const float* __restrict__ ll, const float* __restrict__ band,
                         float* __restrict__ px, const Item& it) {
-  const int W = it.W, c0 = 2 * it.qL;
-  const int64_t ps = d.pix_stride, ls = d.ll_stride, bs = d.band_stride;
-  const AxisW hL = axis_weights(it.qL, W), hR = axis_weights(it.qL + 1, W);
-
-  // prologue: step A (transposed update) of row I0 - 1
-  Quad2<float> p, c;
-  load_adj(ll, ls, band, bs, it, it.I0 - 1, p);
-  load_adj(ll, ls, band, bs, it, it.I0, c);
-  float gc1U_L, gc1U_R, gd1U_L, gd1U_R, gd1UL_L;
-  {
-    const AxisW v = axis_weights(it.I0 - 1, it.H);
-    const float gaN = shfl_dn(p.llL), gaDN = shfl_dn(c.llL), gcN = shfl_dn(p.lhL);
-    float gb1L, gb1R;
-    f32_adj_a(p.llL, p.llR, c.llL, c.llR, p.hlL, c.hlL, p.lhL, p.lhR, p.hhL, hL, v, gb1L, gc1U_L, gd1U_L);
-    f32_adj_a(p.llR, gaN, c.llR, gaDN, p.hlR, c.hlR, p.lhR, gcN, p.hhR, hR, v, gb1R, gc1U_R, gd1U_R);
-    gd1UL_L = shfl_up(gd1U_R);
-  }
-  float gaN = shfl_dn(c.llL);
-
-  for (int i0 = it.I0; i0 < it.I1; i0 += CH) {
-    Quad2<float> qb[CH];
-#pragma unroll
-    for (int m = 0; m < CH; ++m) load_adj(ll, ls, band, bs, it, i0 + m + 1, qb[m]);
+  // halos: lane 0 -> quad qL-1: h0 = LL / LH (parity 0), h1 = HL / HH (parity 1);
+  // lane 63 -> quad qL+2: h0 = LL / LH (parity 0)
+  const BandLoader<float, FAST, false> L = band_loader<float, FAST, false>(ll, d.ll_stride, band, d.band_stride, it,
+                                                                           0, 1, 0, 0);
+  const PxStore<float, FAST> S{px, d.pix_stride, it.W, it.H, 2 * it.qL};
+  const bool first = it.first, last = it.last;
+  const AxisW hL = axis_weights(it.qL, it.W), hR = axis_weights(it.qL + 1, it.W), hH = axis_weights(it.qL - 1, it.W);
+  using Buf = QBuf<float, CH>;
+  auto load_chunk = [&](Buf& b, int i0) {
 #pragma unroll
     for (int m = 0; m < CH; ++m) {
-      const int i = i0 + m;
-      if (i < it.I1) {
-        const Quad2<float> n = qb[m];
-        const AxisW v = axis_weights(i, it.H);
-        const float gaDN = shfl_dn(n.llL), gcN = shfl_dn(c.lhL);
-        float gb1_L, gc1_L, gd1_L, gb1_R, gc1_R, gd1_R;
-        f32_adj_a(c.llL, c.llR, n.llL, n.llR, c.hlL, n.hlL, c.lhL, c.lhR, c.hhL, hL, v, gb1_L, gc1_L, gd1_L);
-        f32_adj_a(c.llR, gaN, n.llR, gaDN, c.hlR, n.hlR, c.lhR, gcN, c.hhR, hR, v, gb1_R, gc1_R, gd1_R);
-        const float gb1P = shfl_up(gb1_R), gd1P = shfl_up(gd1_R);
-        V4<float> e, o;
-        f32_adj_b(c.llL, gb1P, gb1_L, gc1U_L, gc1_L, gd1UL_L, gd1U_L, gd1P, gd1_L, hL, v, e.x, e.y, o.x);
-        f32_adj_b(c.llR, gb1_L, gb1_R, gc1U_R, gc1_R, gd1U_L, gd1U_R, gd1_L, gd1_R, hR, v, e.z, e.w, o.z);
-        o.y = gd1_L;
-        o.w = gd1_R;
-        store_px4(px + (int64_t)(2 * i) * ps, c0, W, e, it.outL, it.outR);
-        if (2 * i + 1 < it.H) store_px4(px + (int64_t)(2 * i + 1) * ps, c0, W, o, it.outL, it.outR);
-        gc1U_L = gc1_L; gc1U_R = gc1_R; gd1U_L = gd1_L; gd1U_R = gd1_R; gd1UL_L = gd1P;
-        c = n;
-        gaN = gaDN;
-      }
+      L.even(i0 + m + 1, b.llL[m], b.llR[m], b.hlL[m], b.hlR[m], b.he0[m], b.he1[m]);
+      L.odd(i0 + m + 1, b.lhL[m], b.lhR[m], b.hhL[m], b.hhR[m], b.ho0[m], b.ho1[m]);
     }
+  };
+  // current coefficient row (starts as row I0 - 1)
+  float ga_L, ga_R, gb_L, gb_R, ge0, ge1, gc_L, gc_R, gd_L, gd_R, go0, go1;
+  L.even(it.I0 - 1, ga_L, ga_R, gb_L, gb_R, ge0, ge1);
+  L.odd(it.I0 - 1, gc_L, gc_R, gd_L, gd_R, go0, go1);
+  float n_llL, n_llR, n_hlL, n_hlR, n_he0, n_he1, n_lhL, n_lhR, n_hhL, n_hhR, n_ho0, n_ho1;
+  L.even(it.I0, n_llL, n_llR, n_hlL, n_hlR, n_he0, n_he1);
+  L.odd(it.I0, n_lhL, n_lhR, n_hhL, n_hhR, n_ho0, n_ho1);
+  Buf A, B;
+  load_chunk(A, it.I0);
+
+  // step A (transposed update) of the current row given the next row's even part
+  auto step_a = [&](int i, float nL, float nR, float nbL, float nbR, float ne0, float ne1, float& gb1L, float& gb1R,
+                    float& gc1L, float& gc1R, float& gd1L, float& gd1R, float& gb1H, float& gd1H) {
+    const AxisW v = axis_weights(i, it.H);
+    const float gaN = nxt(last, ge0, ga_L), gaDN = nxt(last, ne0, nL);
+    const float gcN = nxt(last, go0, gc_L);
+    f32_adj_a(ga_L, ga_R, nL, nR, gb_L, nbL, gc_L, gc_R, gd_L, hL, v, gb1L, gc1L, gd1L);
+    f32_adj_a(ga_R, gaN, nR, gaDN, gb_R, nbR, gc_R, gcN, gd_R, hR, v, gb1R, gc1R, gd1R);
+    float gc1H;
+    f32_adj_a(ge0, ga_L, ne0, nL, ge1, ne1, go0, gc_L, go1, hH, v, gb1H, gc1H, gd1H);
+  };
+  float gc1U_L, gc1U_R, gd1U_L, gd1U_R, gd1UL_L;
+  {
+    float gb1L, gb1R, gb1H, gd1H;
+    step_a(it.I0 - 1, n_llL, n_llR, n_hlL, n_hlR, n_he0, n_he1, gb1L, gb1R, gc1U_L, gc1U_R, gd1U_L, gd1U_R, gb1H,
+           gd1H);
+    gd1UL_L = prv(first, gd1H, gd1U_R);
   }
+  ga_L = n_llL; ga_R = n_llR; gb_L = n_hlL; gb_R = n_hlR; ge0 = n_he0; ge1 = n_he1;
+  gc_L = n_lhL; gc_R = n_lhR; gd_L = n_hhL; gd_R = n_hhR; go0 = n_ho0; go1 = n_ho1;
+
+  auto row = [&](const Buf& b, int m, int i) {
+    float gb1_L, gb1_R, gc1_L, gc1_R, gd1_L, gd1_R, gb1H, gd1H;
+    step_a(i, b.llL[m], b.llR[m], b.hlL[m], b.hlR[m], b.he0[m], b.he1[m], gb1_L, gb1_R, gc1_L, gc1_R, gd1_L, gd1_R,
+           gb1H, gd1H);
+    const float gb1P = prv(first, gb1H, gb1_R);
+    const float gd1P = prv(first, gd1H, gd1_R);
+    const AxisW v = axis_weights(i, it.H);
+    V4<float> e, o;
+    f32_adj_b(ga_L, gb1P, gb1_L, gc1U_L, gc1_L, gd1UL_L, gd1U_L, gd1P, gd1_L, hL, v, e.x, e.y, o.x);
+    f32_adj_b(ga_R, gb1_L, gb1_R, gc1U_R, gc1_R, gd1U_L, gd1U_R, gd1_L, gd1_R, hR, v, e.z, e.w, o.z);
+    o.y = gd1_L;
+    o.w = gd1_R;
+    S.row(2 * i, e);
+    S.row(2 * i + 1, o);
+    gc1U_L = gc1_L; gc1U_R = gc1_R; gd1U_L = gd1_L; gd1U_R = gd1_R; gd1UL_L = gd1P;
+    ga_L = b.llL[m]; ga_R = b.llR[m]; gb_L = b.hlL[m]; gb_R = b.hlR[m]; ge0 = b.he0[m]; ge1 = b.he1[m];
+    gc_L = b.lhL[m]; gc_R = b.lhR[m]; gd_L = b.hhL[m]; gd_R = b.hhR[m]; go0 = b.ho0[m]; go1 = b.ho1[m];
+  };
+  run_rows<CH, FAST>(it.I0, it.I1, A, B, load_chunk, row);
 }
 
 // ---------------------------------------------------------------------------
@@ -636,6 +851,17 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
   return (x < r) ? x * (q + 1) + s : r * (q + 1) + (x - r) * q + s;
 }
 
+// Whether an item can take the branch-free path: every quadruple column of
+// the strip inside both parity bands, rows a whole number of chunk pairs,
+// and (host-checked) aligned pointers and strides.
+template <int DIR, int CH>
+__device__ __forceinline__ bool fast_item(const LevelDesc& d, const Item& it, int strip) {
+  const int rows = it.I1 - it.I0;
+  bool ok = d.fast_ok && kStripQ * (strip + 1) <= it.nd_w && rows > 0 && rows % (2 * CH) == 0 && it.I1 <= it.nd_h;
+  if (DIR == kBwd) ok = ok && it.I0 >= 1 && it.I1 < it.nd_h;
+  return ok;
+}
+
 template <int DIR, typename T, int CH>
 __global__ __launch_bounds__(kBlock) void level_kernel(LevelLaunch a) {
   const int lane = threadIdx.x & (kWave - 1);
@@ -647,21 +873,33 @@ __global__ __launch_bounds__(kBlock) void level_kernel(LevelLaunch a) {
   const int seg = rem / a.d.nstrips;
   const int strip = rem - seg * a.d.nstrips;
   const Item it = make_item(a.d, strip, seg, lane);
-  if (DIR == kFwd) {
+  const bool fast = fast_item<DIR, CH>(a.d, it, strip);
+  if constexpr (DIR == kFwd) {
     const T* px = static_cast<const T*>(a.d.pix_in) + img * a.pix_bstride;
     T* ll = static_cast<T*>(a.d.ll_out) + img * a.ll_bstride;
     T* band = static_cast<T*>(a.d.band_out) + img * a.band_bstride;
-    if constexpr (std::is_same<T, float>::value) fwd_f32<CH>(a.d, (const float*)px, (float*)ll, (float*)band, it);
-    else fwd_i32<CH>(a.d, (const int*)px, (int*)ll, (int*)band, it);
+    if constexpr (std::is_same<T, float>::value) {
+      if (fast) fwd_f32<CH, true>(a.d, px, ll, band, it);
+      else fwd_f32<CH, false>(a.d, px, ll, band, it);
+    } else {
+      if (fast) fwd_i32<CH, true>(a.d, px, ll, band, it);
+      else fwd_i32<CH, false>(a.d, px, ll, band, it);
+    }
   } else {
     const T* ll = static_cast<const T*>(a.d.ll_in) + img * a.ll_bstride;
     const T* band = static_cast<const T*>(a.d.band_in) + img * a.band_bstride;
     T* px = static_cast<T*>(a.d.pix_out) + img * a.pix_bstride;
     if constexpr (DIR == kInv) {
-      if constexpr (std::is_same<T, float>::value) inv_f32<CH>(a.d, (const float*)ll, (const float*)band, (float*)px, it);
-      else inv_i32<CH>(a.d, (const int*)ll, (const int*)band, (int*)px, it);
+      if constexpr (std::is_same<T, float>::value) {
+        if (fast) inv_f32<CH, true>(a.d, ll, band, px, it);
+        else inv_f32<CH, false>(a.d, ll, band, px, it);
+      } else {
+        if (fast) inv_i32<CH, true>(a.d, ll, band, px, it);
+        else inv_i32<CH, false>(a.d, ll, band, px, it);
+      }
     } else {
-      bwd_f32<CH>(a.d, (const float*)ll, (const float*)band, (float*)px, it);
+      if (fast) bwd_f32<CH, true>(a.d, ll, band, px, it);
+      else bwd_f32<CH, false>(a.d, ll, band, px, it);
     }
   }
 }
@@ -673,14 +911,42 @@ hipError_t launch_t(const LevelLaunch& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <int DIR, typename T>
+hipError_t launch_ch(int chunk, const LevelLaunch& a, hipStream_t s) {
+  if (chunk >= 4) return launch_t<DIR, T, 4>(a, s);
+  if (chunk >= 2) return launch_t<DIR, T, 2>(a, s);
+  return launch_t<DIR, T, 1>(a, s);
+}
+
+template <int DIR, typename T, int CH>
+int occ_blocks() {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(&level_kernel<DIR, T, CH>),
+                                                   kBlock, 0) != hipSuccess)
+    n = 0;
+  return n;
+}
+
 }  // namespace
 
 int launch_level(int dir, int mode, int chunk, const LevelLaunch& a, void* stream) {
   hipStream_t s = static_cast<hipStream_t>(stream);
-  (void)chunk;
-  if (dir == kFwd) return mode == DWT2_F32 ? launch_t<kFwd, float, 4>(a, s) : launch_t<kFwd, int, 4>(a, s);
-  if (dir == kInv) return mode == DWT2_F32 ? launch_t<kInv, float, 4>(a, s) : launch_t<kInv, int, 4>(a, s);
-  return launch_t<kBwd, float, 4>(a, s);
+  if (dir == kFwd) return mode == DWT2_F32 ? launch_ch<kFwd, float>(chunk, a, s) : launch_ch<kFwd, int>(chunk, a, s);
+  if (dir == kInv) return mode == DWT2_F32 ? launch_ch<kInv, float>(chunk, a, s) : launch_ch<kInv, int>(chunk, a, s);
+  return launch_ch<kBwd, float>(chunk, a, s);
+}
+
+template <int CH>
+int occ_dir(int dir, int mode) {
+  if (dir == kFwd) return mode == DWT2_F32 ? occ_blocks<kFwd, float, CH>() : occ_blocks<kFwd, int, CH>();
+  if (dir == kInv) return mode == DWT2_F32 ? occ_blocks<kInv, float, CH>() : occ_blocks<kInv, int, CH>();
+  return occ_blocks<kBwd, float, CH>();
+}
+
+int level_blocks_per_cu(int dir, int mode, int chunk) {
+  if (chunk >= 4) return occ_dir<4>(dir, mode);
+  if (chunk >= 2) return occ_dir<2>(dir, mode);
+  return occ_dir<1>(dir, mode);
 }
 
 }  // namespace dwt2

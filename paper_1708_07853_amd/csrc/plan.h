@@ -31,7 +31,12 @@ void clear_error();
 int check_geometry(int32_t width, int32_t height, int32_t levels, Geo& g);
 void ws_layout(const Geo& g, size_t& a_bytes, size_t& b_bytes);
 size_t ws_per_image(const Geo& g);
-int choose_seg(int ns_h, int64_t strips_times_batch);
+struct Tiling {
+  int seg;  // quadruple rows per work item
+  int ch;   // rows per prefetch chunk (kernel template)
+};
+Tiling choose_tiling(int dir, int mode, int ns_h, int64_t strips_times_batch);
+int fast_layout(int dir, const LevelLaunch& a, int batch, int W);
 void fill_level(LevelDesc& d, int W, int H, int seg);
 int run_levels(int dir, const Call& c, const Geo& g, void* stream);
 

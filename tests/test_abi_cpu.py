@@ -114,3 +114,9 @@ def test_batched_validation(lib):
     assert lib.dwt2_fwd_batched(ok, 0, 2, 0, 0, FAKE_WS, 1 << 30, None) == -1
     assert lib.dwt2_fwd_batched(ok, 2, 2, 9, 0, FAKE_WS, 1 << 30, None) == -3
     assert lib.dwt2_fwd_batched(ok, 2, 2, 0, 3, FAKE_WS, 1 << 30, None) == -1
+
+
+def test_set_tiling_validation(lib):
+    assert lib.dwt2_set_tiling(-1, 0) == -1
+    assert lib.dwt2_set_tiling(8, 3) == -1
+    assert lib.dwt2_set_tiling(0, 0) == 0

@@ -227,3 +227,27 @@ def test_config5_adjoint_against_oracle():
     for b in range(2):
         for ch in range(3):
             assert maxdiff(got[b, ch], oracle.adj(g[b, ch].astype(np.float64), levels)) <= TOL
+
+
+@pytest.mark.parametrize("mode", ["f32", "int"])
+def test_results_do_not_depend_on_tiling(mode):
+    """Every tiling (segment height, prefetch chunk) gives bit-identical
+    results, so work-item boundaries introduce neither races nor seams."""
+    d = D()
+    dt = np.float32 if mode == "f32" else np.int32
+    shapes = [(1024, 1024, 4), (777, 1031, 5), (96, 2304, 3)]
+    try:
+        for (h, w, levels) in shapes:
+            x = to_gpu(synth.image(w, h, h + w, dt))
+            d.set_tiling(0, 0)
+            ref_f = d.fwd(x, levels)
+            ref_i = d.inv(ref_f, levels)
+            ref_b = d.bwd(x.float(), levels) if mode == "f32" else None
+            for seg, ch in [(1, 1), (2, 1), (4, 2), (8, 4), (16, 4), (24, 2), (64, 4), (3, 1), (10000, 4)]:
+                d.set_tiling(seg, ch)
+                assert torch.equal(d.fwd(x, levels), ref_f), (h, w, seg, ch)
+                assert torch.equal(d.inv(ref_f, levels), ref_i), (h, w, seg, ch)
+                if ref_b is not None:
+                    assert torch.equal(d.bwd(x.float(), levels), ref_b), (h, w, seg, ch)
+    finally:
+        d.set_tiling(0, 0)
