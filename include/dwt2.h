@@ -159,6 +159,13 @@ int dwt2_fwd_batched(const dwt2_image_t* images, int32_t n, int32_t levels,
  * Returns DWT2_OK, or DWT2_ERR_ARG for values outside those ranges. */
 int dwt2_set_tiling(int32_t seg, int32_t chunk);
 
+/* Process-wide choice of how levels are chained, for tests and
+ * measurements: 0 (default) = one kernel launch per level; 1 = every level
+ * of a call in one cooperative persistent launch whose work items wait only
+ * for the rows they read.  Results are bit-identical.  Returns DWT2_OK or
+ * DWT2_ERR_ARG. */
+int dwt2_set_path(int32_t persistent);
+
 /* Static description of a status code. */
 const char* dwt2_status_string(int status);
 /* Thread-local detail of the last failing call on this thread ("" if none). */

@@ -15,7 +15,7 @@ import torch
 from . import _lib
 from ._lib import DWT2_EXT_SYMMETRIC, DWT2_F32, DWT2_I32_REV
 
-__all__ = ["fwd", "inv", "bwd", "fwd_batched", "DWT2Function", "workspace_size", "level_sizes", "set_tiling",
+__all__ = ["fwd", "inv", "bwd", "fwd_batched", "DWT2Function", "workspace_size", "level_sizes", "set_tiling", "set_path",
            "DWT2_F32", "DWT2_I32_REV"]
 
 
@@ -58,6 +58,12 @@ def _as_batch(t: torch.Tensor):
 def set_tiling(seg: int = 0, chunk: int = 0) -> None:
     """Process-wide tiling override (0 = automatic); results do not change."""
     _lib.check(_lib.load().dwt2_set_tiling(seg, chunk))
+
+
+def set_path(persistent: bool = False) -> None:
+    """False (default): one launch per level; True: all levels in one
+    cooperative persistent launch.  Results are bit-identical."""
+    _lib.check(_lib.load().dwt2_set_path(1 if persistent else 0))
 
 
 def workspace_size(w: int, h: int, levels: int, batch: int = 1, mode: int = DWT2_F32) -> int:

@@ -48,18 +48,26 @@ int check_geometry(int32_t width, int32_t height, int32_t levels, Geo& g) {
   return DWT2_OK;
 }
 
-static size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
+size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
 
-// Per-image workspace: LL buffers A (odd levels) and B (even levels).
-void ws_layout(const Geo& g, size_t& a_bytes, size_t& b_bytes) {
-  a_bytes = g.L >= 2 ? round256((size_t)ll_pitch(g.w[1]) * g.h[1] * 4) : 0;
-  b_bytes = g.L >= 3 ? round256((size_t)ll_pitch(g.w[2]) * g.h[2] * 4) : 0;
+// Per-image workspace: one LL buffer per intermediate level (LL_1 ..
+// LL_{L-1}), each with a row pitch padded to 64 elements.  Levels of a
+// persistent job overlap in time, so no buffer is reused within a call.
+size_t ll_offset(const Geo& g, int m) {
+  size_t off = 0;
+  for (int k = 1; k < m; ++k) off += round256((size_t)ll_pitch(g.w[k]) * g.h[k] * 4);
+  return off;
 }
 
-size_t ws_per_image(const Geo& g) {
-  size_t a, b;
-  ws_layout(g, a, b);
-  return a + b;
+size_t ws_per_image(const Geo& g) { return ll_offset(g, g.L); }
+
+// Synchronisation words of a persistent job: the queue head, the error word
+// and one completion counter per (image, level, segment); a segment holds at
+// least one quadruple row, so sum_k h_k counters per image always suffice.
+size_t sync_bytes(const Geo& g, int64_t batch) {
+  int64_t rows = 0;
+  for (int k = 1; k <= g.L; ++k) rows += g.h[k];
+  return round256((size_t)(kSyncCounters + kCounterStride * batch * rows) * 4);
 }
 
 static int env_int(const char* name) {
@@ -103,15 +111,15 @@ static int64_t resident_waves(int dir, int mode, int ch) {
 // Segment height (quadruple rows per work item) and chunk size: enough
 // segments for one round of resident waves, each a whole number of chunk
 // pairs where possible.
-static std::atomic<int> g_forced_seg{-1}, g_forced_ch{-1};
+static std::atomic<int> g_forced_seg{-1}, g_forced_ch{-1}, g_persistent{-1};
 
-Tiling choose_tiling(int dir, int mode, int ns_h, int64_t strips_times_batch) {
+Tiling choose_tiling(int dir, int mode, int ns_h, int64_t strips_times_batch, int64_t slots_hint) {
   if (g_forced_seg.load() < 0) g_forced_seg.store(env_int("DWT2_SEG") > 0 ? env_int("DWT2_SEG") : 0);
   if (g_forced_ch.load() < 0) g_forced_ch.store(env_int("DWT2_CH") > 0 ? env_int("DWT2_CH") : 0);
   const int forced_seg = g_forced_seg.load(), forced_ch = g_forced_ch.load();
   Tiling t;
   t.ch = forced_ch > 0 ? (forced_ch >= 4 ? 4 : (forced_ch >= 2 ? 2 : 1)) : 2;
-  const int64_t slots = resident_waves(dir, mode, t.ch);
+  const int64_t slots = slots_hint > 0 ? slots_hint : resident_waves(dir, mode, t.ch);
   const int64_t per_strip = slots / strips_times_batch > 1 ? slots / strips_times_batch : 1;
   int seg = (int)((ns_h + per_strip - 1) / per_strip);
   if (forced_ch <= 0 && seg < 2 * t.ch) t.ch = 1;
@@ -144,54 +152,120 @@ int fast_layout(int dir, const LevelLaunch& a, int batch, int W) {
   return px_ok && ll_ok && band_ok;
 }
 
-// LL_m lives in buffer A (m odd) or B (m even) of each image's workspace slice.
-static char* ll_buf(const Call& c, const Geo& g, int m) {
-  size_t a, b;
-  ws_layout(g, a, b);
-  return c.ws + ((m & 1) ? 0 : a);
+// LL_m of each image's workspace slice (the slices follow the sync area).
+static char* ll_buf(const Call& c, const Geo& g, int m) { return c.ws + c.ll_base + ll_offset(g, m); }
+
+// Geometry, pointers and tiling of level k for a call.
+static void level_launch(int dir, const Call& c, const Geo& g, int k, int64_t slots_hint, LevelLaunch& a, int& ch) {
+  const int64_t ws_bs = (int64_t)(ws_per_image(g) / 4);
+  memset(&a, 0, sizeof a);
+  const int W = g.w[k - 1], H = g.h[k - 1];
+  const int64_t strips_batch = (int64_t)num_strips(W) * c.batch;
+  const Tiling t = choose_tiling(dir, c.mode, ceil_half(H), strips_batch, slots_hint);
+  ch = t.ch;
+  fill_level(a.d, W, H, t.seg);
+  // pixels of the level input: the image (k = 1) or LL_{k-1}
+  const bool px_is_image = (k == 1);
+  char* px = px_is_image ? (dir == kFwd ? const_cast<char*>(c.src) : c.dst) : ll_buf(c, g, k - 1);
+  a.d.pix_stride = px_is_image ? (dir == kFwd ? c.src_stride : c.dst_stride) : ll_pitch(g.w[k - 1]);
+  a.pix_bstride = px_is_image ? (dir == kFwd ? c.src_bs : c.dst_bs) : ws_bs;
+  // LL_k: the packed array's corner at the last level, else a workspace buffer
+  const bool ll_is_packed = (k == g.L);
+  char* ll = ll_is_packed ? (dir == kFwd ? c.dst : const_cast<char*>(c.src)) : ll_buf(c, g, k);
+  a.d.ll_stride = ll_is_packed ? (dir == kFwd ? c.dst_stride : c.src_stride) : ll_pitch(g.w[k]);
+  a.ll_bstride = ll_is_packed ? (dir == kFwd ? c.dst_bs : c.src_bs) : ws_bs;
+  if (dir == kFwd) {
+    a.d.pix_in = px;
+    a.d.ll_out = ll;
+    a.d.band_out = c.dst;
+    a.d.band_stride = c.dst_stride;
+    a.band_bstride = c.dst_bs;
+  } else {
+    a.d.pix_out = px;
+    a.d.ll_in = ll;
+    a.d.band_in = c.src;
+    a.d.band_stride = c.src_stride;
+    a.band_bstride = c.src_bs;
+  }
+  a.items_per_image = a.d.nstrips * a.d.nsegs;
+  a.items = (int64_t)a.items_per_image * c.batch;
+  a.d.fast_ok = fast_layout(dir, a, c.batch, W);
 }
 
+// One kernel launch per level (levels meet at kernel boundaries).
 int run_levels(int dir, const Call& c, const Geo& g, void* stream) {
-  const int64_t ws_bs = (int64_t)(ws_per_image(g) / 4);
   const int order_begin = dir == kFwd ? 1 : g.L, order_end = dir == kFwd ? g.L + 1 : 0;
   const int step = dir == kFwd ? 1 : -1;
   for (int k = order_begin; k != order_end; k += step) {
     LevelLaunch a;
-    memset(&a, 0, sizeof a);
-    const int W = g.w[k - 1], H = g.h[k - 1];
-    const int64_t strips_batch = (int64_t)num_strips(W) * c.batch;
-    const Tiling t = choose_tiling(dir, c.mode, ceil_half(H), strips_batch);
-    fill_level(a.d, W, H, t.seg);
-    // pixels of the level input: the image (k = 1) or LL_{k-1}
-    const bool px_is_image = (k == 1);
-    char* px = px_is_image ? (dir == kFwd ? const_cast<char*>(c.src) : c.dst) : ll_buf(c, g, k - 1);
-    a.d.pix_stride = px_is_image ? (dir == kFwd ? c.src_stride : c.dst_stride) : ll_pitch(g.w[k - 1]);
-    a.pix_bstride = px_is_image ? (dir == kFwd ? c.src_bs : c.dst_bs) : ws_bs;
-    // LL_k: the packed array's corner at the last level, else a workspace buffer
-    const bool ll_is_packed = (k == g.L);
-    char* ll = ll_is_packed ? (dir == kFwd ? c.dst : const_cast<char*>(c.src)) : ll_buf(c, g, k);
-    a.d.ll_stride = ll_is_packed ? (dir == kFwd ? c.dst_stride : c.src_stride) : ll_pitch(g.w[k]);
-    a.ll_bstride = ll_is_packed ? (dir == kFwd ? c.dst_bs : c.src_bs) : ws_bs;
-    if (dir == kFwd) {
-      a.d.pix_in = px;
-      a.d.ll_out = ll;
-      a.d.band_out = c.dst;
-      a.d.band_stride = c.dst_stride;
-      a.band_bstride = c.dst_bs;
-    } else {
-      a.d.pix_out = px;
-      a.d.ll_in = ll;
-      a.d.band_in = c.src;
-      a.d.band_stride = c.src_stride;
-      a.band_bstride = c.src_bs;
-    }
-    a.items_per_image = a.d.nstrips * a.d.nsegs;
-    a.items = (int64_t)a.items_per_image * c.batch;
-    a.d.fast_ok = fast_layout(dir, a, c.batch, W);
-    const int err = launch_level(dir, c.mode, t.ch, a, stream);
+    int ch;
+    level_launch(dir, c, g, k, 0, a, ch);
+    const int err = launch_level(dir, c.mode, ch, a, stream);
     if (err != hipSuccess)
       return fail(DWT2_ERR_HIP, "level %d launch failed: %s", k, hipGetErrorString((hipError_t)err));
   }
+  return DWT2_OK;
+}
+
+int64_t job_slots(int dir, int mode, int ch) {
+  static std::mutex mu;
+  static int cache[3][2][3] = {};
+  const int ci = ch >= 4 ? 2 : (ch >= 2 ? 1 : 0);
+  int blocks;
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    int& c = cache[dir][mode][ci];
+    if (!c) {
+      c = job_blocks_per_cu(dir, mode, ch);
+      if (c <= 0) c = 1;
+    }
+    blocks = c;
+  }
+  return (int64_t)blocks;
+}
+
+// All levels in one persistent launch (after a small kernel that clears the
+// synchronisation words).
+int run_job(int dir, const Call& c, const Geo& g, void* stream) {
+  if (g_forced_ch.load() < 0) g_forced_ch.store(env_int("DWT2_CH") > 0 ? env_int("DWT2_CH") : 0);
+  const int forced_ch = g_forced_ch.load();
+  const int ch = forced_ch > 0 ? (forced_ch >= 4 ? 4 : (forced_ch >= 2 ? 2 : 1)) : 2;
+  const int64_t blocks_per_cu = job_slots(dir, c.mode, ch);
+  const int64_t slots = blocks_per_cu * kWavesPerBlock * device_cus();
+  static JobArgs args;  // large; filled per call under the lock below
+  static std::mutex mu;
+  std::lock_guard<std::mutex> lock(mu);
+  memset(&args, 0, sizeof args);
+  int32_t items = 0, counters = 0;
+  for (int t = 0; t < g.L; ++t) {
+    const int k = dir == kFwd ? t + 1 : g.L - t;
+    LevelLaunch a;
+    int ch_unused;
+    level_launch(dir, c, g, k, slots, a, ch_unused);
+    JobDesc& jd = args.inl[t];
+    jd.d = a.d;
+    jd.pix_bstride = a.pix_bstride;
+    jd.ll_bstride = a.ll_bstride;
+    jd.band_bstride = a.band_bstride;
+    jd.nimg = c.batch;
+    jd.item_start = items;
+    jd.items = (int32_t)a.items;
+    jd.cbase = counters;
+    jd.prev = t - 1;
+    items += (int32_t)a.items;
+    counters += c.batch * a.d.nsegs;
+  }
+  args.ndesc = g.L;
+  args.total_items = items;
+  args.sync = reinterpret_cast<uint32_t*>(c.ws);
+  int err = launch_zero(args.sync, kSyncCounters + (int64_t)kCounterStride * counters, stream);
+  if (err == hipSuccess) {
+    const int64_t want = (items + kWavesPerBlock - 1) / kWavesPerBlock;
+    const int64_t cap = blocks_per_cu * device_cus();
+    const int blocks = (int)(want < cap ? want : cap);
+    err = launch_job(dir, c.mode, ch, args, blocks, stream);
+  }
+  if (err != hipSuccess) return fail(DWT2_ERR_HIP, "persistent launch failed: %s", hipGetErrorString((hipError_t)err));
   return DWT2_OK;
 }
 
@@ -213,11 +287,13 @@ static int transform(int dir, const void* src, int64_t src_stride, int64_t src_b
   if (mode != DWT2_F32 && mode != DWT2_I32_REV) return fail(DWT2_ERR_MODE, "unknown mode %d", mode);
   if (dir == kBwd && mode != DWT2_F32) return fail(DWT2_ERR_MODE, "the adjoint exists for DWT2_F32 only");
   if (src == dst) return fail(DWT2_ERR_ALIAS, "src and dst are the same buffer; the transform is out of place");
-  const size_t need = ws_per_image(g) * (size_t)batch;
-  if (need > 0 && (!workspace || workspace_bytes < need))
+  const size_t need = sync_bytes(g, batch) + ws_per_image(g) * (size_t)batch;
+  if (!workspace || workspace_bytes < need)
     return fail(DWT2_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, workspace ? workspace_bytes : 0);
   Call c{static_cast<const char*>(src), src_stride, src_bs, static_cast<char*>(dst), dst_stride, dst_bs, batch, mode,
-         static_cast<char*>(workspace)};
+         static_cast<char*>(workspace), sync_bytes(g, batch)};
+  if (g_persistent.load() < 0) g_persistent.store(env_int("DWT2_PERSISTENT") == 1 ? 1 : 0);
+  if (g_persistent.load() && g.L <= kInlineDescs) return run_job(dir, c, g, stream);
   return run_levels(dir, c, g, stream);
 }
 
@@ -231,7 +307,7 @@ size_t dwt2_workspace_size(int32_t width, int32_t height, int32_t batch, int32_t
   Geo g;
   if (batch < 1 || (mode != DWT2_F32 && mode != DWT2_I32_REV)) return 0;
   if (check_geometry(width, height, levels, g) != DWT2_OK) return 0;
-  return ws_per_image(g) * (size_t)batch;
+  return sync_bytes(g, batch) + ws_per_image(g) * (size_t)batch;
 }
 
 int dwt2_fwd(const void* src, int64_t src_stride, int64_t src_batch_stride, void* dst, int64_t dst_stride,
@@ -270,6 +346,13 @@ const char* dwt2_status_string(int status) {
 }
 
 const char* dwt2_last_error(void) { return g_last_error.c_str(); }
+
+int dwt2_set_path(int32_t persistent) {
+  clear_error();
+  if (persistent != 0 && persistent != 1) return fail(DWT2_ERR_ARG, "persistent must be 0 or 1");
+  g_persistent.store(persistent);
+  return DWT2_OK;
+}
 
 int dwt2_set_tiling(int32_t seg, int32_t chunk) {
   clear_error();

@@ -1,6 +1,23 @@
-// dwt2_fwd_batched: a ragged list of images.
+// dwt2_fwd_batched: a ragged list of images in one persistent launch.
+//
+// Plan (cached per shape set and workspace): every (level, image) becomes one
+// step of a persistent job; the queue holds level 1 of all images (largest
+// first), then level 2, and so on, so an image's next level starts as soon
+// as the rows it reads exist while other images are still at the previous
+// level.  The segment heights come from a small autotuner that times a few
+// policies on the first call.  Each call refreshes the step descriptors
+// (image pointers) in pinned staging and replays a HIP graph:
+//   copy staging -> workspace tables, clear the sync words, persistent job.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "plan.h"
@@ -9,21 +26,343 @@ using namespace dwt2;
 
 namespace {
 
-int validate_images(const dwt2_image_t* images, int32_t n, int32_t levels, int32_t mode, std::vector<Geo>& geos,
-                    size_t& total_ws) {
+constexpr int kBatchCh = 2;     // prefetch chunk of the batched job kernel
+constexpr int kMinSeg = 2 * kBatchCh;
+
+int validate_images(const dwt2_image_t* images, int32_t n, int32_t levels, int32_t mode, std::vector<Geo>& geos) {
   if (!images || n < 1) return fail(DWT2_ERR_ARG, "need a host array of at least one image");
   if (mode != DWT2_F32 && mode != DWT2_I32_REV) return fail(DWT2_ERR_MODE, "unknown mode %d", mode);
   geos.resize(n);
-  total_ws = 0;
   for (int i = 0; i < n; ++i) {
     const dwt2_image_t& im = images[i];
     if (!im.src || !im.dst) return fail(DWT2_ERR_ARG, "image %d: null src or dst", i);
     if (im.width >= 2 && (im.src_stride < im.width || im.dst_stride < im.width))
       return fail(DWT2_ERR_ARG, "image %d: stride < width", i);
     const int st = check_geometry(im.width, im.height, levels, geos[i]);
-    if (st) return fail(st, "image %d: %s", i, dwt2_last_error());
+    if (st) {
+      const std::string why = dwt2_last_error();
+      return fail(st, "image %d: %s", i, why.c_str());
+    }
     if (im.src == im.dst) return fail(DWT2_ERR_ALIAS, "image %d: src == dst", i);
-    total_ws += ws_per_image(geos[i]);
+  }
+  return DWT2_OK;
+}
+
+struct Layout {
+  size_t sync, descs, items, ll;  // byte offsets
+  size_t total;
+  std::vector<size_t> ll_off;     // per image, relative to ll
+  int64_t max_items, max_counters;
+};
+
+// Workspace layout; the bounds assume the smallest segment height.
+Layout layout(const std::vector<Geo>& geos) {
+  Layout L;
+  const int n = (int)geos.size();
+  int64_t counters = 0, items = 0;
+  L.ll_off.resize(n);
+  size_t ll = 0;
+  for (int i = 0; i < n; ++i) {
+    const Geo& g = geos[i];
+    for (int k = 1; k <= g.L; ++k) {
+      const int64_t segs = (ceil_half(g.h[k - 1]) + kMinSeg - 1) / kMinSeg;
+      counters += segs;
+      items += segs * num_strips(g.w[k - 1]);
+    }
+    L.ll_off[i] = ll;
+    ll += ws_per_image(g);
+  }
+  L.max_items = items;
+  L.max_counters = counters;
+  L.sync = 0;
+  L.descs = round256((size_t)(kSyncCounters + kCounterStride * counters) * 4);
+  L.items = L.descs + round256((size_t)n * geos[0].L * sizeof(JobDesc));
+  L.ll = L.items + round256((size_t)items * 4);
+  L.total = L.ll + ll;
+  return L;
+}
+
+// Segment height of level k (quadruple rows of its input) under policy
+// `base`: the level-1 height, halved per level, never below kMinSeg.
+int seg_for(int base, int k, int ns_h) {
+  int s = base >> (k - 1);
+  if (s < kMinSeg) s = kMinSeg;
+  s = (s + kMinSeg - 1) / kMinSeg * kMinSeg;
+  const int cap = (ns_h + kMinSeg - 1) / kMinSeg * kMinSeg;
+  return s < cap ? s : cap;
+}
+
+struct Plan {
+  int n = 0, levels = 0, mode = 0;
+  int base_seg = 32;
+  std::vector<Geo> geos;
+  std::vector<int> order;       // images by decreasing pixel count
+  Layout lay;
+  int32_t ndesc = 0, total_items = 0, counters = 0;
+  std::vector<uint32_t> item_desc;
+  std::vector<int> desc_seg;    // segment height per desc
+  std::vector<int32_t> step0_items;  // items of each level-1 desc
+  // device side
+  char* ws = nullptr;
+  void* staging = nullptr;      // pinned: descs then items
+  size_t staging_bytes = 0;
+  hipEvent_t done = nullptr;
+  bool pending = false;
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+  int blocks = 0;
+  ~Plan() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (done) (void)hipEventDestroy(done);
+    if (staging) (void)hipHostFree(staging);
+  }
+};
+
+std::mutex g_mu;
+std::map<std::string, std::unique_ptr<Plan>> g_plans;
+std::map<std::string, int> g_tuned;  // shape set -> base segment height
+bool g_tune_loaded = false;
+
+std::string shape_key(const dwt2_image_t* images, int n, int levels, int mode) {
+  std::string k;
+  char buf[96];
+  snprintf(buf, sizeof buf, "%d:%d:%d|", n, levels, mode);
+  k += buf;
+  for (int i = 0; i < n; ++i) {
+    snprintf(buf, sizeof buf, "%d,%d;", images[i].width, images[i].height);
+    k += buf;
+  }
+  return k;
+}
+
+std::string hash_key(const std::string& s) {  // FNV-1a, for the tune-cache file
+  uint64_t h = 1469598103934665603ull;
+  for (unsigned char c : s) h = (h ^ c) * 1099511628211ull;
+  char buf[32];
+  snprintf(buf, sizeof buf, "%016llx", (unsigned long long)h);
+  return buf;
+}
+
+void load_tune_cache() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char* path = getenv("DWT2_TUNE_CACHE");
+  if (!path) return;
+  FILE* f = fopen(path, "r");
+  if (!f) return;
+  char key[64];
+  int base;
+  while (fscanf(f, "%63s %d", key, &base) == 2) g_tuned[key] = base;
+  fclose(f);
+}
+
+void save_tune(const std::string& hk, int base) {
+  const char* path = getenv("DWT2_TUNE_CACHE");
+  if (!path) return;
+  FILE* f = fopen(path, "a");
+  if (!f) return;
+  fprintf(f, "%s %d\n", hk.c_str(), base);
+  fclose(f);
+}
+
+// Item table and segment heights for a policy.
+void build_schedule(Plan& p, int base) {
+  p.base_seg = base;
+  p.ndesc = p.n * p.levels;
+  p.desc_seg.assign(p.ndesc, 0);
+  p.step0_items.assign(p.n, 0);
+  p.item_desc.clear();
+  p.counters = 0;
+  for (int t = 0; t < p.levels; ++t) {
+    for (int oi = 0; oi < p.n; ++oi) {
+      const int i = p.order[oi];
+      const Geo& g = p.geos[i];
+      const int k = t + 1;
+      const int ns_h = ceil_half(g.h[k - 1]);
+      const int seg = seg_for(base, k, ns_h);
+      const int j = t * p.n + oi;
+      p.desc_seg[j] = seg;
+      const int nsegs = (ns_h + seg - 1) / seg;
+      const int items = nsegs * num_strips(g.w[k - 1]);
+      p.item_desc.insert(p.item_desc.end(), items, (uint32_t)j);
+      if (t == 0) p.step0_items[oi] = items;
+      p.counters += nsegs;
+    }
+  }
+  p.total_items = (int32_t)p.item_desc.size();
+}
+
+// Step descriptors for the current pointers, written to the staging buffer.
+void fill_descs(Plan& p, const dwt2_image_t* images, JobDesc* out) {
+  int32_t start = 0, cbase = 0;
+  for (int t = 0; t < p.levels; ++t) {
+    for (int oi = 0; oi < p.n; ++oi) {
+      const int i = p.order[oi];
+      const Geo& g = p.geos[i];
+      const int k = t + 1;
+      const int j = t * p.n + oi;
+      const dwt2_image_t& im = images[i];
+      Call c{static_cast<const char*>(im.src), im.src_stride, 0, static_cast<char*>(im.dst), im.dst_stride, 0, 1,
+             p.mode, p.ws, p.lay.ll + p.lay.ll_off[i]};
+      JobDesc& jd = out[j];
+      memset(&jd, 0, sizeof jd);
+      LevelDesc& d = jd.d;
+      const int W = g.w[k - 1], H = g.h[k - 1];
+      fill_level(d, W, H, p.desc_seg[j]);
+      d.pix_in = (k == 1) ? static_cast<const void*>(im.src)
+                          : static_cast<const void*>(c.ws + c.ll_base + ll_offset(g, k - 1));
+      d.pix_stride = (k == 1) ? im.src_stride : ll_pitch(g.w[k - 1]);
+      d.ll_out = (k == g.L) ? im.dst : static_cast<void*>(c.ws + c.ll_base + ll_offset(g, k));
+      d.ll_stride = (k == g.L) ? im.dst_stride : ll_pitch(g.w[k]);
+      d.band_out = im.dst;
+      d.band_stride = im.dst_stride;
+      LevelLaunch a;
+      memset(&a, 0, sizeof a);
+      a.d = d;
+      d.fast_ok = fast_layout(kFwd, a, 1, W);
+      jd.nimg = 1;
+      jd.item_start = start;
+      jd.items = d.nsegs * d.nstrips;
+      jd.cbase = cbase;
+      jd.prev = t > 0 ? (t - 1) * p.n + oi : -1;
+      start += jd.items;
+      cbase += d.nsegs;
+    }
+  }
+}
+
+JobArgs job_args(const Plan& p) {
+  JobArgs a;
+  memset(&a, 0, sizeof a);
+  a.descs = reinterpret_cast<const JobDesc*>(p.ws + p.lay.descs);
+  a.item_desc = reinterpret_cast<const uint32_t*>(p.ws + p.lay.items);
+  a.sync = reinterpret_cast<uint32_t*>(p.ws + p.lay.sync);
+  a.ndesc = p.ndesc;
+  a.total_items = p.total_items;
+  return a;
+}
+
+// Copy the tables, clear the sync words, run the job (on `s`).
+hipError_t enqueue(const Plan& p, hipStream_t s) {
+  const size_t dbytes = (size_t)p.ndesc * sizeof(JobDesc);
+  hipError_t e = hipMemcpyAsync(p.ws + p.lay.descs, p.staging, dbytes, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return e;
+  e = hipMemcpyAsync(p.ws + p.lay.items, static_cast<char*>(p.staging) + round256(dbytes),
+                     (size_t)p.total_items * 4, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return e;
+  int err = launch_zero(reinterpret_cast<uint32_t*>(p.ws + p.lay.sync), kSyncCounters + (int64_t)kCounterStride * p.counters, s);
+  if (err != hipSuccess) return (hipError_t)err;
+  return (hipError_t)launch_job(kFwd, p.mode, kBatchCh, job_args(p), p.blocks, s);
+}
+
+void write_staging(Plan& p, const dwt2_image_t* images) {
+  const size_t dbytes = (size_t)p.ndesc * sizeof(JobDesc);
+  fill_descs(p, images, static_cast<JobDesc*>(p.staging));
+  memcpy(static_cast<char*>(p.staging) + round256(dbytes), p.item_desc.data(), (size_t)p.total_items * 4);
+}
+
+int ensure_staging(Plan& p) {
+  const size_t need = round256((size_t)p.ndesc * sizeof(JobDesc)) + round256((size_t)p.total_items * 4);
+  if (p.staging && p.staging_bytes >= need) return DWT2_OK;
+  if (p.staging) (void)hipHostFree(p.staging);
+  p.staging = nullptr;
+  if (hipHostMalloc(&p.staging, need, hipHostMallocDefault) != hipSuccess || !p.staging)
+    return fail(DWT2_ERR_NOMEM, "pinned staging of %zu bytes", need);
+  p.staging_bytes = need;
+  return DWT2_OK;
+}
+
+// Times the candidate policies once (outside any capture) and keeps the best.
+int autotune(Plan& p, const dwt2_image_t* images, hipStream_t s, const std::string& hk) {
+  static const int candidates[] = {8, 16, 32, 64};
+  const char* forced = getenv("DWT2_BATCH_SEG");
+  if (forced && atoi(forced) > 0) {
+    build_schedule(p, atoi(forced));
+    return DWT2_OK;
+  }
+  auto it = g_tuned.find(hk);
+  if (it != g_tuned.end()) {
+    build_schedule(p, it->second);
+    return DWT2_OK;
+  }
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return fail(DWT2_ERR_HIP, "event creation failed");
+  float best = 1e30f;
+  int best_base = 32;
+  for (int base : candidates) {
+    build_schedule(p, base);
+    if (p.total_items > p.lay.max_items || p.counters > p.lay.max_counters) continue;
+    int st = ensure_staging(p);
+    if (st) return st;
+    write_staging(p, images);
+    float t = 0.f;
+    for (int rep = 0; rep < 2; ++rep) {
+      if (hipEventRecord(e0, s) != hipSuccess || enqueue(p, s) != hipSuccess || hipEventRecord(e1, s) != hipSuccess ||
+          hipEventSynchronize(e1) != hipSuccess)
+        return fail(DWT2_ERR_HIP, "autotune run failed");
+      (void)hipEventElapsedTime(&t, e0, e1);
+    }
+    if (t < best) {
+      best = t;
+      best_base = base;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  build_schedule(p, best_base);
+  g_tuned[hk] = best_base;
+  save_tune(hk, best_base);
+  return DWT2_OK;
+}
+
+int build_plan(Plan& p, const dwt2_image_t* images, int n, int levels, int mode, std::vector<Geo>&& geos, char* ws,
+               hipStream_t s, const std::string& key) {
+  p.n = n;
+  p.levels = levels;
+  p.mode = mode;
+  p.geos = std::move(geos);
+  p.ws = ws;
+  p.lay = layout(p.geos);
+  p.order.resize(n);
+  for (int i = 0; i < n; ++i) p.order[i] = i;
+  std::stable_sort(p.order.begin(), p.order.end(), [&](int a, int b) {
+    return (int64_t)images[a].width * images[a].height > (int64_t)images[b].width * images[b].height;
+  });
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  int bpc = job_blocks_per_cu(kFwd, mode, kBatchCh);
+  p.blocks = (bpc > 0 ? bpc : 1) * (cus > 0 ? cus : 256);
+  load_tune_cache();
+  int st = autotune(p, images, s, hash_key(key));
+  if (st) return st;
+  st = ensure_staging(p);
+  if (st) return st;
+  if (hipEventCreateWithFlags(&p.done, hipEventDisableTiming) != hipSuccess)
+    return fail(DWT2_ERR_HIP, "event creation failed");
+  static const int use_graph = [] {
+    const char* e = getenv("DWT2_BATCH_GRAPH");
+    return e ? atoi(e) : 1;
+  }();
+  if (use_graph) {
+    hipStream_t cap;
+    if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess)
+      return fail(DWT2_ERR_HIP, "capture stream creation failed");
+    bool ok = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    ok = ok && enqueue(p, cap) == hipSuccess;
+    hipGraph_t graph = nullptr;
+    ok = (hipStreamEndCapture(cap, &graph) == hipSuccess) && ok && graph;
+    (void)hipStreamDestroy(cap);
+    // a runtime that cannot capture or instantiate the cooperative launch
+    // keeps the plan on direct launches
+    if (ok) {
+      p.graph = graph;
+      if (hipGraphInstantiate(&p.exec, graph, nullptr, nullptr, 0) != hipSuccess) p.exec = nullptr;
+    } else if (graph) {
+      (void)hipGraphDestroy(graph);
+    }
+    (void)hipGetLastError();
   }
   return DWT2_OK;
 }
@@ -34,9 +373,8 @@ extern "C" {
 
 size_t dwt2_batched_workspace_size(const dwt2_image_t* images, int32_t n, int32_t levels, int32_t mode) {
   std::vector<Geo> geos;
-  size_t total = 0;
-  if (validate_images(images, n, levels, mode, geos, total) != DWT2_OK) return 0;
-  return total;
+  if (validate_images(images, n, levels, mode, geos) != DWT2_OK) return 0;
+  return layout(geos).total;
 }
 
 int dwt2_fwd_batched(const dwt2_image_t* images, int32_t n, int32_t levels, int32_t mode, int32_t boundary,
@@ -44,23 +382,43 @@ int dwt2_fwd_batched(const dwt2_image_t* images, int32_t n, int32_t levels, int3
   clear_error();
   if (boundary != DWT2_EXT_SYMMETRIC) return fail(DWT2_ERR_ARG, "unknown boundary %d", boundary);
   std::vector<Geo> geos;
-  size_t total = 0;
-  int st = validate_images(images, n, levels, mode, geos, total);
+  int st = validate_images(images, n, levels, mode, geos);
   if (st) return st;
-  if (total > 0 && (!workspace || workspace_bytes < total))
+  const size_t total = layout(geos).total;
+  if (!workspace || workspace_bytes < total)
     return fail(DWT2_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", total, workspace ? workspace_bytes : 0);
-  size_t off = 0;
-  for (int i = 0; i < n; ++i) {
-    const dwt2_image_t& im = images[i];
-    Call c{static_cast<const char*>(im.src), im.src_stride, 0, static_cast<char*>(im.dst), im.dst_stride, 0, 1, mode,
-           static_cast<char*>(workspace) + off};
-    st = run_levels(0, c, geos[i], stream);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(DWT2_ERR_HIP, "no current device");
+  std::string key = shape_key(images, n, levels, mode);
+  char wsbuf[64];
+  snprintf(wsbuf, sizeof wsbuf, "|ws%p|dev%d", workspace, dev);
+  const std::string plan_key = key + wsbuf;
+
+  std::lock_guard<std::mutex> lock(g_mu);
+  auto it = g_plans.find(plan_key);
+  if (it == g_plans.end()) {
+    std::unique_ptr<Plan> p(new Plan);
+    st = build_plan(*p, images, n, levels, mode, std::move(geos), static_cast<char*>(workspace), s, key);
     if (st) return st;
-    off += ws_per_image(geos[i]);
+    it = g_plans.emplace(plan_key, std::move(p)).first;
   }
+  Plan& p = *it->second;
+  // the previous call of this plan must have consumed the staging buffer
+  if (p.pending && hipEventSynchronize(p.done) != hipSuccess) return fail(DWT2_ERR_HIP, "event wait failed");
+  write_staging(p, images);
+  hipError_t e = p.exec ? hipGraphLaunch(p.exec, s) : enqueue(p, s);
+  if (e == hipSuccess) e = hipEventRecord(p.done, s);
+  if (e != hipSuccess) return fail(DWT2_ERR_HIP, "batched launch failed: %s", hipGetErrorString(e));
+  p.pending = true;
   return DWT2_OK;
 }
 
-void dwt2_clear_plan_cache(void) {}
+void dwt2_clear_plan_cache(void) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  for (auto& kv : g_plans)
+    if (kv.second->pending) (void)hipEventSynchronize(kv.second->done);
+  g_plans.clear();
+}
 
 }  // extern "C"

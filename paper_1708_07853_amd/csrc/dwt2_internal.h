@@ -62,9 +62,45 @@ inline int64_t ll_pitch(int w) {  // padded row pitch (elements) of an LL buffer
   return ((int64_t)w + 63) & ~(int64_t)63;
 }
 
+// One step of a persistent job: one level of one image, or of a batch of
+// equally sized images (nimg > 1, images `*_bstride` elements apart).
+// Work items of the step occupy queue slots [item_start, item_start + items)
+// in (image, segment, strip) order.  Each (image, segment) has a completion
+// counter at sync[kSyncCounters + kCounterStride * (cbase + image * nsegs +
+// segment)], one per 64-byte line so that polls of different counters do not
+// queue behind each other.
+struct JobDesc {
+  LevelDesc d;
+  int64_t pix_bstride, ll_bstride, band_bstride;
+  int32_t nimg;
+  int32_t item_start;
+  int32_t items;
+  int32_t cbase;
+  int32_t prev;   // step this one reads from (same images), or -1
+  int32_t pad_[3];
+};
+
+constexpr int kInlineDescs = 20;
+constexpr int kSyncError = 1;     // set when a dependency wait gives up
+constexpr int kSyncCounters = 16; // first completion counter
+constexpr int kCounterStride = 16; // words between counters (one 64-byte line each)
+
+struct JobArgs {
+  const JobDesc* descs;       // device table, or null: use inl[]
+  const uint32_t* item_desc;  // device queue-slot -> desc table, or null: scan
+  uint32_t* sync;             // zeroed before every launch
+  int32_t ndesc;
+  int32_t total_items;
+  int32_t pad_[2];
+  JobDesc inl[kInlineDescs];
+};
+
 // Kernel launchers (kernels.hip).  Return hipError_t as int.
 int launch_level(int dir, int mode, int chunk, const LevelLaunch& a, void* stream);
 // Resident 256-thread blocks per CU of the level kernel (0 if unknown).
 int level_blocks_per_cu(int dir, int mode, int chunk);
+int job_blocks_per_cu(int dir, int mode, int chunk);
+int launch_job(int dir, int mode, int chunk, const JobArgs& a, int blocks, void* stream);
+int launch_zero(uint32_t* p, int64_t n, void* stream);
 
 }  // namespace dwt2

@@ -58,7 +58,6 @@ __device__ __forceinline__ int fold_idx(int p, int n) {
 // of length n, following the symmetric extension of the interleaved array.
 __device__ __forceinline__ int band_idx(int q, int n, int par) { return (fold_idx(2 * q + par, n) - par) >> 1; }
 
-__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
 // Lane exchange by full-wave DPP shifts: from_next gives lane i the value of
 // lane i+1 (wave_shl:1), from_prev the value of lane i-1 (wave_shr:1); the
@@ -96,6 +95,84 @@ __device__ __forceinline__ void st4(T* p, const V4<T>& v) {
   Ext4<T> t;
   t.x = v.x; t.y = v.y; t.z = v.z; t.w = v.w;
   *reinterpret_cast<Ext4<T>*>(p) = t;
+}
+
+// Buffer resources: CDNA buffer instructions check every access against the
+// resource's byte size in hardware -- a store outside it is dropped and a
+// load outside it returns 0.  One resource per row (base = row start) masks
+// whole rows (size 0) and columns past the row's end without branches.
+using Rsrc = __amdgpu_buffer_rsrc_t;
+__device__ __forceinline__ Rsrc row_rsrc(const void* base, int64_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, 0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ unsigned ubits(T v) {
+  return __builtin_bit_cast(unsigned, v);
+}
+template <typename T>
+__device__ __forceinline__ T from_bits(unsigned u) {
+  return __builtin_bit_cast(T, u);
+}
+// Element offsets are converted to byte offsets; a negative element offset
+// wraps to a huge byte offset and is therefore out of range.  The main data
+// streams are touched once per level, so they use the non-temporal cache
+// policy (kNT); halo values, which neighbouring lanes and strips read again,
+// use the default policy.
+constexpr int kNT = 2;
+// Cache-policy bits: sc0 = 1, nt = 2, sc1 = 16.  Inside a persistent job the
+// LL rows one item writes are read by items on other XCDs, whose L2s are not
+// coherent with the writer's; those accesses carry sc1 (stores write through,
+// loads miss stale L2 lines) and sc0 (loads skip the CU's L1), so no
+// whole-cache writeback or invalidation is needed between items.
+constexpr int kSC0 = 1, kSC1 = 16;
+#ifndef DWT2_COH_LD
+#define DWT2_COH_LD (kNT | kSC0 | kSC1)
+#endif
+#ifndef DWT2_COH_HALO
+#define DWT2_COH_HALO (kSC0 | kSC1)
+#endif
+#ifndef DWT2_COH_ST
+#define DWT2_COH_ST (kNT | kSC1)
+#endif
+template <bool COH>
+struct Pol {
+  static constexpr int ld = COH ? (DWT2_COH_LD) : kNT;    // main streams
+  static constexpr int halo = COH ? (DWT2_COH_HALO) : 0;  // re-read halo values
+  static constexpr int st = COH ? (DWT2_COH_ST) : kNT;
+};
+template <int POL, typename T>
+__device__ __forceinline__ void bst1(T v, Rsrc r, int e) {
+  __builtin_amdgcn_raw_buffer_store_b32(ubits(v), r, (unsigned)e * 4u, 0, POL);
+}
+template <int POL, typename T>
+__device__ __forceinline__ void bst2(T a, T b, Rsrc r, int e) {
+  typedef unsigned U2 __attribute__((ext_vector_type(2)));
+  U2 u;
+  u.x = ubits(a);
+  u.y = ubits(b);
+  __builtin_amdgcn_raw_buffer_store_b64(u, r, (unsigned)e * 4u, 0, POL);
+}
+template <int POL, typename T>
+__device__ __forceinline__ void bst4(const V4<T>& v, Rsrc r, int e) {
+  typedef unsigned U4 __attribute__((ext_vector_type(4)));
+  U4 u;
+  u.x = ubits(v.x); u.y = ubits(v.y); u.z = ubits(v.z); u.w = ubits(v.w);
+  __builtin_amdgcn_raw_buffer_store_b128(u, r, (unsigned)e * 4u, 0, POL);
+}
+template <typename T, int POL>
+__device__ __forceinline__ T bld1(Rsrc r, int e) {
+  return from_bits<T>(__builtin_amdgcn_raw_buffer_load_b32(r, (unsigned)e * 4u, 0, POL));
+}
+template <int POL, typename T>
+__device__ __forceinline__ void bld2(Rsrc r, int e, T& a, T& b) {
+  const auto u = __builtin_amdgcn_raw_buffer_load_b64(r, (unsigned)e * 4u, 0, POL);
+  a = from_bits<T>(u[0]);
+  b = from_bits<T>(u[1]);
+}
+template <int POL, typename T>
+__device__ __forceinline__ void bld4(Rsrc r, int e, V4<T>& v) {
+  const auto u = __builtin_amdgcn_raw_buffer_load_b128(r, (unsigned)e * 4u, 0, POL);
+  v.x = from_bits<T>(u[0]); v.y = from_bits<T>(u[1]); v.z = from_bits<T>(u[2]); v.w = from_bits<T>(u[3]);
 }
 
 // ---------------------------------------------------------------------------
@@ -257,68 +334,61 @@ __device__ __forceinline__ Item make_item(const LevelDesc& d, int strip, int seg
   return it;
 }
 
-// Double-buffered row pipeline.  The caller has issued the loads of chunk A
-// (rows I0 .. I0+CH-1) before its prologue.  Fast items have a positive
-// multiple of 2*CH rows and run without guards; the others are guarded.
-template <int CH, bool FAST, typename Buf, typename LoadF, typename RowF>
+// Double-buffered row pipeline over ceil((I1 - I0) / (2 CH)) chunk pairs.
+// The caller has issued the loads of chunk A (rows I0 .. I0+CH-1) before its
+// prologue.  Rows past I1 ("phantom" rows of the last pair) are computed on
+// folded or zero inputs and their stores are dropped by the buffer bounds, so
+// the loop has no branches and the compiler's wait counts stay exact.
+template <int CH, typename Buf, typename LoadF, typename RowF>
 __device__ __forceinline__ void run_rows(int I0, int I1, Buf& A, Buf& B, LoadF&& load_chunk, RowF&& row) {
   int i0 = I0;
-  if constexpr (FAST) {
-    const int npairs = (I1 - I0) / (2 * CH);
-    for (int p = 1; p < npairs; ++p) {
-      load_chunk(B, i0 + CH);
-#pragma unroll
-      for (int m = 0; m < CH; ++m) row(A, m, i0 + m);
-      load_chunk(A, i0 + 2 * CH);
-#pragma unroll
-      for (int m = 0; m < CH; ++m) row(B, m, i0 + CH + m);
-      i0 += 2 * CH;
-    }
+  const int npairs = (I1 - I0 + 2 * CH - 1) / (2 * CH);
+  for (int p = 1; p < npairs; ++p) {
     load_chunk(B, i0 + CH);
 #pragma unroll
     for (int m = 0; m < CH; ++m) row(A, m, i0 + m);
+    load_chunk(A, i0 + 2 * CH);
 #pragma unroll
     for (int m = 0; m < CH; ++m) row(B, m, i0 + CH + m);
-  } else {
-    for (;;) {
-#pragma unroll
-      for (int m = 0; m < CH; ++m)
-        if (i0 + m < I1) row(A, m, i0 + m);
-      i0 += CH;
-      if (i0 >= I1) break;
-      load_chunk(A, i0);
-    }
+    i0 += 2 * CH;
   }
+  load_chunk(B, i0 + CH);
+#pragma unroll
+  for (int m = 0; m < CH; ++m) row(A, m, i0 + m);
+#pragma unroll
+  for (int m = 0; m < CH; ++m) row(B, m, i0 + CH + m);
 }
 
 // ---------------------------------------------------------------- forward
 // Pixel rows: four pixels per lane plus two halo pixels (lane 0: the two
 // columns left of the strip; lane 63: the column right of it).
-template <typename T, bool FAST>
+template <typename T, bool FAST, bool COH>
 struct PxLoader {
   const T* base;
   int64_t stride;
-  int H;
+  int W, H;
   int c0;
   int col[4];
   int hc0, hc1;
   __device__ __forceinline__ void load(int r, V4<T>& m, T& h0, T& h1) const {
-    const T* row = base + (int64_t)fold_idx(r, H) * stride;
+    const Rsrc rs = row_rsrc(base + (int64_t)fold_idx(r, H) * stride, (int64_t)W * 4);
     if constexpr (FAST) {
-      const Ext4<T> t = *reinterpret_cast<const Ext4<T>*>(row + c0);
-      m.x = t.x; m.y = t.y; m.z = t.z; m.w = t.w;
+      bld4<Pol<COH>::ld>(rs, c0, m);
     } else {
-      m.x = row[col[0]]; m.y = row[col[1]]; m.z = row[col[2]]; m.w = row[col[3]];
+      m.x = bld1<T, Pol<COH>::ld>(rs, col[0]);
+      m.y = bld1<T, Pol<COH>::ld>(rs, col[1]);
+      m.z = bld1<T, Pol<COH>::ld>(rs, col[2]);
+      m.w = bld1<T, Pol<COH>::ld>(rs, col[3]);
     }
-    h0 = row[hc0];
-    h1 = row[hc1];
+    h0 = bld1<T, Pol<COH>::halo>(rs, hc0);
+    h1 = bld1<T, Pol<COH>::halo>(rs, hc1);
   }
 };
 
-template <typename T, bool FAST>
-__device__ __forceinline__ PxLoader<T, FAST> px_loader(const T* base, int64_t stride, const Item& it) {
-  PxLoader<T, FAST> L;
-  L.base = base; L.stride = stride; L.H = it.H;
+template <typename T, bool FAST, bool COH>
+__device__ __forceinline__ PxLoader<T, FAST, COH> px_loader(const T* base, int64_t stride, const Item& it) {
+  PxLoader<T, FAST, COH> L;
+  L.base = base; L.stride = stride; L.W = it.W; L.H = it.H;
   L.c0 = 2 * it.qL;
   for (int k = 0; k < 4; ++k) L.col[k] = fold_idx(L.c0 + k, it.W);
   if (it.first) {
@@ -338,55 +408,51 @@ struct PxBuf {
   T ho0[CH], ho1[CH], he0[CH], he1[CH];
 };
 
-// Stores of one row of the four bands (forward).
-template <typename T, bool FAST>
+// Stores of one row of the four bands (forward): one buffer resource per band
+// row; rows past I1 (and LH / HH rows past nd_h) have size 0, columns past
+// the band's width are out of range.
+template <typename T, bool FAST, bool COH>
 struct BandStore {
   T* ll;
   int64_t ls;
   T* band;
   int64_t bs;
-  int ns_w, nd_w, ns_h, nd_h, qL;
-  bool okL_s, okR_s, okL_d, okR_d;  // general path: quadruple column valid for L / H parity
+  int ns_w, nd_w, ns_h, nd_h, qL, I1;
   __device__ __forceinline__ void put(int i, T llL, T llR, T hlL, T hlR, T lhL, T lhR, T hhL, T hhR) const {
-    T* rl = ll + (int64_t)i * ls + qL;
-    T* rh = band + (int64_t)i * bs + ns_w + qL;
+    const bool real = i < I1, real2 = real && i < nd_h;
+    const Rsrc rl = row_rsrc(ll + (int64_t)i * ls, real ? ns_w * 4 : 0);
+    const Rsrc rh = row_rsrc(band + (int64_t)i * bs + ns_w, real ? nd_w * 4 : 0);
+    T* row2 = band + (int64_t)(ns_h + i) * bs;
+    const Rsrc rlh = row_rsrc(row2, real2 ? ns_w * 4 : 0);
+    const Rsrc rhh = row_rsrc(row2 + ns_w, real2 ? nd_w * 4 : 0);
+    constexpr int P = Pol<COH>::st;
     if constexpr (FAST) {
-      st2(rl, llL, llR);
-      st2(rh, hlL, hlR);
-      T* r2 = band + (int64_t)(ns_h + i) * bs + qL;
-      st2(r2, lhL, lhR);
-      st2(r2 + ns_w, hhL, hhR);
+      bst2<P>(llL, llR, rl, qL);
+      bst2<P>(hlL, hlR, rh, qL);
+      bst2<P>(lhL, lhR, rlh, qL);
+      bst2<P>(hhL, hhR, rhh, qL);
     } else {
-      if (okL_s) rl[0] = llL;
-      if (okR_s) rl[1] = llR;
-      if (okL_d) rh[0] = hlL;
-      if (okR_d) rh[1] = hlR;
-      if (i < nd_h) {
-        T* r2 = band + (int64_t)(ns_h + i) * bs + qL;
-        if (okL_s) r2[0] = lhL;
-        if (okR_s) r2[1] = lhR;
-        if (okL_d) r2[ns_w] = hhL;
-        if (okR_d) r2[ns_w + 1] = hhR;
-      }
+      bst1<P>(llL, rl, qL); bst1<P>(llR, rl, qL + 1);
+      bst1<P>(hlL, rh, qL); bst1<P>(hlR, rh, qL + 1);
+      bst1<P>(lhL, rlh, qL); bst1<P>(lhR, rlh, qL + 1);
+      bst1<P>(hhL, rhh, qL); bst1<P>(hhR, rhh, qL + 1);
     }
   }
 };
 
-template <typename T, bool FAST>
-__device__ __forceinline__ BandStore<T, FAST> band_store(T* ll, int64_t ls, T* band, int64_t bs, const Item& it) {
-  BandStore<T, FAST> S;
+template <typename T, bool FAST, bool COH>
+__device__ __forceinline__ BandStore<T, FAST, COH> band_store(T* ll, int64_t ls, T* band, int64_t bs, const Item& it) {
+  BandStore<T, FAST, COH> S;
   S.ll = ll; S.ls = ls; S.band = band; S.bs = bs;
-  S.ns_w = it.ns_w; S.nd_w = it.nd_w; S.ns_h = it.ns_h; S.nd_h = it.nd_h; S.qL = it.qL;
-  S.okL_s = it.qL < it.ns_w; S.okR_s = it.qL + 1 < it.ns_w;
-  S.okL_d = it.qL < it.nd_w; S.okR_d = it.qL + 1 < it.nd_w;
+  S.ns_w = it.ns_w; S.nd_w = it.nd_w; S.ns_h = it.ns_h; S.nd_h = it.nd_h; S.qL = it.qL; S.I1 = it.I1;
   return S;
 }
 
-template <int CH, bool FAST>
+template <int CH, bool FAST, bool COH>
 __device__ void fwd_f32(const LevelDesc& d, const float* __restrict__ px, float* __restrict__ ll,
                         float* __restrict__ band, const Item& it) {
-  const PxLoader<float, FAST> L = px_loader<float, FAST>(px, d.pix_stride, it);
-  const BandStore<float, FAST> S = band_store<float, FAST>(ll, d.ll_stride, band, d.band_stride, it);
+  const PxLoader<float, FAST, COH> L = px_loader<float, FAST, COH>(px, d.pix_stride, it);
+  const BandStore<float, FAST, COH> S = band_store<float, FAST, COH>(ll, d.ll_stride, band, d.band_stride, it);
   const bool first = it.first, last = it.last;
   using Buf = PxBuf<float, CH>;
   auto load_chunk = [&](Buf& b, int i0) {
@@ -441,14 +507,14 @@ __device__ void fwd_f32(const LevelDesc& d, const float* __restrict__ px, float*
     hE1 = b.he1[m];
     aN = aDN;
   };
-  run_rows<CH, FAST>(it.I0, it.I1, A, B, load_chunk, row);
+  run_rows<CH>(it.I0, it.I1, A, B, load_chunk, row);
 }
 
-template <int CH, bool FAST>
+template <int CH, bool FAST, bool COH>
 __device__ void fwd_i32(const LevelDesc& d, const int* __restrict__ px, int* __restrict__ ll,
                         int* __restrict__ band, const Item& it) {
-  const PxLoader<int, FAST> L = px_loader<int, FAST>(px, d.pix_stride, it);
-  const BandStore<int, FAST> S = band_store<int, FAST>(ll, d.ll_stride, band, d.band_stride, it);
+  const PxLoader<int, FAST, COH> L = px_loader<int, FAST, COH>(px, d.pix_stride, it);
+  const BandStore<int, FAST, COH> S = band_store<int, FAST, COH>(ll, d.ll_stride, band, d.band_stride, it);
   const bool first = it.first, last = it.last;
   using Buf = PxBuf<int, CH>;
   auto load_chunk = [&](Buf& b, int i0) {
@@ -505,104 +571,79 @@ __device__ void fwd_i32(const LevelDesc& d, const int* __restrict__ px, int* __r
     hE1 = b.he1[m];
     aN = aDN;
   };
-  run_rows<CH, FAST>(it.I0, it.I1, A, B, load_chunk, row);
+  run_rows<CH>(it.I0, it.I1, A, B, load_chunk, row);
 }
 
 // ------------------------------------------------------- inverse / adjoint
 // Band rows for this lane's two quadruples plus two halo values per part
 // (even part: LL and HL rows; odd part: LH and HH rows).  MIRROR reads the
-// symmetric extension of the interleaved coefficients (inverse); otherwise
-// values outside the bands are zero (adjoint).
-template <typename T, bool FAST, bool MIRROR>
+// symmetric extension of the interleaved coefficients (inverse: folded
+// indices, always in range); otherwise values outside the bands are zero
+// (adjoint: bounds-checked buffer loads, rows outside get a size-0 resource).
+template <typename T, bool FAST, bool MIRROR, bool COH>
 struct BandLoader {
   const T* ll;
   int64_t ls;
   const T* band;
   int64_t bs;
-  int H, ns_h, nd_h, ns_w, qL;
-  int cl0, cl1, ch0, ch1;  // general path: columns of quads qL, qL+1 (L / H parity bands)
-  bool zl0, zl1, zh0, zh1; // general path, zero fill: column inside its band
+  int H, ns_h, nd_h, ns_w, nd_w, qL;
+  int cl0, cl1, ch0, ch1;  // general path: columns of quads qL, qL+1 (folded if MIRROR)
   int hp0, hp1;            // halo band parity
-  int hc0, hc1;            // halo columns (inside the band)
-  bool hv0, hv1;           // zero fill: halo inside the band
+  int hc0, hc1;            // halo columns (MIRROR: folded; else raw, may be outside)
 
-  __device__ __forceinline__ void pair(const T* rl, const T* rh, T& lL, T& lR, T& hL, T& hR) const {
+  __device__ __forceinline__ void part(const T* rl, const T* rh, bool valid, T& lL, T& lR, T& hL, T& hR, T& h0,
+                                       T& h1) const {
+    constexpr int P = Pol<COH>::ld, PH = Pol<COH>::halo;
+    const Rsrc bl = row_rsrc(rl, (MIRROR || valid) ? ns_w * 4 : 0);
+    const Rsrc bh = row_rsrc(rh, (MIRROR || valid) ? nd_w * 4 : 0);
     if constexpr (FAST) {
-      const Ext2<T> a = *reinterpret_cast<const Ext2<T>*>(rl + qL);
-      const Ext2<T> b = *reinterpret_cast<const Ext2<T>*>(rh + qL);
-      lL = a.x; lR = a.y; hL = b.x; hR = b.y;
+      bld2<P>(bl, qL, lL, lR);
+      bld2<P>(bh, qL, hL, hR);
     } else {
-      lL = rl[cl0]; lR = rl[cl1]; hL = rh[ch0]; hR = rh[ch1];
-      if constexpr (!MIRROR) {
-        lL = zl0 ? lL : T(0); lR = zl1 ? lR : T(0);
-        hL = zh0 ? hL : T(0); hR = zh1 ? hR : T(0);
-      }
+      lL = bld1<T, P>(bl, cl0); lR = bld1<T, P>(bl, cl1);
+      hL = bld1<T, P>(bh, ch0); hR = bld1<T, P>(bh, ch1);
     }
-  }
-  __device__ __forceinline__ void halos(const T* rl, const T* rh, T& h0, T& h1) const {
-    h0 = (hp0 ? rh : rl)[hc0];
-    h1 = (hp1 ? rh : rl)[hc1];
-    if constexpr (!MIRROR) {
-      h0 = hv0 ? h0 : T(0);
-      h1 = hv1 ? h1 : T(0);
-    }
+    h0 = bld1<T, PH>(hp0 ? bh : bl, hc0);
+    h1 = bld1<T, PH>(hp1 ? bh : bl, hc1);
   }
   // row r of LL and HL
   __device__ __forceinline__ void even(int r, T& lL, T& lR, T& hL, T& hR, T& h0, T& h1) const {
-    if constexpr (!MIRROR && !FAST) {
-      if (r < 0 || r >= ns_h) {
-        lL = lR = hL = hR = h0 = h1 = T(0);
-        return;
-      }
-    }
     const int re = MIRROR ? (fold_idx(2 * r, H) >> 1) : r;
     const T* rl = ll + (int64_t)re * ls;
     const T* rh = band + (int64_t)re * bs + ns_w;
-    pair(rl, rh, lL, lR, hL, hR);
-    halos(rl, rh, h0, h1);
+    part(rl, rh, r >= 0 && r < ns_h, lL, lR, hL, hR, h0, h1);
   }
   // row r of LH and HH
   __device__ __forceinline__ void odd(int r, T& lL, T& lR, T& hL, T& hR, T& h0, T& h1) const {
-    if constexpr (!MIRROR && !FAST) {
-      if (r < 0 || r >= nd_h) {
-        lL = lR = hL = hR = h0 = h1 = T(0);
-        return;
-      }
-    }
     const int ro = MIRROR ? ((fold_idx(2 * r + 1, H) - 1) >> 1) : r;
     const T* rl = band + (int64_t)(ns_h + ro) * bs;
     const T* rh = rl + ns_w;
-    pair(rl, rh, lL, lR, hL, hR);
-    halos(rl, rh, h0, h1);
+    part(rl, rh, r >= 0 && r < nd_h, lL, lR, hL, hR, h0, h1);
   }
 };
 
 // Halo assignment: (parity, quadruple column) of the two halo values of
 // lanes 0 and 63; other lanes read their own first quadruple (unused).
-template <typename T, bool FAST, bool MIRROR>
-__device__ __forceinline__ BandLoader<T, FAST, MIRROR> band_loader(const T* ll, int64_t ls, const T* band,
-                                                                   int64_t bs, const Item& it, int p0_first,
-                                                                   int p1_first, int p0_last, int p1_last) {
-  BandLoader<T, FAST, MIRROR> L;
+template <typename T, bool FAST, bool MIRROR, bool COH>
+__device__ __forceinline__ BandLoader<T, FAST, MIRROR, COH> band_loader(const T* ll, int64_t ls, const T* band,
+                                                                        int64_t bs, const Item& it, int p0_first,
+                                                                        int p1_first, int p0_last, int p1_last) {
+  BandLoader<T, FAST, MIRROR, COH> L;
   L.ll = ll; L.ls = ls; L.band = band; L.bs = bs;
-  L.H = it.H; L.ns_h = it.ns_h; L.nd_h = it.nd_h; L.ns_w = it.ns_w; L.qL = it.qL;
-  const int W = it.W, ns = it.ns_w, nd = it.nd_w, q = it.qL;
-  auto col = [&](int qq, int par, bool& valid) {
-    const int n = par ? nd : ns;
-    valid = qq >= 0 && qq < n;
-    return MIRROR ? band_idx(qq, W, par) : clampi(qq, 0, n - 1);
-  };
-  L.cl0 = col(q, 0, L.zl0); L.cl1 = col(q + 1, 0, L.zl1);
-  L.ch0 = col(q, 1, L.zh0); L.ch1 = col(q + 1, 1, L.zh1);
-  int qq0 = q, qq1 = q;
+  L.H = it.H; L.ns_h = it.ns_h; L.nd_h = it.nd_h; L.ns_w = it.ns_w; L.nd_w = it.nd_w; L.qL = it.qL;
+  const int W = it.W, q = it.qL;
+  auto col = [&](int qq, int par) { return MIRROR ? band_idx(qq, W, par) : qq; };
+  L.cl0 = col(q, 0); L.cl1 = col(q + 1, 0);
+  L.ch0 = col(q, 1); L.ch1 = col(q + 1, 1);
+  int qq = q;
   L.hp0 = 0; L.hp1 = 0;
   if (it.first) {
-    qq0 = q - 1; qq1 = q - 1; L.hp0 = p0_first; L.hp1 = p1_first;
+    qq = q - 1; L.hp0 = p0_first; L.hp1 = p1_first;
   } else if (it.last) {
-    qq0 = q + 2; qq1 = q + 2; L.hp0 = p0_last; L.hp1 = p1_last;
+    qq = q + 2; L.hp0 = p0_last; L.hp1 = p1_last;
   }
-  L.hc0 = col(qq0, L.hp0, L.hv0);
-  L.hc1 = col(qq1, L.hp1, L.hv1);
+  L.hc0 = col(qq, L.hp0);
+  L.hc1 = col(qq, L.hp1);
   return L;
 }
 
@@ -612,35 +653,32 @@ struct QBuf {
   T lhL[CH], lhR[CH], hhL[CH], hhR[CH], ho0[CH], ho1[CH];
 };
 
-// Stores of two pixel rows (inverse / adjoint): four pixels per lane.
-template <typename T, bool FAST>
+// Stores of pixel rows (inverse / adjoint): four pixels per lane, one buffer
+// resource per row (size 0 for rows past I1's last pixel row or past H).
+template <typename T, bool FAST, bool COH>
 struct PxStore {
   T* base;
   int64_t stride;
-  int W, H, c0;
+  int W, H, c0, rows_end;  // rows_end: first pixel row not to write (min(2 I1, H))
   __device__ __forceinline__ void row(int r, const V4<T>& v) const {
-    T* p = base + (int64_t)r * stride + c0;
+    const Rsrc rs = row_rsrc(base + (int64_t)r * stride, r < rows_end ? W * 4 : 0);
+    constexpr int P = Pol<COH>::st;
     if constexpr (FAST) {
-      st4(p, v);
+      bst4<P>(v, rs, c0);
     } else {
-      if (r < H) {
-        if (c0 < W) p[0] = v.x;
-        if (c0 + 1 < W) p[1] = v.y;
-        if (c0 + 2 < W) p[2] = v.z;
-        if (c0 + 3 < W) p[3] = v.w;
-      }
+      bst1<P>(v.x, rs, c0); bst1<P>(v.y, rs, c0 + 1); bst1<P>(v.z, rs, c0 + 2); bst1<P>(v.w, rs, c0 + 3);
     }
   }
 };
 
-template <int CH, bool FAST>
+template <int CH, bool FAST, bool COH>
 __device__ void inv_f32(const LevelDesc& d, const float* __restrict__ ll, const float* __restrict__ band,
                         float* __restrict__ px, const Item& it) {
   // halos: lane 0 -> HL / HH of quad qL-1 (parity 1); lane 63 -> quad qL+2:
   // h0 = LL / LH (parity 0), h1 = HL / HH (parity 1)
-  const BandLoader<float, FAST, true> L = band_loader<float, FAST, true>(ll, d.ll_stride, band, d.band_stride, it,
-                                                                         1, 1, 0, 1);
-  const PxStore<float, FAST> S{px, d.pix_stride, it.W, it.H, 2 * it.qL};
+  const BandLoader<float, FAST, true, COH> L =
+      band_loader<float, FAST, true, COH>(ll, d.ll_stride, band, d.band_stride, it, 1, 1, 0, 1);
+  const PxStore<float, FAST, COH> S{px, d.pix_stride, it.W, it.H, 2 * it.qL, min(2 * it.I1, it.H)};
   const bool first = it.first, last = it.last;
   using Buf = QBuf<float, CH>;
   auto load_chunk = [&](Buf& b, int i0) {
@@ -695,15 +733,15 @@ __device__ void inv_f32(const LevelDesc& d, const float* __restrict__ ll, const 
     hh_L = b.hhL[m];
     hh_R = b.hhR[m];
   };
-  run_rows<CH, FAST>(it.I0, it.I1, A, B, load_chunk, row);
+  run_rows<CH>(it.I0, it.I1, A, B, load_chunk, row);
 }
 
-template <int CH, bool FAST>
+template <int CH, bool FAST, bool COH>
 __device__ void inv_i32(const LevelDesc& d, const int* __restrict__ ll, const int* __restrict__ band,
                         int* __restrict__ px, const Item& it) {
-  const BandLoader<int, FAST, true> L = band_loader<int, FAST, true>(ll, d.ll_stride, band, d.band_stride, it,
-                                                                     1, 1, 0, 1);
-  const PxStore<int, FAST> S{px, d.pix_stride, it.W, it.H, 2 * it.qL};
+  const BandLoader<int, FAST, true, COH> L =
+      band_loader<int, FAST, true, COH>(ll, d.ll_stride, band, d.band_stride, it, 1, 1, 0, 1);
+  const PxStore<int, FAST, COH> S{px, d.pix_stride, it.W, it.H, 2 * it.qL, min(2 * it.I1, it.H)};
   const bool first = it.first, last = it.last;
   using Buf = QBuf<int, CH>;
   auto load_chunk = [&](Buf& b, int i0) {
@@ -766,17 +804,17 @@ __device__ void inv_i32(const LevelDesc& d, const int* __restrict__ ll, const in
     hh_L = b.hhL[m];
     hh_R = b.hhR[m];
   };
-  run_rows<CH, FAST>(it.I0, it.I1, A, B, load_chunk, row);
+  run_rows<CH>(it.I0, it.I1, A, B, load_chunk, row);
 }
 
-template <int CH, bool FAST>
+template <int CH, bool FAST, bool COH>
 __device__ void bwd_f32(const LevelDesc& d, const float* __restrict__ ll, const float* __restrict__ band,
                         float* __restrict__ px, const Item& it) {
   // halos: lane 0 -> quad qL-1: h0 = LL / LH (parity 0), h1 = HL / HH (parity 1);
   // lane 63 -> quad qL+2: h0 = LL / LH (parity 0)
-  const BandLoader<float, FAST, false> L = band_loader<float, FAST, false>(ll, d.ll_stride, band, d.band_stride, it,
-                                                                           0, 1, 0, 0);
-  const PxStore<float, FAST> S{px, d.pix_stride, it.W, it.H, 2 * it.qL};
+  const BandLoader<float, FAST, false, COH> L =
+      band_loader<float, FAST, false, COH>(ll, d.ll_stride, band, d.band_stride, it, 0, 1, 0, 0);
+  const PxStore<float, FAST, COH> S{px, d.pix_stride, it.W, it.H, 2 * it.qL, min(2 * it.I1, it.H)};
   const bool first = it.first, last = it.last;
   const AxisW hL = axis_weights(it.qL, it.W), hR = axis_weights(it.qL + 1, it.W), hH = axis_weights(it.qL - 1, it.W);
   using Buf = QBuf<float, CH>;
@@ -836,7 +874,7 @@ __device__ void bwd_f32(const LevelDesc& d, const float* __restrict__ ll, const 
     ga_L = b.llL[m]; ga_R = b.llR[m]; gb_L = b.hlL[m]; gb_R = b.hlR[m]; ge0 = b.he0[m]; ge1 = b.he1[m];
     gc_L = b.lhL[m]; gc_R = b.lhR[m]; gd_L = b.hhL[m]; gd_R = b.hhR[m]; go0 = b.ho0[m]; go1 = b.ho1[m];
   };
-  run_rows<CH, FAST>(it.I0, it.I1, A, B, load_chunk, row);
+  run_rows<CH>(it.I0, it.I1, A, B, load_chunk, row);
 }
 
 // ---------------------------------------------------------------------------
@@ -851,57 +889,159 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
   return (x < r) ? x * (q + 1) + s : r * (q + 1) + (x - r) * q + s;
 }
 
-// Whether an item can take the branch-free path: every quadruple column of
-// the strip inside both parity bands, rows a whole number of chunk pairs,
-// and (host-checked) aligned pointers and strides.
-template <int DIR, int CH>
+// Whether an item can use vector loads and stores: every quadruple column
+// of the strip inside both parity bands, and (host-checked) aligned pointers
+// and strides.  Other items gather and scatter single elements; both run the
+// same branch-free pipeline.
 __device__ __forceinline__ bool fast_item(const LevelDesc& d, const Item& it, int strip) {
-  const int rows = it.I1 - it.I0;
-  bool ok = d.fast_ok && kStripQ * (strip + 1) <= it.nd_w && rows > 0 && rows % (2 * CH) == 0 && it.I1 <= it.nd_h;
-  if (DIR == kBwd) ok = ok && it.I0 >= 1 && it.I1 < it.nd_h;
-  return ok;
+  return d.fast_ok && kStripQ * (strip + 1) <= it.nd_w;
 }
 
+// One work item: (image pointers already offset, strip, segment).
+template <int DIR, typename T, int CH, bool COH>
+__device__ __forceinline__ void run_item(const LevelDesc& d, int64_t pix_off, int64_t ll_off, int64_t band_off,
+                                         int strip, int seg, int lane) {
+  const Item it = make_item(d, strip, seg, lane);
+  const bool fast = fast_item(d, it, strip);
+  if constexpr (DIR == kFwd) {
+    const T* px = static_cast<const T*>(d.pix_in) + pix_off;
+    T* ll = static_cast<T*>(d.ll_out) + ll_off;
+    T* band = static_cast<T*>(d.band_out) + band_off;
+    if constexpr (std::is_same<T, float>::value) {
+      if (fast) fwd_f32<CH, true, COH>(d, px, ll, band, it);
+      else fwd_f32<CH, false, COH>(d, px, ll, band, it);
+    } else {
+      if (fast) fwd_i32<CH, true, COH>(d, px, ll, band, it);
+      else fwd_i32<CH, false, COH>(d, px, ll, band, it);
+    }
+  } else {
+    const T* ll = static_cast<const T*>(d.ll_in) + ll_off;
+    const T* band = static_cast<const T*>(d.band_in) + band_off;
+    T* px = static_cast<T*>(d.pix_out) + pix_off;
+    if constexpr (DIR == kInv) {
+      if constexpr (std::is_same<T, float>::value) {
+        if (fast) inv_f32<CH, true, COH>(d, ll, band, px, it);
+        else inv_f32<CH, false, COH>(d, ll, band, px, it);
+      } else {
+        if (fast) inv_i32<CH, true, COH>(d, ll, band, px, it);
+        else inv_i32<CH, false, COH>(d, ll, band, px, it);
+      }
+    } else {
+      if (fast) bwd_f32<CH, true, COH>(d, ll, band, px, it);
+      else bwd_f32<CH, false, COH>(d, ll, band, px, it);
+    }
+  }
+}
+
+// One launch per level: one wave per work item.
 template <int DIR, typename T, int CH>
 __global__ __launch_bounds__(kBlock) void level_kernel(LevelLaunch a) {
   const int lane = threadIdx.x & (kWave - 1);
-  const int wave = threadIdx.x / kWave;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
   const int64_t item = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + wave;
   if (item >= a.items) return;
   const int img = (int)(item / a.items_per_image);
   const int rem = (int)(item - (int64_t)img * a.items_per_image);
   const int seg = rem / a.d.nstrips;
   const int strip = rem - seg * a.d.nstrips;
-  const Item it = make_item(a.d, strip, seg, lane);
-  const bool fast = fast_item<DIR, CH>(a.d, it, strip);
-  if constexpr (DIR == kFwd) {
-    const T* px = static_cast<const T*>(a.d.pix_in) + img * a.pix_bstride;
-    T* ll = static_cast<T*>(a.d.ll_out) + img * a.ll_bstride;
-    T* band = static_cast<T*>(a.d.band_out) + img * a.band_bstride;
-    if constexpr (std::is_same<T, float>::value) {
-      if (fast) fwd_f32<CH, true>(a.d, px, ll, band, it);
-      else fwd_f32<CH, false>(a.d, px, ll, band, it);
-    } else {
-      if (fast) fwd_i32<CH, true>(a.d, px, ll, band, it);
-      else fwd_i32<CH, false>(a.d, px, ll, band, it);
-    }
-  } else {
-    const T* ll = static_cast<const T*>(a.d.ll_in) + img * a.ll_bstride;
-    const T* band = static_cast<const T*>(a.d.band_in) + img * a.band_bstride;
-    T* px = static_cast<T*>(a.d.pix_out) + img * a.pix_bstride;
-    if constexpr (DIR == kInv) {
-      if constexpr (std::is_same<T, float>::value) {
-        if (fast) inv_f32<CH, true>(a.d, ll, band, px, it);
-        else inv_f32<CH, false>(a.d, ll, band, px, it);
-      } else {
-        if (fast) inv_i32<CH, true>(a.d, ll, band, px, it);
-        else inv_i32<CH, false>(a.d, ll, band, px, it);
+  run_item<DIR, T, CH, false>(a.d, img * a.pix_bstride, img * a.ll_bstride, img * a.band_bstride, strip, seg, lane);
+}
+
+// ---------------------------------------------------------------------------
+// Persistent job: all levels of a transform (of one or many images) in one
+// cooperative launch.  Work items are numbered step by step (a step is one
+// level of one image, or of a batch of images); wave w takes items w,
+// w + N, w + 2N, ... (N waves, all co-resident by the cooperative launch).
+// An item of step t first waits until the items of step t-1 that produced
+// the rows it reads have finished (per-segment completion counters), so
+// levels overlap instead of meeting at a grid-wide barrier.  An item waits
+// only for items with smaller numbers, each owned by a running wave that
+// reaches it after finishing its own smaller items, so the schedule cannot
+// deadlock; a wait that exceeds a fixed poll budget sets the error word and
+// gives up rather than hang.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kSpinLimit = 1u << 16;  // polls (~2 us each once backed off)
+
+// Wait until rows [r_lo, r_hi] of the output of step p (image img) exist.
+// `pixels`: the rows are pixel rows of p's output (inverse / adjoint, two per
+// quadruple row); otherwise they are p's LL rows (forward, one per row).
+__device__ __forceinline__ void wait_rows(const JobDesc& p, uint32_t* sync, int img, int r_lo, int r_hi,
+                                          bool pixels) {
+  const int ns_h = (p.d.H + 1) >> 1;
+  int q_lo = pixels ? (r_lo >> 1) : r_lo, q_hi = pixels ? (r_hi >> 1) : r_hi;
+  q_lo = q_lo < 0 ? 0 : q_lo;
+  q_hi = q_hi > ns_h - 1 ? ns_h - 1 : q_hi;
+  const int g_lo = q_lo / p.d.seg, g_hi = q_hi / p.d.seg;
+  uint32_t* ctr = sync + kSyncCounters + (int64_t)kCounterStride * (p.cbase + img * p.d.nsegs);
+  for (int g = g_lo; g <= g_hi; ++g) {
+    uint32_t spins = 0, nap = 1;
+    // every lane reads the same word; readfirstlane makes the loop wave-uniform
+    while (__builtin_amdgcn_readfirstlane(__hip_atomic_load(ctr + (int64_t)kCounterStride * g, __ATOMIC_RELAXED,
+                                                            __HIP_MEMORY_SCOPE_AGENT)) < (uint32_t)p.d.nstrips) {
+      if (++spins > kSpinLimit) {
+        __hip_atomic_store(sync + kSyncError, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
       }
-    } else {
-      if (fast) bwd_f32<CH, true>(a.d, ll, band, px, it);
-      else bwd_f32<CH, false>(a.d, ll, band, px, it);
+      // back off (s_sleep n pauses about 64 n clocks), up to ~2 us per poll
+      for (uint32_t k = 0; k < nap; ++k) __builtin_amdgcn_s_sleep(32);
+      nap = nap < 32 ? 2 * nap : 32;
     }
   }
+  // the item's loads of the producers' rows are coherent (sc0 sc1) and are
+  // issued only after the counters were seen; the fence keeps the compiler
+  // from moving them above the wait
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// TABLE: descriptors and the slot -> descriptor map live in device memory
+// (ragged batches); otherwise the descriptors are kernel arguments and the
+// descriptor of a slot is found by a scan (at most kInlineDescs steps).
+// Either way they are wave-uniform and stay in scalar registers.
+template <int DIR, typename T, int CH, bool TABLE>
+__global__ __launch_bounds__(kBlock) void job_kernel(JobArgs a) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const JobDesc* __restrict__ D = TABLE ? a.descs : a.inl;
+  uint32_t* sync = a.sync;
+  const uint32_t one = lane == 0 ? 1u : 0u;  // wave-uniform atomic: lane 0 adds 1, the rest add 0
+  const uint32_t wave = (uint32_t)xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock +
+                        __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const uint32_t nwaves = gridDim.x * kWavesPerBlock;
+  int j = 0;
+  for (uint32_t q = wave; q < (uint32_t)a.total_items; q += nwaves) {
+    if constexpr (TABLE) {
+      j = __builtin_amdgcn_readfirstlane(((const uint32_t* __restrict__)a.item_desc)[q]);
+    } else {
+      while (j + 1 < a.ndesc && a.inl[j + 1].item_start <= (int)q) ++j;  // items only move forward
+    }
+    const JobDesc jd = D[j];
+    const int item = (int)q - jd.item_start;
+    const int per_img = jd.d.nsegs * jd.d.nstrips;
+    const int img = item / per_img;
+    const int rem = item - img * per_img;
+    const int seg = rem / jd.d.nstrips;
+    const int strip = rem - seg * jd.d.nstrips;
+    if (jd.prev >= 0) {
+      const JobDesc p = D[jd.prev];
+      const int I0 = seg * jd.d.seg;
+      const int I1 = min(I0 + jd.d.seg, (jd.d.H + 1) >> 1);
+      // rows this item reads from p's output, with a margin that covers the
+      // symmetric folds at the image edges
+      if (DIR == kFwd) wait_rows(p, sync, img, 2 * I0 - 4, 2 * I1 + 2, false);
+      else wait_rows(p, sync, img, I0 - 3, I1 + 2, true);
+    }
+    run_item<DIR, T, CH, true>(jd.d, img * jd.pix_bstride, img * jd.ll_bstride, img * jd.band_bstride, strip, seg, lane);
+    // publish: the item's stores write through (sc1); once they have
+    // completed (s_waitcnt 0) the count makes them visible to every XCD
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __hip_atomic_fetch_add(sync + kSyncCounters + (int64_t)kCounterStride * (jd.cbase + img * jd.d.nsegs + seg), one,
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+__global__ void zero_kernel(uint32_t* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
 }
 
 template <int DIR, typename T, int CH>
@@ -927,7 +1067,61 @@ int occ_blocks() {
   return n;
 }
 
+// Cooperative launch: the runtime places every block at once or fails.
+template <int DIR, typename T, int CH>
+hipError_t launch_job_t(const JobArgs& a, int blocks, hipStream_t s) {
+  void* args[] = {const_cast<JobArgs*>(&a)};
+  const void* f = a.descs ? reinterpret_cast<const void*>(&job_kernel<DIR, T, CH, true>)
+                          : reinterpret_cast<const void*>(&job_kernel<DIR, T, CH, false>);
+  return hipLaunchCooperativeKernel(f, dim3((unsigned)blocks), dim3(kBlock), args, 0, s);
+}
+
+template <int DIR, typename T>
+hipError_t launch_job_ch(int chunk, const JobArgs& a, int blocks, hipStream_t s) {
+  if (chunk >= 4) return launch_job_t<DIR, T, 4>(a, blocks, s);
+  if (chunk >= 2) return launch_job_t<DIR, T, 2>(a, blocks, s);
+  return launch_job_t<DIR, T, 1>(a, blocks, s);
+}
+
+template <int DIR, typename T, int CH>
+int occ_job() {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(&job_kernel<DIR, T, CH, false>),
+                                                   kBlock, 0) != hipSuccess)
+    n = 0;
+  return n;
+}
+
+template <int CH>
+int occ_job_dir(int dir, int mode) {
+  if (dir == kFwd) return mode == DWT2_F32 ? occ_job<kFwd, float, CH>() : occ_job<kFwd, int, CH>();
+  if (dir == kInv) return mode == DWT2_F32 ? occ_job<kInv, float, CH>() : occ_job<kInv, int, CH>();
+  return occ_job<kBwd, float, CH>();
+}
+
 }  // namespace
+
+int launch_job(int dir, int mode, int chunk, const JobArgs& a, int blocks, void* stream) {
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (dir == kFwd)
+    return mode == DWT2_F32 ? launch_job_ch<kFwd, float>(chunk, a, blocks, s) : launch_job_ch<kFwd, int>(chunk, a, blocks, s);
+  if (dir == kInv)
+    return mode == DWT2_F32 ? launch_job_ch<kInv, float>(chunk, a, blocks, s) : launch_job_ch<kInv, int>(chunk, a, blocks, s);
+  return launch_job_ch<kBwd, float>(chunk, a, blocks, s);
+}
+
+int job_blocks_per_cu(int dir, int mode, int chunk) {
+  if (chunk >= 4) return occ_job_dir<4>(dir, mode);
+  if (chunk >= 2) return occ_job_dir<2>(dir, mode);
+  return occ_job_dir<1>(dir, mode);
+}
+
+int launch_zero(uint32_t* p, int64_t n, void* stream) {
+  const int64_t blocks = n < 256 * 256 ? (n + 255) / 256 : 256;
+  hipLaunchKernelGGL(zero_kernel, dim3((unsigned)(blocks > 0 ? blocks : 1)), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), p, n);
+  return hipGetLastError();
+}
 
 int launch_level(int dir, int mode, int chunk, const LevelLaunch& a, void* stream) {
   hipStream_t s = static_cast<hipStream_t>(stream);

@@ -24,20 +24,24 @@ struct Call {
   int32_t batch;
   int32_t mode;
   char* ws;
+  size_t ll_base;  // byte offset of the first image's LL buffers in ws
 };
 
 int fail(int code, const char* fmt, ...);
 void clear_error();
 int check_geometry(int32_t width, int32_t height, int32_t levels, Geo& g);
-void ws_layout(const Geo& g, size_t& a_bytes, size_t& b_bytes);
+size_t round256(size_t b);
+size_t ll_offset(const Geo& g, int m);
 size_t ws_per_image(const Geo& g);
+size_t sync_bytes(const Geo& g, int64_t batch);
 struct Tiling {
   int seg;  // quadruple rows per work item
   int ch;   // rows per prefetch chunk (kernel template)
 };
-Tiling choose_tiling(int dir, int mode, int ns_h, int64_t strips_times_batch);
+Tiling choose_tiling(int dir, int mode, int ns_h, int64_t strips_times_batch, int64_t slots_hint = 0);
 int fast_layout(int dir, const LevelLaunch& a, int batch, int W);
 void fill_level(LevelDesc& d, int W, int H, int seg);
 int run_levels(int dir, const Call& c, const Geo& g, void* stream);
+int run_job(int dir, const Call& c, const Geo& g, void* stream);
 
 }  // namespace dwt2

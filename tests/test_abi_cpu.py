@@ -45,15 +45,24 @@ def test_missing_library_fails_loudly(tmp_path):
         _lib._lib = saved
 
 
+def _sync_bytes(h, levels, batch):
+    rows, hh = 0, h
+    for _ in range(levels):
+        hh = (hh + 1) // 2
+        rows += hh
+    return ((16 + 16 * batch * rows) * 4 + 255) // 256 * 256
+
+
 def test_workspace_sizes(lib):
-    assert lib.dwt2_workspace_size(512, 512, 1, 1, 0) == 0          # one level: no LL buffer
-    # two levels: LL_1 (256 x 256, pitch 256) only
-    assert lib.dwt2_workspace_size(512, 512, 1, 2, 0) == 256 * 256 * 4
-    # three levels: LL_1 and LL_2
-    assert lib.dwt2_workspace_size(512, 512, 1, 3, 0) == (256 * 256 + 128 * 128) * 4
-    assert lib.dwt2_workspace_size(512, 512, 3, 3, 1) == 3 * (256 * 256 + 128 * 128) * 4
-    # pitch padded to 64 elements: 101 -> ceil 51 -> 64
-    assert lib.dwt2_workspace_size(101, 40, 1, 2, 0) == ((64 * 20 * 4 + 255) // 256) * 256
+    # sync area: 16 words + one counter (on its own 64-byte line) per level
+    # row, rounded up to 256 bytes; then one LL buffer per intermediate level
+    # with the row pitch padded to 64 elements
+    assert lib.dwt2_workspace_size(512, 512, 1, 1, 0) == _sync_bytes(512, 1, 1)
+    assert lib.dwt2_workspace_size(512, 512, 1, 2, 0) == _sync_bytes(512, 2, 1) + 256 * 256 * 4
+    assert lib.dwt2_workspace_size(512, 512, 1, 3, 0) == _sync_bytes(512, 3, 1) + (256 * 256 + 128 * 128) * 4
+    assert lib.dwt2_workspace_size(512, 512, 3, 3, 1) == _sync_bytes(512, 3, 3) + 3 * (256 * 256 + 128 * 128) * 4
+    assert lib.dwt2_workspace_size(101, 40, 1, 2, 0) == _sync_bytes(40, 2, 1) + 64 * 20 * 4   # 51 -> pitch 64
+    assert _sync_bytes(512, 1, 1) == 16640
     assert lib.dwt2_workspace_size(4, 4, 1, 3, 0) == 0               # invalid: level 3 input 1 x 1
     assert lib.dwt2_workspace_size(4, 4, 1, 2, 5) == 0               # invalid mode
 
@@ -114,6 +123,12 @@ def test_batched_validation(lib):
     assert lib.dwt2_fwd_batched(ok, 0, 2, 0, 0, FAKE_WS, 1 << 30, None) == -1
     assert lib.dwt2_fwd_batched(ok, 2, 2, 9, 0, FAKE_WS, 1 << 30, None) == -3
     assert lib.dwt2_fwd_batched(ok, 2, 2, 0, 3, FAKE_WS, 1 << 30, None) == -1
+
+
+def test_set_path_validation(lib):
+    assert lib.dwt2_set_path(2) == -1
+    assert lib.dwt2_set_path(1) == 0
+    assert lib.dwt2_set_path(0) == 0
 
 
 def test_set_tiling_validation(lib):

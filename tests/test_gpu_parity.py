@@ -230,24 +230,45 @@ def test_config5_adjoint_against_oracle():
 
 
 @pytest.mark.parametrize("mode", ["f32", "int"])
-def test_results_do_not_depend_on_tiling(mode):
-    """Every tiling (segment height, prefetch chunk) gives bit-identical
-    results, so work-item boundaries introduce neither races nor seams."""
+def test_results_do_not_depend_on_tiling_or_path(mode):
+    """Every tiling (segment height, prefetch chunk) and both ways of chaining
+    levels (one persistent launch, one launch per level) give bit-identical
+    results, so work-item boundaries and level overlap introduce neither
+    races nor seams."""
     d = D()
     dt = np.float32 if mode == "f32" else np.int32
-    shapes = [(1024, 1024, 4), (777, 1031, 5), (96, 2304, 3)]
+    shapes = [(1024, 1024, 4), (777, 1031, 5), (96, 2304, 3), (2, 515, 1)]
     try:
         for (h, w, levels) in shapes:
             x = to_gpu(synth.image(w, h, h + w, dt))
             d.set_tiling(0, 0)
+            d.set_path(False)
             ref_f = d.fwd(x, levels)
             ref_i = d.inv(ref_f, levels)
             ref_b = d.bwd(x.float(), levels) if mode == "f32" else None
-            for seg, ch in [(1, 1), (2, 1), (4, 2), (8, 4), (16, 4), (24, 2), (64, 4), (3, 1), (10000, 4)]:
-                d.set_tiling(seg, ch)
-                assert torch.equal(d.fwd(x, levels), ref_f), (h, w, seg, ch)
-                assert torch.equal(d.inv(ref_f, levels), ref_i), (h, w, seg, ch)
-                if ref_b is not None:
-                    assert torch.equal(d.bwd(x.float(), levels), ref_b), (h, w, seg, ch)
+            for persistent in (True, False):
+                d.set_path(persistent)
+                for seg, ch in [(0, 0), (1, 1), (2, 1), (4, 2), (8, 4), (16, 4), (24, 2), (64, 4), (3, 1), (10000, 4)]:
+                    d.set_tiling(seg, ch)
+                    assert torch.equal(d.fwd(x, levels), ref_f), (h, w, seg, ch, persistent)
+                    assert torch.equal(d.inv(ref_f, levels), ref_i), (h, w, seg, ch, persistent)
+                    if ref_b is not None:
+                        assert torch.equal(d.bwd(x.float(), levels), ref_b), (h, w, seg, ch, persistent)
     finally:
         d.set_tiling(0, 0)
+        d.set_path(False)
+
+
+def test_batched_equals_plain_on_ragged_set():
+    """A ragged set like the benchmark's (uneven, odd sizes), smaller: the
+    one-launch batched path reproduces per-image calls bit for bit, on the
+    first call (plan + tuning) and on replays with new pointers."""
+    d = D()
+    sizes = synth.ragged_sizes(24, 7, 16, 700)
+    for dt in (np.float32, np.int32):
+        imgs = [to_gpu(synth.image(w, h, 300 + i, dt)) for i, (w, h) in enumerate(sizes)]
+        for rep in range(3):
+            outs = d.fwd_batched(imgs, 3)
+            for im, o in zip(imgs, outs):
+                assert torch.equal(o, d.fwd(im, 3)), rep
+            imgs = [im.clone() for im in imgs]   # fresh pointers for the next replay
