@@ -11,6 +11,12 @@ value = pixels transformed per second over the step, in Gpixel/s (each of the
 three passes counts the image's 8192^2 pixels once, whatever the number of
 levels).
 
+roofline: the dominant kernel is the level-1 forward launch (about two
+thirds of the forward's time).  Its duration is recorded live in every timed
+step with HIP events that the library places around that one launch on the
+call's stream (dwt2_set_probe); achieved = its algorithmic bytes (read the
+8192^2 image once, write as many coefficients) / the mean duration.
+
 Side measurements reported in "detail": per-direction times and effective
 bandwidth, the integer 16384^2 forward/inverse, the ragged 256-image batch
 (one persistent launch vs 256 plain launches), the 32 x 3 x 1024^2 autograd
@@ -58,7 +64,7 @@ def kernel_sources_digest():
 def read_traffic(kernel_key):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
     was taken on the current kernel sources."""
-    path = os.path.join(ROOT, "profiles", "traffic.txt")
+    path = os.path.join(ROOT, "profiles", "level1_fwd_8192_f32_traffic.txt")
     if not os.path.exists(path):
         return None
     rec = {}
@@ -96,8 +102,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-detail", action="store_true", help="skip the side measurements")
-    ap.add_argument("--only", choices=["step", "fwd", "inv", "bwd", "copy"], default=None,
-                    help="profiling aid: run only this part, untimed JSON omitted")
+    ap.add_argument("--only", choices=["step", "fwd", "fwd1", "inv", "bwd", "copy"], default=None,
+                    help="profiling aid: run only this part (fwd1: the level-1 forward kernel alone, "
+                         "as a 1-level call with the same grid), untimed JSON omitted")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -144,6 +151,8 @@ def main():
             s = sets[i & 1]
             if args.only in ("step", "fwd"):
                 fwd(s)
+            if args.only == "fwd1":
+                dwt.fwd(s["x"], 1, out=s["c"], workspace=ws)
             if args.only in ("step", "inv"):
                 inv(s)
             if args.only in ("step", "bwd"):
@@ -159,32 +168,36 @@ def main():
         s = sets[i & 1]
         fwd(s); inv(s); bwd(s)
     torch.cuda.synchronize()
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(args.steps)]
+    for e in ev:  # create the HIP events before the timed region
+        for x_ in e:
+            x_.record()
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
         s = sets[i & 1]
         e = ev[i]
+        dwt.set_probe("fwd", 1, e[4], e[5])  # level-1 forward launch of this step
         e[0].record(); fwd(s); e[1].record(); inv(s); e[2].record(); bwd(s); e[3].record()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    dwt.set_probe(None)
     ms_step = (t1 - t0) * 1e3 / args.steps
     per_dir = {k: float(np.median([e[j].elapsed_time(e[j + 1]) for e in ev]))
                for j, k in enumerate(("fwd", "inv", "bwd"))}
     value = 3 * npx / (ms_step * 1e-3) / 1e9
 
-    # ---- dominant kernel: the level-1 forward kernel of the 6-level call --
-    # (a 1-level call launches exactly that kernel with the same grid; only
-    # its LL destination differs)
-    s0 = sets[0]
-    l1 = timer(lambda: dwt.fwd(s0["x"], 1, out=s0["c"]), max(args.steps, 20))
+    # ---- dominant kernel: level-1 forward launch, timed inside every step --
+    l1 = [e[4].elapsed_time(e[5]) for e in ev]
     l1_ms = float(np.mean(l1))
     l1_bytes = 2 * 4 * npx
     achieved = l1_bytes / (l1_ms * 1e-3) / 1e9
     traffic = read_traffic("fwd_level1_8192")
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
-                "kernel": "level_kernel<fwd, float> level 1, 8192x8192",
-                "bytes_per_launch": l1_bytes, "avg_launch_ms": round(l1_ms, 5)}
+                "kernel": "level_kernel<fwd, float, 2> at level 1 of the 8192x8192 6-level forward",
+                "bytes_per_launch": l1_bytes, "avg_launch_ms": round(l1_ms, 5),
+                "launch_ms_p10_p90": [round(float(np.percentile(l1, 10)), 5), round(float(np.percentile(l1, 90)), 5)]}
 
     detail = {"ms_per_direction": {k: round(v, 4) for k, v in per_dir.items()},
               "direction_GBps_alg": {k: round(alg_bytes(W, H, L) / (v * 1e-3) / 1e9, 1) for k, v in per_dir.items()},
@@ -219,33 +232,43 @@ def main():
         imgs = [synth.image_device(w, h, 4000 + i, device=dev) for i, (w, h) in enumerate(sizes)]
         outs = [torch.empty_like(t) for t in imgs]
         wss = [torch.empty(max(1, dwt.workspace_size(w, h, 3)), dtype=torch.uint8, device=dev) for (w, h) in sizes]
+        bws = torch.empty(dwt.batched_workspace_size(imgs, 3), dtype=torch.uint8, device=dev)
 
         def plain():
             for im, o, w_ in zip(imgs, outs, wss):
                 dwt.fwd(im, 3, out=o, workspace=w_)
 
         t_build = time.perf_counter()
-        dwt.fwd_batched(imgs, 3, outs=outs)
+        dwt.fwd_batched(imgs, 3, outs=outs, workspace=bws)
         torch.cuda.synchronize()
         t_build = time.perf_counter() - t_build
         plain()
-        tp = timer(plain, 5)
-        tb = timer(lambda: dwt.fwd_batched(imgs, 3, outs=outs), 5)
+        tp = timer(plain, 10)
+        tb = timer(lambda: dwt.fwd_batched(imgs, 3, outs=outs, workspace=bws), 10)
         gpx = sum(w * h for w, h in sizes)
         detail["ragged_256_L3"] = {
             "plain_ms": round(float(np.median(tp)), 3), "batched_ms": round(float(np.median(tb)), 3),
             "plain_images_per_s": round(256 / (np.median(tp) * 1e-3), 1),
             "batched_images_per_s": round(256 / (np.median(tb) * 1e-3), 1),
             "batched_Gpx_s": round(gpx / (np.median(tb) * 1e-3) / 1e9, 1),
+            "batched_GBps_alg": round(sum(alg_bytes(w, h, 3) for w, h in sizes) / (np.median(tb) * 1e-3) / 1e9, 1),
+            "batched_over_plain": round(float(np.median(tp) / np.median(tb)), 3),
             "first_call_s": round(t_build, 3), "Gpx": round(gpx / 1e9, 3)}
-        del imgs, outs, wss
+        del imgs, outs, wss, bws
         # autograd: 32 x 3 x 1024^2, 4 levels, forward + loss + backward
         xb = torch.stack([synth.image_device(1024, 1024, 5000 + k, device=dev) for k in range(96)]).reshape(32, 3, 1024, 1024)
         xb.requires_grad_()
+        # loss: sum over levels k = 1..4 of 2^k times the L1 norms of HL_k, LH_k, HH_k
+        wk = torch.zeros((1024, 1024), device=dev)
+        dims = level_sizes(1024, 1024, 4)
+        for k in range(4, 0, -1):
+            (w0, h0), (w1, h1) = dims[k - 1], dims[k]
+            wk[:h0, :w0] = 2.0 ** k
+            wk[:h1, :w1] = 0.0
 
         def fb():
             y = dwt.DWT2Function.apply(xb, 4)
-            y.abs().sum().backward()
+            (y.abs() * wk).sum().backward()
 
         fb()
         ta = timer(fb, 5)
@@ -253,21 +276,20 @@ def main():
         del xb
         torch.cuda.empty_cache()
 
-    # ---- CPU baseline: the oracle on a bounded sample --------------------
+    # ---- CPU baseline: the oracle on one step's work ---------------------
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
-        side = 4096
-        crop = sets[0]["x"][:side, :side].double().cpu().numpy()
-        g = sets[0]["g"][:side, :side].double().cpu().numpy()
+        x64 = sets[0]["x"].double().cpu().numpy()
+        g64 = sets[0]["g"].double().cpu().numpy()
         t = time.perf_counter()
-        c = oracle.fwd(crop, L)
+        c = oracle.fwd(x64, L)
         oracle.inv(c, L)
-        oracle.adj(g, L)
+        oracle.adj(g64, L)
         dt = time.perf_counter() - t
-        cpu = {"value": round(3 * side * side / dt / 1e9, 5), "unit": "Gpixel/s", "cores": 1, "kind": "oracle",
-               "sample": f"{side}x{side} top-left crop of the 8192x8192 image, {L} levels, float64 "
-                         f"forward + inverse + adjoint, numpy (single thread), {dt:.2f} s"}
+        cpu = {"value": round(3 * npx / dt / 1e9, 5), "unit": "Gpixel/s", "cores": 1, "kind": "oracle",
+               "sample": f"one step: the {W}x{H} image, {L} levels, float64 forward + inverse + adjoint "
+                         f"(numpy, one thread), {dt:.2f} s"}
 
     out = {"metric": METRIC, "value": round(value, 3), "unit": "Gpixel/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",

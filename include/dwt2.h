@@ -135,7 +135,9 @@ typedef struct {
   int32_t height;
 } dwt2_image_t;
 
-/* Workspace bytes for dwt2_fwd_batched over this list of images. */
+/* Workspace bytes for dwt2_fwd_batched over this list of images.  Only the
+ * width and height of each entry are read; returns 0 if n < 1, levels or
+ * mode are invalid, or an image is too small for the levels. */
 size_t dwt2_batched_workspace_size(const dwt2_image_t* images, int32_t n,
                                    int32_t levels, int32_t mode);
 
@@ -165,6 +167,18 @@ int dwt2_set_tiling(int32_t seg, int32_t chunk);
  * for the rows they read.  Results are bit-identical.  Returns DWT2_OK or
  * DWT2_ERR_ARG. */
 int dwt2_set_path(int32_t persistent);
+
+/* Process-wide timing probe, a measurement aid: while set, every
+ * dwt2_fwd (dir 0), dwt2_inv (dir 1) or dwt2_bwd (dir 2) call on the
+ * per-level path records ev_begin on its stream just before the launch of
+ * level `level` (1 = finest) and ev_end just after it, so hipEventElapsedTime
+ * of the pair is that one kernel's duration.  ev_begin / ev_end are
+ * hipEvent_t handles owned by the caller, created on the device of the
+ * calls.  The persistent path has no per-level launches and records
+ * nothing.  dir < 0 clears the probe.  Must not race with running calls.
+ * Returns DWT2_OK, or DWT2_ERR_ARG for a dir above 2, a level outside
+ * 1..DWT2_MAX_LEVELS or a null event. */
+int dwt2_set_probe(int32_t dir, int32_t level, void* ev_begin, void* ev_end);
 
 /* Static description of a status code. */
 const char* dwt2_status_string(int status);

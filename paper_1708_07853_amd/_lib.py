@@ -25,6 +25,7 @@ EXPORTS = [
     "dwt2_workspace_size", "dwt2_fwd", "dwt2_inv", "dwt2_bwd",
     "dwt2_batched_workspace_size", "dwt2_fwd_batched",
     "dwt2_status_string", "dwt2_last_error", "dwt2_clear_plan_cache", "dwt2_set_tiling", "dwt2_set_path",
+    "dwt2_set_probe",
 ]
 
 
@@ -79,6 +80,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dwt2_set_tiling.restype = ctypes.c_int
     lib.dwt2_set_path.argtypes = [i32]
     lib.dwt2_set_path.restype = ctypes.c_int
+    lib.dwt2_set_probe.argtypes = [i32, i32, vp, vp]
+    lib.dwt2_set_probe.restype = ctypes.c_int
     lib.dwt2_clear_plan_cache.argtypes = []
     lib.dwt2_clear_plan_cache.restype = None
     _lib = lib

@@ -66,6 +66,26 @@ def set_path(persistent: bool = False) -> None:
     _lib.check(_lib.load().dwt2_set_path(1 if persistent else 0))
 
 
+_PROBE_DIRS = {"fwd": 0, "inv": 1, "bwd": 2}
+
+
+def set_probe(direction: str | None, level: int = 1, begin: "torch.cuda.Event | None" = None,
+              end: "torch.cuda.Event | None" = None) -> None:
+    """Record `begin` / `end` (timing-enabled torch.cuda.Event) around the
+    launch of `level` in every later `direction` call on the per-level path;
+    `direction=None` clears the probe (see dwt2_set_probe)."""
+    lib = _lib.load()
+    if direction is None:
+        _lib.check(lib.dwt2_set_probe(-1, 0, None, None))
+        return
+    if direction not in _PROBE_DIRS or begin is None or end is None:
+        raise ValueError("direction must be 'fwd', 'inv' or 'bwd', with two events")
+    for ev in (begin, end):
+        if not ev.cuda_event:  # torch creates the HIP event on its first record
+            ev.record()
+    _lib.check(lib.dwt2_set_probe(_PROBE_DIRS[direction], level, begin.cuda_event, end.cuda_event))
+
+
 def workspace_size(w: int, h: int, levels: int, batch: int = 1, mode: int = DWT2_F32) -> int:
     return int(_lib.load().dwt2_workspace_size(w, h, batch, levels, mode))
 
@@ -132,10 +152,21 @@ def _image_table(srcs: Sequence[torch.Tensor], dsts: Sequence[torch.Tensor]):
     return arr
 
 
+def batched_workspace_size(images: Sequence[torch.Tensor], levels: int, mode=None) -> int:
+    """Bytes of device workspace dwt2_fwd_batched needs for these images."""
+    if not images:
+        return 0
+    mode = _mode_of(images[0], mode)
+    arr = _image_table(images, images)
+    return int(_lib.load().dwt2_batched_workspace_size(arr, len(images), levels, mode))
+
+
 def fwd_batched(images: Sequence[torch.Tensor], levels: int, mode=None,
-                outs: Sequence[torch.Tensor] | None = None) -> List[torch.Tensor]:
+                outs: Sequence[torch.Tensor] | None = None,
+                workspace: torch.Tensor | None = None) -> List[torch.Tensor]:
     """Forward transform of a ragged list of 2-D images in one persistent
-    launch (see dwt2_fwd_batched)."""
+    launch (see dwt2_fwd_batched).  Plans are cached per image geometry and
+    workspace address: pass the same `workspace` on repeated calls."""
     lib = _lib.load()
     if not images:
         return []
@@ -149,7 +180,12 @@ def fwd_batched(images: Sequence[torch.Tensor], levels: int, mode=None,
     arr = _image_table(images, outs)
     n = len(images)
     nbytes = int(lib.dwt2_batched_workspace_size(arr, n, levels, mode))
-    ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=images[0].device)
+    if workspace is None:
+        ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=images[0].device)
+    else:
+        if workspace.device != images[0].device or workspace.numel() * workspace.element_size() < nbytes:
+            raise ValueError(f"workspace must be a tensor of at least {nbytes} bytes on {images[0].device}")
+        ws = workspace
     with torch.cuda.device(images[0].device):
         status = lib.dwt2_fwd_batched(arr, n, levels, mode, DWT2_EXT_SYMMETRIC, ws.data_ptr(), nbytes, _stream())
     _lib.check(status)

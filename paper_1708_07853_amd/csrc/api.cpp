@@ -193,16 +193,33 @@ static void level_launch(int dir, const Call& c, const Geo& g, int k, int64_t sl
 }
 
 // One kernel launch per level (levels meet at kernel boundaries).
+// Timing probe (dwt2_set_probe): events recorded around one level's launch.
+struct Probe {
+  int dir = -1, level = 0;
+  hipEvent_t begin = nullptr, end = nullptr;
+};
+std::mutex g_probe_mu;
+Probe g_probe;
+
 int run_levels(int dir, const Call& c, const Geo& g, void* stream) {
   const int order_begin = dir == kFwd ? 1 : g.L, order_end = dir == kFwd ? g.L + 1 : 0;
   const int step = dir == kFwd ? 1 : -1;
+  Probe pr;
+  {
+    std::lock_guard<std::mutex> lock(g_probe_mu);
+    pr = g_probe;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
   for (int k = order_begin; k != order_end; k += step) {
     LevelLaunch a;
     int ch;
     level_launch(dir, c, g, k, 0, a, ch);
+    const bool probed = pr.dir == dir && pr.level == k;
+    if (probed && hipEventRecord(pr.begin, s) != hipSuccess) return fail(DWT2_ERR_HIP, "probe event record failed");
     const int err = launch_level(dir, c.mode, ch, a, stream);
     if (err != hipSuccess)
       return fail(DWT2_ERR_HIP, "level %d launch failed: %s", k, hipGetErrorString((hipError_t)err));
+    if (probed && hipEventRecord(pr.end, s) != hipSuccess) return fail(DWT2_ERR_HIP, "probe event record failed");
   }
   return DWT2_OK;
 }
@@ -252,6 +269,7 @@ int run_job(int dir, const Call& c, const Geo& g, void* stream) {
     jd.items = (int32_t)a.items;
     jd.cbase = counters;
     jd.prev = t - 1;
+    jd.coh = (t > 0 ? 1 : 0) | (t + 1 < g.L ? 2 : 0);
     items += (int32_t)a.items;
     counters += c.batch * a.d.nsegs;
   }
@@ -346,6 +364,22 @@ const char* dwt2_status_string(int status) {
 }
 
 const char* dwt2_last_error(void) { return g_last_error.c_str(); }
+
+int dwt2_set_probe(int32_t dir, int32_t level, void* ev_begin, void* ev_end) {
+  clear_error();
+  std::lock_guard<std::mutex> lock(g_probe_mu);
+  if (dir < 0) {
+    g_probe = Probe();
+    return DWT2_OK;
+  }
+  if (dir > 2 || level < 1 || level > DWT2_MAX_LEVELS || !ev_begin || !ev_end)
+    return fail(DWT2_ERR_ARG, "probe needs dir 0..2, level 1..%d and two events", DWT2_MAX_LEVELS);
+  g_probe.dir = dir;
+  g_probe.level = level;
+  g_probe.begin = static_cast<hipEvent_t>(ev_begin);
+  g_probe.end = static_cast<hipEvent_t>(ev_end);
+  return DWT2_OK;
+}
 
 int dwt2_set_path(int32_t persistent) {
   clear_error();

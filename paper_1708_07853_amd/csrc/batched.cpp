@@ -29,21 +29,24 @@ namespace {
 constexpr int kBatchCh = 2;     // prefetch chunk of the batched job kernel
 constexpr int kMinSeg = 2 * kBatchCh;
 
-int validate_images(const dwt2_image_t* images, int32_t n, int32_t levels, int32_t mode, std::vector<Geo>& geos) {
+// `pointers`: also check pointers, strides and aliasing (a size query reads
+// only the geometry).
+int validate_images(const dwt2_image_t* images, int32_t n, int32_t levels, int32_t mode, std::vector<Geo>& geos,
+                    bool pointers = true) {
   if (!images || n < 1) return fail(DWT2_ERR_ARG, "need a host array of at least one image");
   if (mode != DWT2_F32 && mode != DWT2_I32_REV) return fail(DWT2_ERR_MODE, "unknown mode %d", mode);
   geos.resize(n);
   for (int i = 0; i < n; ++i) {
     const dwt2_image_t& im = images[i];
-    if (!im.src || !im.dst) return fail(DWT2_ERR_ARG, "image %d: null src or dst", i);
-    if (im.width >= 2 && (im.src_stride < im.width || im.dst_stride < im.width))
+    if (pointers && (!im.src || !im.dst)) return fail(DWT2_ERR_ARG, "image %d: null src or dst", i);
+    if (pointers && im.width >= 2 && (im.src_stride < im.width || im.dst_stride < im.width))
       return fail(DWT2_ERR_ARG, "image %d: stride < width", i);
     const int st = check_geometry(im.width, im.height, levels, geos[i]);
     if (st) {
       const std::string why = dwt2_last_error();
       return fail(st, "image %d: %s", i, why.c_str());
     }
-    if (im.src == im.dst) return fail(DWT2_ERR_ALIAS, "image %d: src == dst", i);
+    if (pointers && im.src == im.dst) return fail(DWT2_ERR_ALIAS, "image %d: src == dst", i);
   }
   return DWT2_OK;
 }
@@ -226,6 +229,7 @@ void fill_descs(Plan& p, const dwt2_image_t* images, JobDesc* out) {
       jd.items = d.nsegs * d.nstrips;
       jd.cbase = cbase;
       jd.prev = t > 0 ? (t - 1) * p.n + oi : -1;
+      jd.coh = (t > 0 ? 1 : 0) | (t + 1 < p.levels ? 2 : 0);
       start += jd.items;
       cbase += d.nsegs;
     }
@@ -373,7 +377,7 @@ extern "C" {
 
 size_t dwt2_batched_workspace_size(const dwt2_image_t* images, int32_t n, int32_t levels, int32_t mode) {
   std::vector<Geo> geos;
-  if (validate_images(images, n, levels, mode, geos) != DWT2_OK) return 0;
+  if (validate_images(images, n, levels, mode, geos, false) != DWT2_OK) return 0;
   return layout(geos).total;
 }
 

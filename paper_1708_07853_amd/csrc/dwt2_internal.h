@@ -77,7 +77,8 @@ struct JobDesc {
   int32_t items;
   int32_t cbase;
   int32_t prev;   // step this one reads from (same images), or -1
-  int32_t pad_[3];
+  int32_t coh;    // bit 0: input LL rows come from step `prev`; bit 1: a later step reads the LL output
+  int32_t pad_[2];
 };
 
 constexpr int kInlineDescs = 20;

@@ -362,7 +362,7 @@ __device__ __forceinline__ void run_rows(int I0, int I1, Buf& A, Buf& B, LoadF&&
 // ---------------------------------------------------------------- forward
 // Pixel rows: four pixels per lane plus two halo pixels (lane 0: the two
 // columns left of the strip; lane 63: the column right of it).
-template <typename T, bool FAST, bool COH>
+template <typename T, bool FAST, bool COH>  // COH: rows written earlier in the same job
 struct PxLoader {
   const T* base;
   int64_t stride;
@@ -425,17 +425,18 @@ struct BandStore {
     T* row2 = band + (int64_t)(ns_h + i) * bs;
     const Rsrc rlh = row_rsrc(row2, real2 ? ns_w * 4 : 0);
     const Rsrc rhh = row_rsrc(row2 + ns_w, real2 ? nd_w * 4 : 0);
-    constexpr int P = Pol<COH>::st;
+    // only LL rows are read again inside a job; the bands are final
+    constexpr int P = Pol<COH>::st, PB = kNT;
     if constexpr (FAST) {
       bst2<P>(llL, llR, rl, qL);
-      bst2<P>(hlL, hlR, rh, qL);
-      bst2<P>(lhL, lhR, rlh, qL);
-      bst2<P>(hhL, hhR, rhh, qL);
+      bst2<PB>(hlL, hlR, rh, qL);
+      bst2<PB>(lhL, lhR, rlh, qL);
+      bst2<PB>(hhL, hhR, rhh, qL);
     } else {
       bst1<P>(llL, rl, qL); bst1<P>(llR, rl, qL + 1);
-      bst1<P>(hlL, rh, qL); bst1<P>(hlR, rh, qL + 1);
-      bst1<P>(lhL, rlh, qL); bst1<P>(lhR, rlh, qL + 1);
-      bst1<P>(hhL, rhh, qL); bst1<P>(hhR, rhh, qL + 1);
+      bst1<PB>(hlL, rh, qL); bst1<PB>(hlR, rh, qL + 1);
+      bst1<PB>(lhL, rlh, qL); bst1<PB>(lhR, rlh, qL + 1);
+      bst1<PB>(hhL, rhh, qL); bst1<PB>(hhR, rhh, qL + 1);
     }
   }
 };
@@ -448,11 +449,11 @@ __device__ __forceinline__ BandStore<T, FAST, COH> band_store(T* ll, int64_t ls,
   return S;
 }
 
-template <int CH, bool FAST, bool COH>
+template <int CH, bool FAST, bool CI, bool CO>
 __device__ void fwd_f32(const LevelDesc& d, const float* __restrict__ px, float* __restrict__ ll,
                         float* __restrict__ band, const Item& it) {
-  const PxLoader<float, FAST, COH> L = px_loader<float, FAST, COH>(px, d.pix_stride, it);
-  const BandStore<float, FAST, COH> S = band_store<float, FAST, COH>(ll, d.ll_stride, band, d.band_stride, it);
+  const PxLoader<float, FAST, CI> L = px_loader<float, FAST, CI>(px, d.pix_stride, it);
+  const BandStore<float, FAST, CO> S = band_store<float, FAST, CO>(ll, d.ll_stride, band, d.band_stride, it);
   const bool first = it.first, last = it.last;
   using Buf = PxBuf<float, CH>;
   auto load_chunk = [&](Buf& b, int i0) {
@@ -510,11 +511,11 @@ __device__ void fwd_f32(const LevelDesc& d, const float* __restrict__ px, float*
   run_rows<CH>(it.I0, it.I1, A, B, load_chunk, row);
 }
 
-template <int CH, bool FAST, bool COH>
+template <int CH, bool FAST, bool CI, bool CO>
 __device__ void fwd_i32(const LevelDesc& d, const int* __restrict__ px, int* __restrict__ ll,
                         int* __restrict__ band, const Item& it) {
-  const PxLoader<int, FAST, COH> L = px_loader<int, FAST, COH>(px, d.pix_stride, it);
-  const BandStore<int, FAST, COH> S = band_store<int, FAST, COH>(ll, d.ll_stride, band, d.band_stride, it);
+  const PxLoader<int, FAST, CI> L = px_loader<int, FAST, CI>(px, d.pix_stride, it);
+  const BandStore<int, FAST, CO> S = band_store<int, FAST, CO>(ll, d.ll_stride, band, d.band_stride, it);
   const bool first = it.first, last = it.last;
   using Buf = PxBuf<int, CH>;
   auto load_chunk = [&](Buf& b, int i0) {
@@ -591,17 +592,24 @@ struct BandLoader {
   int hp0, hp1;            // halo band parity
   int hc0, hc1;            // halo columns (MIRROR: folded; else raw, may be outside)
 
-  __device__ __forceinline__ void part(const T* rl, const T* rh, bool valid, T& lL, T& lR, T& hL, T& hR, T& h0,
-                                       T& h1) const {
-    constexpr int P = Pol<COH>::ld, PH = Pol<COH>::halo;
+  // `ll_row`: rl is an LL row (written earlier in the same job when COH);
+  // H-band rows are job inputs and take the plain policies
+  __device__ __forceinline__ void part(const T* rl, const T* rh, bool valid, bool ll_row, T& lL, T& lR, T& hL, T& hR,
+                                       T& h0, T& h1) const {
+    constexpr int P = Pol<COH>::ld, PH = Pol<COH>::halo, PB = kNT;
     const Rsrc bl = row_rsrc(rl, (MIRROR || valid) ? ns_w * 4 : 0);
     const Rsrc bh = row_rsrc(rh, (MIRROR || valid) ? nd_w * 4 : 0);
     if constexpr (FAST) {
-      bld2<P>(bl, qL, lL, lR);
-      bld2<P>(bh, qL, hL, hR);
+      if (ll_row) bld2<P>(bl, qL, lL, lR);
+      else bld2<PB>(bl, qL, lL, lR);
+      bld2<PB>(bh, qL, hL, hR);
     } else {
-      lL = bld1<T, P>(bl, cl0); lR = bld1<T, P>(bl, cl1);
-      hL = bld1<T, P>(bh, ch0); hR = bld1<T, P>(bh, ch1);
+      if (ll_row) {
+        lL = bld1<T, P>(bl, cl0); lR = bld1<T, P>(bl, cl1);
+      } else {
+        lL = bld1<T, PB>(bl, cl0); lR = bld1<T, PB>(bl, cl1);
+      }
+      hL = bld1<T, PB>(bh, ch0); hR = bld1<T, PB>(bh, ch1);
     }
     h0 = bld1<T, PH>(hp0 ? bh : bl, hc0);
     h1 = bld1<T, PH>(hp1 ? bh : bl, hc1);
@@ -611,14 +619,14 @@ struct BandLoader {
     const int re = MIRROR ? (fold_idx(2 * r, H) >> 1) : r;
     const T* rl = ll + (int64_t)re * ls;
     const T* rh = band + (int64_t)re * bs + ns_w;
-    part(rl, rh, r >= 0 && r < ns_h, lL, lR, hL, hR, h0, h1);
+    part(rl, rh, r >= 0 && r < ns_h, true, lL, lR, hL, hR, h0, h1);
   }
   // row r of LH and HH
   __device__ __forceinline__ void odd(int r, T& lL, T& lR, T& hL, T& hR, T& h0, T& h1) const {
     const int ro = MIRROR ? ((fold_idx(2 * r + 1, H) - 1) >> 1) : r;
     const T* rl = band + (int64_t)(ns_h + ro) * bs;
     const T* rh = rl + ns_w;
-    part(rl, rh, r >= 0 && r < nd_h, lL, lR, hL, hR, h0, h1);
+    part(rl, rh, r >= 0 && r < nd_h, false, lL, lR, hL, hR, h0, h1);
   }
 };
 
@@ -671,14 +679,14 @@ struct PxStore {
   }
 };
 
-template <int CH, bool FAST, bool COH>
+template <int CH, bool FAST, bool CI, bool CO>
 __device__ void inv_f32(const LevelDesc& d, const float* __restrict__ ll, const float* __restrict__ band,
                         float* __restrict__ px, const Item& it) {
   // halos: lane 0 -> HL / HH of quad qL-1 (parity 1); lane 63 -> quad qL+2:
   // h0 = LL / LH (parity 0), h1 = HL / HH (parity 1)
-  const BandLoader<float, FAST, true, COH> L =
-      band_loader<float, FAST, true, COH>(ll, d.ll_stride, band, d.band_stride, it, 1, 1, 0, 1);
-  const PxStore<float, FAST, COH> S{px, d.pix_stride, it.W, it.H, 2 * it.qL, min(2 * it.I1, it.H)};
+  const BandLoader<float, FAST, true, CI> L =
+      band_loader<float, FAST, true, CI>(ll, d.ll_stride, band, d.band_stride, it, 1, 1, 0, 1);
+  const PxStore<float, FAST, CO> S{px, d.pix_stride, it.W, it.H, 2 * it.qL, min(2 * it.I1, it.H)};
   const bool first = it.first, last = it.last;
   using Buf = QBuf<float, CH>;
   auto load_chunk = [&](Buf& b, int i0) {
@@ -736,12 +744,12 @@ __device__ void inv_f32(const LevelDesc& d, const float* __restrict__ ll, const 
   run_rows<CH>(it.I0, it.I1, A, B, load_chunk, row);
 }
 
-template <int CH, bool FAST, bool COH>
+template <int CH, bool FAST, bool CI, bool CO>
 __device__ void inv_i32(const LevelDesc& d, const int* __restrict__ ll, const int* __restrict__ band,
                         int* __restrict__ px, const Item& it) {
-  const BandLoader<int, FAST, true, COH> L =
-      band_loader<int, FAST, true, COH>(ll, d.ll_stride, band, d.band_stride, it, 1, 1, 0, 1);
-  const PxStore<int, FAST, COH> S{px, d.pix_stride, it.W, it.H, 2 * it.qL, min(2 * it.I1, it.H)};
+  const BandLoader<int, FAST, true, CI> L =
+      band_loader<int, FAST, true, CI>(ll, d.ll_stride, band, d.band_stride, it, 1, 1, 0, 1);
+  const PxStore<int, FAST, CO> S{px, d.pix_stride, it.W, it.H, 2 * it.qL, min(2 * it.I1, it.H)};
   const bool first = it.first, last = it.last;
   using Buf = QBuf<int, CH>;
   auto load_chunk = [&](Buf& b, int i0) {
@@ -807,14 +815,14 @@ __device__ void inv_i32(const LevelDesc& d, const int* __restrict__ ll, const in
   run_rows<CH>(it.I0, it.I1, A, B, load_chunk, row);
 }
 
-template <int CH, bool FAST, bool COH>
+template <int CH, bool FAST, bool CI, bool CO>
 __device__ void bwd_f32(const LevelDesc& d, const float* __restrict__ ll, const float* __restrict__ band,
                         float* __restrict__ px, const Item& it) {
   // halos: lane 0 -> quad qL-1: h0 = LL / LH (parity 0), h1 = HL / HH (parity 1);
   // lane 63 -> quad qL+2: h0 = LL / LH (parity 0)
-  const BandLoader<float, FAST, false, COH> L =
-      band_loader<float, FAST, false, COH>(ll, d.ll_stride, band, d.band_stride, it, 0, 1, 0, 0);
-  const PxStore<float, FAST, COH> S{px, d.pix_stride, it.W, it.H, 2 * it.qL, min(2 * it.I1, it.H)};
+  const BandLoader<float, FAST, false, CI> L =
+      band_loader<float, FAST, false, CI>(ll, d.ll_stride, band, d.band_stride, it, 0, 1, 0, 0);
+  const PxStore<float, FAST, CO> S{px, d.pix_stride, it.W, it.H, 2 * it.qL, min(2 * it.I1, it.H)};
   const bool first = it.first, last = it.last;
   const AxisW hL = axis_weights(it.qL, it.W), hR = axis_weights(it.qL + 1, it.W), hH = axis_weights(it.qL - 1, it.W);
   using Buf = QBuf<float, CH>;
@@ -897,10 +905,12 @@ __device__ __forceinline__ bool fast_item(const LevelDesc& d, const Item& it, in
   return d.fast_ok && kStripQ * (strip + 1) <= it.nd_w;
 }
 
-// One work item: (image pointers already offset, strip, segment).
-template <int DIR, typename T, int CH, bool COH>
-__device__ __forceinline__ void run_item(const LevelDesc& d, int64_t pix_off, int64_t ll_off, int64_t band_off,
-                                         int strip, int seg, int lane) {
+// One work item: (image pointers already offset, strip, segment), with the
+// LL input rows coherent (CI: written earlier in the same job) and the LL
+// output rows coherent (CO: read later in the same job).
+template <int DIR, typename T, int CH, bool CI, bool CO>
+__device__ __forceinline__ void run_item_p(const LevelDesc& d, int64_t pix_off, int64_t ll_off, int64_t band_off,
+                                           int strip, int seg, int lane) {
   const Item it = make_item(d, strip, seg, lane);
   const bool fast = fast_item(d, it, strip);
   if constexpr (DIR == kFwd) {
@@ -908,11 +918,11 @@ __device__ __forceinline__ void run_item(const LevelDesc& d, int64_t pix_off, in
     T* ll = static_cast<T*>(d.ll_out) + ll_off;
     T* band = static_cast<T*>(d.band_out) + band_off;
     if constexpr (std::is_same<T, float>::value) {
-      if (fast) fwd_f32<CH, true, COH>(d, px, ll, band, it);
-      else fwd_f32<CH, false, COH>(d, px, ll, band, it);
+      if (fast) fwd_f32<CH, true, CI, CO>(d, px, ll, band, it);
+      else fwd_f32<CH, false, CI, CO>(d, px, ll, band, it);
     } else {
-      if (fast) fwd_i32<CH, true, COH>(d, px, ll, band, it);
-      else fwd_i32<CH, false, COH>(d, px, ll, band, it);
+      if (fast) fwd_i32<CH, true, CI, CO>(d, px, ll, band, it);
+      else fwd_i32<CH, false, CI, CO>(d, px, ll, band, it);
     }
   } else {
     const T* ll = static_cast<const T*>(d.ll_in) + ll_off;
@@ -920,15 +930,31 @@ __device__ __forceinline__ void run_item(const LevelDesc& d, int64_t pix_off, in
     T* px = static_cast<T*>(d.pix_out) + pix_off;
     if constexpr (DIR == kInv) {
       if constexpr (std::is_same<T, float>::value) {
-        if (fast) inv_f32<CH, true, COH>(d, ll, band, px, it);
-        else inv_f32<CH, false, COH>(d, ll, band, px, it);
+        if (fast) inv_f32<CH, true, CI, CO>(d, ll, band, px, it);
+        else inv_f32<CH, false, CI, CO>(d, ll, band, px, it);
       } else {
-        if (fast) inv_i32<CH, true, COH>(d, ll, band, px, it);
-        else inv_i32<CH, false, COH>(d, ll, band, px, it);
+        if (fast) inv_i32<CH, true, CI, CO>(d, ll, band, px, it);
+        else inv_i32<CH, false, CI, CO>(d, ll, band, px, it);
       }
     } else {
-      if (fast) bwd_f32<CH, true, COH>(d, ll, band, px, it);
-      else bwd_f32<CH, false, COH>(d, ll, band, px, it);
+      if (fast) bwd_f32<CH, true, CI, CO>(d, ll, band, px, it);
+      else bwd_f32<CH, false, CI, CO>(d, ll, band, px, it);
+    }
+  }
+}
+
+// `coh` bit 0: CI, bit 1: CO (persistent job steps); level launches use 0.
+template <int DIR, typename T, int CH, bool JOB>
+__device__ __forceinline__ void run_item(const LevelDesc& d, int coh, int64_t pix_off, int64_t ll_off,
+                                         int64_t band_off, int strip, int seg, int lane) {
+  if constexpr (!JOB) {
+    run_item_p<DIR, T, CH, false, false>(d, pix_off, ll_off, band_off, strip, seg, lane);
+  } else {
+    switch (coh & 3) {
+      case 0: run_item_p<DIR, T, CH, false, false>(d, pix_off, ll_off, band_off, strip, seg, lane); break;
+      case 1: run_item_p<DIR, T, CH, true, false>(d, pix_off, ll_off, band_off, strip, seg, lane); break;
+      case 2: run_item_p<DIR, T, CH, false, true>(d, pix_off, ll_off, band_off, strip, seg, lane); break;
+      default: run_item_p<DIR, T, CH, true, true>(d, pix_off, ll_off, band_off, strip, seg, lane); break;
     }
   }
 }
@@ -944,7 +970,7 @@ __global__ __launch_bounds__(kBlock) void level_kernel(LevelLaunch a) {
   const int rem = (int)(item - (int64_t)img * a.items_per_image);
   const int seg = rem / a.d.nstrips;
   const int strip = rem - seg * a.d.nstrips;
-  run_item<DIR, T, CH, false>(a.d, img * a.pix_bstride, img * a.ll_bstride, img * a.band_bstride, strip, seg, lane);
+  run_item<DIR, T, CH, false>(a.d, 0, img * a.pix_bstride, img * a.ll_bstride, img * a.band_bstride, strip, seg, lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -960,7 +986,11 @@ __global__ __launch_bounds__(kBlock) void level_kernel(LevelLaunch a) {
 // deadlock; a wait that exceeds a fixed poll budget sets the error word and
 // gives up rather than hang.
 // ---------------------------------------------------------------------------
-constexpr uint32_t kSpinLimit = 1u << 16;  // polls (~2 us each once backed off)
+// s_sleep(16) pauses about 16 * 64 clocks (~0.43 us at 2.4 GHz); a poll
+// backs off to at most kNapCap of them (~1.7 us), so a waiter sees a finished
+// producer within about that time, and gives up after kSpinLimit polls (~2 s).
+constexpr uint32_t kNapCap = 4;
+constexpr uint32_t kSpinLimit = 1u << 20;
 
 // Wait until rows [r_lo, r_hi] of the output of step p (image img) exist.
 // `pixels`: the rows are pixel rows of p's output (inverse / adjoint, two per
@@ -982,9 +1012,8 @@ __device__ __forceinline__ void wait_rows(const JobDesc& p, uint32_t* sync, int 
         __hip_atomic_store(sync + kSyncError, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         break;
       }
-      // back off (s_sleep n pauses about 64 n clocks), up to ~2 us per poll
-      for (uint32_t k = 0; k < nap; ++k) __builtin_amdgcn_s_sleep(32);
-      nap = nap < 32 ? 2 * nap : 32;
+      for (uint32_t k = 0; k < nap; ++k) __builtin_amdgcn_s_sleep(16);
+      nap = nap < kNapCap ? 2 * nap : kNapCap;
     }
   }
   // the item's loads of the producers' rows are coherent (sc0 sc1) and are
@@ -1029,7 +1058,8 @@ __global__ __launch_bounds__(kBlock) void job_kernel(JobArgs a) {
       if (DIR == kFwd) wait_rows(p, sync, img, 2 * I0 - 4, 2 * I1 + 2, false);
       else wait_rows(p, sync, img, I0 - 3, I1 + 2, true);
     }
-    run_item<DIR, T, CH, true>(jd.d, img * jd.pix_bstride, img * jd.ll_bstride, img * jd.band_bstride, strip, seg, lane);
+    run_item<DIR, T, CH, true>(jd.d, jd.coh, img * jd.pix_bstride, img * jd.ll_bstride, img * jd.band_bstride, strip,
+                               seg, lane);
     // publish: the item's stores write through (sc1); once they have
     // completed (s_waitcnt 0) the count makes them visible to every XCD
     __builtin_amdgcn_s_waitcnt(0);

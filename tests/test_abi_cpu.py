@@ -114,6 +114,11 @@ def _images(specs):
 def test_batched_validation(lib):
     ok = _images([(64, 64, 64), (33, 17, 40)])
     assert lib.dwt2_batched_workspace_size(ok, 2, 2, 0) > 0
+    geo_only = _images([(64, 64, 64), (33, 17, 40)])       # the size query reads only the geometry
+    for i in range(2):
+        geo_only[i].src = geo_only[i].dst = None
+    assert lib.dwt2_batched_workspace_size(geo_only, 2, 2, 0) == lib.dwt2_batched_workspace_size(ok, 2, 2, 0)
+    assert lib.dwt2_batched_workspace_size(_images([(64, 64, 64), (3, 3, 3)]), 2, 3, 0) == 0
     bad = _images([(64, 64, 64), (33, 17, 20)])           # image 1: stride < width
     assert lib.dwt2_fwd_batched(bad, 2, 2, 0, 0, FAKE_WS, 1 << 30, None) == -1
     assert "image 1" in lib.dwt2_last_error().decode()
@@ -129,6 +134,15 @@ def test_set_path_validation(lib):
     assert lib.dwt2_set_path(2) == -1
     assert lib.dwt2_set_path(1) == 0
     assert lib.dwt2_set_path(0) == 0
+
+
+def test_set_probe_validation(lib):
+    ev = 0x1000
+    assert lib.dwt2_set_probe(3, 1, ev, ev) == -1
+    assert lib.dwt2_set_probe(0, 0, ev, ev) == -1
+    assert lib.dwt2_set_probe(0, 25, ev, ev) == -1
+    assert lib.dwt2_set_probe(0, 1, None, ev) == -1
+    assert lib.dwt2_set_probe(-1, 0, None, None) == 0
 
 
 def test_set_tiling_validation(lib):

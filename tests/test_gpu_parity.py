@@ -229,6 +229,29 @@ def test_config5_adjoint_against_oracle():
             assert maxdiff(got[b, ch], oracle.adj(g[b, ch].astype(np.float64), levels)) <= TOL
 
 
+def test_probe_times_one_level_and_changes_nothing():
+    """dwt2_set_probe records its events around exactly one level's launch:
+    the probed level-1 time is positive and below the whole call's, and the
+    coefficients are unchanged."""
+    d = D()
+    x = to_gpu(synth.image(1024, 768, 11, np.float32))
+    ref = d.fwd(x, 4)
+    b, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    try:
+        d.set_path(False)
+        d.set_probe("fwd", 1, b, e)
+        c0.record()
+        got = d.fwd(x, 4)
+        c1.record()
+        torch.cuda.synchronize()
+        t1, tall = b.elapsed_time(e), c0.elapsed_time(c1)
+        assert 0 < t1 <= tall, (t1, tall)
+        assert torch.equal(got, ref)
+    finally:
+        d.set_probe(None)
+
+
 @pytest.mark.parametrize("mode", ["f32", "int"])
 def test_results_do_not_depend_on_tiling_or_path(mode):
     """Every tiling (segment height, prefetch chunk) and both ways of chaining
