@@ -90,40 +90,44 @@ static int device_cus() {
   return cache[dev];
 }
 
-// Resident waves of the level kernel over the whole device (cached).
-static int64_t resident_waves(int dir, int mode, int ch) {
-  static std::mutex mu;
-  static int cache[3][2][3] = {};
-  const int ci = ch >= 4 ? 2 : (ch >= 2 ? 1 : 0);
-  int blocks;
-  {
-    std::lock_guard<std::mutex> lock(mu);
-    int& c = cache[dir][mode][ci];
-    if (!c) {
-      c = level_blocks_per_cu(dir, mode, ch);
-      if (c <= 0) c = 2;
-    }
-    blocks = c;
-  }
-  return (int64_t)blocks * kWavesPerBlock * device_cus();
+// Segment height (quadruple rows per work item) and chunk size.
+// Per-level launches: about kLevelWavesPerCU waves per compute unit, each
+// walking a power-of-two number of quadruple rows.  Measured on MI355X
+// (float32 and int32, levels from 16384^2 down to 2048^2), this beats
+// filling every resident wave slot: longer walks re-read fewer halo rows at
+// segment starts, and power-of-two heights avoided slow address patterns
+// that other heights hit (8192^2 level 1: 91 us at 64 rows, 105-117 us at
+// 24 or 48).  Below ~1024^2 a level costs the launch latency whatever the
+// tiling.  The persistent job passes its resident capacity as `slots_hint`
+// and keeps one round of items for it, each a whole number of chunk pairs.
+static std::atomic<int> g_forced_seg{-1}, g_forced_ch{-1}, g_persistent{-1};
+constexpr int kLevelWavesPerCU = 8;
+
+static int pow2_ceil(int v) {
+  int p = 1;
+  while (p < v) p <<= 1;
+  return p;
 }
 
-// Segment height (quadruple rows per work item) and chunk size: enough
-// segments for one round of resident waves, each a whole number of chunk
-// pairs where possible.
-static std::atomic<int> g_forced_seg{-1}, g_forced_ch{-1}, g_persistent{-1};
-
-Tiling choose_tiling(int dir, int mode, int ns_h, int64_t strips_times_batch, int64_t slots_hint) {
+Tiling choose_tiling(int ns_h, int64_t strips_times_batch, int64_t slots_hint) {
   if (g_forced_seg.load() < 0) g_forced_seg.store(env_int("DWT2_SEG") > 0 ? env_int("DWT2_SEG") : 0);
   if (g_forced_ch.load() < 0) g_forced_ch.store(env_int("DWT2_CH") > 0 ? env_int("DWT2_CH") : 0);
   const int forced_seg = g_forced_seg.load(), forced_ch = g_forced_ch.load();
   Tiling t;
   t.ch = forced_ch > 0 ? (forced_ch >= 4 ? 4 : (forced_ch >= 2 ? 2 : 1)) : 2;
-  const int64_t slots = slots_hint > 0 ? slots_hint : resident_waves(dir, mode, t.ch);
-  const int64_t per_strip = slots / strips_times_batch > 1 ? slots / strips_times_batch : 1;
-  int seg = (int)((ns_h + per_strip - 1) / per_strip);
-  if (forced_ch <= 0 && seg < 2 * t.ch) t.ch = 1;
-  seg = (seg + 2 * t.ch - 1) / (2 * t.ch) * (2 * t.ch);
+  int seg;
+  if (slots_hint > 0) {
+    const int64_t per_strip = slots_hint / strips_times_batch > 1 ? slots_hint / strips_times_batch : 1;
+    seg = (int)((ns_h + per_strip - 1) / per_strip);
+    if (forced_ch <= 0 && seg < 2 * t.ch) t.ch = 1;
+    seg = (seg + 2 * t.ch - 1) / (2 * t.ch) * (2 * t.ch);
+  } else {
+    const int64_t waves = (int64_t)kLevelWavesPerCU * device_cus();
+    const int64_t per_strip = waves / strips_times_batch > 1 ? waves / strips_times_batch : 1;
+    seg = pow2_ceil((int)((ns_h + per_strip - 1) / per_strip));
+    if (seg < 2) seg = 2;
+    if (forced_ch <= 0 && seg < 2 * t.ch) t.ch = 1;
+  }
   t.seg = forced_seg > 0 ? forced_seg : seg;
   return t;
 }
@@ -161,7 +165,7 @@ static void level_launch(int dir, const Call& c, const Geo& g, int k, int64_t sl
   memset(&a, 0, sizeof a);
   const int W = g.w[k - 1], H = g.h[k - 1];
   const int64_t strips_batch = (int64_t)num_strips(W) * c.batch;
-  const Tiling t = choose_tiling(dir, c.mode, ceil_half(H), strips_batch, slots_hint);
+  const Tiling t = choose_tiling(ceil_half(H), strips_batch, slots_hint);
   ch = t.ch;
   fill_level(a.d, W, H, t.seg);
   // pixels of the level input: the image (k = 1) or LL_{k-1}

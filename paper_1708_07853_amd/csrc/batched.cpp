@@ -368,6 +368,10 @@ int build_plan(Plan& p, const dwt2_image_t* images, int n, int levels, int mode,
     }
     (void)hipGetLastError();
   }
+  const char* verbose = getenv("DWT2_VERBOSE");
+  if (verbose && atoi(verbose) > 0)
+    fprintf(stderr, "dwt2_fwd_batched plan: %d images, %d levels, segment policy %d, %d items, %d blocks, %s\n", n,
+            levels, p.base_seg, p.total_items, p.blocks, p.exec ? "graph replay" : "direct launches");
   return DWT2_OK;
 }
 

@@ -98,8 +98,6 @@ struct JobArgs {
 
 // Kernel launchers (kernels.hip).  Return hipError_t as int.
 int launch_level(int dir, int mode, int chunk, const LevelLaunch& a, void* stream);
-// Resident 256-thread blocks per CU of the level kernel (0 if unknown).
-int level_blocks_per_cu(int dir, int mode, int chunk);
 int job_blocks_per_cu(int dir, int mode, int chunk);
 int launch_job(int dir, int mode, int chunk, const JobArgs& a, int blocks, void* stream);
 int launch_zero(uint32_t* p, int64_t n, void* stream);

@@ -397,7 +397,9 @@ __device__ __forceinline__ PxLoader<T, FAST, COH> px_loader(const T* base, int64
   } else if (it.last) {
     L.hc0 = L.hc1 = fold_idx(L.c0 + 4, it.W);
   } else {
-    L.hc0 = L.hc1 = L.col[0];
+    // interior lanes take their neighbours' values over DPP and never use
+    // the halo: an out-of-range offset makes the hardware drop their request
+    L.hc0 = L.hc1 = -1;
   }
   return L;
 }
@@ -631,7 +633,7 @@ struct BandLoader {
 };
 
 // Halo assignment: (parity, quadruple column) of the two halo values of
-// lanes 0 and 63; other lanes read their own first quadruple (unused).
+// lanes 0 and 63; the other lanes issue out-of-range loads (no memory request).
 template <typename T, bool FAST, bool MIRROR, bool COH>
 __device__ __forceinline__ BandLoader<T, FAST, MIRROR, COH> band_loader(const T* ll, int64_t ls, const T* band,
                                                                         int64_t bs, const Item& it, int p0_first,
@@ -652,6 +654,7 @@ __device__ __forceinline__ BandLoader<T, FAST, MIRROR, COH> band_loader(const T*
   }
   L.hc0 = col(qq, L.hp0);
   L.hc1 = col(qq, L.hp1);
+  if (!it.first && !it.last) L.hc0 = L.hc1 = -1;  // unused: out of range, no memory request
   return L;
 }
 
@@ -1088,14 +1091,6 @@ hipError_t launch_ch(int chunk, const LevelLaunch& a, hipStream_t s) {
   return launch_t<DIR, T, 1>(a, s);
 }
 
-template <int DIR, typename T, int CH>
-int occ_blocks() {
-  int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(&level_kernel<DIR, T, CH>),
-                                                   kBlock, 0) != hipSuccess)
-    n = 0;
-  return n;
-}
 
 // Cooperative launch: the runtime places every block at once or fails.
 template <int DIR, typename T, int CH>
@@ -1158,19 +1153,6 @@ int launch_level(int dir, int mode, int chunk, const LevelLaunch& a, void* strea
   if (dir == kFwd) return mode == DWT2_F32 ? launch_ch<kFwd, float>(chunk, a, s) : launch_ch<kFwd, int>(chunk, a, s);
   if (dir == kInv) return mode == DWT2_F32 ? launch_ch<kInv, float>(chunk, a, s) : launch_ch<kInv, int>(chunk, a, s);
   return launch_ch<kBwd, float>(chunk, a, s);
-}
-
-template <int CH>
-int occ_dir(int dir, int mode) {
-  if (dir == kFwd) return mode == DWT2_F32 ? occ_blocks<kFwd, float, CH>() : occ_blocks<kFwd, int, CH>();
-  if (dir == kInv) return mode == DWT2_F32 ? occ_blocks<kInv, float, CH>() : occ_blocks<kInv, int, CH>();
-  return occ_blocks<kBwd, float, CH>();
-}
-
-int level_blocks_per_cu(int dir, int mode, int chunk) {
-  if (chunk >= 4) return occ_dir<4>(dir, mode);
-  if (chunk >= 2) return occ_dir<2>(dir, mode);
-  return occ_dir<1>(dir, mode);
 }
 
 }  // namespace dwt2

@@ -38,7 +38,7 @@ struct Tiling {
   int seg;  // quadruple rows per work item
   int ch;   // rows per prefetch chunk (kernel template)
 };
-Tiling choose_tiling(int dir, int mode, int ns_h, int64_t strips_times_batch, int64_t slots_hint = 0);
+Tiling choose_tiling(int ns_h, int64_t strips_times_batch, int64_t slots_hint = 0);
 int fast_layout(int dir, const LevelLaunch& a, int batch, int W);
 void fill_level(LevelDesc& d, int W, int H, int seg);
 int run_levels(int dir, const Call& c, const Geo& g, void* stream);
