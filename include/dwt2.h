@@ -69,8 +69,9 @@ enum { DWT2_EXT_SYMMETRIC = 0 };
 /* status codes */
 enum {
   DWT2_OK = 0,
-  DWT2_ERR_ARG = -1,       /* null pointer, width/height < 2, stride < width,
-                              batch < 1, batch stride too small, bad boundary */
+  DWT2_ERR_ARG = -1,       /* null pointer, pointer not 4-byte aligned,
+                              width/height < 2, stride < width, batch < 1,
+                              batch stride too small, bad boundary */
   DWT2_ERR_SIZE = -2,      /* levels < 1, a level input below 2 x 2, or a
                               dimension above DWT2_MAX_DIM */
   DWT2_ERR_MODE = -3,      /* unknown mode, or integer mode in dwt2_bwd */
@@ -141,15 +142,23 @@ typedef struct {
 size_t dwt2_batched_workspace_size(const dwt2_image_t* images, int32_t n,
                                    int32_t levels, int32_t mode);
 
-/* Forward transform of n images of unequal sizes in one persistent kernel
- * launch, replayed from a HIP graph that is cached per shape set.
+/* Forward transform of n images of unequal sizes (Mallat recursion of §2
+ * with the spatial steps of §3, eq. (5), per image), replayed from a HIP
+ * graph that is cached per shape set and workspace.
  *   images  HOST array of n descriptors; every image is validated like a
  *           dwt2_fwd call (the detail string names the failing image).
- * Results are bit-identical to n separate dwt2_fwd calls.  The first call
- * for a new shape set builds the plan (tile choice, schedule, graph) and is
- * therefore not capture-safe; later calls only update the descriptor table
- * and launch the graph on `stream`.  Calls sharing a workspace must be
- * stream-ordered. */
+ * The work items (image, level, strip, segment) of all images run under one
+ * of two schedules, picked per shape set by timing both on the first call:
+ * one cooperative persistent launch in which an item waits only for the
+ * rows of the previous level of its own image, or one launch per level over
+ * every image.  The environment variables DWT2_BATCH_SCHEDULE (0 persistent,
+ * 1 per level) and DWT2_BATCH_SEG (level-1 segment height) force a policy,
+ * and DWT2_TUNE_CACHE names a file that keeps tuning results.
+ * Results are bit-identical to n separate dwt2_fwd calls under every
+ * policy.  The first call for a new shape set builds the plan (tuning,
+ * schedule, graph) and is therefore not capture-safe; later calls only
+ * update the descriptor table and launch the graph on `stream`.  Calls
+ * sharing a workspace must be stream-ordered. */
 int dwt2_fwd_batched(const dwt2_image_t* images, int32_t n, int32_t levels,
                      int32_t mode, int32_t boundary, void* workspace,
                      size_t workspace_bytes, void* stream);

@@ -140,22 +140,6 @@ void fill_level(LevelDesc& d, int W, int H, int seg) {
   d.nsegs = (ceil_half(H) + seg - 1) / seg;
 }
 
-static bool al(const void* p, unsigned bytes) { return ((uintptr_t)p & (bytes - 1)) == 0; }
-
-// Whether the vector path's alignment assumptions hold for this level:
-// 16-byte pixel rows and 8-byte band rows (even band origins).
-int fast_layout(int dir, const LevelLaunch& a, int batch, int W) {
-  const LevelDesc& d = a.d;
-  const bool many = batch > 1;
-  const bool px_ok = al(dir == kFwd ? d.pix_in : d.pix_out, 16) && d.pix_stride % 4 == 0 &&
-                     (!many || a.pix_bstride % 4 == 0);
-  const bool ll_ok = al(dir == kFwd ? d.ll_out : d.ll_in, 8) && d.ll_stride % 2 == 0 &&
-                     (!many || a.ll_bstride % 2 == 0);
-  const bool band_ok = al(dir == kFwd ? d.band_out : d.band_in, 8) && d.band_stride % 2 == 0 &&
-                       (!many || a.band_bstride % 2 == 0) && ceil_half(W) % 2 == 0;
-  return px_ok && ll_ok && band_ok;
-}
-
 // LL_m of each image's workspace slice (the slices follow the sync area).
 static char* ll_buf(const Call& c, const Geo& g, int m) { return c.ws + c.ll_base + ll_offset(g, m); }
 
@@ -193,7 +177,6 @@ static void level_launch(int dir, const Call& c, const Geo& g, int k, int64_t sl
   }
   a.items_per_image = a.d.nstrips * a.d.nsegs;
   a.items = (int64_t)a.items_per_image * c.batch;
-  a.d.fast_ok = fast_layout(dir, a, c.batch, W);
 }
 
 // One kernel launch per level (levels meet at kernel boundaries).
@@ -296,6 +279,8 @@ static int transform(int dir, const void* src, int64_t src_stride, int64_t src_b
                      int32_t boundary, void* workspace, size_t workspace_bytes, void* stream) {
   clear_error();
   if (!src || !dst) return fail(DWT2_ERR_ARG, "null src or dst");
+  if (((uintptr_t)src | (uintptr_t)dst | (uintptr_t)workspace) & 3)
+    return fail(DWT2_ERR_ARG, "src, dst and workspace must be 4-byte aligned");
   if (boundary != DWT2_EXT_SYMMETRIC) return fail(DWT2_ERR_ARG, "unknown boundary %d", boundary);
   if (batch < 1) return fail(DWT2_ERR_ARG, "batch must be >= 1 (got %d)", batch);
   if (width >= 2 && (src_stride < width || dst_stride < width))

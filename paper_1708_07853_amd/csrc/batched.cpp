@@ -28,6 +28,12 @@ namespace {
 
 constexpr int kBatchCh = 2;     // prefetch chunk of the batched job kernel
 constexpr int kMinSeg = 2 * kBatchCh;
+// Schedules: one cooperative persistent launch whose items wait for the rows
+// of the previous level of the same image (kChained), or one launch per
+// level over every image's items (kLevelSync; levels meet at kernel
+// boundaries, nothing waits).  A policy is a schedule plus the level-1
+// segment height, coded as kind * kPolicyKind + base.
+constexpr int kChained = 0, kLevelSync = 1, kPolicyKind = 10000;
 
 // `pointers`: also check pointers, strides and aliasing (a size query reads
 // only the geometry).
@@ -39,6 +45,8 @@ int validate_images(const dwt2_image_t* images, int32_t n, int32_t levels, int32
   for (int i = 0; i < n; ++i) {
     const dwt2_image_t& im = images[i];
     if (pointers && (!im.src || !im.dst)) return fail(DWT2_ERR_ARG, "image %d: null src or dst", i);
+    if (pointers && (((uintptr_t)im.src | (uintptr_t)im.dst) & 3))
+      return fail(DWT2_ERR_ARG, "image %d: src and dst must be 4-byte aligned", i);
     if (pointers && im.width >= 2 && (im.src_stride < im.width || im.dst_stride < im.width))
       return fail(DWT2_ERR_ARG, "image %d: stride < width", i);
     const int st = check_geometry(im.width, im.height, levels, geos[i]);
@@ -97,6 +105,7 @@ int seg_for(int base, int k, int ns_h) {
 
 struct Plan {
   int n = 0, levels = 0, mode = 0;
+  int kind = 0;                 // kChained or kLevelSync
   int base_seg = 32;
   std::vector<Geo> geos;
   std::vector<int> order;       // images by decreasing pixel count
@@ -104,7 +113,7 @@ struct Plan {
   int32_t ndesc = 0, total_items = 0, counters = 0;
   std::vector<uint32_t> item_desc;
   std::vector<int> desc_seg;    // segment height per desc
-  std::vector<int32_t> step0_items;  // items of each level-1 desc
+  std::vector<int32_t> step_begin;   // first item of each level, plus the total
   // device side
   char* ws = nullptr;
   void* staging = nullptr;      // pinned: descs then items
@@ -124,7 +133,7 @@ struct Plan {
 
 std::mutex g_mu;
 std::map<std::string, std::unique_ptr<Plan>> g_plans;
-std::map<std::string, int> g_tuned;  // shape set -> base segment height
+std::map<std::string, int> g_tuned;  // shape set -> policy code (kind * kPolicyKind + base)
 bool g_tune_loaded = false;
 
 std::string shape_key(const dwt2_image_t* images, int n, int levels, int mode) {
@@ -170,14 +179,17 @@ void save_tune(const std::string& hk, int base) {
 }
 
 // Item table and segment heights for a policy.
-void build_schedule(Plan& p, int base) {
+void build_schedule(Plan& p, int policy) {
+  const int base = policy % kPolicyKind;
+  p.kind = policy / kPolicyKind;
   p.base_seg = base;
   p.ndesc = p.n * p.levels;
   p.desc_seg.assign(p.ndesc, 0);
-  p.step0_items.assign(p.n, 0);
+  p.step_begin.assign(p.levels + 1, 0);
   p.item_desc.clear();
   p.counters = 0;
   for (int t = 0; t < p.levels; ++t) {
+    p.step_begin[t] = (int32_t)p.item_desc.size();
     for (int oi = 0; oi < p.n; ++oi) {
       const int i = p.order[oi];
       const Geo& g = p.geos[i];
@@ -189,11 +201,11 @@ void build_schedule(Plan& p, int base) {
       const int nsegs = (ns_h + seg - 1) / seg;
       const int items = nsegs * num_strips(g.w[k - 1]);
       p.item_desc.insert(p.item_desc.end(), items, (uint32_t)j);
-      if (t == 0) p.step0_items[oi] = items;
       p.counters += nsegs;
     }
   }
   p.total_items = (int32_t)p.item_desc.size();
+  p.step_begin[p.levels] = p.total_items;
 }
 
 // Step descriptors for the current pointers, written to the staging buffer.
@@ -220,16 +232,12 @@ void fill_descs(Plan& p, const dwt2_image_t* images, JobDesc* out) {
       d.ll_stride = (k == g.L) ? im.dst_stride : ll_pitch(g.w[k]);
       d.band_out = im.dst;
       d.band_stride = im.dst_stride;
-      LevelLaunch a;
-      memset(&a, 0, sizeof a);
-      a.d = d;
-      d.fast_ok = fast_layout(kFwd, a, 1, W);
       jd.nimg = 1;
       jd.item_start = start;
       jd.items = d.nsegs * d.nstrips;
       jd.cbase = cbase;
       jd.prev = t > 0 ? (t - 1) * p.n + oi : -1;
-      jd.coh = (t > 0 ? 1 : 0) | (t + 1 < p.levels ? 2 : 0);
+      jd.coh = p.kind == kChained ? ((t > 0 ? 1 : 0) | (t + 1 < p.levels ? 2 : 0)) : 0;
       start += jd.items;
       cbase += d.nsegs;
     }
@@ -247,7 +255,9 @@ JobArgs job_args(const Plan& p) {
   return a;
 }
 
-// Copy the tables, clear the sync words, run the job (on `s`).
+// Copy the tables, then run the schedule (on `s`): chained = clear the sync
+// words and launch the persistent job; level-synchronous = one launch per
+// level over that level's item range.
 hipError_t enqueue(const Plan& p, hipStream_t s) {
   const size_t dbytes = (size_t)p.ndesc * sizeof(JobDesc);
   hipError_t e = hipMemcpyAsync(p.ws + p.lay.descs, p.staging, dbytes, hipMemcpyHostToDevice, s);
@@ -255,6 +265,18 @@ hipError_t enqueue(const Plan& p, hipStream_t s) {
   e = hipMemcpyAsync(p.ws + p.lay.items, static_cast<char*>(p.staging) + round256(dbytes),
                      (size_t)p.total_items * 4, hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return e;
+  if (p.kind == kLevelSync) {
+    for (int t = 0; t < p.levels; ++t) {
+      TableArgs a;
+      a.descs = reinterpret_cast<const JobDesc*>(p.ws + p.lay.descs);
+      a.item_desc = reinterpret_cast<const uint32_t*>(p.ws + p.lay.items);
+      a.item_begin = p.step_begin[t];
+      a.items = p.step_begin[t + 1] - p.step_begin[t];
+      const int err = launch_table(p.mode, kBatchCh, a, s);
+      if (err != hipSuccess) return (hipError_t)err;
+    }
+    return hipSuccess;
+  }
   int err = launch_zero(reinterpret_cast<uint32_t*>(p.ws + p.lay.sync), kSyncCounters + (int64_t)kCounterStride * p.counters, s);
   if (err != hipSuccess) return (hipError_t)err;
   return (hipError_t)launch_job(kFwd, p.mode, kBatchCh, job_args(p), p.blocks, s);
@@ -277,12 +299,21 @@ int ensure_staging(Plan& p) {
   return DWT2_OK;
 }
 
-// Times the candidate policies once (outside any capture) and keeps the best.
+// Times the candidate policies once (outside any capture) and keeps the
+// best.  DWT2_BATCH_SCHEDULE (0 chained, 1 level-synchronous) and
+// DWT2_BATCH_SEG (level-1 segment height) force a policy.
 int autotune(Plan& p, const dwt2_image_t* images, hipStream_t s, const std::string& hk) {
-  static const int candidates[] = {8, 16, 32, 64};
-  const char* forced = getenv("DWT2_BATCH_SEG");
-  if (forced && atoi(forced) > 0) {
-    build_schedule(p, atoi(forced));
+  static const int candidates[] = {kChained * kPolicyKind + 8,    kChained * kPolicyKind + 16,
+                                   kChained * kPolicyKind + 32,   kChained * kPolicyKind + 64,
+                                   kLevelSync * kPolicyKind + 8,  kLevelSync * kPolicyKind + 16,
+                                   kLevelSync * kPolicyKind + 32, kLevelSync * kPolicyKind + 64,
+                                   kLevelSync * kPolicyKind + 128};
+  const char* fk = getenv("DWT2_BATCH_SCHEDULE");
+  const char* fs = getenv("DWT2_BATCH_SEG");
+  const int forced_kind = fk ? atoi(fk) : -1;
+  const int forced_seg = fs ? atoi(fs) : 0;
+  if (forced_kind == kChained || forced_kind == kLevelSync) {
+    build_schedule(p, forced_kind * kPolicyKind + (forced_seg > 0 ? forced_seg : 32));
     return DWT2_OK;
   }
   auto it = g_tuned.find(hk);
@@ -294,9 +325,9 @@ int autotune(Plan& p, const dwt2_image_t* images, hipStream_t s, const std::stri
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
     return fail(DWT2_ERR_HIP, "event creation failed");
   float best = 1e30f;
-  int best_base = 32;
-  for (int base : candidates) {
-    build_schedule(p, base);
+  int best_policy = kLevelSync * kPolicyKind + 32;
+  for (int policy : candidates) {
+    build_schedule(p, policy);
     if (p.total_items > p.lay.max_items || p.counters > p.lay.max_counters) continue;
     int st = ensure_staging(p);
     if (st) return st;
@@ -310,14 +341,14 @@ int autotune(Plan& p, const dwt2_image_t* images, hipStream_t s, const std::stri
     }
     if (t < best) {
       best = t;
-      best_base = base;
+      best_policy = policy;
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  build_schedule(p, best_base);
-  g_tuned[hk] = best_base;
-  save_tune(hk, best_base);
+  build_schedule(p, best_policy);
+  g_tuned[hk] = best_policy;
+  save_tune(hk, best_policy);
   return DWT2_OK;
 }
 
@@ -370,8 +401,9 @@ int build_plan(Plan& p, const dwt2_image_t* images, int n, int levels, int mode,
   }
   const char* verbose = getenv("DWT2_VERBOSE");
   if (verbose && atoi(verbose) > 0)
-    fprintf(stderr, "dwt2_fwd_batched plan: %d images, %d levels, segment policy %d, %d items, %d blocks, %s\n", n,
-            levels, p.base_seg, p.total_items, p.blocks, p.exec ? "graph replay" : "direct launches");
+    fprintf(stderr, "dwt2_fwd_batched plan: %d images, %d levels, %s schedule, level-1 segment %d, %d items, %s\n",
+            n, levels, p.kind == kLevelSync ? "level-synchronous" : "chained persistent", p.base_seg, p.total_items,
+            p.exec ? "graph replay" : "direct launches");
   return DWT2_OK;
 }
 

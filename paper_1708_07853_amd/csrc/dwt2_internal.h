@@ -40,7 +40,7 @@ struct LevelDesc {
   int32_t seg;          // quadruple rows per work item
   int32_t nstrips;
   int32_t nsegs;
-  int32_t fast_ok;      // pointers/strides aligned for the vector path
+  int32_t pad_;
 };
 
 // Plain (uniform-geometry) launch of one level over a batch of images.
@@ -96,10 +96,20 @@ struct JobArgs {
   JobDesc inl[kInlineDescs];
 };
 
+// One level-synchronous launch over items [item_begin, item_begin + items)
+// of a ragged batch's item table (forward only).
+struct TableArgs {
+  const JobDesc* descs;
+  const uint32_t* item_desc;
+  int32_t item_begin;
+  int32_t items;
+};
+
 // Kernel launchers (kernels.hip).  Return hipError_t as int.
 int launch_level(int dir, int mode, int chunk, const LevelLaunch& a, void* stream);
 int job_blocks_per_cu(int dir, int mode, int chunk);
 int launch_job(int dir, int mode, int chunk, const JobArgs& a, int blocks, void* stream);
 int launch_zero(uint32_t* p, int64_t n, void* stream);
+int launch_table(int mode, int chunk, const TableArgs& a, void* stream);
 
 }  // namespace dwt2

@@ -141,10 +141,6 @@ struct Pol {
   static constexpr int st = COH ? (DWT2_COH_ST) : kNT;
 };
 template <int POL, typename T>
-__device__ __forceinline__ void bst1(T v, Rsrc r, int e) {
-  __builtin_amdgcn_raw_buffer_store_b32(ubits(v), r, (unsigned)e * 4u, 0, POL);
-}
-template <int POL, typename T>
 __device__ __forceinline__ void bst2(T a, T b, Rsrc r, int e) {
   typedef unsigned U2 __attribute__((ext_vector_type(2)));
   U2 u;
@@ -361,36 +357,42 @@ __device__ __forceinline__ void run_rows(int I0, int I1, Buf& A, Buf& B, LoadF&&
 
 // ---------------------------------------------------------------- forward
 // Pixel rows: four pixels per lane plus two halo pixels (lane 0: the two
-// columns left of the strip; lane 63: the column right of it).
-template <typename T, bool FAST, bool COH>  // COH: rows written earlier in the same job
+// columns left of the strip; lane 63: the column right of it).  Each lane
+// reads its four pixels with one 16-byte load at any 4-byte alignment (the
+// hardware splits accesses that cross a cache line).  EDGE: the strip
+// reaches the image's right edge; lanes whose pixels lie past it take the
+// mirrored columns from single-element loads (the other lanes pass an
+// out-of-range offset, which issues no request) and a select.
+template <typename T, bool EDGE, bool COH>  // COH: rows written earlier in the same job
 struct PxLoader {
   const T* base;
   int64_t stride;
   int W, H;
   int c0;
-  int col[4];
+  int pcol[4];  // EDGE: mirrored column of pixel c0 + k past the edge, else -1
   int hc0, hc1;
   __device__ __forceinline__ void load(int r, V4<T>& m, T& h0, T& h1) const {
     const Rsrc rs = row_rsrc(base + (int64_t)fold_idx(r, H) * stride, (int64_t)W * 4);
-    if constexpr (FAST) {
-      bld4<Pol<COH>::ld>(rs, c0, m);
-    } else {
-      m.x = bld1<T, Pol<COH>::ld>(rs, col[0]);
-      m.y = bld1<T, Pol<COH>::ld>(rs, col[1]);
-      m.z = bld1<T, Pol<COH>::ld>(rs, col[2]);
-      m.w = bld1<T, Pol<COH>::ld>(rs, col[3]);
+    bld4<Pol<COH>::ld>(rs, c0, m);
+    if constexpr (EDGE) {
+      const T p0 = bld1<T, Pol<COH>::halo>(rs, pcol[0]), p1 = bld1<T, Pol<COH>::halo>(rs, pcol[1]);
+      const T p2 = bld1<T, Pol<COH>::halo>(rs, pcol[2]), p3 = bld1<T, Pol<COH>::halo>(rs, pcol[3]);
+      m.x = pcol[0] >= 0 ? p0 : m.x;
+      m.y = pcol[1] >= 0 ? p1 : m.y;
+      m.z = pcol[2] >= 0 ? p2 : m.z;
+      m.w = pcol[3] >= 0 ? p3 : m.w;
     }
     h0 = bld1<T, Pol<COH>::halo>(rs, hc0);
     h1 = bld1<T, Pol<COH>::halo>(rs, hc1);
   }
 };
 
-template <typename T, bool FAST, bool COH>
-__device__ __forceinline__ PxLoader<T, FAST, COH> px_loader(const T* base, int64_t stride, const Item& it) {
-  PxLoader<T, FAST, COH> L;
+template <typename T, bool EDGE, bool COH>
+__device__ __forceinline__ PxLoader<T, EDGE, COH> px_loader(const T* base, int64_t stride, const Item& it) {
+  PxLoader<T, EDGE, COH> L;
   L.base = base; L.stride = stride; L.W = it.W; L.H = it.H;
   L.c0 = 2 * it.qL;
-  for (int k = 0; k < 4; ++k) L.col[k] = fold_idx(L.c0 + k, it.W);
+  for (int k = 0; k < 4; ++k) L.pcol[k] = (L.c0 + k < it.W) ? -1 : fold_idx(L.c0 + k, it.W);
   if (it.first) {
     L.hc0 = fold_idx(L.c0 - 2, it.W);
     L.hc1 = fold_idx(L.c0 - 1, it.W);
@@ -411,9 +413,10 @@ struct PxBuf {
 };
 
 // Stores of one row of the four bands (forward): one buffer resource per band
-// row; rows past I1 (and LH / HH rows past nd_h) have size 0, columns past
-// the band's width are out of range.
-template <typename T, bool FAST, bool COH>
+// row; rows past I1 (and LH / HH rows past nd_h) have size 0.  Each lane
+// writes its two quadruples with one 8-byte store at any 4-byte alignment;
+// the range check drops every dword past the band's width on its own.
+template <typename T, bool EDGE, bool COH>
 struct BandStore {
   T* ll;
   int64_t ls;
@@ -429,33 +432,26 @@ struct BandStore {
     const Rsrc rhh = row_rsrc(row2 + ns_w, real2 ? nd_w * 4 : 0);
     // only LL rows are read again inside a job; the bands are final
     constexpr int P = Pol<COH>::st, PB = kNT;
-    if constexpr (FAST) {
-      bst2<P>(llL, llR, rl, qL);
-      bst2<PB>(hlL, hlR, rh, qL);
-      bst2<PB>(lhL, lhR, rlh, qL);
-      bst2<PB>(hhL, hhR, rhh, qL);
-    } else {
-      bst1<P>(llL, rl, qL); bst1<P>(llR, rl, qL + 1);
-      bst1<PB>(hlL, rh, qL); bst1<PB>(hlR, rh, qL + 1);
-      bst1<PB>(lhL, rlh, qL); bst1<PB>(lhR, rlh, qL + 1);
-      bst1<PB>(hhL, rhh, qL); bst1<PB>(hhR, rhh, qL + 1);
-    }
+    bst2<P>(llL, llR, rl, qL);
+    bst2<PB>(hlL, hlR, rh, qL);
+    bst2<PB>(lhL, lhR, rlh, qL);
+    bst2<PB>(hhL, hhR, rhh, qL);
   }
 };
 
-template <typename T, bool FAST, bool COH>
-__device__ __forceinline__ BandStore<T, FAST, COH> band_store(T* ll, int64_t ls, T* band, int64_t bs, const Item& it) {
-  BandStore<T, FAST, COH> S;
+template <typename T, bool EDGE, bool COH>
+__device__ __forceinline__ BandStore<T, EDGE, COH> band_store(T* ll, int64_t ls, T* band, int64_t bs, const Item& it) {
+  BandStore<T, EDGE, COH> S;
   S.ll = ll; S.ls = ls; S.band = band; S.bs = bs;
   S.ns_w = it.ns_w; S.nd_w = it.nd_w; S.ns_h = it.ns_h; S.nd_h = it.nd_h; S.qL = it.qL; S.I1 = it.I1;
   return S;
 }
 
-template <int CH, bool FAST, bool CI, bool CO>
+template <int CH, bool EDGE, bool CI, bool CO>
 __device__ void fwd_f32(const LevelDesc& d, const float* __restrict__ px, float* __restrict__ ll,
                         float* __restrict__ band, const Item& it) {
-  const PxLoader<float, FAST, CI> L = px_loader<float, FAST, CI>(px, d.pix_stride, it);
-  const BandStore<float, FAST, CO> S = band_store<float, FAST, CO>(ll, d.ll_stride, band, d.band_stride, it);
+  const PxLoader<float, EDGE, CI> L = px_loader<float, EDGE, CI>(px, d.pix_stride, it);
+  const BandStore<float, EDGE, CO> S = band_store<float, EDGE, CO>(ll, d.ll_stride, band, d.band_stride, it);
   const bool first = it.first, last = it.last;
   using Buf = PxBuf<float, CH>;
   auto load_chunk = [&](Buf& b, int i0) {
@@ -513,11 +509,11 @@ __device__ void fwd_f32(const LevelDesc& d, const float* __restrict__ px, float*
   run_rows<CH>(it.I0, it.I1, A, B, load_chunk, row);
 }
 
-template <int CH, bool FAST, bool CI, bool CO>
+template <int CH, bool EDGE, bool CI, bool CO>
 __device__ void fwd_i32(const LevelDesc& d, const int* __restrict__ px, int* __restrict__ ll,
                         int* __restrict__ band, const Item& it) {
-  const PxLoader<int, FAST, CI> L = px_loader<int, FAST, CI>(px, d.pix_stride, it);
-  const BandStore<int, FAST, CO> S = band_store<int, FAST, CO>(ll, d.ll_stride, band, d.band_stride, it);
+  const PxLoader<int, EDGE, CI> L = px_loader<int, EDGE, CI>(px, d.pix_stride, it);
+  const BandStore<int, EDGE, CO> S = band_store<int, EDGE, CO>(ll, d.ll_stride, band, d.band_stride, it);
   const bool first = it.first, last = it.last;
   using Buf = PxBuf<int, CH>;
   auto load_chunk = [&](Buf& b, int i0) {
@@ -583,35 +579,41 @@ __device__ void fwd_i32(const LevelDesc& d, const int* __restrict__ px, int* __r
 // symmetric extension of the interleaved coefficients (inverse: folded
 // indices, always in range); otherwise values outside the bands are zero
 // (adjoint: bounds-checked buffer loads, rows outside get a size-0 resource).
-template <typename T, bool FAST, bool MIRROR, bool COH>
+// Patch offset that marks "keep the vector load's value"; it is out of any
+// buffer's range, so its single-element load issues no request.
+constexpr int kNoPatch = -1;
+
+template <typename T, bool EDGE, bool MIRROR, bool COH>
 struct BandLoader {
   const T* ll;
   int64_t ls;
   const T* band;
   int64_t bs;
   int H, ns_h, nd_h, ns_w, nd_w, qL;
-  int cl0, cl1, ch0, ch1;  // general path: columns of quads qL, qL+1 (folded if MIRROR)
+  int pl0, pl1, ph0, ph1;  // EDGE: columns re-read for quads qL, qL+1 of L / H rows, or kNoPatch
   int hp0, hp1;            // halo band parity
   int hc0, hc1;            // halo columns (MIRROR: folded; else raw, may be outside)
 
   // `ll_row`: rl is an LL row (written earlier in the same job when COH);
-  // H-band rows are job inputs and take the plain policies
+  // H-band rows are job inputs and take the plain policies.  Each lane reads
+  // its two quadruples of a band row with one 8-byte load; EDGE lanes whose
+  // quadruples reach the band's end re-read them one by one at the folded
+  // (MIRROR) or raw (else: past the end reads 0) columns.
   __device__ __forceinline__ void part(const T* rl, const T* rh, bool valid, bool ll_row, T& lL, T& lR, T& hL, T& hR,
                                        T& h0, T& h1) const {
     constexpr int P = Pol<COH>::ld, PH = Pol<COH>::halo, PB = kNT;
     const Rsrc bl = row_rsrc(rl, (MIRROR || valid) ? ns_w * 4 : 0);
     const Rsrc bh = row_rsrc(rh, (MIRROR || valid) ? nd_w * 4 : 0);
-    if constexpr (FAST) {
-      if (ll_row) bld2<P>(bl, qL, lL, lR);
-      else bld2<PB>(bl, qL, lL, lR);
-      bld2<PB>(bh, qL, hL, hR);
-    } else {
-      if (ll_row) {
-        lL = bld1<T, P>(bl, cl0); lR = bld1<T, P>(bl, cl1);
-      } else {
-        lL = bld1<T, PB>(bl, cl0); lR = bld1<T, PB>(bl, cl1);
-      }
-      hL = bld1<T, PB>(bh, ch0); hR = bld1<T, PB>(bh, ch1);
+    if (ll_row) bld2<P>(bl, qL, lL, lR);
+    else bld2<PB>(bl, qL, lL, lR);
+    bld2<PB>(bh, qL, hL, hR);
+    if constexpr (EDGE) {
+      const T a0 = bld1<T, PH>(bl, pl0), a1 = bld1<T, PH>(bl, pl1);
+      const T b0 = bld1<T, PH>(bh, ph0), b1 = bld1<T, PH>(bh, ph1);
+      lL = pl0 != kNoPatch ? a0 : lL;
+      lR = pl1 != kNoPatch ? a1 : lR;
+      hL = ph0 != kNoPatch ? b0 : hL;
+      hR = ph1 != kNoPatch ? b1 : hR;
     }
     h0 = bld1<T, PH>(hp0 ? bh : bl, hc0);
     h1 = bld1<T, PH>(hp1 ? bh : bl, hc1);
@@ -634,17 +636,21 @@ struct BandLoader {
 
 // Halo assignment: (parity, quadruple column) of the two halo values of
 // lanes 0 and 63; the other lanes issue out-of-range loads (no memory request).
-template <typename T, bool FAST, bool MIRROR, bool COH>
-__device__ __forceinline__ BandLoader<T, FAST, MIRROR, COH> band_loader(const T* ll, int64_t ls, const T* band,
+template <typename T, bool EDGE, bool MIRROR, bool COH>
+__device__ __forceinline__ BandLoader<T, EDGE, MIRROR, COH> band_loader(const T* ll, int64_t ls, const T* band,
                                                                         int64_t bs, const Item& it, int p0_first,
                                                                         int p1_first, int p0_last, int p1_last) {
-  BandLoader<T, FAST, MIRROR, COH> L;
+  BandLoader<T, EDGE, MIRROR, COH> L;
   L.ll = ll; L.ls = ls; L.band = band; L.bs = bs;
   L.H = it.H; L.ns_h = it.ns_h; L.nd_h = it.nd_h; L.ns_w = it.ns_w; L.nd_w = it.nd_w; L.qL = it.qL;
   const int W = it.W, q = it.qL;
   auto col = [&](int qq, int par) { return MIRROR ? band_idx(qq, W, par) : qq; };
-  L.cl0 = col(q, 0); L.cl1 = col(q + 1, 0);
-  L.ch0 = col(q, 1); L.ch1 = col(q + 1, 1);
+  // a lane whose pair of quadruples reaches a band's end re-reads both
+  const bool lpatch = q + 1 >= it.ns_w, hpatch = q + 1 >= it.nd_w;
+  L.pl0 = lpatch ? col(q, 0) : kNoPatch;
+  L.pl1 = lpatch ? col(q + 1, 0) : kNoPatch;
+  L.ph0 = hpatch ? col(q, 1) : kNoPatch;
+  L.ph1 = hpatch ? col(q + 1, 1) : kNoPatch;
   int qq = q;
   L.hp0 = 0; L.hp1 = 0;
   if (it.first) {
@@ -666,30 +672,27 @@ struct QBuf {
 
 // Stores of pixel rows (inverse / adjoint): four pixels per lane, one buffer
 // resource per row (size 0 for rows past I1's last pixel row or past H).
-template <typename T, bool FAST, bool COH>
+template <typename T, bool EDGE, bool COH>
 struct PxStore {
   T* base;
   int64_t stride;
   int W, H, c0, rows_end;  // rows_end: first pixel row not to write (min(2 I1, H))
+  // one 16-byte store per lane at any 4-byte alignment; dwords past the
+  // row's end are dropped one by one by the range check
   __device__ __forceinline__ void row(int r, const V4<T>& v) const {
     const Rsrc rs = row_rsrc(base + (int64_t)r * stride, r < rows_end ? W * 4 : 0);
-    constexpr int P = Pol<COH>::st;
-    if constexpr (FAST) {
-      bst4<P>(v, rs, c0);
-    } else {
-      bst1<P>(v.x, rs, c0); bst1<P>(v.y, rs, c0 + 1); bst1<P>(v.z, rs, c0 + 2); bst1<P>(v.w, rs, c0 + 3);
-    }
+    bst4<Pol<COH>::st>(v, rs, c0);
   }
 };
 
-template <int CH, bool FAST, bool CI, bool CO>
+template <int CH, bool EDGE, bool CI, bool CO>
 __device__ void inv_f32(const LevelDesc& d, const float* __restrict__ ll, const float* __restrict__ band,
                         float* __restrict__ px, const Item& it) {
   // halos: lane 0 -> HL / HH of quad qL-1 (parity 1); lane 63 -> quad qL+2:
   // h0 = LL / LH (parity 0), h1 = HL / HH (parity 1)
-  const BandLoader<float, FAST, true, CI> L =
-      band_loader<float, FAST, true, CI>(ll, d.ll_stride, band, d.band_stride, it, 1, 1, 0, 1);
-  const PxStore<float, FAST, CO> S{px, d.pix_stride, it.W, it.H, 2 * it.qL, min(2 * it.I1, it.H)};
+  const BandLoader<float, EDGE, true, CI> L =
+      band_loader<float, EDGE, true, CI>(ll, d.ll_stride, band, d.band_stride, it, 1, 1, 0, 1);
+  const PxStore<float, EDGE, CO> S{px, d.pix_stride, it.W, it.H, 2 * it.qL, min(2 * it.I1, it.H)};
   const bool first = it.first, last = it.last;
   using Buf = QBuf<float, CH>;
   auto load_chunk = [&](Buf& b, int i0) {
@@ -747,12 +750,12 @@ __device__ void inv_f32(const LevelDesc& d, const float* __restrict__ ll, const 
   run_rows<CH>(it.I0, it.I1, A, B, load_chunk, row);
 }
 
-template <int CH, bool FAST, bool CI, bool CO>
+template <int CH, bool EDGE, bool CI, bool CO>
 __device__ void inv_i32(const LevelDesc& d, const int* __restrict__ ll, const int* __restrict__ band,
                         int* __restrict__ px, const Item& it) {
-  const BandLoader<int, FAST, true, CI> L =
-      band_loader<int, FAST, true, CI>(ll, d.ll_stride, band, d.band_stride, it, 1, 1, 0, 1);
-  const PxStore<int, FAST, CO> S{px, d.pix_stride, it.W, it.H, 2 * it.qL, min(2 * it.I1, it.H)};
+  const BandLoader<int, EDGE, true, CI> L =
+      band_loader<int, EDGE, true, CI>(ll, d.ll_stride, band, d.band_stride, it, 1, 1, 0, 1);
+  const PxStore<int, EDGE, CO> S{px, d.pix_stride, it.W, it.H, 2 * it.qL, min(2 * it.I1, it.H)};
   const bool first = it.first, last = it.last;
   using Buf = QBuf<int, CH>;
   auto load_chunk = [&](Buf& b, int i0) {
@@ -818,14 +821,14 @@ __device__ void inv_i32(const LevelDesc& d, const int* __restrict__ ll, const in
   run_rows<CH>(it.I0, it.I1, A, B, load_chunk, row);
 }
 
-template <int CH, bool FAST, bool CI, bool CO>
+template <int CH, bool EDGE, bool CI, bool CO>
 __device__ void bwd_f32(const LevelDesc& d, const float* __restrict__ ll, const float* __restrict__ band,
                         float* __restrict__ px, const Item& it) {
   // halos: lane 0 -> quad qL-1: h0 = LL / LH (parity 0), h1 = HL / HH (parity 1);
   // lane 63 -> quad qL+2: h0 = LL / LH (parity 0)
-  const BandLoader<float, FAST, false, CI> L =
-      band_loader<float, FAST, false, CI>(ll, d.ll_stride, band, d.band_stride, it, 0, 1, 0, 0);
-  const PxStore<float, FAST, CO> S{px, d.pix_stride, it.W, it.H, 2 * it.qL, min(2 * it.I1, it.H)};
+  const BandLoader<float, EDGE, false, CI> L =
+      band_loader<float, EDGE, false, CI>(ll, d.ll_stride, band, d.band_stride, it, 0, 1, 0, 0);
+  const PxStore<float, EDGE, CO> S{px, d.pix_stride, it.W, it.H, 2 * it.qL, min(2 * it.I1, it.H)};
   const bool first = it.first, last = it.last;
   const AxisW hL = axis_weights(it.qL, it.W), hR = axis_weights(it.qL + 1, it.W), hH = axis_weights(it.qL - 1, it.W);
   using Buf = QBuf<float, CH>;
@@ -900,13 +903,10 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
   return (x < r) ? x * (q + 1) + s : r * (q + 1) + (x - r) * q + s;
 }
 
-// Whether an item can use vector loads and stores: every quadruple column
-// of the strip inside both parity bands, and (host-checked) aligned pointers
-// and strides.  Other items gather and scatter single elements; both run the
-// same branch-free pipeline.
-__device__ __forceinline__ bool fast_item(const LevelDesc& d, const Item& it, int strip) {
-  return d.fast_ok && kStripQ * (strip + 1) <= it.nd_w;
-}
+// Whether an item's strip reaches the right edge of the image or of a band:
+// then lanes past the edge patch their vector loads with mirrored (inverse
+// / forward) or zero (adjoint) single elements.
+__device__ __forceinline__ bool edge_item(const Item& it, int strip) { return kStripQ * (strip + 1) > it.nd_w; }
 
 // One work item: (image pointers already offset, strip, segment), with the
 // LL input rows coherent (CI: written earlier in the same job) and the LL
@@ -915,16 +915,16 @@ template <int DIR, typename T, int CH, bool CI, bool CO>
 __device__ __forceinline__ void run_item_p(const LevelDesc& d, int64_t pix_off, int64_t ll_off, int64_t band_off,
                                            int strip, int seg, int lane) {
   const Item it = make_item(d, strip, seg, lane);
-  const bool fast = fast_item(d, it, strip);
+  const bool edge = edge_item(it, strip);
   if constexpr (DIR == kFwd) {
     const T* px = static_cast<const T*>(d.pix_in) + pix_off;
     T* ll = static_cast<T*>(d.ll_out) + ll_off;
     T* band = static_cast<T*>(d.band_out) + band_off;
     if constexpr (std::is_same<T, float>::value) {
-      if (fast) fwd_f32<CH, true, CI, CO>(d, px, ll, band, it);
+      if (edge) fwd_f32<CH, true, CI, CO>(d, px, ll, band, it);
       else fwd_f32<CH, false, CI, CO>(d, px, ll, band, it);
     } else {
-      if (fast) fwd_i32<CH, true, CI, CO>(d, px, ll, band, it);
+      if (edge) fwd_i32<CH, true, CI, CO>(d, px, ll, band, it);
       else fwd_i32<CH, false, CI, CO>(d, px, ll, band, it);
     }
   } else {
@@ -933,14 +933,14 @@ __device__ __forceinline__ void run_item_p(const LevelDesc& d, int64_t pix_off, 
     T* px = static_cast<T*>(d.pix_out) + pix_off;
     if constexpr (DIR == kInv) {
       if constexpr (std::is_same<T, float>::value) {
-        if (fast) inv_f32<CH, true, CI, CO>(d, ll, band, px, it);
+        if (edge) inv_f32<CH, true, CI, CO>(d, ll, band, px, it);
         else inv_f32<CH, false, CI, CO>(d, ll, band, px, it);
       } else {
-        if (fast) inv_i32<CH, true, CI, CO>(d, ll, band, px, it);
+        if (edge) inv_i32<CH, true, CI, CO>(d, ll, band, px, it);
         else inv_i32<CH, false, CI, CO>(d, ll, band, px, it);
       }
     } else {
-      if (fast) bwd_f32<CH, true, CI, CO>(d, ll, band, px, it);
+      if (edge) bwd_f32<CH, true, CI, CO>(d, ll, band, px, it);
       else bwd_f32<CH, false, CI, CO>(d, ll, band, px, it);
     }
   }
@@ -1072,6 +1072,28 @@ __global__ __launch_bounds__(kBlock) void job_kernel(JobArgs a) {
   }
 }
 
+// One step range of a ragged batch per launch (level-synchronous schedule):
+// one wave per work item, the item's step found through the device
+// item -> step table.  Steps of one launch never depend on each other.
+template <typename T, int CH>
+__global__ __launch_bounds__(kBlock) void table_kernel(TableArgs a) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int64_t w = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + wave;
+  if (w >= a.items) return;
+  const int q = a.item_begin + (int)w;
+  const int j = __builtin_amdgcn_readfirstlane(((const uint32_t* __restrict__)a.item_desc)[q]);
+  const JobDesc jd = ((const JobDesc* __restrict__)a.descs)[j];
+  const int item = q - jd.item_start;
+  const int per_img = jd.d.nsegs * jd.d.nstrips;
+  const int img = item / per_img;
+  const int rem = item - img * per_img;
+  const int seg = rem / jd.d.nstrips;
+  const int strip = rem - seg * jd.d.nstrips;
+  run_item<kFwd, T, CH, false>(jd.d, 0, img * jd.pix_bstride, img * jd.ll_bstride, img * jd.band_bstride, strip, seg,
+                               lane);
+}
+
 __global__ void zero_kernel(uint32_t* p, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     p[i] = 0u;
@@ -1139,6 +1161,20 @@ int job_blocks_per_cu(int dir, int mode, int chunk) {
   if (chunk >= 4) return occ_job_dir<4>(dir, mode);
   if (chunk >= 2) return occ_job_dir<2>(dir, mode);
   return occ_job_dir<1>(dir, mode);
+}
+
+int launch_table(int mode, int chunk, const TableArgs& a, void* stream) {
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (a.items <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((a.items + kWavesPerBlock - 1) / kWavesPerBlock));
+  if (mode == DWT2_F32) {
+    if (chunk >= 2) hipLaunchKernelGGL((table_kernel<float, 2>), grid, dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL((table_kernel<float, 1>), grid, dim3(kBlock), 0, s, a);
+  } else {
+    if (chunk >= 2) hipLaunchKernelGGL((table_kernel<int, 2>), grid, dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL((table_kernel<int, 1>), grid, dim3(kBlock), 0, s, a);
+  }
+  return hipGetLastError();
 }
 
 int launch_zero(uint32_t* p, int64_t n, void* stream) {

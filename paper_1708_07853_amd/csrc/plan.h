@@ -39,7 +39,6 @@ struct Tiling {
   int ch;   // rows per prefetch chunk (kernel template)
 };
 Tiling choose_tiling(int ns_h, int64_t strips_times_batch, int64_t slots_hint = 0);
-int fast_layout(int dir, const LevelLaunch& a, int batch, int W);
 void fill_level(LevelDesc& d, int W, int H, int seg);
 int run_levels(int dir, const Call& c, const Geo& g, void* stream);
 int run_job(int dir, const Call& c, const Geo& g, void* stream);

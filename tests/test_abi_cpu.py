@@ -81,6 +81,7 @@ BAD = [
     (dict(boundary=1), -1), (dict(levels=0), -2), (dict(levels=7), -2), (dict(levels=99), -2),
     (dict(w=1 << 29, ss=1 << 29, ds=1 << 29), -2), (dict(mode=2), -3), (dict(dst=FAKE_A), -5),
     (dict(ws=None), -4), (dict(wsb=100), -4),
+    (dict(src=FAKE_A + 2), -1), (dict(dst=FAKE_B + 6), -1), (dict(ws=FAKE_WS + 1), -1),
 ]
 
 
@@ -119,6 +120,10 @@ def test_batched_validation(lib):
         geo_only[i].src = geo_only[i].dst = None
     assert lib.dwt2_batched_workspace_size(geo_only, 2, 2, 0) == lib.dwt2_batched_workspace_size(ok, 2, 2, 0)
     assert lib.dwt2_batched_workspace_size(_images([(64, 64, 64), (3, 3, 3)]), 2, 3, 0) == 0
+    misaligned = _images([(64, 64, 64), (33, 17, 40)])
+    misaligned[1].dst += 2                                 # image 1: dst not 4-byte aligned
+    assert lib.dwt2_fwd_batched(misaligned, 2, 2, 0, 0, FAKE_WS, 1 << 30, None) == -1
+    assert "image 1" in lib.dwt2_last_error().decode()
     bad = _images([(64, 64, 64), (33, 17, 20)])           # image 1: stride < width
     assert lib.dwt2_fwd_batched(bad, 2, 2, 0, 0, FAKE_WS, 1 << 30, None) == -1
     assert "image 1" in lib.dwt2_last_error().decode()

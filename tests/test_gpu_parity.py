@@ -295,3 +295,34 @@ def test_batched_equals_plain_on_ragged_set():
             for im, o in zip(imgs, outs):
                 assert torch.equal(o, d.fwd(im, 3)), rep
             imgs = [im.clone() for im in imgs]   # fresh pointers for the next replay
+
+
+def test_batched_every_schedule_equals_plain():
+    """Both batched schedules (chained persistent, level-synchronous), each
+    at several level-1 segment heights, reproduce per-image calls bit for
+    bit (float and integer), including replays with new pointers."""
+    import os
+    from paper_1708_07853_amd import _lib
+    d = D()
+    lib = _lib.load()
+    sizes = synth.ragged_sizes(20, 11, 16, 900)
+    saved = {k: os.environ.get(k) for k in ("DWT2_BATCH_SCHEDULE", "DWT2_BATCH_SEG")}
+    try:
+        for dt in (np.float32, np.int32):
+            imgs = [to_gpu(synth.image(w, h, 500 + i, dt)) for i, (w, h) in enumerate(sizes)]
+            refs = [d.fwd(im, 3) for im in imgs]
+            for kind in ("0", "1"):
+                for seg in ("4", "8", "32", "128"):
+                    os.environ["DWT2_BATCH_SCHEDULE"], os.environ["DWT2_BATCH_SEG"] = kind, seg
+                    lib.dwt2_clear_plan_cache()
+                    for rep in range(2):
+                        outs = d.fwd_batched(imgs, 3)
+                        for i, (o, r) in enumerate(zip(outs, refs)):
+                            assert torch.equal(o, r), (dt, kind, seg, rep, i, sizes[i])
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+        lib.dwt2_clear_plan_cache()
