@@ -371,19 +371,28 @@ struct PxLoader {
   int c0;
   int pcol[4];  // EDGE: mirrored column of pixel c0 + k past the edge, else -1
   int hc0, hc1;
-  __device__ __forceinline__ void load(int r, V4<T>& m, T& h0, T& h1) const {
+  // Loads row r: the vector `m`, the EDGE patch values `pm` (applied later
+  // by fix(), when the row is consumed, so that prefetched loads stay in
+  // flight) and the halo pair.
+  __device__ __forceinline__ void load(int r, V4<T>& m, V4<T>& pm, T& h0, T& h1) const {
     const Rsrc rs = row_rsrc(base + (int64_t)fold_idx(r, H) * stride, (int64_t)W * 4);
     bld4<Pol<COH>::ld>(rs, c0, m);
     if constexpr (EDGE) {
-      const T p0 = bld1<T, Pol<COH>::halo>(rs, pcol[0]), p1 = bld1<T, Pol<COH>::halo>(rs, pcol[1]);
-      const T p2 = bld1<T, Pol<COH>::halo>(rs, pcol[2]), p3 = bld1<T, Pol<COH>::halo>(rs, pcol[3]);
-      m.x = pcol[0] >= 0 ? p0 : m.x;
-      m.y = pcol[1] >= 0 ? p1 : m.y;
-      m.z = pcol[2] >= 0 ? p2 : m.z;
-      m.w = pcol[3] >= 0 ? p3 : m.w;
+      pm.x = bld1<T, Pol<COH>::halo>(rs, pcol[0]);
+      pm.y = bld1<T, Pol<COH>::halo>(rs, pcol[1]);
+      pm.z = bld1<T, Pol<COH>::halo>(rs, pcol[2]);
+      pm.w = bld1<T, Pol<COH>::halo>(rs, pcol[3]);
     }
     h0 = bld1<T, Pol<COH>::halo>(rs, hc0);
     h1 = bld1<T, Pol<COH>::halo>(rs, hc1);
+  }
+  __device__ __forceinline__ void fix(V4<T>& m, const V4<T>& pm) const {
+    if constexpr (EDGE) {
+      m.x = pcol[0] >= 0 ? pm.x : m.x;
+      m.y = pcol[1] >= 0 ? pm.y : m.y;
+      m.z = pcol[2] >= 0 ? pm.z : m.z;
+      m.w = pcol[3] >= 0 ? pm.w : m.w;
+    }
   }
 };
 
@@ -409,6 +418,7 @@ __device__ __forceinline__ PxLoader<T, EDGE, COH> px_loader(const T* base, int64
 template <typename T, int CH>
 struct PxBuf {
   V4<T> o[CH], e[CH];
+  V4<T> po[CH], pe[CH];  // edge patches (EDGE items only)
   T ho0[CH], ho1[CH], he0[CH], he1[CH];
 };
 
@@ -457,15 +467,18 @@ __device__ void fwd_f32(const LevelDesc& d, const float* __restrict__ px, float*
   auto load_chunk = [&](Buf& b, int i0) {
 #pragma unroll
     for (int m = 0; m < CH; ++m) {
-      L.load(2 * (i0 + m) + 1, b.o[m], b.ho0[m], b.ho1[m]);
-      L.load(2 * (i0 + m) + 2, b.e[m], b.he0[m], b.he1[m]);
+      L.load(2 * (i0 + m) + 1, b.o[m], b.po[m], b.ho0[m], b.ho1[m]);
+      L.load(2 * (i0 + m) + 2, b.e[m], b.pe[m], b.he0[m], b.he1[m]);
     }
   };
-  V4<float> E, O, E1;
+  V4<float> E, O, E1, pE, pO, pE1;
   float hE0, hE1, hO0, hO1, hN0, hN1;
-  L.load(2 * it.I0 - 2, E, hE0, hE1);
-  L.load(2 * it.I0 - 1, O, hO0, hO1);
-  L.load(2 * it.I0, E1, hN0, hN1);
+  L.load(2 * it.I0 - 2, E, pE, hE0, hE1);
+  L.load(2 * it.I0 - 1, O, pO, hO0, hO1);
+  L.load(2 * it.I0, E1, pE1, hN0, hN1);
+  L.fix(E, pE);
+  L.fix(O, pO);
+  L.fix(E1, pE1);
   Buf A, B;
   load_chunk(A, it.I0);
 
@@ -486,8 +499,9 @@ __device__ void fwd_f32(const LevelDesc& d, const float* __restrict__ px, float*
   float aN = nxt(last, hE0, E.x);
 
   auto row = [&](const Buf& b, int m, int i) {
-    const V4<float>& o = b.o[m];
-    const V4<float>& e1 = b.e[m];
+    V4<float> o = b.o[m], e1 = b.e[m];
+    L.fix(o, b.po[m]);
+    L.fix(e1, b.pe[m]);
     const float aDN = nxt(last, b.he0[m], e1.x);
     const float cN = nxt(last, b.ho0[m], o.x);
     float bpL, cpL, dpL, bpR, cpR, dpR, bpH, cpH, dpH;
@@ -519,15 +533,18 @@ __device__ void fwd_i32(const LevelDesc& d, const int* __restrict__ px, int* __r
   auto load_chunk = [&](Buf& b, int i0) {
 #pragma unroll
     for (int m = 0; m < CH; ++m) {
-      L.load(2 * (i0 + m) + 1, b.o[m], b.ho0[m], b.ho1[m]);
-      L.load(2 * (i0 + m) + 2, b.e[m], b.he0[m], b.he1[m]);
+      L.load(2 * (i0 + m) + 1, b.o[m], b.po[m], b.ho0[m], b.ho1[m]);
+      L.load(2 * (i0 + m) + 2, b.e[m], b.pe[m], b.he0[m], b.he1[m]);
     }
   };
-  V4<int> E, O, E1;
+  V4<int> E, O, E1, pE, pO, pE1;
   int hE0, hE1, hO0, hO1, hN0, hN1;
-  L.load(2 * it.I0 - 2, E, hE0, hE1);
-  L.load(2 * it.I0 - 1, O, hO0, hO1);
-  L.load(2 * it.I0, E1, hN0, hN1);
+  L.load(2 * it.I0 - 2, E, pE, hE0, hE1);
+  L.load(2 * it.I0 - 1, O, pO, hO0, hO1);
+  L.load(2 * it.I0, E1, pE1, hN0, hN1);
+  L.fix(E, pE);
+  L.fix(O, pO);
+  L.fix(E1, pE1);
   Buf A, B;
   load_chunk(A, it.I0);
 
@@ -549,8 +566,9 @@ __device__ void fwd_i32(const LevelDesc& d, const int* __restrict__ px, int* __r
   int aN = nxt(last, hE0, E.x);
 
   auto row = [&](const Buf& b, int m, int i) {
-    const V4<int>& o = b.o[m];
-    const V4<int>& e1 = b.e[m];
+    V4<int> o = b.o[m], e1 = b.e[m];
+    L.fix(o, b.po[m]);
+    L.fix(e1, b.pe[m]);
     const int aDN = nxt(last, b.he0[m], e1.x);
     const int cN = nxt(last, b.ho0[m], o.x);
     int b1L, c1L, d2L, b1R, c1R, d2R, b1H, c1H, d2H;
@@ -599,38 +617,47 @@ struct BandLoader {
   // its two quadruples of a band row with one 8-byte load; EDGE lanes whose
   // quadruples reach the band's end re-read them one by one at the folded
   // (MIRROR) or raw (else: past the end reads 0) columns.
+  // The patch values go to `pt` and are applied by fix() when the row is
+  // consumed, so that prefetched loads stay in flight.  Without MIRROR the
+  // per-dword range check already yields the zeros past a band's end.
   __device__ __forceinline__ void part(const T* rl, const T* rh, bool valid, bool ll_row, T& lL, T& lR, T& hL, T& hR,
-                                       T& h0, T& h1) const {
+                                       V4<T>& pt, T& h0, T& h1) const {
     constexpr int P = Pol<COH>::ld, PH = Pol<COH>::halo, PB = kNT;
     const Rsrc bl = row_rsrc(rl, (MIRROR || valid) ? ns_w * 4 : 0);
     const Rsrc bh = row_rsrc(rh, (MIRROR || valid) ? nd_w * 4 : 0);
     if (ll_row) bld2<P>(bl, qL, lL, lR);
     else bld2<PB>(bl, qL, lL, lR);
     bld2<PB>(bh, qL, hL, hR);
-    if constexpr (EDGE) {
-      const T a0 = bld1<T, PH>(bl, pl0), a1 = bld1<T, PH>(bl, pl1);
-      const T b0 = bld1<T, PH>(bh, ph0), b1 = bld1<T, PH>(bh, ph1);
-      lL = pl0 != kNoPatch ? a0 : lL;
-      lR = pl1 != kNoPatch ? a1 : lR;
-      hL = ph0 != kNoPatch ? b0 : hL;
-      hR = ph1 != kNoPatch ? b1 : hR;
+    if constexpr (EDGE && MIRROR) {
+      pt.x = bld1<T, PH>(bl, pl0);
+      pt.y = bld1<T, PH>(bl, pl1);
+      pt.z = bld1<T, PH>(bh, ph0);
+      pt.w = bld1<T, PH>(bh, ph1);
     }
     h0 = bld1<T, PH>(hp0 ? bh : bl, hc0);
     h1 = bld1<T, PH>(hp1 ? bh : bl, hc1);
   }
+  __device__ __forceinline__ void fix(const V4<T>& pt, T& lL, T& lR, T& hL, T& hR) const {
+    if constexpr (EDGE && MIRROR) {
+      lL = pl0 != kNoPatch ? pt.x : lL;
+      lR = pl1 != kNoPatch ? pt.y : lR;
+      hL = ph0 != kNoPatch ? pt.z : hL;
+      hR = ph1 != kNoPatch ? pt.w : hR;
+    }
+  }
   // row r of LL and HL
-  __device__ __forceinline__ void even(int r, T& lL, T& lR, T& hL, T& hR, T& h0, T& h1) const {
+  __device__ __forceinline__ void even(int r, T& lL, T& lR, T& hL, T& hR, V4<T>& pt, T& h0, T& h1) const {
     const int re = MIRROR ? (fold_idx(2 * r, H) >> 1) : r;
     const T* rl = ll + (int64_t)re * ls;
     const T* rh = band + (int64_t)re * bs + ns_w;
-    part(rl, rh, r >= 0 && r < ns_h, true, lL, lR, hL, hR, h0, h1);
+    part(rl, rh, r >= 0 && r < ns_h, true, lL, lR, hL, hR, pt, h0, h1);
   }
   // row r of LH and HH
-  __device__ __forceinline__ void odd(int r, T& lL, T& lR, T& hL, T& hR, T& h0, T& h1) const {
+  __device__ __forceinline__ void odd(int r, T& lL, T& lR, T& hL, T& hR, V4<T>& pt, T& h0, T& h1) const {
     const int ro = MIRROR ? ((fold_idx(2 * r + 1, H) - 1) >> 1) : r;
     const T* rl = band + (int64_t)(ns_h + ro) * bs;
     const T* rh = rl + ns_w;
-    part(rl, rh, r >= 0 && r < nd_h, false, lL, lR, hL, hR, h0, h1);
+    part(rl, rh, r >= 0 && r < nd_h, false, lL, lR, hL, hR, pt, h0, h1);
   }
 };
 
@@ -668,6 +695,7 @@ template <typename T, int CH>
 struct QBuf {
   T llL[CH], llR[CH], hlL[CH], hlR[CH], he0[CH], he1[CH];
   T lhL[CH], lhR[CH], hhL[CH], hhR[CH], ho0[CH], ho1[CH];
+  V4<T> pe[CH], po[CH];  // edge patches (EDGE items of the inverse only)
 };
 
 // Stores of pixel rows (inverse / adjoint): four pixels per lane, one buffer
@@ -698,15 +726,27 @@ __device__ void inv_f32(const LevelDesc& d, const float* __restrict__ ll, const 
   auto load_chunk = [&](Buf& b, int i0) {
 #pragma unroll
     for (int m = 0; m < CH; ++m) {
-      L.even(i0 + m + 1, b.llL[m], b.llR[m], b.hlL[m], b.hlR[m], b.he0[m], b.he1[m]);
-      L.odd(i0 + m + 1, b.lhL[m], b.lhR[m], b.hhL[m], b.hhR[m], b.ho0[m], b.ho1[m]);
+      L.even(i0 + m + 1, b.llL[m], b.llR[m], b.hlL[m], b.hlR[m], b.pe[m], b.he0[m], b.he1[m]);
+      L.odd(i0 + m + 1, b.lhL[m], b.lhR[m], b.hhL[m], b.hhR[m], b.po[m], b.ho0[m], b.ho1[m]);
     }
   };
   float lhU_L, lhU_R, hhU_L, hhU_R, hoU0, hoU1;
-  L.odd(it.I0 - 1, lhU_L, lhU_R, hhU_L, hhU_R, hoU0, hoU1);
+  {
+    V4<float> pt_;
+    L.odd(it.I0 - 1, lhU_L, lhU_R, hhU_L, hhU_R, pt_, hoU0, hoU1);
+    L.fix(pt_, lhU_L, lhU_R, hhU_L, hhU_R);
+  }
   float q_llL, q_llR, q_hlL, q_hlR, q_he0, q_he1, q_lhL, q_lhR, q_hhL, q_hhR, q_ho0, q_ho1;
-  L.even(it.I0, q_llL, q_llR, q_hlL, q_hlR, q_he0, q_he1);
-  L.odd(it.I0, q_lhL, q_lhR, q_hhL, q_hhR, q_ho0, q_ho1);
+  {
+    V4<float> pt_;
+    L.even(it.I0, q_llL, q_llR, q_hlL, q_hlR, pt_, q_he0, q_he1);
+    L.fix(pt_, q_llL, q_llR, q_hlL, q_hlR);
+  }
+  {
+    V4<float> pt_;
+    L.odd(it.I0, q_lhL, q_lhR, q_hhL, q_hhR, pt_, q_ho0, q_ho1);
+    L.fix(pt_, q_lhL, q_lhR, q_hhL, q_hhR);
+  }
   Buf A, B;
   load_chunk(A, it.I0);
 
@@ -732,9 +772,13 @@ __device__ void inv_f32(const LevelDesc& d, const float* __restrict__ ll, const 
   hh_R = q_hhR;
 
   auto row = [&](const Buf& b, int m, int i) {
+    float r_llL = b.llL[m], r_llR = b.llR[m], r_hlL = b.hlL[m], r_hlR = b.hlR[m];
+    float r_lhL = b.lhL[m], r_lhR = b.lhR[m], r_hhL = b.hhL[m], r_hhR = b.hhR[m];
+    L.fix(b.pe[m], r_llL, r_llR, r_hlL, r_hlR);
+    L.fix(b.po[m], r_lhL, r_lhR, r_hhL, r_hhR);
     float a1_L, a1_R, bp1_L, bp1_R, cp1_L, cp1_R, aN1, cpN1;
-    undo_update(b.llL[m], b.llR[m], b.hlL[m], b.hlR[m], b.he0[m], b.he1[m], b.lhL[m], b.lhR[m], b.hhL[m],
-                b.hhR[m], b.ho0[m], b.ho1[m], a1_L, a1_R, bp1_L, bp1_R, cp1_L, cp1_R, aN1, cpN1);
+    undo_update(r_llL, r_llR, r_hlL, r_hlR, b.he0[m], b.he1[m], r_lhL, r_lhR, r_hhL,
+                r_hhR, b.ho0[m], b.ho1[m], a1_L, a1_R, bp1_L, bp1_R, cp1_L, cp1_R, aN1, cpN1);
     V4<float> e, o;
     e.x = a_L;
     e.z = a_R;
@@ -744,8 +788,8 @@ __device__ void inv_f32(const LevelDesc& d, const float* __restrict__ ll, const 
     S.row(2 * i + 1, o);
     a_L = a1_L; a_R = a1_R; bp_L = bp1_L; bp_R = bp1_R; cp_L = cp1_L; cp_R = cp1_R;
     aN = aN1; cpN = cpN1;
-    hh_L = b.hhL[m];
-    hh_R = b.hhR[m];
+    hh_L = r_hhL;
+    hh_R = r_hhR;
   };
   run_rows<CH>(it.I0, it.I1, A, B, load_chunk, row);
 }
@@ -761,17 +805,29 @@ __device__ void inv_i32(const LevelDesc& d, const int* __restrict__ ll, const in
   auto load_chunk = [&](Buf& b, int i0) {
 #pragma unroll
     for (int m = 0; m < CH; ++m) {
-      L.even(i0 + m + 1, b.llL[m], b.llR[m], b.hlL[m], b.hlR[m], b.he0[m], b.he1[m]);
-      L.odd(i0 + m + 1, b.lhL[m], b.lhR[m], b.hhL[m], b.hhR[m], b.ho0[m], b.ho1[m]);
+      L.even(i0 + m + 1, b.llL[m], b.llR[m], b.hlL[m], b.hlR[m], b.pe[m], b.he0[m], b.he1[m]);
+      L.odd(i0 + m + 1, b.lhL[m], b.lhR[m], b.hhL[m], b.hhR[m], b.po[m], b.ho0[m], b.ho1[m]);
     }
   };
   // state of the previous coefficient row: LH (c2U) and HH (d2U) of L, R;
   // odd halos (lane 0: HH of quad qL-1; lane 63: LH / HH of quad qL+2)
   int lhU_L, lhU_R, hhU_L, hhU_R, hoU0, hoU1;
-  L.odd(it.I0 - 1, lhU_L, lhU_R, hhU_L, hhU_R, hoU0, hoU1);
+  {
+    V4<int> pt_;
+    L.odd(it.I0 - 1, lhU_L, lhU_R, hhU_L, hhU_R, pt_, hoU0, hoU1);
+    L.fix(pt_, lhU_L, lhU_R, hhU_L, hhU_R);
+  }
   int q_llL, q_llR, q_hlL, q_hlR, q_he0, q_he1, q_lhL, q_lhR, q_hhL, q_hhR, q_ho0, q_ho1;
-  L.even(it.I0, q_llL, q_llR, q_hlL, q_hlR, q_he0, q_he1);
-  L.odd(it.I0, q_lhL, q_lhR, q_hhL, q_hhR, q_ho0, q_ho1);
+  {
+    V4<int> pt_;
+    L.even(it.I0, q_llL, q_llR, q_hlL, q_hlR, pt_, q_he0, q_he1);
+    L.fix(pt_, q_llL, q_llR, q_hlL, q_hlR);
+  }
+  {
+    V4<int> pt_;
+    L.odd(it.I0, q_lhL, q_lhR, q_hhL, q_hhR, pt_, q_ho0, q_ho1);
+    L.fix(pt_, q_lhL, q_lhR, q_hhL, q_hhR);
+  }
   Buf A, B;
   load_chunk(A, it.I0);
 
@@ -798,9 +854,13 @@ __device__ void inv_i32(const LevelDesc& d, const int* __restrict__ ll, const in
   int hh_L = hh0_L, hh_R = hh0_R;
 
   auto row = [&](const Buf& b, int m, int i) {
+    int r_llL = b.llL[m], r_llR = b.llR[m], r_hlL = b.hlL[m], r_hlR = b.hlR[m];
+    int r_lhL = b.lhL[m], r_lhR = b.lhR[m], r_hhL = b.hhL[m], r_hhR = b.hhR[m];
+    L.fix(b.pe[m], r_llL, r_llR, r_hlL, r_hlR);
+    L.fix(b.po[m], r_lhL, r_lhR, r_hhL, r_hhR);
     int b1n_L, b1n_R, an_L, an_R, an_X, c1n_L, c1n_R, c1n_X;
-    first_half(b.llL[m], b.llR[m], b.hlL[m], b.hlR[m], b.he0[m], b.he1[m], b.lhL[m], b.lhR[m], b.hhL[m],
-               b.hhR[m], b.ho0[m], b.ho1[m], b1n_L, b1n_R, an_L, an_R, an_X, c1n_L, c1n_R, c1n_X);
+    first_half(r_llL, r_llR, r_hlL, r_hlR, b.he0[m], b.he1[m], r_lhL, r_lhR, r_hhL,
+               r_hhR, b.ho0[m], b.ho1[m], b1n_L, b1n_R, an_L, an_R, an_X, c1n_L, c1n_R, c1n_X);
     const int c_L = i32_inv_c(c1_L, a_L, an_L), c_R = i32_inv_c(c1_R, a_R, an_R);
     const int c_X = i32_inv_c(c1_X, a_X, an_X);
     const int aN = nxt(last, a_X, a_L);
@@ -815,8 +875,8 @@ __device__ void inv_i32(const LevelDesc& d, const int* __restrict__ ll, const in
     S.row(2 * i, e);
     S.row(2 * i + 1, o);
     a_L = an_L; a_R = an_R; a_X = an_X; b1_L = b1n_L; b1_R = b1n_R; c1_L = c1n_L; c1_R = c1n_R; c1_X = c1n_X;
-    hh_L = b.hhL[m];
-    hh_R = b.hhR[m];
+    hh_L = r_hhL;
+    hh_R = r_hhR;
   };
   run_rows<CH>(it.I0, it.I1, A, B, load_chunk, row);
 }
@@ -835,17 +895,33 @@ __device__ void bwd_f32(const LevelDesc& d, const float* __restrict__ ll, const 
   auto load_chunk = [&](Buf& b, int i0) {
 #pragma unroll
     for (int m = 0; m < CH; ++m) {
-      L.even(i0 + m + 1, b.llL[m], b.llR[m], b.hlL[m], b.hlR[m], b.he0[m], b.he1[m]);
-      L.odd(i0 + m + 1, b.lhL[m], b.lhR[m], b.hhL[m], b.hhR[m], b.ho0[m], b.ho1[m]);
+      L.even(i0 + m + 1, b.llL[m], b.llR[m], b.hlL[m], b.hlR[m], b.pe[m], b.he0[m], b.he1[m]);
+      L.odd(i0 + m + 1, b.lhL[m], b.lhR[m], b.hhL[m], b.hhR[m], b.po[m], b.ho0[m], b.ho1[m]);
     }
   };
   // current coefficient row (starts as row I0 - 1)
   float ga_L, ga_R, gb_L, gb_R, ge0, ge1, gc_L, gc_R, gd_L, gd_R, go0, go1;
-  L.even(it.I0 - 1, ga_L, ga_R, gb_L, gb_R, ge0, ge1);
-  L.odd(it.I0 - 1, gc_L, gc_R, gd_L, gd_R, go0, go1);
+  {
+    V4<float> pt_;
+    L.even(it.I0 - 1, ga_L, ga_R, gb_L, gb_R, pt_, ge0, ge1);
+    L.fix(pt_, ga_L, ga_R, gb_L, gb_R);
+  }
+  {
+    V4<float> pt_;
+    L.odd(it.I0 - 1, gc_L, gc_R, gd_L, gd_R, pt_, go0, go1);
+    L.fix(pt_, gc_L, gc_R, gd_L, gd_R);
+  }
   float n_llL, n_llR, n_hlL, n_hlR, n_he0, n_he1, n_lhL, n_lhR, n_hhL, n_hhR, n_ho0, n_ho1;
-  L.even(it.I0, n_llL, n_llR, n_hlL, n_hlR, n_he0, n_he1);
-  L.odd(it.I0, n_lhL, n_lhR, n_hhL, n_hhR, n_ho0, n_ho1);
+  {
+    V4<float> pt_;
+    L.even(it.I0, n_llL, n_llR, n_hlL, n_hlR, pt_, n_he0, n_he1);
+    L.fix(pt_, n_llL, n_llR, n_hlL, n_hlR);
+  }
+  {
+    V4<float> pt_;
+    L.odd(it.I0, n_lhL, n_lhR, n_hhL, n_hhR, pt_, n_ho0, n_ho1);
+    L.fix(pt_, n_lhL, n_lhR, n_hhL, n_hhR);
+  }
   Buf A, B;
   load_chunk(A, it.I0);
 
@@ -871,8 +947,12 @@ __device__ void bwd_f32(const LevelDesc& d, const float* __restrict__ ll, const 
   gc_L = n_lhL; gc_R = n_lhR; gd_L = n_hhL; gd_R = n_hhR; go0 = n_ho0; go1 = n_ho1;
 
   auto row = [&](const Buf& b, int m, int i) {
+    float r_llL = b.llL[m], r_llR = b.llR[m], r_hlL = b.hlL[m], r_hlR = b.hlR[m];
+    float r_lhL = b.lhL[m], r_lhR = b.lhR[m], r_hhL = b.hhL[m], r_hhR = b.hhR[m];
+    L.fix(b.pe[m], r_llL, r_llR, r_hlL, r_hlR);
+    L.fix(b.po[m], r_lhL, r_lhR, r_hhL, r_hhR);
     float gb1_L, gb1_R, gc1_L, gc1_R, gd1_L, gd1_R, gb1H, gd1H;
-    step_a(i, b.llL[m], b.llR[m], b.hlL[m], b.hlR[m], b.he0[m], b.he1[m], gb1_L, gb1_R, gc1_L, gc1_R, gd1_L, gd1_R,
+    step_a(i, r_llL, r_llR, r_hlL, r_hlR, b.he0[m], b.he1[m], gb1_L, gb1_R, gc1_L, gc1_R, gd1_L, gd1_R,
            gb1H, gd1H);
     const float gb1P = prv(first, gb1H, gb1_R);
     const float gd1P = prv(first, gd1H, gd1_R);
@@ -885,8 +965,8 @@ __device__ void bwd_f32(const LevelDesc& d, const float* __restrict__ ll, const 
     S.row(2 * i, e);
     S.row(2 * i + 1, o);
     gc1U_L = gc1_L; gc1U_R = gc1_R; gd1U_L = gd1_L; gd1U_R = gd1_R; gd1UL_L = gd1P;
-    ga_L = b.llL[m]; ga_R = b.llR[m]; gb_L = b.hlL[m]; gb_R = b.hlR[m]; ge0 = b.he0[m]; ge1 = b.he1[m];
-    gc_L = b.lhL[m]; gc_R = b.lhR[m]; gd_L = b.hhL[m]; gd_R = b.hhR[m]; go0 = b.ho0[m]; go1 = b.ho1[m];
+    ga_L = r_llL; ga_R = r_llR; gb_L = r_hlL; gb_R = r_hlR; ge0 = b.he0[m]; ge1 = b.he1[m];
+    gc_L = r_lhL; gc_R = r_lhR; gd_L = r_hhL; gd_R = r_hhR; go0 = b.ho0[m]; go1 = b.ho1[m];
   };
   run_rows<CH>(it.I0, it.I1, A, B, load_chunk, row);
 }
