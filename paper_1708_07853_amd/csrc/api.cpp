@@ -175,6 +175,11 @@ static void level_launch(int dir, const Call& c, const Geo& g, int k, int64_t sl
     a.d.band_stride = c.src_stride;
     a.band_bstride = c.src_bs;
   }
+  // the LL output feeds the next level's launch (forward: LL_k, k < L;
+  // inverse / adjoint: LL_{k-1}, k > 1) and fits the caches
+  const int ko = dir == kFwd ? k : k - 1;
+  const bool feeds = dir == kFwd ? (k < g.L) : (k > 1);
+  a.d.keep_out = feeds && (int64_t)g.w[ko] * g.h[ko] * 4 * c.batch <= kKeepBytes;
   a.items_per_image = a.d.nstrips * a.d.nsegs;
   a.items = (int64_t)a.items_per_image * c.batch;
 }

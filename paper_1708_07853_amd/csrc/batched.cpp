@@ -114,6 +114,7 @@ struct Plan {
   std::vector<uint32_t> item_desc;
   std::vector<int> desc_seg;    // segment height per desc
   std::vector<int32_t> step_begin;   // first item of each level, plus the total
+  std::vector<int64_t> step_ll_bytes;  // LL output bytes of each level over all images
   // device side
   char* ws = nullptr;
   void* staging = nullptr;      // pinned: descs then items
@@ -186,6 +187,7 @@ void build_schedule(Plan& p, int policy) {
   p.ndesc = p.n * p.levels;
   p.desc_seg.assign(p.ndesc, 0);
   p.step_begin.assign(p.levels + 1, 0);
+  p.step_ll_bytes.assign(p.levels, 0);
   p.item_desc.clear();
   p.counters = 0;
   for (int t = 0; t < p.levels; ++t) {
@@ -202,6 +204,7 @@ void build_schedule(Plan& p, int policy) {
       const int items = nsegs * num_strips(g.w[k - 1]);
       p.item_desc.insert(p.item_desc.end(), items, (uint32_t)j);
       p.counters += nsegs;
+      p.step_ll_bytes[t] += (int64_t)g.w[k] * g.h[k] * 4;
     }
   }
   p.total_items = (int32_t)p.item_desc.size();
@@ -238,6 +241,7 @@ void fill_descs(Plan& p, const dwt2_image_t* images, JobDesc* out) {
       jd.cbase = cbase;
       jd.prev = t > 0 ? (t - 1) * p.n + oi : -1;
       jd.coh = p.kind == kChained ? ((t > 0 ? 1 : 0) | (t + 1 < p.levels ? 2 : 0)) : 0;
+      d.keep_out = p.kind == kLevelSync && t + 1 < p.levels && p.step_ll_bytes[t] <= kKeepBytes;
       start += jd.items;
       cbase += d.nsegs;
     }

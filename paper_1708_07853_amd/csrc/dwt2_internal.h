@@ -40,7 +40,7 @@ struct LevelDesc {
   int32_t seg;          // quadruple rows per work item
   int32_t nstrips;
   int32_t nsegs;
-  int32_t pad_;
+  int32_t keep_out;     // a later launch reads this level's LL output (cache it)
 };
 
 // Plain (uniform-geometry) launch of one level over a batch of images.
@@ -80,6 +80,10 @@ struct JobDesc {
   int32_t coh;    // bit 0: input LL rows come from step `prev`; bit 1: a later step reads the LL output
   int32_t pad_[2];
 };
+
+// Largest intermediate LL (bytes over a launch) stored with the caching
+// policy: half of MI355X's 256 MB Infinity Cache.
+constexpr int64_t kKeepBytes = 128ll << 20;
 
 constexpr int kInlineDescs = 20;
 constexpr int kSyncError = 1;     // set when a dependency wait gives up

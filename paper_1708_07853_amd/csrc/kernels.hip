@@ -119,10 +119,10 @@ __device__ __forceinline__ T from_bits(unsigned u) {
 // policy (kNT); halo values, which neighbouring lanes and strips read again,
 // use the default policy.
 constexpr int kNT = 2;
-// Cache-policy bits: sc0 = 1, nt = 2, sc1 = 16.  Inside a persistent job the
-// LL rows one item writes are read by items on other XCDs, whose L2s are not
-// coherent with the writer's; those accesses carry sc1 (stores write through,
-// loads miss stale L2 lines) and sc0 (loads skip the CU's L1), so no
+// Cache-policy bits: sc0 = 1, nt = 2, sc1 = 16.  Inside a persistent job
+// the LL rows one item writes are read by items on other XCDs, whose L2s are
+// not coherent with the writer's; those accesses carry sc1 (stores write
+// through, loads miss stale L2 lines) and sc0 (loads skip the CU's L1), so no
 // whole-cache writeback or invalidation is needed between items.
 constexpr int kSC0 = 1, kSC1 = 16;
 #ifndef DWT2_COH_LD
@@ -134,11 +134,20 @@ constexpr int kSC0 = 1, kSC1 = 16;
 #ifndef DWT2_COH_ST
 #define DWT2_COH_ST (kNT | kSC1)
 #endif
-template <bool COH>
+// Access modes of the LL rows a level reads or writes:
+//   kStream: final results and job inputs (non-temporal: they are touched
+//            once, and keeping them would evict data still to be read);
+//   kKeep:   an intermediate LL the next level's launch reads (default
+//            policy, so that it can be served from the caches);
+//   kCoh:    an LL shared between items of one persistent job (above).
+// Measured on MI355X, keeping only the intermediate LL rows beats both
+// streaming everything and keeping every output.
+constexpr int kStream = 0, kKeep = 1, kCoh = 2;
+template <int M>
 struct Pol {
-  static constexpr int ld = COH ? (DWT2_COH_LD) : kNT;    // main streams
-  static constexpr int halo = COH ? (DWT2_COH_HALO) : 0;  // re-read halo values
-  static constexpr int st = COH ? (DWT2_COH_ST) : kNT;
+  static constexpr int ld = M == kCoh ? (DWT2_COH_LD) : kNT;    // main streams
+  static constexpr int halo = M == kCoh ? (DWT2_COH_HALO) : 0;  // re-read halo values
+  static constexpr int st = M == kCoh ? (DWT2_COH_ST) : (M == kKeep ? 0 : kNT);
 };
 template <int POL, typename T>
 __device__ __forceinline__ void bst2(T a, T b, Rsrc r, int e) {
@@ -363,7 +372,7 @@ __device__ __forceinline__ void run_rows(int I0, int I1, Buf& A, Buf& B, LoadF&&
 // reaches the image's right edge; lanes whose pixels lie past it take the
 // mirrored columns from single-element loads (the other lanes pass an
 // out-of-range offset, which issues no request) and a select.
-template <typename T, bool EDGE, bool COH>  // COH: rows written earlier in the same job
+template <typename T, bool EDGE, int COH>  // COH: access mode of the rows (kStream or kCoh)
 struct PxLoader {
   const T* base;
   int64_t stride;
@@ -396,7 +405,7 @@ struct PxLoader {
   }
 };
 
-template <typename T, bool EDGE, bool COH>
+template <typename T, bool EDGE, int COH>
 __device__ __forceinline__ PxLoader<T, EDGE, COH> px_loader(const T* base, int64_t stride, const Item& it) {
   PxLoader<T, EDGE, COH> L;
   L.base = base; L.stride = stride; L.W = it.W; L.H = it.H;
@@ -426,7 +435,7 @@ struct PxBuf {
 // row; rows past I1 (and LH / HH rows past nd_h) have size 0.  Each lane
 // writes its two quadruples with one 8-byte store at any 4-byte alignment;
 // the range check drops every dword past the band's width on its own.
-template <typename T, bool EDGE, bool COH>
+template <typename T, bool EDGE, int COH>  // COH: mode of the LL rows
 struct BandStore {
   T* ll;
   int64_t ls;
@@ -449,7 +458,7 @@ struct BandStore {
   }
 };
 
-template <typename T, bool EDGE, bool COH>
+template <typename T, bool EDGE, int COH>
 __device__ __forceinline__ BandStore<T, EDGE, COH> band_store(T* ll, int64_t ls, T* band, int64_t bs, const Item& it) {
   BandStore<T, EDGE, COH> S;
   S.ll = ll; S.ls = ls; S.band = band; S.bs = bs;
@@ -457,7 +466,7 @@ __device__ __forceinline__ BandStore<T, EDGE, COH> band_store(T* ll, int64_t ls,
   return S;
 }
 
-template <int CH, bool EDGE, bool CI, bool CO>
+template <int CH, bool EDGE, int CI, int CO>
 __device__ void fwd_f32(const LevelDesc& d, const float* __restrict__ px, float* __restrict__ ll,
                         float* __restrict__ band, const Item& it) {
   const PxLoader<float, EDGE, CI> L = px_loader<float, EDGE, CI>(px, d.pix_stride, it);
@@ -523,7 +532,7 @@ __device__ void fwd_f32(const LevelDesc& d, const float* __restrict__ px, float*
   run_rows<CH>(it.I0, it.I1, A, B, load_chunk, row);
 }
 
-template <int CH, bool EDGE, bool CI, bool CO>
+template <int CH, bool EDGE, int CI, int CO>
 __device__ void fwd_i32(const LevelDesc& d, const int* __restrict__ px, int* __restrict__ ll,
                         int* __restrict__ band, const Item& it) {
   const PxLoader<int, EDGE, CI> L = px_loader<int, EDGE, CI>(px, d.pix_stride, it);
@@ -601,7 +610,7 @@ __device__ void fwd_i32(const LevelDesc& d, const int* __restrict__ px, int* __r
 // buffer's range, so its single-element load issues no request.
 constexpr int kNoPatch = -1;
 
-template <typename T, bool EDGE, bool MIRROR, bool COH>
+template <typename T, bool EDGE, bool MIRROR, int COH>  // COH: mode of the LL rows
 struct BandLoader {
   const T* ll;
   int64_t ls;
@@ -663,7 +672,7 @@ struct BandLoader {
 
 // Halo assignment: (parity, quadruple column) of the two halo values of
 // lanes 0 and 63; the other lanes issue out-of-range loads (no memory request).
-template <typename T, bool EDGE, bool MIRROR, bool COH>
+template <typename T, bool EDGE, bool MIRROR, int COH>
 __device__ __forceinline__ BandLoader<T, EDGE, MIRROR, COH> band_loader(const T* ll, int64_t ls, const T* band,
                                                                         int64_t bs, const Item& it, int p0_first,
                                                                         int p1_first, int p0_last, int p1_last) {
@@ -700,7 +709,7 @@ struct QBuf {
 
 // Stores of pixel rows (inverse / adjoint): four pixels per lane, one buffer
 // resource per row (size 0 for rows past I1's last pixel row or past H).
-template <typename T, bool EDGE, bool COH>
+template <typename T, bool EDGE, int COH>  // COH: mode of the pixel rows
 struct PxStore {
   T* base;
   int64_t stride;
@@ -713,7 +722,7 @@ struct PxStore {
   }
 };
 
-template <int CH, bool EDGE, bool CI, bool CO>
+template <int CH, bool EDGE, int CI, int CO>
 __device__ void inv_f32(const LevelDesc& d, const float* __restrict__ ll, const float* __restrict__ band,
                         float* __restrict__ px, const Item& it) {
   // halos: lane 0 -> HL / HH of quad qL-1 (parity 1); lane 63 -> quad qL+2:
@@ -794,7 +803,7 @@ __device__ void inv_f32(const LevelDesc& d, const float* __restrict__ ll, const 
   run_rows<CH>(it.I0, it.I1, A, B, load_chunk, row);
 }
 
-template <int CH, bool EDGE, bool CI, bool CO>
+template <int CH, bool EDGE, int CI, int CO>
 __device__ void inv_i32(const LevelDesc& d, const int* __restrict__ ll, const int* __restrict__ band,
                         int* __restrict__ px, const Item& it) {
   const BandLoader<int, EDGE, true, CI> L =
@@ -881,7 +890,7 @@ __device__ void inv_i32(const LevelDesc& d, const int* __restrict__ ll, const in
   run_rows<CH>(it.I0, it.I1, A, B, load_chunk, row);
 }
 
-template <int CH, bool EDGE, bool CI, bool CO>
+template <int CH, bool EDGE, int CI, int CO>
 __device__ void bwd_f32(const LevelDesc& d, const float* __restrict__ ll, const float* __restrict__ band,
                         float* __restrict__ px, const Item& it) {
   // halos: lane 0 -> quad qL-1: h0 = LL / LH (parity 0), h1 = HL / HH (parity 1);
@@ -991,7 +1000,7 @@ __device__ __forceinline__ bool edge_item(const Item& it, int strip) { return kS
 // One work item: (image pointers already offset, strip, segment), with the
 // LL input rows coherent (CI: written earlier in the same job) and the LL
 // output rows coherent (CO: read later in the same job).
-template <int DIR, typename T, int CH, bool CI, bool CO>
+template <int DIR, typename T, int CH, int CI, int CO>
 __device__ __forceinline__ void run_item_p(const LevelDesc& d, int64_t pix_off, int64_t ll_off, int64_t band_off,
                                            int strip, int seg, int lane) {
   const Item it = make_item(d, strip, seg, lane);
@@ -1026,18 +1035,22 @@ __device__ __forceinline__ void run_item_p(const LevelDesc& d, int64_t pix_off, 
   }
 }
 
-// `coh` bit 0: CI, bit 1: CO (persistent job steps); level launches use 0.
+// Level launches: the level's LL output is kept (kKeep) when a later launch
+// reads it (d.keep_out), else streamed.  Persistent job steps: `coh` bit 0
+// marks LL input rows written earlier in the job, bit 1 LL output rows read
+// later in it (both kCoh).
 template <int DIR, typename T, int CH, bool JOB>
 __device__ __forceinline__ void run_item(const LevelDesc& d, int coh, int64_t pix_off, int64_t ll_off,
                                          int64_t band_off, int strip, int seg, int lane) {
   if constexpr (!JOB) {
-    run_item_p<DIR, T, CH, false, false>(d, pix_off, ll_off, band_off, strip, seg, lane);
+    if (d.keep_out) run_item_p<DIR, T, CH, kStream, kKeep>(d, pix_off, ll_off, band_off, strip, seg, lane);
+    else run_item_p<DIR, T, CH, kStream, kStream>(d, pix_off, ll_off, band_off, strip, seg, lane);
   } else {
     switch (coh & 3) {
-      case 0: run_item_p<DIR, T, CH, false, false>(d, pix_off, ll_off, band_off, strip, seg, lane); break;
-      case 1: run_item_p<DIR, T, CH, true, false>(d, pix_off, ll_off, band_off, strip, seg, lane); break;
-      case 2: run_item_p<DIR, T, CH, false, true>(d, pix_off, ll_off, band_off, strip, seg, lane); break;
-      default: run_item_p<DIR, T, CH, true, true>(d, pix_off, ll_off, band_off, strip, seg, lane); break;
+      case 0: run_item_p<DIR, T, CH, kStream, kStream>(d, pix_off, ll_off, band_off, strip, seg, lane); break;
+      case 1: run_item_p<DIR, T, CH, kCoh, kStream>(d, pix_off, ll_off, band_off, strip, seg, lane); break;
+      case 2: run_item_p<DIR, T, CH, kStream, kCoh>(d, pix_off, ll_off, band_off, strip, seg, lane); break;
+      default: run_item_p<DIR, T, CH, kCoh, kCoh>(d, pix_off, ll_off, band_off, strip, seg, lane); break;
     }
   }
 }
