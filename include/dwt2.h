@@ -126,6 +126,27 @@ int dwt2_bwd(const void* src, int64_t src_stride, int64_t src_batch_stride,
              int32_t mode, int32_t boundary, void* workspace,
              size_t workspace_bytes, void* stream);
 
+/* Baseline for comparison, not the product path: the same forward
+ * transform computed with the separable lifting scheme of §2, eq. (3), that
+ * the non-separable scheme of §3, eq. (5), regroups.  Every lifting step of
+ * a level (horizontal predict, vertical predict, horizontal update, vertical
+ * update, in that order) is its own kernel launch and its own pass over the
+ * level in HBM, the last one writing the Mallat layout.  Arguments, layout,
+ * ownership and errors are those of dwt2_fwd, except that the workspace
+ * must hold dwt2_separable_workspace_size bytes (it adds one work array of
+ * the image's size per image).  Integer results are identical to
+ * dwt2_fwd's; float results agree up to rounding, since eq. (5) regroups the
+ * same arithmetic. */
+size_t dwt2_separable_workspace_size(int32_t width, int32_t height,
+                                     int32_t batch, int32_t levels,
+                                     int32_t mode);
+int dwt2_fwd_separable(const void* src, int64_t src_stride,
+                       int64_t src_batch_stride, void* dst, int64_t dst_stride,
+                       int64_t dst_batch_stride, int32_t width, int32_t height,
+                       int32_t batch, int32_t levels, int32_t mode,
+                       int32_t boundary, void* workspace,
+                       size_t workspace_bytes, void* stream);
+
 /* One image of a ragged batch (all pointers device pointers). */
 typedef struct {
   const void* src;

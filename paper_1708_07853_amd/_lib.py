@@ -25,7 +25,7 @@ EXPORTS = [
     "dwt2_workspace_size", "dwt2_fwd", "dwt2_inv", "dwt2_bwd",
     "dwt2_batched_workspace_size", "dwt2_fwd_batched",
     "dwt2_status_string", "dwt2_last_error", "dwt2_clear_plan_cache", "dwt2_set_tiling", "dwt2_set_path",
-    "dwt2_set_probe",
+    "dwt2_set_probe", "dwt2_separable_workspace_size", "dwt2_fwd_separable",
 ]
 
 
@@ -64,7 +64,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     i32, i64, vp, sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p, ctypes.c_size_t
     lib.dwt2_workspace_size.argtypes = [i32, i32, i32, i32, i32]
     lib.dwt2_workspace_size.restype = sz
-    for name in ("dwt2_fwd", "dwt2_inv", "dwt2_bwd"):
+    lib.dwt2_separable_workspace_size.argtypes = [i32, i32, i32, i32, i32]
+    lib.dwt2_separable_workspace_size.restype = sz
+    for name in ("dwt2_fwd", "dwt2_inv", "dwt2_bwd", "dwt2_fwd_separable"):
         fn = getattr(lib, name)
         fn.argtypes = [vp, i64, i64, vp, i64, i64, i32, i32, i32, i32, i32, i32, vp, sz, vp]
         fn.restype = ctypes.c_int

@@ -94,6 +94,17 @@ def _stream() -> int:
     return torch.cuda.current_stream().cuda_stream
 
 
+def fwd_separable(x: torch.Tensor, levels: int, mode=None, out=None, workspace=None) -> torch.Tensor:
+    """The same forward transform by the separable lifting baseline (one
+    kernel launch and one HBM pass per lifting step; see dwt2_fwd_separable).
+    For comparisons, not for production use."""
+    return _run("dwt2_fwd_separable", x, levels, mode, out, workspace)
+
+
+def separable_workspace_size(w: int, h: int, levels: int, batch: int = 1, mode: int = DWT2_F32) -> int:
+    return int(_lib.load().dwt2_separable_workspace_size(w, h, batch, levels, mode))
+
+
 def _run(name: str, x: torch.Tensor, levels: int, mode, out: torch.Tensor | None,
          workspace: torch.Tensor | None = None) -> torch.Tensor:
     lib = _lib.load()
@@ -107,7 +118,8 @@ def _run(name: str, x: torch.Tensor, levels: int, mode, out: torch.Tensor | None
         raise ValueError("out must match the input's shape and dtype")
     if ob.data_ptr() != out.data_ptr() or (out.dim() > 2 and not out.is_contiguous()):
         raise ValueError("out must be a contiguous tensor")
-    nbytes = int(lib.dwt2_workspace_size(w, h, batch, levels, mode))
+    size_fn = lib.dwt2_separable_workspace_size if name == "dwt2_fwd_separable" else lib.dwt2_workspace_size
+    nbytes = int(size_fn(w, h, batch, levels, mode))
     ws = None
     if nbytes:
         if workspace is not None and workspace.numel() * workspace.element_size() >= nbytes:

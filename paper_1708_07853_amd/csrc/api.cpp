@@ -279,9 +279,54 @@ int run_job(int dir, const Call& c, const Geo& g, void* stream) {
   return DWT2_OK;
 }
 
+// Separable baseline: the plain workspace followed by one work array per
+// image (the level-1 input's size, rows padded like the LL buffers).
+static size_t sep_work_per_image(const Geo& g) { return round256((size_t)ll_pitch(g.w[0]) * g.h[0] * 4); }
+
+static int run_separable(const Call& c, const Geo& g, void* stream) {
+  const size_t work_base = c.ll_base + ws_per_image(g) * (size_t)c.batch;
+  const int64_t ws_bs = (int64_t)(ws_per_image(g) / 4);
+  for (int k = 1; k <= g.L; ++k) {
+    SepLevel a;
+    memset(&a, 0, sizeof a);
+    a.W = g.w[k - 1];
+    a.H = g.h[k - 1];
+    a.batch = c.batch;
+    if (k == 1) {
+      a.src = c.src;
+      a.src_stride = c.src_stride;
+      a.src_bstride = c.src_bs;
+    } else {
+      a.src = ll_buf(c, g, k - 1);
+      a.src_stride = ll_pitch(g.w[k - 1]);
+      a.src_bstride = ws_bs;
+    }
+    a.work = c.ws + work_base;
+    a.work_pitch = ll_pitch(g.w[0]);
+    a.work_bstride = (int64_t)(sep_work_per_image(g) / 4);
+    if (k == g.L) {
+      a.ll = c.dst;
+      a.ll_stride = c.dst_stride;
+      a.ll_bstride = c.dst_bs;
+    } else {
+      a.ll = ll_buf(c, g, k);
+      a.ll_stride = ll_pitch(g.w[k]);
+      a.ll_bstride = ws_bs;
+    }
+    a.band = c.dst;
+    a.band_stride = c.dst_stride;
+    a.band_bstride = c.dst_bs;
+    const int err = launch_separable_level(c.mode, a, stream);
+    if (err != hipSuccess)
+      return fail(DWT2_ERR_HIP, "separable level %d launch failed: %s", k, hipGetErrorString((hipError_t)err));
+  }
+  return DWT2_OK;
+}
+
 static int transform(int dir, const void* src, int64_t src_stride, int64_t src_bs, void* dst, int64_t dst_stride,
                      int64_t dst_bs, int32_t width, int32_t height, int32_t batch, int32_t levels, int32_t mode,
-                     int32_t boundary, void* workspace, size_t workspace_bytes, void* stream) {
+                     int32_t boundary, void* workspace, size_t workspace_bytes, void* stream,
+                     bool separable = false) {
   clear_error();
   if (!src || !dst) return fail(DWT2_ERR_ARG, "null src or dst");
   if (((uintptr_t)src | (uintptr_t)dst | (uintptr_t)workspace) & 3)
@@ -299,11 +344,13 @@ static int transform(int dir, const void* src, int64_t src_stride, int64_t src_b
   if (mode != DWT2_F32 && mode != DWT2_I32_REV) return fail(DWT2_ERR_MODE, "unknown mode %d", mode);
   if (dir == kBwd && mode != DWT2_F32) return fail(DWT2_ERR_MODE, "the adjoint exists for DWT2_F32 only");
   if (src == dst) return fail(DWT2_ERR_ALIAS, "src and dst are the same buffer; the transform is out of place");
-  const size_t need = sync_bytes(g, batch) + ws_per_image(g) * (size_t)batch;
+  const size_t need =
+      sync_bytes(g, batch) + (ws_per_image(g) + (separable ? sep_work_per_image(g) : 0)) * (size_t)batch;
   if (!workspace || workspace_bytes < need)
     return fail(DWT2_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, workspace ? workspace_bytes : 0);
   Call c{static_cast<const char*>(src), src_stride, src_bs, static_cast<char*>(dst), dst_stride, dst_bs, batch, mode,
          static_cast<char*>(workspace), sync_bytes(g, batch)};
+  if (separable) return run_separable(c, g, stream);
   if (g_persistent.load() < 0) g_persistent.store(env_int("DWT2_PERSISTENT") == 1 ? 1 : 0);
   if (g_persistent.load() && g.L <= kInlineDescs) return run_job(dir, c, g, stream);
   return run_levels(dir, c, g, stream);
@@ -320,6 +367,20 @@ size_t dwt2_workspace_size(int32_t width, int32_t height, int32_t batch, int32_t
   if (batch < 1 || (mode != DWT2_F32 && mode != DWT2_I32_REV)) return 0;
   if (check_geometry(width, height, levels, g) != DWT2_OK) return 0;
   return sync_bytes(g, batch) + ws_per_image(g) * (size_t)batch;
+}
+
+size_t dwt2_separable_workspace_size(int32_t width, int32_t height, int32_t batch, int32_t levels, int32_t mode) {
+  Geo g;
+  if (batch < 1 || (mode != DWT2_F32 && mode != DWT2_I32_REV)) return 0;
+  if (check_geometry(width, height, levels, g) != DWT2_OK) return 0;
+  return sync_bytes(g, batch) + (ws_per_image(g) + sep_work_per_image(g)) * (size_t)batch;
+}
+
+int dwt2_fwd_separable(const void* src, int64_t src_stride, int64_t src_batch_stride, void* dst, int64_t dst_stride,
+                       int64_t dst_batch_stride, int32_t width, int32_t height, int32_t batch, int32_t levels,
+                       int32_t mode, int32_t boundary, void* workspace, size_t workspace_bytes, void* stream) {
+  return transform(kFwd, src, src_stride, src_batch_stride, dst, dst_stride, dst_batch_stride, width, height, batch,
+                   levels, mode, boundary, workspace, workspace_bytes, stream, true);
 }
 
 int dwt2_fwd(const void* src, int64_t src_stride, int64_t src_batch_stride, void* dst, int64_t dst_stride,

@@ -109,6 +109,21 @@ struct TableArgs {
   int32_t items;
 };
 
+// One level of the separable baseline (separable.hip): the level input, a
+// work array of the level's size, and the LL / band destinations.
+struct SepLevel {
+  const void* src;
+  int64_t src_stride, src_bstride;
+  void* work;
+  int64_t work_pitch, work_bstride;
+  void* ll;
+  int64_t ll_stride, ll_bstride;
+  void* band;
+  int64_t band_stride, band_bstride;
+  int32_t W, H, batch, pad_;
+};
+int launch_separable_level(int mode, const SepLevel& a, void* stream);
+
 // Kernel launchers (kernels.hip).  Return hipError_t as int.
 int launch_level(int dir, int mode, int chunk, const LevelLaunch& a, void* stream);
 int job_blocks_per_cu(int dir, int mode, int chunk);

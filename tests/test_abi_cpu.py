@@ -67,6 +67,16 @@ def test_workspace_sizes(lib):
     assert lib.dwt2_workspace_size(4, 4, 1, 2, 5) == 0               # invalid mode
 
 
+def test_separable_workspace_adds_one_work_array_per_image(lib):
+    for (w, h, b, L, m) in [(512, 512, 1, 3, 0), (101, 40, 2, 2, 1), (4096, 64, 3, 1, 0)]:
+        work = ((w + 63) // 64 * 64 * h * 4 + 255) // 256 * 256
+        assert lib.dwt2_separable_workspace_size(w, h, b, L, m) == lib.dwt2_workspace_size(w, h, b, L, m) + b * work
+    assert lib.dwt2_separable_workspace_size(4, 4, 1, 3, 0) == 0
+    # the plain transform's workspace is too small for the separable baseline
+    need = lib.dwt2_separable_workspace_size(64, 64, 1, 2, 0)
+    assert call(lib, "dwt2_fwd_separable", wsb=need - 1) == -4
+
+
 def call(lib, fn, **kw):
     a = dict(src=FAKE_A, ss=64, sb=0, dst=FAKE_B, ds=64, db=0, w=64, h=64, batch=1, levels=2,
              mode=0, boundary=0, ws=FAKE_WS, wsb=1 << 30, stream=None)
@@ -85,7 +95,7 @@ BAD = [
 ]
 
 
-@pytest.mark.parametrize("fn", ["dwt2_fwd", "dwt2_inv", "dwt2_bwd"])
+@pytest.mark.parametrize("fn", ["dwt2_fwd", "dwt2_inv", "dwt2_bwd", "dwt2_fwd_separable"])
 @pytest.mark.parametrize("kw,code", BAD, ids=[str(b[0]) for b in BAD])
 def test_validation_errors(lib, fn, kw, code):
     assert call(lib, fn, **kw) == code
