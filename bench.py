@@ -278,7 +278,23 @@ def main():
             "batched_GBps_alg": round(sum(alg_bytes(w, h, 3) for w, h in sizes) / (np.median(tb) * 1e-3) / 1e9, 1),
             "batched_over_plain": round(float(np.median(tp) / np.median(tb)), 3),
             "first_call_s": round(t_build, 3), "Gpx": round(gpx / 1e9, 3)}
-        del imgs, outs, wss, bws
+        # batched inverse and adjoint on the same set (coefficients from above)
+        recs = [torch.empty_like(t) for t in imgs]
+
+        def plain_inv():
+            for o, r, w_ in zip(outs, recs, wss):
+                dwt.inv(o, 3, out=r, workspace=w_)
+
+        dwt.inv_batched(outs, 3, outs=recs, workspace=bws)
+        dwt.bwd_batched(outs, 3, outs=recs, workspace=bws)
+        plain_inv()
+        tpi = timer(plain_inv, 10)
+        tbi = timer(lambda: dwt.inv_batched(outs, 3, outs=recs, workspace=bws), 10)
+        tbb = timer(lambda: dwt.bwd_batched(outs, 3, outs=recs, workspace=bws), 10)
+        detail["ragged_256_L3"].update({
+            "inv_plain_ms": round(float(np.median(tpi)), 3), "inv_batched_ms": round(float(np.median(tbi)), 3),
+            "adj_batched_ms": round(float(np.median(tbb)), 3)})
+        del imgs, outs, wss, bws, recs
         # autograd: 32 x 3 x 1024^2, 4 levels, forward + loss + backward
         xb = torch.stack([synth.image_device(1024, 1024, 5000 + k, device=dev) for k in range(96)]).reshape(32, 3, 1024, 1024)
         xb.requires_grad_()

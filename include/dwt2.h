@@ -184,6 +184,19 @@ int dwt2_fwd_batched(const dwt2_image_t* images, int32_t n, int32_t levels,
                      int32_t mode, int32_t boundary, void* workspace,
                      size_t workspace_bytes, void* stream);
 
+/* Inverse (dwt2_inv per image: src = packed coefficients, dst = image) and
+ * adjoint (dwt2_bwd per image, DWT2_F32 only: src = coefficient gradient,
+ * dst = image gradient) of a ragged set, with the plans, schedules, tuning,
+ * workspace (dwt2_batched_workspace_size) and rules of dwt2_fwd_batched;
+ * levels run coarsest first.  Results are bit-identical to the per-image
+ * calls.  dwt2_bwd_batched returns DWT2_ERR_MODE for integer mode. */
+int dwt2_inv_batched(const dwt2_image_t* images, int32_t n, int32_t levels,
+                     int32_t mode, int32_t boundary, void* workspace,
+                     size_t workspace_bytes, void* stream);
+int dwt2_bwd_batched(const dwt2_image_t* images, int32_t n, int32_t levels,
+                     int32_t mode, int32_t boundary, void* workspace,
+                     size_t workspace_bytes, void* stream);
+
 /* Process-wide tiling override, for tuning sweeps and tests: seg = quadruple
  * rows per work item (0 = automatic), chunk = quadruple rows per prefetch
  * chunk (1, 2 or 4; 0 = automatic).  Results are bit-identical for every

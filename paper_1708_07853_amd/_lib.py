@@ -23,7 +23,7 @@ STATUS = {
 # Every symbol that include/dwt2.h declares.
 EXPORTS = [
     "dwt2_workspace_size", "dwt2_fwd", "dwt2_inv", "dwt2_bwd",
-    "dwt2_batched_workspace_size", "dwt2_fwd_batched",
+    "dwt2_batched_workspace_size", "dwt2_fwd_batched", "dwt2_inv_batched", "dwt2_bwd_batched",
     "dwt2_status_string", "dwt2_last_error", "dwt2_clear_plan_cache", "dwt2_set_tiling", "dwt2_set_path",
     "dwt2_set_probe", "dwt2_separable_workspace_size", "dwt2_fwd_separable",
 ]
@@ -72,8 +72,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         fn.restype = ctypes.c_int
     lib.dwt2_batched_workspace_size.argtypes = [ctypes.POINTER(Dwt2Image), i32, i32, i32]
     lib.dwt2_batched_workspace_size.restype = sz
-    lib.dwt2_fwd_batched.argtypes = [ctypes.POINTER(Dwt2Image), i32, i32, i32, i32, vp, sz, vp]
-    lib.dwt2_fwd_batched.restype = ctypes.c_int
+    for name in ("dwt2_fwd_batched", "dwt2_inv_batched", "dwt2_bwd_batched"):
+        fn = getattr(lib, name)
+        fn.argtypes = [ctypes.POINTER(Dwt2Image), i32, i32, i32, i32, vp, sz, vp]
+        fn.restype = ctypes.c_int
     lib.dwt2_status_string.argtypes = [ctypes.c_int]
     lib.dwt2_status_string.restype = ctypes.c_char_p
     lib.dwt2_last_error.argtypes = []

@@ -173,12 +173,7 @@ def batched_workspace_size(images: Sequence[torch.Tensor], levels: int, mode=Non
     return int(_lib.load().dwt2_batched_workspace_size(arr, len(images), levels, mode))
 
 
-def fwd_batched(images: Sequence[torch.Tensor], levels: int, mode=None,
-                outs: Sequence[torch.Tensor] | None = None,
-                workspace: torch.Tensor | None = None) -> List[torch.Tensor]:
-    """Forward transform of a ragged list of 2-D images in one persistent
-    launch (see dwt2_fwd_batched).  Plans are cached per image geometry and
-    workspace address: pass the same `workspace` on repeated calls."""
+def _batched(name: str, images: Sequence[torch.Tensor], levels: int, mode, outs, workspace) -> List[torch.Tensor]:
     lib = _lib.load()
     if not images:
         return []
@@ -199,9 +194,33 @@ def fwd_batched(images: Sequence[torch.Tensor], levels: int, mode=None,
             raise ValueError(f"workspace must be a tensor of at least {nbytes} bytes on {images[0].device}")
         ws = workspace
     with torch.cuda.device(images[0].device):
-        status = lib.dwt2_fwd_batched(arr, n, levels, mode, DWT2_EXT_SYMMETRIC, ws.data_ptr(), nbytes, _stream())
+        status = getattr(lib, name)(arr, n, levels, mode, DWT2_EXT_SYMMETRIC, ws.data_ptr(), nbytes, _stream())
     _lib.check(status)
     return list(outs)
+
+
+def fwd_batched(images: Sequence[torch.Tensor], levels: int, mode=None,
+                outs: Sequence[torch.Tensor] | None = None,
+                workspace: torch.Tensor | None = None) -> List[torch.Tensor]:
+    """Forward transform of a ragged list of 2-D images in one batched call
+    (see dwt2_fwd_batched).  Plans are cached per image geometry and
+    workspace address: pass the same `workspace` on repeated calls."""
+    return _batched("dwt2_fwd_batched", images, levels, mode, outs, workspace)
+
+
+def inv_batched(coeffs: Sequence[torch.Tensor], levels: int, mode=None,
+                outs: Sequence[torch.Tensor] | None = None,
+                workspace: torch.Tensor | None = None) -> List[torch.Tensor]:
+    """Inverse of fwd_batched (see dwt2_inv_batched)."""
+    return _batched("dwt2_inv_batched", coeffs, levels, mode, outs, workspace)
+
+
+def bwd_batched(grads: Sequence[torch.Tensor], levels: int,
+                outs: Sequence[torch.Tensor] | None = None,
+                workspace: torch.Tensor | None = None) -> List[torch.Tensor]:
+    """Adjoint of the float forward transform on a ragged list (see
+    dwt2_bwd_batched)."""
+    return _batched("dwt2_bwd_batched", grads, levels, DWT2_F32, outs, workspace)
 
 
 class DWT2Function(torch.autograd.Function):

@@ -144,37 +144,44 @@ void fill_level(LevelDesc& d, int W, int H, int seg) {
 static char* ll_buf(const Call& c, const Geo& g, int m) { return c.ws + c.ll_base + ll_offset(g, m); }
 
 // Geometry, pointers and tiling of level k for a call.
-static void level_launch(int dir, const Call& c, const Geo& g, int k, int64_t slots_hint, LevelLaunch& a, int& ch) {
+// Buffers of level k in direction `dir` (element strides between images in
+// *_bs): the level input / output pixels are the image (k = 1) or LL_{k-1};
+// LL_k is the packed array's corner at the last level, else a workspace
+// buffer; the H bands live in the packed array.
+void level_pointers(int dir, const Call& c, const Geo& g, int k, LevelDesc& d, int64_t& pix_bs, int64_t& ll_bs,
+                    int64_t& band_bs) {
   const int64_t ws_bs = (int64_t)(ws_per_image(g) / 4);
+  const bool px_is_image = (k == 1);
+  char* px = px_is_image ? (dir == kFwd ? const_cast<char*>(c.src) : c.dst) : ll_buf(c, g, k - 1);
+  d.pix_stride = px_is_image ? (dir == kFwd ? c.src_stride : c.dst_stride) : ll_pitch(g.w[k - 1]);
+  pix_bs = px_is_image ? (dir == kFwd ? c.src_bs : c.dst_bs) : ws_bs;
+  const bool ll_is_packed = (k == g.L);
+  char* ll = ll_is_packed ? (dir == kFwd ? c.dst : const_cast<char*>(c.src)) : ll_buf(c, g, k);
+  d.ll_stride = ll_is_packed ? (dir == kFwd ? c.dst_stride : c.src_stride) : ll_pitch(g.w[k]);
+  ll_bs = ll_is_packed ? (dir == kFwd ? c.dst_bs : c.src_bs) : ws_bs;
+  if (dir == kFwd) {
+    d.pix_in = px;
+    d.ll_out = ll;
+    d.band_out = c.dst;
+    d.band_stride = c.dst_stride;
+    band_bs = c.dst_bs;
+  } else {
+    d.pix_out = px;
+    d.ll_in = ll;
+    d.band_in = c.src;
+    d.band_stride = c.src_stride;
+    band_bs = c.src_bs;
+  }
+}
+
+static void level_launch(int dir, const Call& c, const Geo& g, int k, int64_t slots_hint, LevelLaunch& a, int& ch) {
   memset(&a, 0, sizeof a);
   const int W = g.w[k - 1], H = g.h[k - 1];
   const int64_t strips_batch = (int64_t)num_strips(W) * c.batch;
   const Tiling t = choose_tiling(ceil_half(H), strips_batch, slots_hint);
   ch = t.ch;
   fill_level(a.d, W, H, t.seg);
-  // pixels of the level input: the image (k = 1) or LL_{k-1}
-  const bool px_is_image = (k == 1);
-  char* px = px_is_image ? (dir == kFwd ? const_cast<char*>(c.src) : c.dst) : ll_buf(c, g, k - 1);
-  a.d.pix_stride = px_is_image ? (dir == kFwd ? c.src_stride : c.dst_stride) : ll_pitch(g.w[k - 1]);
-  a.pix_bstride = px_is_image ? (dir == kFwd ? c.src_bs : c.dst_bs) : ws_bs;
-  // LL_k: the packed array's corner at the last level, else a workspace buffer
-  const bool ll_is_packed = (k == g.L);
-  char* ll = ll_is_packed ? (dir == kFwd ? c.dst : const_cast<char*>(c.src)) : ll_buf(c, g, k);
-  a.d.ll_stride = ll_is_packed ? (dir == kFwd ? c.dst_stride : c.src_stride) : ll_pitch(g.w[k]);
-  a.ll_bstride = ll_is_packed ? (dir == kFwd ? c.dst_bs : c.src_bs) : ws_bs;
-  if (dir == kFwd) {
-    a.d.pix_in = px;
-    a.d.ll_out = ll;
-    a.d.band_out = c.dst;
-    a.d.band_stride = c.dst_stride;
-    a.band_bstride = c.dst_bs;
-  } else {
-    a.d.pix_out = px;
-    a.d.ll_in = ll;
-    a.d.band_in = c.src;
-    a.d.band_stride = c.src_stride;
-    a.band_bstride = c.src_bs;
-  }
+  level_pointers(dir, c, g, k, a.d, a.pix_bstride, a.ll_bstride, a.band_bstride);
   // the LL output feeds the next level's launch (forward: LL_k, k < L;
   // inverse / adjoint: LL_{k-1}, k > 1) and fits the caches
   const int ko = dir == kFwd ? k : k - 1;

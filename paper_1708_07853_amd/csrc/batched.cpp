@@ -105,6 +105,7 @@ int seg_for(int base, int k, int ns_h) {
 
 struct Plan {
   int n = 0, levels = 0, mode = 0;
+  int dir = kFwd;               // kFwd, kInv or kBwd
   int kind = 0;                 // kChained or kLevelSync
   int base_seg = 32;
   std::vector<Geo> geos;
@@ -137,10 +138,10 @@ std::map<std::string, std::unique_ptr<Plan>> g_plans;
 std::map<std::string, int> g_tuned;  // shape set -> policy code (kind * kPolicyKind + base)
 bool g_tune_loaded = false;
 
-std::string shape_key(const dwt2_image_t* images, int n, int levels, int mode) {
+std::string shape_key(int dir, const dwt2_image_t* images, int n, int levels, int mode) {
   std::string k;
   char buf[96];
-  snprintf(buf, sizeof buf, "%d:%d:%d|", n, levels, mode);
+  snprintf(buf, sizeof buf, "d%d:%d:%d:%d|", dir, n, levels, mode);
   k += buf;
   for (int i = 0; i < n; ++i) {
     snprintf(buf, sizeof buf, "%d,%d;", images[i].width, images[i].height);
@@ -195,7 +196,7 @@ void build_schedule(Plan& p, int policy) {
     for (int oi = 0; oi < p.n; ++oi) {
       const int i = p.order[oi];
       const Geo& g = p.geos[i];
-      const int k = t + 1;
+      const int k = p.dir == kFwd ? t + 1 : p.levels - t;  // level of step t
       const int ns_h = ceil_half(g.h[k - 1]);
       const int seg = seg_for(base, k, ns_h);
       const int j = t * p.n + oi;
@@ -204,7 +205,8 @@ void build_schedule(Plan& p, int policy) {
       const int items = nsegs * num_strips(g.w[k - 1]);
       p.item_desc.insert(p.item_desc.end(), items, (uint32_t)j);
       p.counters += nsegs;
-      p.step_ll_bytes[t] += (int64_t)g.w[k] * g.h[k] * 4;
+      const int ko = p.dir == kFwd ? k : k - 1;  // the step's LL output
+      p.step_ll_bytes[t] += (int64_t)g.w[ko] * g.h[ko] * 4;
     }
   }
   p.total_items = (int32_t)p.item_desc.size();
@@ -218,7 +220,7 @@ void fill_descs(Plan& p, const dwt2_image_t* images, JobDesc* out) {
     for (int oi = 0; oi < p.n; ++oi) {
       const int i = p.order[oi];
       const Geo& g = p.geos[i];
-      const int k = t + 1;
+      const int k = p.dir == kFwd ? t + 1 : p.levels - t;
       const int j = t * p.n + oi;
       const dwt2_image_t& im = images[i];
       Call c{static_cast<const char*>(im.src), im.src_stride, 0, static_cast<char*>(im.dst), im.dst_stride, 0, 1,
@@ -228,13 +230,7 @@ void fill_descs(Plan& p, const dwt2_image_t* images, JobDesc* out) {
       LevelDesc& d = jd.d;
       const int W = g.w[k - 1], H = g.h[k - 1];
       fill_level(d, W, H, p.desc_seg[j]);
-      d.pix_in = (k == 1) ? static_cast<const void*>(im.src)
-                          : static_cast<const void*>(c.ws + c.ll_base + ll_offset(g, k - 1));
-      d.pix_stride = (k == 1) ? im.src_stride : ll_pitch(g.w[k - 1]);
-      d.ll_out = (k == g.L) ? im.dst : static_cast<void*>(c.ws + c.ll_base + ll_offset(g, k));
-      d.ll_stride = (k == g.L) ? im.dst_stride : ll_pitch(g.w[k]);
-      d.band_out = im.dst;
-      d.band_stride = im.dst_stride;
+      level_pointers(p.dir, c, g, k, d, jd.pix_bstride, jd.ll_bstride, jd.band_bstride);
       jd.nimg = 1;
       jd.item_start = start;
       jd.items = d.nsegs * d.nstrips;
@@ -276,14 +272,14 @@ hipError_t enqueue(const Plan& p, hipStream_t s) {
       a.item_desc = reinterpret_cast<const uint32_t*>(p.ws + p.lay.items);
       a.item_begin = p.step_begin[t];
       a.items = p.step_begin[t + 1] - p.step_begin[t];
-      const int err = launch_table(p.mode, kBatchCh, a, s);
+      const int err = launch_table(p.dir, p.mode, kBatchCh, a, s);
       if (err != hipSuccess) return (hipError_t)err;
     }
     return hipSuccess;
   }
   int err = launch_zero(reinterpret_cast<uint32_t*>(p.ws + p.lay.sync), kSyncCounters + (int64_t)kCounterStride * p.counters, s);
   if (err != hipSuccess) return (hipError_t)err;
-  return (hipError_t)launch_job(kFwd, p.mode, kBatchCh, job_args(p), p.blocks, s);
+  return (hipError_t)launch_job(p.dir, p.mode, kBatchCh, job_args(p), p.blocks, s);
 }
 
 void write_staging(Plan& p, const dwt2_image_t* images) {
@@ -356,8 +352,9 @@ int autotune(Plan& p, const dwt2_image_t* images, hipStream_t s, const std::stri
   return DWT2_OK;
 }
 
-int build_plan(Plan& p, const dwt2_image_t* images, int n, int levels, int mode, std::vector<Geo>&& geos, char* ws,
-               hipStream_t s, const std::string& key) {
+int build_plan(Plan& p, int dir, const dwt2_image_t* images, int n, int levels, int mode, std::vector<Geo>&& geos,
+               char* ws, hipStream_t s, const std::string& key) {
+  p.dir = dir;
   p.n = n;
   p.levels = levels;
   p.mode = mode;
@@ -371,7 +368,7 @@ int build_plan(Plan& p, const dwt2_image_t* images, int n, int levels, int mode,
   });
   int dev = 0, cus = 256;
   if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  int bpc = job_blocks_per_cu(kFwd, mode, kBatchCh);
+  int bpc = job_blocks_per_cu(dir, mode, kBatchCh);
   p.blocks = (bpc > 0 ? bpc : 1) * (cus > 0 ? cus : 256);
   load_tune_cache();
   int st = autotune(p, images, s, hash_key(key));
@@ -405,9 +402,48 @@ int build_plan(Plan& p, const dwt2_image_t* images, int n, int levels, int mode,
   }
   const char* verbose = getenv("DWT2_VERBOSE");
   if (verbose && atoi(verbose) > 0)
-    fprintf(stderr, "dwt2_fwd_batched plan: %d images, %d levels, %s schedule, level-1 segment %d, %d items, %s\n",
-            n, levels, p.kind == kLevelSync ? "level-synchronous" : "chained persistent", p.base_seg, p.total_items,
+    fprintf(stderr, "dwt2 batched %s plan: %d images, %d levels, %s schedule, level-1 segment %d, %d items, %s\n",
+            dir == kFwd ? "forward" : (dir == kInv ? "inverse" : "adjoint"), n, levels,
+            p.kind == kLevelSync ? "level-synchronous" : "chained persistent", p.base_seg, p.total_items,
             p.exec ? "graph replay" : "direct launches");
+  return DWT2_OK;
+}
+
+static int batched(int dir, const dwt2_image_t* images, int32_t n, int32_t levels, int32_t mode, int32_t boundary,
+                   void* workspace, size_t workspace_bytes, void* stream) {
+  clear_error();
+  if (boundary != DWT2_EXT_SYMMETRIC) return fail(DWT2_ERR_ARG, "unknown boundary %d", boundary);
+  std::vector<Geo> geos;
+  int st = validate_images(images, n, levels, mode, geos);
+  if (st) return st;
+  if (dir == kBwd && mode != DWT2_F32) return fail(DWT2_ERR_MODE, "the adjoint exists for DWT2_F32 only");
+  const size_t total = layout(geos).total;
+  if (!workspace || workspace_bytes < total)
+    return fail(DWT2_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", total, workspace ? workspace_bytes : 0);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(DWT2_ERR_HIP, "no current device");
+  std::string key = shape_key(dir, images, n, levels, mode);
+  char wsbuf[64];
+  snprintf(wsbuf, sizeof wsbuf, "|ws%p|dev%d", workspace, dev);
+  const std::string plan_key = key + wsbuf;
+
+  std::lock_guard<std::mutex> lock(g_mu);
+  auto it = g_plans.find(plan_key);
+  if (it == g_plans.end()) {
+    std::unique_ptr<Plan> p(new Plan);
+    st = build_plan(*p, dir, images, n, levels, mode, std::move(geos), static_cast<char*>(workspace), s, key);
+    if (st) return st;
+    it = g_plans.emplace(plan_key, std::move(p)).first;
+  }
+  Plan& p = *it->second;
+  // the previous call of this plan must have consumed the staging buffer
+  if (p.pending && hipEventSynchronize(p.done) != hipSuccess) return fail(DWT2_ERR_HIP, "event wait failed");
+  write_staging(p, images);
+  hipError_t e = p.exec ? hipGraphLaunch(p.exec, s) : enqueue(p, s);
+  if (e == hipSuccess) e = hipEventRecord(p.done, s);
+  if (e != hipSuccess) return fail(DWT2_ERR_HIP, "batched launch failed: %s", hipGetErrorString(e));
+  p.pending = true;
   return DWT2_OK;
 }
 
@@ -423,39 +459,17 @@ size_t dwt2_batched_workspace_size(const dwt2_image_t* images, int32_t n, int32_
 
 int dwt2_fwd_batched(const dwt2_image_t* images, int32_t n, int32_t levels, int32_t mode, int32_t boundary,
                      void* workspace, size_t workspace_bytes, void* stream) {
-  clear_error();
-  if (boundary != DWT2_EXT_SYMMETRIC) return fail(DWT2_ERR_ARG, "unknown boundary %d", boundary);
-  std::vector<Geo> geos;
-  int st = validate_images(images, n, levels, mode, geos);
-  if (st) return st;
-  const size_t total = layout(geos).total;
-  if (!workspace || workspace_bytes < total)
-    return fail(DWT2_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", total, workspace ? workspace_bytes : 0);
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return fail(DWT2_ERR_HIP, "no current device");
-  std::string key = shape_key(images, n, levels, mode);
-  char wsbuf[64];
-  snprintf(wsbuf, sizeof wsbuf, "|ws%p|dev%d", workspace, dev);
-  const std::string plan_key = key + wsbuf;
+  return batched(kFwd, images, n, levels, mode, boundary, workspace, workspace_bytes, stream);
+}
 
-  std::lock_guard<std::mutex> lock(g_mu);
-  auto it = g_plans.find(plan_key);
-  if (it == g_plans.end()) {
-    std::unique_ptr<Plan> p(new Plan);
-    st = build_plan(*p, images, n, levels, mode, std::move(geos), static_cast<char*>(workspace), s, key);
-    if (st) return st;
-    it = g_plans.emplace(plan_key, std::move(p)).first;
-  }
-  Plan& p = *it->second;
-  // the previous call of this plan must have consumed the staging buffer
-  if (p.pending && hipEventSynchronize(p.done) != hipSuccess) return fail(DWT2_ERR_HIP, "event wait failed");
-  write_staging(p, images);
-  hipError_t e = p.exec ? hipGraphLaunch(p.exec, s) : enqueue(p, s);
-  if (e == hipSuccess) e = hipEventRecord(p.done, s);
-  if (e != hipSuccess) return fail(DWT2_ERR_HIP, "batched launch failed: %s", hipGetErrorString(e));
-  p.pending = true;
-  return DWT2_OK;
+int dwt2_inv_batched(const dwt2_image_t* images, int32_t n, int32_t levels, int32_t mode, int32_t boundary,
+                     void* workspace, size_t workspace_bytes, void* stream) {
+  return batched(kInv, images, n, levels, mode, boundary, workspace, workspace_bytes, stream);
+}
+
+int dwt2_bwd_batched(const dwt2_image_t* images, int32_t n, int32_t levels, int32_t mode, int32_t boundary,
+                     void* workspace, size_t workspace_bytes, void* stream) {
+  return batched(kBwd, images, n, levels, mode, boundary, workspace, workspace_bytes, stream);
 }
 
 void dwt2_clear_plan_cache(void) {

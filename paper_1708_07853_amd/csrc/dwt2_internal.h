@@ -101,7 +101,7 @@ struct JobArgs {
 };
 
 // One level-synchronous launch over items [item_begin, item_begin + items)
-// of a ragged batch's item table (forward only).
+// of a ragged batch's item table.
 struct TableArgs {
   const JobDesc* descs;
   const uint32_t* item_desc;
@@ -129,6 +129,6 @@ int launch_level(int dir, int mode, int chunk, const LevelLaunch& a, void* strea
 int job_blocks_per_cu(int dir, int mode, int chunk);
 int launch_job(int dir, int mode, int chunk, const JobArgs& a, int blocks, void* stream);
 int launch_zero(uint32_t* p, int64_t n, void* stream);
-int launch_table(int mode, int chunk, const TableArgs& a, void* stream);
+int launch_table(int dir, int mode, int chunk, const TableArgs& a, void* stream);
 
 }  // namespace dwt2

@@ -1165,10 +1165,11 @@ __global__ __launch_bounds__(kBlock) void job_kernel(JobArgs a) {
   }
 }
 
-// One step range of a ragged batch per launch (level-synchronous schedule):
+// One step range of a ragged batch per launch (level-synchronous schedule,
+// any direction):
 // one wave per work item, the item's step found through the device
 // item -> step table.  Steps of one launch never depend on each other.
-template <typename T, int CH>
+template <int DIR, typename T, int CH>
 __global__ __launch_bounds__(kBlock) void table_kernel(TableArgs a) {
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
@@ -1183,8 +1184,8 @@ __global__ __launch_bounds__(kBlock) void table_kernel(TableArgs a) {
   const int rem = item - img * per_img;
   const int seg = rem / jd.d.nstrips;
   const int strip = rem - seg * jd.d.nstrips;
-  run_item<kFwd, T, CH, false>(jd.d, 0, img * jd.pix_bstride, img * jd.ll_bstride, img * jd.band_bstride, strip, seg,
-                               lane);
+  run_item<DIR, T, CH, false>(jd.d, 0, img * jd.pix_bstride, img * jd.ll_bstride, img * jd.band_bstride, strip, seg,
+                              lane);
 }
 
 __global__ void zero_kernel(uint32_t* p, int64_t n) {
@@ -1256,18 +1257,22 @@ int job_blocks_per_cu(int dir, int mode, int chunk) {
   return occ_job_dir<1>(dir, mode);
 }
 
-int launch_table(int mode, int chunk, const TableArgs& a, void* stream) {
+template <int DIR, typename T>
+hipError_t launch_table_t(int chunk, const TableArgs& a, hipStream_t s) {
+  const dim3 grid((unsigned)((a.items + kWavesPerBlock - 1) / kWavesPerBlock));
+  if (chunk >= 2) hipLaunchKernelGGL((table_kernel<DIR, T, 2>), grid, dim3(kBlock), 0, s, a);
+  else hipLaunchKernelGGL((table_kernel<DIR, T, 1>), grid, dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+int launch_table(int dir, int mode, int chunk, const TableArgs& a, void* stream) {
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (a.items <= 0) return hipSuccess;
-  const dim3 grid((unsigned)((a.items + kWavesPerBlock - 1) / kWavesPerBlock));
-  if (mode == DWT2_F32) {
-    if (chunk >= 2) hipLaunchKernelGGL((table_kernel<float, 2>), grid, dim3(kBlock), 0, s, a);
-    else hipLaunchKernelGGL((table_kernel<float, 1>), grid, dim3(kBlock), 0, s, a);
-  } else {
-    if (chunk >= 2) hipLaunchKernelGGL((table_kernel<int, 2>), grid, dim3(kBlock), 0, s, a);
-    else hipLaunchKernelGGL((table_kernel<int, 1>), grid, dim3(kBlock), 0, s, a);
-  }
-  return hipGetLastError();
+  if (dir == kFwd)
+    return mode == DWT2_F32 ? launch_table_t<kFwd, float>(chunk, a, s) : launch_table_t<kFwd, int>(chunk, a, s);
+  if (dir == kInv)
+    return mode == DWT2_F32 ? launch_table_t<kInv, float>(chunk, a, s) : launch_table_t<kInv, int>(chunk, a, s);
+  return launch_table_t<kBwd, float>(chunk, a, s);
 }
 
 int launch_zero(uint32_t* p, int64_t n, void* stream) {

@@ -122,7 +122,9 @@ def _images(specs):
     return arr
 
 
-def test_batched_validation(lib):
+@pytest.mark.parametrize("fn", ["dwt2_fwd_batched", "dwt2_inv_batched", "dwt2_bwd_batched"])
+def test_batched_validation(lib, fn):
+    call_b = getattr(lib, fn)
     ok = _images([(64, 64, 64), (33, 17, 40)])
     assert lib.dwt2_batched_workspace_size(ok, 2, 2, 0) > 0
     geo_only = _images([(64, 64, 64), (33, 17, 40)])       # the size query reads only the geometry
@@ -132,17 +134,20 @@ def test_batched_validation(lib):
     assert lib.dwt2_batched_workspace_size(_images([(64, 64, 64), (3, 3, 3)]), 2, 3, 0) == 0
     misaligned = _images([(64, 64, 64), (33, 17, 40)])
     misaligned[1].dst += 2                                 # image 1: dst not 4-byte aligned
-    assert lib.dwt2_fwd_batched(misaligned, 2, 2, 0, 0, FAKE_WS, 1 << 30, None) == -1
+    assert call_b(misaligned, 2, 2, 0, 0, FAKE_WS, 1 << 30, None) == -1
     assert "image 1" in lib.dwt2_last_error().decode()
     bad = _images([(64, 64, 64), (33, 17, 20)])           # image 1: stride < width
-    assert lib.dwt2_fwd_batched(bad, 2, 2, 0, 0, FAKE_WS, 1 << 30, None) == -1
+    assert call_b(bad, 2, 2, 0, 0, FAKE_WS, 1 << 30, None) == -1
     assert "image 1" in lib.dwt2_last_error().decode()
     tiny = _images([(64, 64, 64), (3, 3, 3)])             # image 1: level 2 input 2 x 2 ok, level 3 not
-    assert lib.dwt2_fwd_batched(tiny, 2, 3, 0, 0, FAKE_WS, 1 << 30, None) == -2
-    assert lib.dwt2_fwd_batched(ok, 2, 2, 0, 0, FAKE_WS, 10, None) == -4
-    assert lib.dwt2_fwd_batched(ok, 0, 2, 0, 0, FAKE_WS, 1 << 30, None) == -1
-    assert lib.dwt2_fwd_batched(ok, 2, 2, 9, 0, FAKE_WS, 1 << 30, None) == -3
-    assert lib.dwt2_fwd_batched(ok, 2, 2, 0, 3, FAKE_WS, 1 << 30, None) == -1
+    assert call_b(tiny, 2, 3, 0, 0, FAKE_WS, 1 << 30, None) == -2
+    assert call_b(ok, 2, 2, 0, 0, FAKE_WS, 10, None) == -4
+    assert call_b(ok, 0, 2, 0, 0, FAKE_WS, 1 << 30, None) == -1
+    assert call_b(ok, 2, 2, 9, 0, FAKE_WS, 1 << 30, None) == -3
+    assert call_b(ok, 2, 2, 0, 3, FAKE_WS, 1 << 30, None) == -1
+    if fn == "dwt2_bwd_batched":
+        assert call_b(ok, 2, 2, 1, 0, FAKE_WS, 1 << 30, None) == -3   # the adjoint is float only
+        assert "F32" in lib.dwt2_last_error().decode()
 
 
 def test_set_path_validation(lib):
