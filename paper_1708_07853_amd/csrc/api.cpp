@@ -232,7 +232,7 @@ int64_t job_slots(int dir, int mode, int ch) {
     std::lock_guard<std::mutex> lock(mu);
     int& c = cache[dir][mode][ci];
     if (!c) {
-      c = job_blocks_per_cu(dir, mode, ch);
+      c = job_blocks_per_cu(dir, mode, ch, false);
       if (c <= 0) c = 1;
     }
     blocks = c;

@@ -334,9 +334,23 @@ int autotune(Plan& p, const dwt2_image_t* images, hipStream_t s, const std::stri
     write_staging(p, images);
     float t = 0.f;
     for (int rep = 0; rep < 2; ++rep) {
-      if (hipEventRecord(e0, s) != hipSuccess || enqueue(p, s) != hipSuccess || hipEventRecord(e1, s) != hipSuccess ||
-          hipEventSynchronize(e1) != hipSuccess)
-        return fail(DWT2_ERR_HIP, "autotune run failed");
+      hipError_t e = hipEventRecord(e0, s);
+      const char* what = "event record";
+      if (e == hipSuccess) {
+        e = enqueue(p, s);
+        what = "launch";
+      }
+      if (e == hipSuccess) e = hipEventRecord(e1, s);
+      if (e == hipSuccess) {
+        e = hipEventSynchronize(e1);
+        what = "run";
+      }
+      if (e != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        return fail(DWT2_ERR_HIP, "autotune %s of %s schedule, segment %d failed: %s", what,
+                    p.kind == kLevelSync ? "level-synchronous" : "chained", p.base_seg, hipGetErrorString(e));
+      }
       (void)hipEventElapsedTime(&t, e0, e1);
     }
     if (t < best) {
@@ -368,7 +382,7 @@ int build_plan(Plan& p, int dir, const dwt2_image_t* images, int n, int levels, 
   });
   int dev = 0, cus = 256;
   if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  int bpc = job_blocks_per_cu(dir, mode, kBatchCh);
+  int bpc = job_blocks_per_cu(dir, mode, kBatchCh, true);
   p.blocks = (bpc > 0 ? bpc : 1) * (cus > 0 ? cus : 256);
   load_tune_cache();
   int st = autotune(p, images, s, hash_key(key));

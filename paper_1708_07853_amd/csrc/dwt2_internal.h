@@ -126,7 +126,7 @@ int launch_separable_level(int mode, const SepLevel& a, void* stream);
 
 // Kernel launchers (kernels.hip).  Return hipError_t as int.
 int launch_level(int dir, int mode, int chunk, const LevelLaunch& a, void* stream);
-int job_blocks_per_cu(int dir, int mode, int chunk);
+int job_blocks_per_cu(int dir, int mode, int chunk, bool table);
 int launch_job(int dir, int mode, int chunk, const JobArgs& a, int blocks, void* stream);
 int launch_zero(uint32_t* p, int64_t n, void* stream);
 int launch_table(int dir, int mode, int chunk, const TableArgs& a, void* stream);

@@ -1224,20 +1224,23 @@ hipError_t launch_job_ch(int chunk, const JobArgs& a, int blocks, hipStream_t s)
   return launch_job_t<DIR, T, 1>(a, blocks, s);
 }
 
+// Resident blocks per CU of the job kernel variant that a launch uses
+// (TABLE: descriptors in device memory); the cooperative launch fails if
+// the grid exceeds what this variant can hold at once.
 template <int DIR, typename T, int CH>
-int occ_job() {
+int occ_job(bool table) {
   int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(&job_kernel<DIR, T, CH, false>),
-                                                   kBlock, 0) != hipSuccess)
-    n = 0;
+  const void* f = table ? reinterpret_cast<const void*>(&job_kernel<DIR, T, CH, true>)
+                        : reinterpret_cast<const void*>(&job_kernel<DIR, T, CH, false>);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, kBlock, 0) != hipSuccess) n = 0;
   return n;
 }
 
 template <int CH>
-int occ_job_dir(int dir, int mode) {
-  if (dir == kFwd) return mode == DWT2_F32 ? occ_job<kFwd, float, CH>() : occ_job<kFwd, int, CH>();
-  if (dir == kInv) return mode == DWT2_F32 ? occ_job<kInv, float, CH>() : occ_job<kInv, int, CH>();
-  return occ_job<kBwd, float, CH>();
+int occ_job_dir(int dir, int mode, bool table) {
+  if (dir == kFwd) return mode == DWT2_F32 ? occ_job<kFwd, float, CH>(table) : occ_job<kFwd, int, CH>(table);
+  if (dir == kInv) return mode == DWT2_F32 ? occ_job<kInv, float, CH>(table) : occ_job<kInv, int, CH>(table);
+  return occ_job<kBwd, float, CH>(table);
 }
 
 }  // namespace
@@ -1251,10 +1254,10 @@ int launch_job(int dir, int mode, int chunk, const JobArgs& a, int blocks, void*
   return launch_job_ch<kBwd, float>(chunk, a, blocks, s);
 }
 
-int job_blocks_per_cu(int dir, int mode, int chunk) {
-  if (chunk >= 4) return occ_job_dir<4>(dir, mode);
-  if (chunk >= 2) return occ_job_dir<2>(dir, mode);
-  return occ_job_dir<1>(dir, mode);
+int job_blocks_per_cu(int dir, int mode, int chunk, bool table) {
+  if (chunk >= 4) return occ_job_dir<4>(dir, mode, table);
+  if (chunk >= 2) return occ_job_dir<2>(dir, mode, table);
+  return occ_job_dir<1>(dir, mode, table);
 }
 
 template <int DIR, typename T>

@@ -443,6 +443,16 @@ def test_batched_inverse_and_adjoint_every_schedule():
                 back = d.inv_batched(d.fwd_batched(imgs, 3), 3)
                 for im, b in zip(imgs, back):
                     assert torch.equal(im, b)
+        # unforced: the autotuner runs every candidate policy directly
+        for k in saved:
+            os.environ.pop(k, None)
+        lib.dwt2_clear_plan_cache()
+        imgs = [to_gpu(synth.image(w, h, 800 + i)) for i, (w, h) in enumerate(sizes)]
+        coefs = d.fwd_batched(imgs, 3)
+        for o, r in zip(d.inv_batched(coefs, 3), [d.inv(c, 3) for c in coefs]):
+            assert torch.equal(o, r)
+        for o, r in zip(d.bwd_batched(coefs, 3), [d.bwd(c, 3) for c in coefs]):
+            assert torch.equal(o, r)
     finally:
         for k, v in saved.items():
             if v is None:
