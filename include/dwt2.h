@@ -205,11 +205,14 @@ int dwt2_bwd_batched(const dwt2_image_t* images, int32_t n, int32_t levels,
 int dwt2_set_tiling(int32_t seg, int32_t chunk);
 
 /* Process-wide choice of how levels are chained, for tests and
- * measurements: 0 (default) = one kernel launch per level; 1 = every level
- * of a call in one cooperative persistent launch whose work items wait only
- * for the rows they read.  Results are bit-identical.  Returns DWT2_OK or
+ * measurements: 0 (default) = one kernel launch per level, except that the
+ * forward's last 2-3 levels, when their inputs hold at most 1024 x 1024
+ * pixels over the batch, share one launch (each workgroup runs them in LDS
+ * on its tile plus a recompute halo); 1 = every level of a call in one cooperative persistent launch
+ * whose work items wait only for the rows they read; 2 = one launch per
+ * level throughout.  Results are bit-identical.  Returns DWT2_OK or
  * DWT2_ERR_ARG. */
-int dwt2_set_path(int32_t persistent);
+int dwt2_set_path(int32_t path);
 
 /* Process-wide timing probe, a measurement aid: while set, every
  * dwt2_fwd (dir 0), dwt2_inv (dir 1) or dwt2_bwd (dir 2) call on the
@@ -217,7 +220,8 @@ int dwt2_set_path(int32_t persistent);
  * level `level` (1 = finest) and ev_end just after it, so hipEventElapsedTime
  * of the pair is that one kernel's duration.  ev_begin / ev_end are
  * hipEvent_t handles owned by the caller, created on the device of the
- * calls.  The persistent path has no per-level launches and records
+ * calls.  Levels that share the fused tail launch record around that
+ * launch; the persistent path has no per-level launches and records
  * nothing.  dir < 0 clears the probe.  Must not race with running calls.
  * Returns DWT2_OK, or DWT2_ERR_ARG for a dir above 2, a level outside
  * 1..DWT2_MAX_LEVELS or a null event. */

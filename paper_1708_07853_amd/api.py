@@ -60,10 +60,20 @@ def set_tiling(seg: int = 0, chunk: int = 0) -> None:
     _lib.check(_lib.load().dwt2_set_tiling(seg, chunk))
 
 
-def set_path(persistent: bool = False) -> None:
-    """False (default): one launch per level; True: all levels in one
-    cooperative persistent launch.  Results are bit-identical."""
-    _lib.check(_lib.load().dwt2_set_path(1 if persistent else 0))
+PATHS = {"levels": 0, "persistent": 1, "levels-only": 2}
+
+
+def set_path(path="levels") -> None:
+    """How levels are chained (see dwt2_set_path): "levels" (default: one
+    launch per level, the forward's small last levels fused into one),
+    "persistent" (one cooperative launch), "levels-only" (one launch per
+    level throughout).  True / False select "persistent" / "levels".
+    Results are bit-identical."""
+    if isinstance(path, bool):
+        path = "persistent" if path else "levels"
+    if path not in PATHS:
+        raise ValueError(f"path must be one of {sorted(PATHS)}")
+    _lib.check(_lib.load().dwt2_set_path(PATHS[path]))
 
 
 _PROBE_DIRS = {"fwd": 0, "inv": 1, "bwd": 2}

@@ -200,8 +200,51 @@ struct Probe {
 std::mutex g_probe_mu;
 Probe g_probe;
 
-int run_levels(int dir, const Call& c, const Geo& g, void* stream) {
-  const int order_begin = dir == kFwd ? 1 : g.L, order_end = dir == kFwd ? g.L + 1 : 0;
+// First level of the fused tail (0: none): the last 2..kTailMaxLevels
+// levels whose inputs hold at most kTailArea pixels over the whole batch.
+// Larger levels are bandwidth-bound and run faster in the strip kernels
+// than with the tail's recomputed halos; the tail wins only where launch
+// latency dominates.
+static int tail_first_level(int dir, const Geo& g, int batch) {
+  if (dir != kFwd) return 0;
+  int k = g.L, n = 0;
+  while (k >= 1 && n < kTailMaxLevels && (int64_t)g.w[k - 1] * g.h[k - 1] * batch <= kTailArea) {
+    --k;
+    ++n;
+  }
+  return n >= 2 ? k + 1 : 0;
+}
+
+static int launch_tail_levels(int dir, const Call& c, const Geo& g, int k0, void* stream) {
+  TailArgs t;
+  memset(&t, 0, sizeof t);
+  const int64_t ws_bs = (int64_t)(ws_per_image(g) / 4);
+  t.n = g.L - k0 + 1;
+  t.batch = c.batch;
+  for (int m = 0; m <= t.n; ++m) {
+    t.W[m] = g.w[k0 - 1 + m];
+    t.H[m] = g.h[k0 - 1 + m];
+  }
+  t.tiles_x = (t.W[0] + kTailS - 1) / kTailS;
+  t.tiles_y = (t.H[0] + kTailS - 1) / kTailS;
+  if (k0 == 1) {
+    t.in = c.src;
+    t.in_stride = c.src_stride;
+    t.in_bstride = c.src_bs;
+  } else {
+    t.in = ll_buf(c, g, k0 - 1);
+    t.in_stride = ll_pitch(g.w[k0 - 1]);
+    t.in_bstride = ws_bs;
+  }
+  t.out = c.dst;
+  t.out_stride = c.dst_stride;
+  t.out_bstride = c.dst_bs;
+  return launch_tail(dir, c.mode, t, stream);
+}
+
+int run_levels(int dir, const Call& c, const Geo& g, void* stream, bool tail) {
+  const int k0 = tail ? tail_first_level(dir, g, c.batch) : 0;
+  const int order_begin = dir == kFwd ? 1 : g.L, order_end = dir == kFwd ? (k0 ? k0 : g.L + 1) : 0;
   const int step = dir == kFwd ? 1 : -1;
   Probe pr;
   {
@@ -218,6 +261,15 @@ int run_levels(int dir, const Call& c, const Geo& g, void* stream) {
     const int err = launch_level(dir, c.mode, ch, a, stream);
     if (err != hipSuccess)
       return fail(DWT2_ERR_HIP, "level %d launch failed: %s", k, hipGetErrorString((hipError_t)err));
+    if (probed && hipEventRecord(pr.end, s) != hipSuccess) return fail(DWT2_ERR_HIP, "probe event record failed");
+  }
+  if (k0) {
+    // the tail levels share one launch; a probe on any of them times it
+    const bool probed = pr.dir == dir && pr.level >= k0;
+    if (probed && hipEventRecord(pr.begin, s) != hipSuccess) return fail(DWT2_ERR_HIP, "probe event record failed");
+    const int err = launch_tail_levels(dir, c, g, k0, stream);
+    if (err != hipSuccess)
+      return fail(DWT2_ERR_HIP, "tail levels %d..%d launch failed: %s", k0, g.L, hipGetErrorString((hipError_t)err));
     if (probed && hipEventRecord(pr.end, s) != hipSuccess) return fail(DWT2_ERR_HIP, "probe event record failed");
   }
   return DWT2_OK;
@@ -359,8 +411,10 @@ static int transform(int dir, const void* src, int64_t src_stride, int64_t src_b
          static_cast<char*>(workspace), sync_bytes(g, batch)};
   if (separable) return run_separable(c, g, stream);
   if (g_persistent.load() < 0) g_persistent.store(env_int("DWT2_PERSISTENT") == 1 ? 1 : 0);
-  if (g_persistent.load() && g.L <= kInlineDescs) return run_job(dir, c, g, stream);
-  return run_levels(dir, c, g, stream);
+  const int path = g_persistent.load();
+  if (path == 1 && g.L <= kInlineDescs) return run_job(dir, c, g, stream);
+  if (path == 2) return run_levels(dir, c, g, stream, false);
+  return run_levels(dir, c, g, stream, true);
 }
 
 }  // namespace dwt2
@@ -443,10 +497,10 @@ int dwt2_set_probe(int32_t dir, int32_t level, void* ev_begin, void* ev_end) {
   return DWT2_OK;
 }
 
-int dwt2_set_path(int32_t persistent) {
+int dwt2_set_path(int32_t path) {
   clear_error();
-  if (persistent != 0 && persistent != 1) return fail(DWT2_ERR_ARG, "persistent must be 0 or 1");
-  g_persistent.store(persistent);
+  if (path < 0 || path > 2) return fail(DWT2_ERR_ARG, "path must be 0, 1 or 2");
+  g_persistent.store(path);
   return DWT2_OK;
 }
 

@@ -1188,6 +1188,162 @@ __global__ __launch_bounds__(kBlock) void table_kernel(TableArgs a) {
                               lane);
 }
 
+// ---------------------------------------------------------------------------
+// Tail kernel: the last n (2 or 3) levels of a transform, whose inputs are
+// small, in one launch.  Each workgroup owns a kTailS x kTailS tile of the
+// first tail level's input and runs every remaining level in LDS on that
+// tile plus a recompute halo of 2^(n+1) - 2 pixels (a 5/3 level reads two
+// pixels on each side of a quadruple, so each coarser level doubles the
+// halo and adds two), then writes the coefficients of its own tile.  Every
+// read goes through the symmetric fold of its level, so values past an
+// edge are the ones the strip kernels see, and the per-quadruple arithmetic
+// is the strip kernels' own: results are bit-identical.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int tail_halo(int n, int m) { return (2 << (n - m)) - 2; }
+
+// The symmetric fold for positions in [-2, n + 1] (all that the tail reads,
+// n >= 2), without the division of the general fold: one reflection at 0,
+// one at n - 1, and a last one at 0 for n = 2.
+__device__ __forceinline__ int fold_near(int p, int n) {
+  int q = p < 0 ? -p : p;
+  q = q > n - 1 ? 2 * (n - 1) - q : q;
+  return q < 0 ? -q : q;
+}
+
+// Threads walk 2-D ranges in rows of 64 (one wave per row), so that no
+// division is needed and a wave touches consecutive columns.
+constexpr int kTailRowT = 64, kTailRows = kTailBlock / kTailRowT;
+// loads per thread that cover the largest level-0 region (n = 3)
+constexpr int kTailLoads = ((kTailS + 2 * 14) * (kTailS + 2 * 14) + kTailBlock - 1) / kTailBlock;
+
+template <typename T>
+__global__ __launch_bounds__(kTailBlock) void tail_fwd(TailArgs a) {
+  __shared__ T lds[kTailLds];
+  const int lx = threadIdx.x & (kTailRowT - 1), ly = threadIdx.x / kTailRowT;
+  const int tx = blockIdx.x % a.tiles_x, ty = blockIdx.x / a.tiles_x;
+  const int n = a.n;
+  // region arrays, one per level, then the three predict arrays
+  int base[kTailMaxLevels];
+  int acc = 0;
+  for (int m = 0; m < n; ++m) {
+    base[m] = acc;
+    const int N = (kTailS >> m) + 2 * tail_halo(n, m);
+    acc += N * N;
+  }
+  const int NP = (kTailS >> 1) + 2 * tail_halo(n, 1) + 1;
+  T* P0 = lds + acc;
+  T* P1 = P0 + NP * NP;
+  T* P2 = P1 + NP * NP;
+  for (int img = blockIdx.y; img < a.batch; img += gridDim.y) {
+    const T* in = static_cast<const T*>(a.in) + img * a.in_bstride;
+    T* dst = static_cast<T*>(a.out) + img * a.out_bstride;
+    // level 0 input: the in-image part of the region.  Every thread issues
+    // all its loads before the first LDS store, so they are in flight
+    // together; surplus lanes load a valid element and discard it.
+    {
+      const int r = tail_halo(n, 0), N = kTailS + 2 * r;
+      const int ox = tx * kTailS - r, oy = ty * kTailS - r;
+      const int x0 = max(ox, 0), x1 = min(ox + N, a.W[0]), y0 = max(oy, 0), y1 = min(oy + N, a.H[0]);
+      const int w = x1 - x0, cnt = w * (y1 - y0);
+      // element e = threadIdx.x + k * kTailBlock sits at (y0 + e / w, x0 + e % w);
+      // one division, then steps of kTailBlock elements
+      const int dq = kTailBlock / w, dr = kTailBlock - dq * w;
+      int ey = (int)threadIdx.x / w, ex = (int)threadIdx.x - ey * w;
+      T v[kTailLoads];
+      int slot[kTailLoads];
+#pragma unroll
+      for (int k = 0; k < kTailLoads; ++k) {
+        const bool ok = (int)threadIdx.x + k * kTailBlock < cnt;
+        const int gy = ok ? y0 + ey : y0, gx = ok ? x0 + ex : x0;  // surplus lanes reload a valid element
+        v[k] = in[(int64_t)gy * a.in_stride + gx];
+        slot[k] = ok ? base[0] + (gy - oy) * N + (gx - ox) : -1;
+        ex += dr;
+        ey += dq;
+        if (ex >= w) {
+          ex -= w;
+          ++ey;
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < kTailLoads; ++k)
+        if (slot[k] >= 0) lds[slot[k]] = v[k];
+    }
+    __syncthreads();
+    for (int m = 0; m < n; ++m) {
+      const int Wm = a.W[m], Hm = a.H[m];
+      const int r = tail_halo(n, m);
+      const int N = (kTailS >> m) + 2 * r, ox = tx * (kTailS >> m) - r, oy = ty * (kTailS >> m) - r;
+      const T* A = lds + base[m];
+      // quadruples this level produces: the next region (or, at the last
+      // level, the core), inside the image
+      const int rn = m + 1 < n ? tail_halo(n, m + 1) : 0;
+      const int S1 = kTailS >> (m + 1), cx = tx * S1, cy = ty * S1;
+      const int ns_w = (Wm + 1) >> 1, ns_h = (Hm + 1) >> 1, nd_w = Wm >> 1, nd_h = Hm >> 1;
+      const int ux0 = max(cx - rn, 0), ux1 = min(cx + S1 + rn, ns_w);
+      const int uy0 = max(cy - rn, 0), uy1 = min(cy + S1 + rn, ns_h);
+      // predict over the produced quadruples and one more on the left and top
+      const int px0 = ux0 - 1, py0 = uy0 - 1;
+      // the ranges are at most NP <= kTailRowT quadruples wide, so each
+      // thread owns one column: its folded LDS columns are fixed per level
+      const int qx = px0 + lx;
+      const int c0 = fold_near(2 * qx, Wm) - ox, c1 = fold_near(2 * qx + 1, Wm) - ox;
+      const int c2 = fold_near(2 * qx + 2, Wm) - ox;
+      for (int qy = py0 + ly; qy < uy1; qy += kTailRows) {
+        // folded rows 2qy .. 2qy+2 as LDS offsets
+        const int r0 = (fold_near(2 * qy, Hm) - oy) * N, r1 = (fold_near(2 * qy + 1, Hm) - oy) * N;
+        const int r2 = (fold_near(2 * qy + 2, Hm) - oy) * N;
+        if (qx < ux1) {
+          const int o = (qy - py0) * NP + (qx - px0);
+          if constexpr (std::is_same<T, float>::value)
+            f32_predict(A[r0 + c0], A[r0 + c2], A[r2 + c0], A[r2 + c2], A[r0 + c1], A[r2 + c1], A[r1 + c0],
+                        A[r1 + c2], A[r1 + c1], P0[o], P1[o], P2[o]);
+          else
+            i32_predict(A[r0 + c0], A[r0 + c2], A[r2 + c0], A[r2 + c2], A[r0 + c1], A[r2 + c1], A[r1 + c0],
+                        A[r1 + c2], A[r1 + c1], P0[o], P1[o], P2[o]);
+        }
+      }
+      __syncthreads();
+      const bool last = m + 1 == n;
+      const int rn_base = last ? 0 : base[m + 1];
+      const int Nn = S1 + 2 * rn, oxn = cx - rn, oyn = cy - rn;
+      const int ux = ux0 + lx;
+      const int cu = fold_near(2 * ux, Wm) - ox;
+      const bool own_col = ux >= cx && ux < cx + S1;
+      for (int qy = uy0 + ly; qy < uy1; qy += kTailRows) {
+        const int r0 = (fold_near(2 * qy, Hm) - oy) * N;
+        const bool own_row = qy >= cy && qy < cy + S1;
+        if (ux < ux1) {
+          const int qx = ux;
+          const int o = (qy - py0) * NP + (qx - px0);
+          const T va = A[r0 + cu];
+          T ll, hl, lh, hh;
+          if constexpr (std::is_same<T, float>::value) {
+            f32_update(va, P0[o - 1], P0[o], P1[o - NP], P1[o], P2[o - NP - 1], P2[o - NP], P2[o - 1], P2[o], ll, hl,
+                       lh);
+            hh = P2[o];
+          } else {
+            const int c2 = i32_c2(P1[o], P2[o - 1], P2[o]);
+            const int c2U = i32_c2(P1[o - NP], P2[o - NP - 1], P2[o - NP]);
+            i32_update(va, P0[o - 1], P0[o], c2U, c2, P2[o - NP], P2[o], ll, hl);
+            lh = c2;
+            hh = P2[o];
+          }
+          if (!last) lds[rn_base + (qy - oyn) * Nn + (qx - oxn)] = ll;
+          if (own_row && own_col) {  // this tile's own quadruples
+            if (last) dst[(int64_t)qy * a.out_stride + qx] = ll;
+            if (qx < nd_w) dst[(int64_t)qy * a.out_stride + ns_w + qx] = hl;
+            if (qy < nd_h) {
+              dst[(int64_t)(ns_h + qy) * a.out_stride + qx] = lh;
+              if (qx < nd_w) dst[(int64_t)(ns_h + qy) * a.out_stride + ns_w + qx] = hh;
+            }
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
 __global__ void zero_kernel(uint32_t* p, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     p[i] = 0u;
@@ -1276,6 +1432,15 @@ int launch_table(int dir, int mode, int chunk, const TableArgs& a, void* stream)
   if (dir == kInv)
     return mode == DWT2_F32 ? launch_table_t<kInv, float>(chunk, a, s) : launch_table_t<kInv, int>(chunk, a, s);
   return launch_table_t<kBwd, float>(chunk, a, s);
+}
+
+int launch_tail(int dir, int mode, const TailArgs& a, void* stream) {
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const dim3 grid((unsigned)(a.tiles_x * a.tiles_y), (unsigned)(a.batch < 65535 ? a.batch : 65535));
+  if (dir != kFwd) return hipErrorInvalidValue;
+  if (mode == DWT2_F32) hipLaunchKernelGGL(tail_fwd<float>, grid, dim3(kTailBlock), 0, s, a);
+  else hipLaunchKernelGGL(tail_fwd<int>, grid, dim3(kTailBlock), 0, s, a);
+  return hipGetLastError();
 }
 
 int launch_zero(uint32_t* p, int64_t n, void* stream) {

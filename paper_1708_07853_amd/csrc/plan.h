@@ -42,7 +42,7 @@ Tiling choose_tiling(int ns_h, int64_t strips_times_batch, int64_t slots_hint = 
 void fill_level(LevelDesc& d, int W, int H, int seg);
 void level_pointers(int dir, const Call& c, const Geo& g, int k, LevelDesc& d, int64_t& pix_bs, int64_t& ll_bs,
                     int64_t& band_bs);
-int run_levels(int dir, const Call& c, const Geo& g, void* stream);
+int run_levels(int dir, const Call& c, const Geo& g, void* stream, bool tail);
 int run_job(int dir, const Call& c, const Geo& g, void* stream);
 
 }  // namespace dwt2

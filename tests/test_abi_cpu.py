@@ -151,9 +151,10 @@ def test_batched_validation(lib, fn):
 
 
 def test_set_path_validation(lib):
-    assert lib.dwt2_set_path(2) == -1
-    assert lib.dwt2_set_path(1) == 0
-    assert lib.dwt2_set_path(0) == 0
+    assert lib.dwt2_set_path(3) == -1
+    assert lib.dwt2_set_path(-1) == -1
+    for path in (1, 2, 0):
+        assert lib.dwt2_set_path(path) == 0
 
 
 def test_set_probe_validation(lib):

@@ -265,11 +265,11 @@ def test_results_do_not_depend_on_tiling_or_path(mode):
         for (h, w, levels) in shapes:
             x = to_gpu(synth.image(w, h, h + w, dt))
             d.set_tiling(0, 0)
-            d.set_path(False)
+            d.set_path("levels-only")
             ref_f = d.fwd(x, levels)
             ref_i = d.inv(ref_f, levels)
             ref_b = d.bwd(x.float(), levels) if mode == "f32" else None
-            for persistent in (True, False):
+            for persistent in ("persistent", "levels"):
                 d.set_path(persistent)
                 for seg, ch in [(0, 0), (1, 1), (2, 1), (4, 2), (8, 4), (16, 4), (24, 2), (64, 4), (3, 1), (10000, 4)]:
                     d.set_tiling(seg, ch)
@@ -279,7 +279,7 @@ def test_results_do_not_depend_on_tiling_or_path(mode):
                         assert torch.equal(d.bwd(x.float(), levels), ref_b), (h, w, seg, ch, persistent)
     finally:
         d.set_tiling(0, 0)
-        d.set_path(False)
+        d.set_path("levels")
 
 
 def test_batched_equals_plain_on_ragged_set():
