@@ -206,12 +206,15 @@ Probe g_probe;
 // than with the tail's recomputed halos; the tail wins only where launch
 // latency dominates.
 static int tail_first_level(int dir, const Geo& g, int batch) {
-  if (dir != kFwd) return 0;
+  if (dir == kBwd) return 0;
   int k = g.L, n = 0;
   while (k >= 1 && n < kTailMaxLevels && (int64_t)g.w[k - 1] * g.h[k - 1] * batch <= kTailArea) {
     --k;
     ++n;
   }
+  // the inverse tail reads at most two quadruples past an edge through a
+  // division-free fold, exact for levels of at least 4 x 4
+  if (dir == kInv && (g.w[g.L - 1] < 4 || g.h[g.L - 1] < 4)) return 0;
   return n >= 2 ? k + 1 : 0;
 }
 
@@ -227,24 +230,33 @@ static int launch_tail_levels(int dir, const Call& c, const Geo& g, int k0, void
   }
   t.tiles_x = (t.W[0] + kTailS - 1) / kTailS;
   t.tiles_y = (t.H[0] + kTailS - 1) / kTailS;
-  if (k0 == 1) {
+  // the finest tail level's pixels: the image (k0 = 1) or LL_{k0-1}
+  const void* px = k0 == 1 ? (dir == kFwd ? static_cast<const void*>(c.src) : static_cast<const void*>(c.dst))
+                           : static_cast<const void*>(ll_buf(c, g, k0 - 1));
+  const int64_t px_stride = k0 == 1 ? (dir == kFwd ? c.src_stride : c.dst_stride) : ll_pitch(g.w[k0 - 1]);
+  const int64_t px_bs = k0 == 1 ? (dir == kFwd ? c.src_bs : c.dst_bs) : ws_bs;
+  if (dir == kFwd) {  // pixels in, packed coefficients out
+    t.in = px;
+    t.in_stride = px_stride;
+    t.in_bstride = px_bs;
+    t.out = c.dst;
+    t.out_stride = c.dst_stride;
+    t.out_bstride = c.dst_bs;
+  } else {  // packed coefficients in, pixels out
     t.in = c.src;
     t.in_stride = c.src_stride;
     t.in_bstride = c.src_bs;
-  } else {
-    t.in = ll_buf(c, g, k0 - 1);
-    t.in_stride = ll_pitch(g.w[k0 - 1]);
-    t.in_bstride = ws_bs;
+    t.out = const_cast<void*>(px);
+    t.out_stride = px_stride;
+    t.out_bstride = px_bs;
   }
-  t.out = c.dst;
-  t.out_stride = c.dst_stride;
-  t.out_bstride = c.dst_bs;
   return launch_tail(dir, c.mode, t, stream);
 }
 
 int run_levels(int dir, const Call& c, const Geo& g, void* stream, bool tail) {
   const int k0 = tail ? tail_first_level(dir, g, c.batch) : 0;
-  const int order_begin = dir == kFwd ? 1 : g.L, order_end = dir == kFwd ? (k0 ? k0 : g.L + 1) : 0;
+  // forward: levels 1 .. k0-1, then the tail; inverse: the tail, then k0-1 .. 1
+  const int order_begin = dir == kFwd ? 1 : (k0 ? k0 - 1 : g.L), order_end = dir == kFwd ? (k0 ? k0 : g.L + 1) : 0;
   const int step = dir == kFwd ? 1 : -1;
   Probe pr;
   {
@@ -252,6 +264,20 @@ int run_levels(int dir, const Call& c, const Geo& g, void* stream, bool tail) {
     pr = g_probe;
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
+  auto run_tail = [&]() -> int {
+    // the tail levels share one launch; a probe on any of them times it
+    const bool probed = pr.dir == dir && pr.level >= k0;
+    if (probed && hipEventRecord(pr.begin, s) != hipSuccess) return fail(DWT2_ERR_HIP, "probe event record failed");
+    const int err = launch_tail_levels(dir, c, g, k0, stream);
+    if (err != hipSuccess)
+      return fail(DWT2_ERR_HIP, "tail levels %d..%d launch failed: %s", k0, g.L, hipGetErrorString((hipError_t)err));
+    if (probed && hipEventRecord(pr.end, s) != hipSuccess) return fail(DWT2_ERR_HIP, "probe event record failed");
+    return DWT2_OK;
+  };
+  if (k0 && dir != kFwd) {
+    const int st = run_tail();
+    if (st) return st;
+  }
   for (int k = order_begin; k != order_end; k += step) {
     LevelLaunch a;
     int ch;
@@ -263,15 +289,7 @@ int run_levels(int dir, const Call& c, const Geo& g, void* stream, bool tail) {
       return fail(DWT2_ERR_HIP, "level %d launch failed: %s", k, hipGetErrorString((hipError_t)err));
     if (probed && hipEventRecord(pr.end, s) != hipSuccess) return fail(DWT2_ERR_HIP, "probe event record failed");
   }
-  if (k0) {
-    // the tail levels share one launch; a probe on any of them times it
-    const bool probed = pr.dir == dir && pr.level >= k0;
-    if (probed && hipEventRecord(pr.begin, s) != hipSuccess) return fail(DWT2_ERR_HIP, "probe event record failed");
-    const int err = launch_tail_levels(dir, c, g, k0, stream);
-    if (err != hipSuccess)
-      return fail(DWT2_ERR_HIP, "tail levels %d..%d launch failed: %s", k0, g.L, hipGetErrorString((hipError_t)err));
-    if (probed && hipEventRecord(pr.end, s) != hipSuccess) return fail(DWT2_ERR_HIP, "probe event record failed");
-  }
+  if (k0 && dir == kFwd) return run_tail();
   return DWT2_OK;
 }
 

@@ -124,8 +124,8 @@ struct SepLevel {
 };
 int launch_separable_level(int mode, const SepLevel& a, void* stream);
 
-// Tail kernel (the last 2..kTailMaxLevels levels of a plain call in one
-// launch): tile edge at the first tail level's input, workgroup size, LDS
+// Tail kernels (the last 2..kTailMaxLevels levels of a plain forward or
+// inverse call in one launch): tile edge at the first tail level's input, workgroup size, LDS
 // elements (region arrays of the n levels plus three predict arrays, n = 3),
 // and the largest first-tail-level input (pixels over the batch) it takes.
 constexpr int kTailMaxLevels = 3;
@@ -134,9 +134,11 @@ constexpr int kTailBlock = 1024;
 constexpr int kTailLds = 17024;
 constexpr int64_t kTailArea = 1024 * 1024;
 struct TailArgs {
-  const void* in;        // forward: the first tail level's input (image or LL buffer)
+  const void* in;        // forward: the finest tail level's pixels (image or LL buffer);
+                         // inverse: the packed coefficient array
   int64_t in_stride, in_bstride;
-  void* out;             // forward: the packed coefficient array
+  void* out;             // forward: the packed coefficient array; inverse: the finest
+                         // tail level's pixels
   int64_t out_stride, out_bstride;
   int32_t n, batch, tiles_x, tiles_y;
   int32_t W[kTailMaxLevels + 1], H[kTailMaxLevels + 1];  // level sizes from the first tail input

@@ -1344,6 +1344,158 @@ __global__ __launch_bounds__(kTailBlock) void tail_fwd(TailArgs a) {
   }
 }
 
+// Inverse tail: the last n levels of an inverse (coarsest first) in one
+// launch.  Each workgroup owns a kTailS x kTailS tile of the finest tail
+// output and works back through the coarser levels: output pixels [d0, d1)
+// of a level need its quadruples q0..q1, their coefficients one quadruple
+// around (read through the symmetric extension of the interleaved array, as
+// the strip kernels read them), and the LL pixels the update at q0..q1+1
+// reads, which the coarser level produces (the coarsest reads them from the
+// packed array).  Every array is kTailInvE wide; the index facts are walked
+// on the CPU for many sizes.
+constexpr int kTailInvE = kTailS / 2 + 2;
+constexpr int kTailInvPasses = (kTailInvE + kTailRows - 1) / kTailRows;
+
+__device__ __forceinline__ int band_near(int q, int n, int par) { return (fold_near(2 * q + par, n) - par) >> 1; }
+
+template <typename T>
+__global__ __launch_bounds__(kTailBlock) void tail_inv(TailArgs a) {
+  __shared__ T lds[8 * kTailInvE * kTailInvE];
+  constexpr int E = kTailInvE, EE = E * E;
+  T* CHL = lds;           // coefficients over quadruples [q0 - 1, q1 + 1]
+  T* CLH = CHL + EE;
+  T* CHH = CLH + EE;
+  T* U0 = CHH + EE;       // undone update (float: a, b', c'; int: b1, a, c1)
+  T* U1 = U0 + EE;
+  T* U2 = U1 + EE;
+  T* XB[2] = {U2 + EE, U2 + 2 * EE};  // LL input of a level / its output
+  const int lx = threadIdx.x & (kTailRowT - 1), ly = threadIdx.x / kTailRowT;
+  const int tx = blockIdx.x % a.tiles_x, ty = blockIdx.x / a.tiles_x;
+  const int n = a.n;
+  // ranges per level (x, y): output pixels [d0, d1), quadruples [q0, q1]
+  int d0x[kTailMaxLevels + 1], d1x[kTailMaxLevels + 1], d0y[kTailMaxLevels + 1], d1y[kTailMaxLevels + 1];
+  d0x[0] = tx * kTailS;
+  d1x[0] = min(tx * kTailS + kTailS, a.W[0]);
+  d0y[0] = ty * kTailS;
+  d1y[0] = min(ty * kTailS + kTailS, a.H[0]);
+  for (int m = 0; m < n; ++m) {
+    const int q0x = d0x[m] >> 1, q1x = (d1x[m] - 1) >> 1, q0y = d0y[m] >> 1, q1y = (d1y[m] - 1) >> 1;
+    d0x[m + 1] = min(q0x, band_near(q1x + 1, a.W[m], 0));
+    d1x[m + 1] = min(q1x + 2, a.W[m + 1]);
+    d0y[m + 1] = min(q0y, band_near(q1y + 1, a.H[m], 0));
+    d1y[m + 1] = min(q1y + 2, a.H[m + 1]);
+  }
+  for (int img = blockIdx.y; img < a.batch; img += gridDim.y) {
+    const T* src = static_cast<const T*>(a.in) + img * a.in_bstride;
+    T* out = static_cast<T*>(a.out) + img * a.out_bstride;
+    int cur = 0;  // XB[cur]: LL input of the level being inverted
+    // the coarsest level's LL from the packed array
+    {
+      const int x0 = d0x[n], y0 = d0y[n], w = d1x[n] - x0, h = d1y[n] - y0;
+      T v[kTailInvPasses];
+#pragma unroll
+      for (int k = 0; k < kTailInvPasses; ++k) {
+        const int y = min(ly + k * kTailRows, h - 1), x = min(lx, w - 1);
+        v[k] = src[(int64_t)(y0 + y) * a.in_stride + x0 + x];
+      }
+#pragma unroll
+      for (int k = 0; k < kTailInvPasses; ++k)
+        if (lx < w && ly + k * kTailRows < h) XB[cur][(ly + k * kTailRows) * E + lx] = v[k];
+    }
+    for (int m = n - 1; m >= 0; --m) {
+      const int Wm = a.W[m], Hm = a.H[m];
+      const int ns_w = (Wm + 1) >> 1, ns_h = (Hm + 1) >> 1;
+      const int q0x = d0x[m] >> 1, q1x = (d1x[m] - 1) >> 1, q0y = d0y[m] >> 1, q1y = (d1y[m] - 1) >> 1;
+      const int bx = q0x - 1, by = q0y - 1;  // array origin (quadruples)
+      // this thread's column: quadruple bx + lx, with its folded band columns
+      const int qx = bx + lx;
+      const bool col_c = qx <= q1x + 1;  // inside the coefficient range
+      const int cl = band_near(qx, Wm, 0), ch = ns_w + band_near(qx, Wm, 1);
+      // coefficients HL, LH, HH over [q0 - 1, q1 + 1]
+      {
+        const int h = q1y - q0y + 3;
+        T vhl[kTailInvPasses], vlh[kTailInvPasses], vhh[kTailInvPasses];
+#pragma unroll
+        for (int k = 0; k < kTailInvPasses; ++k) {
+          const int qy = by + min(ly + k * kTailRows, h - 1);
+          const int re = band_near(qy, Hm, 0), ro = ns_h + band_near(qy, Hm, 1);
+          const int c0 = col_c ? cl : 0, c1 = col_c ? ch : 0;
+          vhl[k] = src[(int64_t)re * a.in_stride + c1];
+          vlh[k] = src[(int64_t)ro * a.in_stride + c0];
+          vhh[k] = src[(int64_t)ro * a.in_stride + c1];
+        }
+#pragma unroll
+        for (int k = 0; k < kTailInvPasses; ++k) {
+          const int row = ly + k * kTailRows;
+          if (col_c && row < h) {
+            CHL[row * E + lx] = vhl[k];
+            CLH[row * E + lx] = vlh[k];
+            CHH[row * E + lx] = vhh[k];
+          }
+        }
+      }
+      __syncthreads();
+      const T* LL = XB[cur];
+      const int lx0 = d0x[m + 1], ly0 = d0y[m + 1];
+      const int llc = band_near(qx, Wm, 0) - lx0;  // this column's LL position in XB[cur]
+      if constexpr (std::is_same<T, float>::value) {
+        // undo the update at [q0, q1 + 1]
+        for (int qy = q0y + ly; qy <= q1y + 1; qy += kTailRows) {
+          if (qx < q0x || qx > q1x + 1) continue;
+          const int o = (qy - by) * E + lx;
+          const T ll = LL[(band_near(qy, Hm, 0) - ly0) * E + llc];
+          f32_inv_update(ll, CHL[o - 1], CHL[o], CLH[o - E], CLH[o], CHH[o - E - 1], CHH[o - E], CHH[o - 1], CHH[o],
+                         U0[o], U1[o], U2[o]);
+        }
+      } else {
+        // b1 over columns [q0 - 1, q1 + 1], rows [q0, q1 + 1]
+        for (int qy = q0y + ly; qy <= q1y + 1; qy += kTailRows) {
+          if (!col_c) continue;
+          const int o = (qy - by) * E + lx;
+          U0[o] = i32_inv_b1(CHL[o], CHH[o - E], CHH[o]);
+        }
+        __syncthreads();
+        for (int qy = q0y + ly; qy <= q1y + 1; qy += kTailRows) {
+          if (qx < q0x || qx > q1x + 1) continue;
+          const int o = (qy - by) * E + lx;
+          const T ll = LL[(band_near(qy, Hm, 0) - ly0) * E + llc];
+          i32_inv_update(ll, CLH[o - E], CLH[o], U0[o - 1], U0[o], CHH[o - 1], CHH[o], U1[o], U2[o]);
+        }
+      }
+      __syncthreads();
+      // undo the predict at [q0, q1]: pixels of quadruple (qx, qy)
+      T* X = m > 0 ? XB[cur ^ 1] : nullptr;
+      const int ox = d0x[m], oy = d0y[m];
+      for (int qy = q0y + ly; qy <= q1y; qy += kTailRows) {
+        if (qx < q0x || qx > q1x) continue;
+        const int o = (qy - by) * E + lx;
+        T va, vb, vc, vd;
+        if constexpr (std::is_same<T, float>::value) {
+          va = U0[o];
+          f32_inv_predict(U0[o], U0[o + 1], U0[o + E], U0[o + E + 1], U1[o], U1[o + E], U2[o], U2[o + 1], CHH[o], vb,
+                          vc, vd);
+        } else {
+          va = U1[o];
+          vc = i32_inv_c(U2[o], U1[o], U1[o + E]);
+          const int cR = i32_inv_c(U2[o + 1], U1[o + 1], U1[o + E + 1]);
+          i32_inv_predict(U1[o], U1[o + 1], U0[o], U0[o + E], vc, cR, CHH[o], vb, vd);
+        }
+        const int px = 2 * qx, py = 2 * qy;
+        const T vals[4] = {va, vb, vc, vd};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int x = px + (k & 1), y = py + (k >> 1);
+          if (x < d0x[m] || x >= d1x[m] || y < d0y[m] || y >= d1y[m]) continue;
+          if (m > 0) X[(y - oy) * E + (x - ox)] = vals[k];
+          else out[(int64_t)y * a.out_stride + x] = vals[k];
+        }
+      }
+      __syncthreads();
+      cur ^= 1;
+    }
+  }
+}
+
 __global__ void zero_kernel(uint32_t* p, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     p[i] = 0u;
@@ -1437,9 +1589,15 @@ int launch_table(int dir, int mode, int chunk, const TableArgs& a, void* stream)
 int launch_tail(int dir, int mode, const TailArgs& a, void* stream) {
   hipStream_t s = static_cast<hipStream_t>(stream);
   const dim3 grid((unsigned)(a.tiles_x * a.tiles_y), (unsigned)(a.batch < 65535 ? a.batch : 65535));
-  if (dir != kFwd) return hipErrorInvalidValue;
-  if (mode == DWT2_F32) hipLaunchKernelGGL(tail_fwd<float>, grid, dim3(kTailBlock), 0, s, a);
-  else hipLaunchKernelGGL(tail_fwd<int>, grid, dim3(kTailBlock), 0, s, a);
+  if (dir == kFwd) {
+    if (mode == DWT2_F32) hipLaunchKernelGGL(tail_fwd<float>, grid, dim3(kTailBlock), 0, s, a);
+    else hipLaunchKernelGGL(tail_fwd<int>, grid, dim3(kTailBlock), 0, s, a);
+  } else if (dir == kInv) {
+    if (mode == DWT2_F32) hipLaunchKernelGGL(tail_inv<float>, grid, dim3(kTailBlock), 0, s, a);
+    else hipLaunchKernelGGL(tail_inv<int>, grid, dim3(kTailBlock), 0, s, a);
+  } else {
+    return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

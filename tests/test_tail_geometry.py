@@ -144,3 +144,96 @@ def test_tail_geometry_random():
             continue
         walk(w0, h0, n)
         done += 1
+
+
+# ------------------------------------------------------------- inverse tail
+
+def band_idx(q, n, par):
+    return (fold(2 * q + par, n) - par) >> 1
+
+
+def inv_ranges(d0, d1, n_levels, sizes):
+    """Per level m (0 = finest), the needed output pixel range [d0, d1) and
+    the quadruple range [q0, q1] on one axis.  Level m + 1 must produce the
+    LL pixels the update at [q0, q1 + 1] reads through the fold: from
+    min(q0, fold of q1 + 1) (the fold decreases past the edge) to
+    min(q1 + 2, sizes[m + 1])."""
+    out = []
+    for m in range(n_levels):
+        q0, q1 = d0 >> 1, (d1 - 1) >> 1
+        out.append((d0, d1, q0, q1))
+        d0, d1 = min(q0, band_idx(q1 + 1, sizes[m], 0)), min(q1 + 2, sizes[m + 1])
+    out.append((d0, d1, None, None))         # LL range of the coarsest level, read from the packed array
+    return out
+
+
+def walk_inv(w0, h0, n):
+    W, H = sizes_from(w0, h0, n)
+    tiles_x, tiles_y = -(-w0 // K_TAIL_S), -(-h0 // K_TAIL_S)
+    E = K_TAIL_S // 2 + 2                      # largest coefficient range per axis
+    assert 8 * E * E <= K_TAIL_LDS
+    written0 = {}
+    for ty in range(tiles_y):
+        for tx in range(tiles_x):
+            rx = inv_ranges(tx * K_TAIL_S, min(tx * K_TAIL_S + K_TAIL_S, w0), n, W)
+            ry = inv_ranges(ty * K_TAIL_S, min(ty * K_TAIL_S + K_TAIL_S, h0), n, H)
+            produced = None                  # LL pixels the coarser level produced (level m's LL input)
+            for m in reversed(range(n)):
+                d0x, d1x, q0x, q1x = rx[m]
+                d0y, d1y, q0y, q1y = ry[m]
+                assert q1x - q0x + 3 <= E and q1y - q0y + 3 <= E
+                # LL range this level reads (stored in an E x E array)
+                assert rx[m + 1][1] - rx[m + 1][0] <= E and ry[m + 1][1] - ry[m + 1][0] <= E
+                for (q, size, par) in [(q, W[m], p) for q in range(q0x - 1, q1x + 2) for p in (0, 1)] + \
+                        [(q, H[m], p) for q in range(q0y - 1, q1y + 2) for p in (0, 1)]:
+                    assert -2 <= 2 * q + par <= size + 2, (w0, h0, n, m, q)
+                    assert fold_near(2 * q + par, size) == fold(2 * q + par, size)
+                # LL reads of the inverse update at [q0, q1 + 1]
+                for qy in range(q0y, q1y + 2):
+                    for qx in range(q0x, q1x + 2):
+                        ly, lx = band_idx(qy, H[m], 0), band_idx(qx, W[m], 0)
+                        if m + 1 < n:
+                            assert (lx, ly) in produced, (w0, h0, n, m, qx, qy)
+                            d0n_x, d1n_x = rx[m + 1][0], rx[m + 1][1]
+                            d0n_y, d1n_y = ry[m + 1][0], ry[m + 1][1]
+                            assert d0n_x <= lx < d1n_x and d0n_y <= ly < d1n_y
+                        else:
+                            assert rx[n][0] <= lx < rx[n][1] and ry[n][0] <= ly < ry[n][1]
+                            assert 0 <= lx < W[m + 1] and 0 <= ly < H[m + 1]
+                # this level's output pixels
+                out = {(x, y) for y in range(2 * q0y, 2 * q1y + 2) for x in range(2 * q0x, 2 * q1x + 2)
+                       if d0x <= x < d1x and d0y <= y < d1y}
+                assert len(out) == (d1x - d0x) * (d1y - d0y)
+                if m == 0:
+                    for p in out:
+                        assert p not in written0
+                        written0[p] = (tx, ty)
+                produced = out
+    assert len(written0) == w0 * h0
+
+
+@pytest.mark.parametrize("w0,h0,n", [(16, 16, 3), (17, 33, 3), (64, 64, 3), (65, 65, 3), (130, 200, 3),
+                                     (1024, 1024, 3), (8, 9, 2), (127, 66, 2), (300, 17, 2)])
+def test_inverse_tail_geometry(w0, h0, n):
+    W, H = sizes_from(w0, h0, n)
+    assert min(W[:n]) >= 4 and min(H[:n]) >= 4
+    walk_inv(w0, h0, n)
+
+
+def test_inverse_tail_geometry_random():
+    rng = random.Random(29)
+    done = 0
+    while done < 25:
+        n = rng.choice([2, 3])
+        w0, h0 = rng.randint(4, 400), rng.randint(4, 400)
+        W, H = sizes_from(w0, h0, n)
+        if min(W[:n]) < 4 or min(H[:n]) < 4:
+            continue
+        walk_inv(w0, h0, n)
+        done += 1
+
+
+def test_fold_near_covers_the_inverse_range():
+    for n in range(4, 40):
+        for p in range(-2, n + 3):
+            assert fold_near(p, n) == fold(p, n), (p, n)
