@@ -206,7 +206,6 @@ Probe g_probe;
 // than with the tail's recomputed halos; the tail wins only where launch
 // latency dominates.
 static int tail_first_level(int dir, const Geo& g, int batch) {
-  if (dir == kBwd) return 0;
   int k = g.L, n = 0;
   while (k >= 1 && n < kTailMaxLevels && (int64_t)g.w[k - 1] * g.h[k - 1] * batch <= kTailArea) {
     --k;

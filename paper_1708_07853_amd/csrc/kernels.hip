@@ -1496,6 +1496,113 @@ __global__ __launch_bounds__(kTailBlock) void tail_inv(TailArgs a) {
   }
 }
 
+// Adjoint tail: the last n levels of W^T (coarsest first) in one launch, on
+// the inverse tail's tiles.  The adjoint reads no symmetric extension:
+// coefficients outside their bands are zero and the transposed boundary
+// weights of the axis carry the edges, exactly as in the strip kernel.
+// Output pixels [d0, d1) of a level need its quadruples q0..q1, the
+// transposed update at q0-1..q1, coefficients at q0-1..q1+1, and LL pixels
+// [max(q0 - 1, 0), min(q1 + 2, size)) from the coarser level.
+__global__ __launch_bounds__(kTailBlock) void tail_bwd(TailArgs a) {
+  __shared__ float lds[8 * kTailInvE * kTailInvE];
+  constexpr int E = kTailInvE, EE = E * E;
+  float* CLL = lds;          // coefficients over quadruples [q0 - 1, q1 + 1]
+  float* CHL = CLL + EE;
+  float* CLH = CHL + EE;
+  float* CHH = CLH + EE;
+  float* GB = CHH + EE;      // transposed update over [q0 - 1, q1]
+  float* GC = GB + EE;
+  float* GD = GC + EE;
+  float* XO = GD + EE;       // a level's output pixels (the finer level's LL)
+  const int lx = threadIdx.x & (kTailRowT - 1), ly = threadIdx.x / kTailRowT;
+  const int tx = blockIdx.x % a.tiles_x, ty = blockIdx.x / a.tiles_x;
+  const int n = a.n;
+  int d0x[kTailMaxLevels + 1], d1x[kTailMaxLevels + 1], d0y[kTailMaxLevels + 1], d1y[kTailMaxLevels + 1];
+  d0x[0] = tx * kTailS;
+  d1x[0] = min(tx * kTailS + kTailS, a.W[0]);
+  d0y[0] = ty * kTailS;
+  d1y[0] = min(ty * kTailS + kTailS, a.H[0]);
+  for (int m = 0; m < n; ++m) {
+    const int q0x = d0x[m] >> 1, q1x = (d1x[m] - 1) >> 1, q0y = d0y[m] >> 1, q1y = (d1y[m] - 1) >> 1;
+    d0x[m + 1] = max(q0x - 1, 0);
+    d1x[m + 1] = min(q1x + 2, a.W[m + 1]);
+    d0y[m + 1] = max(q0y - 1, 0);
+    d1y[m + 1] = min(q1y + 2, a.H[m + 1]);
+  }
+  for (int img = blockIdx.y; img < a.batch; img += gridDim.y) {
+    const float* src = static_cast<const float*>(a.in) + img * a.in_bstride;
+    float* out = static_cast<float*>(a.out) + img * a.out_bstride;
+    for (int m = n - 1; m >= 0; --m) {
+      const int Wm = a.W[m], Hm = a.H[m];
+      const int ns_w = (Wm + 1) >> 1, ns_h = (Hm + 1) >> 1, nd_w = Wm >> 1, nd_h = Hm >> 1;
+      const int q0x = d0x[m] >> 1, q1x = (d1x[m] - 1) >> 1, q0y = d0y[m] >> 1, q1y = (d1y[m] - 1) >> 1;
+      const int bx = q0x - 1, by = q0y - 1;
+      const int qx = bx + lx;
+      const bool col_c = qx <= q1x + 1;
+      // coefficients over [q0 - 1, q1 + 1]; zero outside their bands.  LL
+      // comes from the packed array at the coarsest level, else from the
+      // coarser level's output in XO (LDS).
+      {
+        const int h = q1y - q0y + 3;
+        const int lxo = d0x[m + 1], lyo = d0y[m + 1];
+        float vll[kTailInvPasses], vhl[kTailInvPasses], vlh[kTailInvPasses], vhh[kTailInvPasses];
+#pragma unroll
+        for (int k = 0; k < kTailInvPasses; ++k) {
+          const int qy = by + min(ly + k * kTailRows, h - 1);
+          const bool rl = qy >= 0 && qy < ns_h, rh = qy >= 0 && qy < nd_h;
+          const bool cl = qx >= 0 && qx < ns_w, chh = qx >= 0 && qx < nd_w;
+          const int ry = rl ? qy : 0, ryo = ns_h + (rh ? qy : 0), cx = cl ? qx : 0, cxh = ns_w + (chh ? qx : 0);
+          const bool ok = col_c;
+          vhl[k] = (ok && rl && chh) ? src[(int64_t)ry * a.in_stride + cxh] : 0.f;
+          vlh[k] = (ok && rh && cl) ? src[(int64_t)ryo * a.in_stride + cx] : 0.f;
+          vhh[k] = (ok && rh && chh) ? src[(int64_t)ryo * a.in_stride + cxh] : 0.f;
+          if (m == n - 1) vll[k] = (ok && rl && cl) ? src[(int64_t)ry * a.in_stride + cx] : 0.f;
+          else vll[k] = (ok && rl && cl) ? XO[(ry - lyo) * E + (cx - lxo)] : 0.f;
+        }
+#pragma unroll
+        for (int k = 0; k < kTailInvPasses; ++k) {
+          const int row = ly + k * kTailRows;
+          if (col_c && row < h) {
+            CLL[row * E + lx] = vll[k];
+            CHL[row * E + lx] = vhl[k];
+            CLH[row * E + lx] = vlh[k];
+            CHH[row * E + lx] = vhh[k];
+          }
+        }
+      }
+      __syncthreads();
+      // transposed update at [q0 - 1, q1]
+      const AxisW h0 = axis_weights(qx, Wm);
+      for (int qy = by + ly; qy <= q1y; qy += kTailRows) {
+        if (qx > q1x) continue;
+        const int o = (qy - by) * E + lx;
+        f32_adj_a(CLL[o], CLL[o + 1], CLL[o + E], CLL[o + E + 1], CHL[o], CHL[o + E], CLH[o], CLH[o + 1], CHH[o], h0,
+                  axis_weights(qy, Hm), GB[o], GC[o], GD[o]);
+      }
+      __syncthreads();
+      // transposed predict at [q0, q1]: pixels of quadruple (qx, qy)
+      const int ox = d0x[m], oy = d0y[m];
+      for (int qy = q0y + ly; qy <= q1y; qy += kTailRows) {
+        if (qx < q0x || qx > q1x) continue;
+        const int o = (qy - by) * E + lx;
+        float ga2, gb2, gc2;
+        f32_adj_b(CLL[o], GB[o - 1], GB[o], GC[o - E], GC[o], GD[o - E - 1], GD[o - E], GD[o - 1], GD[o], h0,
+                  axis_weights(qy, Hm), ga2, gb2, gc2);
+        const float vals[4] = {ga2, gb2, gc2, GD[o]};
+        const int px = 2 * qx, py = 2 * qy;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int x = px + (k & 1), y = py + (k >> 1);
+          if (x < d0x[m] || x >= d1x[m] || y < d0y[m] || y >= d1y[m]) continue;
+          if (m > 0) XO[(y - oy) * E + (x - ox)] = vals[k];
+          else out[(int64_t)y * a.out_stride + x] = vals[k];
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
 __global__ void zero_kernel(uint32_t* p, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     p[i] = 0u;
@@ -1596,7 +1703,8 @@ int launch_tail(int dir, int mode, const TailArgs& a, void* stream) {
     if (mode == DWT2_F32) hipLaunchKernelGGL(tail_inv<float>, grid, dim3(kTailBlock), 0, s, a);
     else hipLaunchKernelGGL(tail_inv<int>, grid, dim3(kTailBlock), 0, s, a);
   } else {
-    return hipErrorInvalidValue;
+    if (mode != DWT2_F32) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(tail_bwd, grid, dim3(kTailBlock), 0, s, a);
   }
   return hipGetLastError();
 }

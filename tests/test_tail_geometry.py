@@ -237,3 +237,58 @@ def test_fold_near_covers_the_inverse_range():
     for n in range(4, 40):
         for p in range(-2, n + 3):
             assert fold_near(p, n) == fold(p, n), (p, n)
+
+
+# ------------------------------------------------------------- adjoint tail
+
+def adj_ranges(d0, d1, n_levels, sizes):
+    """Adjoint tail, one axis: output pixels [d0, d1) of level m need
+    quadruples [q0, q1], the transposed update at [q0 - 1, q1], coefficients
+    at [q0 - 1, q1 + 1] (zero outside the bands: nothing folds) and LL pixels
+    [max(q0 - 1, 0), min(q1 + 2, sizes[m + 1])) from the coarser level."""
+    out = []
+    for m in range(n_levels):
+        q0, q1 = d0 >> 1, (d1 - 1) >> 1
+        out.append((d0, d1, q0, q1))
+        d0, d1 = max(q0 - 1, 0), min(q1 + 2, sizes[m + 1])
+    out.append((d0, d1, None, None))
+    return out
+
+
+def walk_adj(w0, h0, n):
+    W, H = sizes_from(w0, h0, n)
+    tiles_x, tiles_y = -(-w0 // K_TAIL_S), -(-h0 // K_TAIL_S)
+    E = K_TAIL_S // 2 + 2
+    written0 = {}
+    for ty in range(tiles_y):
+        for tx in range(tiles_x):
+            rx = adj_ranges(tx * K_TAIL_S, min(tx * K_TAIL_S + K_TAIL_S, w0), n, W)
+            ry = adj_ranges(ty * K_TAIL_S, min(ty * K_TAIL_S + K_TAIL_S, h0), n, H)
+            produced = None
+            for m in reversed(range(n)):
+                d0x, d1x, q0x, q1x = rx[m]
+                d0y, d1y, q0y, q1y = ry[m]
+                assert q1x - q0x + 3 <= E and q1y - q0y + 3 <= E
+                assert rx[m + 1][1] - rx[m + 1][0] <= E and ry[m + 1][1] - ry[m + 1][0] <= E
+                ns_w, ns_h = W[m + 1], H[m + 1]
+                for qy in range(q0y - 1, q1y + 2):
+                    for qx in range(q0x - 1, q1x + 2):
+                        if 0 <= qx < ns_w and 0 <= qy < ns_h:   # an LL read that is not a zero
+                            if m + 1 < n:
+                                assert (qx, qy) in produced, (w0, h0, n, m, qx, qy)
+                            assert rx[m + 1][0] <= qx < rx[m + 1][1] and ry[m + 1][0] <= qy < ry[m + 1][1]
+                out = {(x, y) for y in range(2 * q0y, 2 * q1y + 2) for x in range(2 * q0x, 2 * q1x + 2)
+                       if d0x <= x < d1x and d0y <= y < d1y}
+                assert len(out) == (d1x - d0x) * (d1y - d0y)
+                if m == 0:
+                    for p in out:
+                        assert p not in written0
+                        written0[p] = (tx, ty)
+                produced = out
+    assert len(written0) == w0 * h0
+
+
+@pytest.mark.parametrize("w0,h0,n", [(4, 4, 2), (5, 3, 2), (16, 16, 3), (65, 65, 3), (130, 200, 3),
+                                     (1024, 1024, 3), (9, 15, 3), (300, 17, 2)])
+def test_adjoint_tail_geometry(w0, h0, n):
+    walk_adj(w0, h0, n)
