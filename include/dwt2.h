@@ -206,11 +206,13 @@ int dwt2_set_tiling(int32_t seg, int32_t chunk);
 
 /* Process-wide choice of how levels are chained, for tests and
  * measurements: 0 (default) = one kernel launch per level, except that the
- * forward's last 2-3 levels, when their inputs hold at most 1024 x 1024
- * pixels over the batch, share one launch (each workgroup runs them in LDS
- * on its tile plus a recompute halo); 1 = every level of a call in one cooperative persistent launch
- * whose work items wait only for the rows they read; 2 = one launch per
- * level throughout.  Results are bit-identical.  Returns DWT2_OK or
+ * 2-3 coarsest levels, when their inputs hold at most 1024 x 1024 pixels
+ * over the batch, share one launch (each workgroup runs them in LDS on its
+ * tile plus a recompute halo; the forward's last levels, the inverse's and
+ * the adjoint's first ones; the inverse also needs the coarsest input at
+ * least 4 x 4); 1 = every level of a call in one cooperative persistent
+ * launch whose work items wait only for the rows they read; 2 = one launch
+ * per level throughout.  Results are bit-identical.  Returns DWT2_OK or
  * DWT2_ERR_ARG. */
 int dwt2_set_path(int32_t path);
 
