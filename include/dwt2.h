@@ -147,6 +147,29 @@ int dwt2_fwd_separable(const void* src, int64_t src_stride,
                        int32_t boundary, void* workspace,
                        size_t workspace_bytes, void* stream);
 
+/* Second baseline for comparison, not the product path: the forward
+ * transform with one launch per level in which each 256-thread workgroup
+ * copies a 128 x 32-pixel tile of the level input plus a 2-pixel halo
+ * (through the symmetric extension) into LDS, lifts it there and stores its
+ * 64 x 16 quadruples' coefficients.  Consecutive lifting steps are separated
+ * by a workgroup barrier, the GPU form of the paper's synchronisation
+ * steps, so the two schemes differ only in their step count:
+ *   scheme DWT2_SCHEME_SEPARABLE:    horizontal predict, vertical predict,
+ *       horizontal update, vertical update (§2, eq. (3)): four steps;
+ *   scheme DWT2_SCHEME_NONSEPARABLE: spatial predict, spatial update (§3,
+ *       eq. (5)): two steps.
+ * Arguments, layout, ownership and errors are those of dwt2_fwd, with the
+ * workspace of dwt2_workspace_size; an unknown scheme is DWT2_ERR_ARG.
+ * Integer results equal dwt2_fwd's for both schemes.  Float results of the
+ * non-separable scheme equal dwt2_fwd's bit for bit; those of the separable
+ * scheme equal dwt2_fwd_separable's bit for bit. */
+enum { DWT2_SCHEME_SEPARABLE = 0, DWT2_SCHEME_NONSEPARABLE = 1 };
+int dwt2_fwd_lds(const void* src, int64_t src_stride, int64_t src_batch_stride,
+                 void* dst, int64_t dst_stride, int64_t dst_batch_stride,
+                 int32_t width, int32_t height, int32_t batch, int32_t levels,
+                 int32_t mode, int32_t boundary, int32_t scheme,
+                 void* workspace, size_t workspace_bytes, void* stream);
+
 /* One image of a ragged batch (all pointers device pointers). */
 typedef struct {
   const void* src;

@@ -111,12 +111,26 @@ def fwd_separable(x: torch.Tensor, levels: int, mode=None, out=None, workspace=N
     return _run("dwt2_fwd_separable", x, levels, mode, out, workspace)
 
 
+SCHEMES = {"separable": 0, "nonseparable": 1}
+
+
+def fwd_lds(x: torch.Tensor, levels: int, scheme: str = "nonseparable", mode=None, out=None,
+            workspace=None) -> torch.Tensor:
+    """The same forward transform by the LDS-tiled comparison kernels
+    (see dwt2_fwd_lds): scheme "separable" lifts each tile in four
+    barrier-separated steps (eq. (3)), "nonseparable" in two (eq. (5)).
+    For comparisons, not for production use."""
+    if scheme not in SCHEMES:
+        raise ValueError(f"scheme must be one of {sorted(SCHEMES)}")
+    return _run("dwt2_fwd_lds", x, levels, mode, out, workspace, extra=(SCHEMES[scheme],))
+
+
 def separable_workspace_size(w: int, h: int, levels: int, batch: int = 1, mode: int = DWT2_F32) -> int:
     return int(_lib.load().dwt2_separable_workspace_size(w, h, batch, levels, mode))
 
 
 def _run(name: str, x: torch.Tensor, levels: int, mode, out: torch.Tensor | None,
-         workspace: torch.Tensor | None = None) -> torch.Tensor:
+         workspace: torch.Tensor | None = None, extra: tuple = ()) -> torch.Tensor:
     lib = _lib.load()
     mode = _mode_of(x, mode)
     xb = _as_batch(x)
@@ -140,7 +154,7 @@ def _run(name: str, x: torch.Tensor, levels: int, mode, out: torch.Tensor | None
         status = getattr(lib, name)(
             xb.data_ptr(), xb.stride(1), xb.stride(0) if batch > 1 else 0,
             ob.data_ptr(), ob.stride(1), ob.stride(0) if batch > 1 else 0,
-            w, h, batch, levels, mode, DWT2_EXT_SYMMETRIC,
+            w, h, batch, levels, mode, DWT2_EXT_SYMMETRIC, *extra,
             ws.data_ptr() if ws is not None else None, nbytes, _stream())
     _lib.check(status)
     return out

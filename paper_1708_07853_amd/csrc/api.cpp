@@ -399,10 +399,55 @@ static int run_separable(const Call& c, const Geo& g, void* stream) {
   return DWT2_OK;
 }
 
+// LDS-tiled comparison kernels: one launch per level, LL through the plain
+// workspace's buffers.
+static int run_lds(bool separable, const Call& c, const Geo& g, void* stream) {
+  const int64_t ws_bs = (int64_t)(ws_per_image(g) / 4);
+  for (int k = 1; k <= g.L; ++k) {
+    SepLevel a;
+    memset(&a, 0, sizeof a);
+    a.W = g.w[k - 1];
+    a.H = g.h[k - 1];
+    a.batch = c.batch;
+    int tx, ty;
+    if (!lds_tiles(a.W, a.H, tx, ty)) return fail(DWT2_ERR_SIZE, "level %d needs more tiles than a launch holds", k);
+    if (k == 1) {
+      a.src = c.src;
+      a.src_stride = c.src_stride;
+      a.src_bstride = c.src_bs;
+    } else {
+      a.src = ll_buf(c, g, k - 1);
+      a.src_stride = ll_pitch(g.w[k - 1]);
+      a.src_bstride = ws_bs;
+    }
+    if (k == g.L) {
+      a.ll = c.dst;
+      a.ll_stride = c.dst_stride;
+      a.ll_bstride = c.dst_bs;
+    } else {
+      a.ll = ll_buf(c, g, k);
+      a.ll_stride = ll_pitch(g.w[k]);
+      a.ll_bstride = ws_bs;
+    }
+    a.band = c.dst;
+    a.band_stride = c.dst_stride;
+    a.band_bstride = c.dst_bs;
+    const int err = launch_lds_level(separable, c.mode, a, stream);
+    if (err != hipSuccess)
+      return fail(DWT2_ERR_HIP, "LDS-tiled level %d launch failed: %s", k, hipGetErrorString((hipError_t)err));
+  }
+  return DWT2_OK;
+}
+
+// Which kernels compute a call: the product path, or one of the comparison
+// baselines (separable passes, LDS-tiled separable, LDS-tiled non-separable).
+enum { kProduct = 0, kSepPasses = 1, kLdsSep = 2, kLdsNonSep = 3 };
+
 static int transform(int dir, const void* src, int64_t src_stride, int64_t src_bs, void* dst, int64_t dst_stride,
                      int64_t dst_bs, int32_t width, int32_t height, int32_t batch, int32_t levels, int32_t mode,
                      int32_t boundary, void* workspace, size_t workspace_bytes, void* stream,
-                     bool separable = false) {
+                     int variant = kProduct) {
+  const bool separable = variant == kSepPasses;
   clear_error();
   if (!src || !dst) return fail(DWT2_ERR_ARG, "null src or dst");
   if (((uintptr_t)src | (uintptr_t)dst | (uintptr_t)workspace) & 3)
@@ -427,6 +472,7 @@ static int transform(int dir, const void* src, int64_t src_stride, int64_t src_b
   Call c{static_cast<const char*>(src), src_stride, src_bs, static_cast<char*>(dst), dst_stride, dst_bs, batch, mode,
          static_cast<char*>(workspace), sync_bytes(g, batch)};
   if (separable) return run_separable(c, g, stream);
+  if (variant == kLdsSep || variant == kLdsNonSep) return run_lds(variant == kLdsSep, c, g, stream);
   if (g_persistent.load() < 0) g_persistent.store(env_int("DWT2_PERSISTENT") == 1 ? 1 : 0);
   const int path = g_persistent.load();
   if (path == 1 && g.L <= kInlineDescs) return run_job(dir, c, g, stream);
@@ -458,7 +504,19 @@ int dwt2_fwd_separable(const void* src, int64_t src_stride, int64_t src_batch_st
                        int64_t dst_batch_stride, int32_t width, int32_t height, int32_t batch, int32_t levels,
                        int32_t mode, int32_t boundary, void* workspace, size_t workspace_bytes, void* stream) {
   return transform(kFwd, src, src_stride, src_batch_stride, dst, dst_stride, dst_batch_stride, width, height, batch,
-                   levels, mode, boundary, workspace, workspace_bytes, stream, true);
+                   levels, mode, boundary, workspace, workspace_bytes, stream, kSepPasses);
+}
+
+int dwt2_fwd_lds(const void* src, int64_t src_stride, int64_t src_batch_stride, void* dst, int64_t dst_stride,
+                 int64_t dst_batch_stride, int32_t width, int32_t height, int32_t batch, int32_t levels, int32_t mode,
+                 int32_t boundary, int32_t scheme, void* workspace, size_t workspace_bytes, void* stream) {
+  if (scheme != DWT2_SCHEME_SEPARABLE && scheme != DWT2_SCHEME_NONSEPARABLE) {
+    clear_error();
+    return fail(DWT2_ERR_ARG, "unknown scheme %d", scheme);
+  }
+  return transform(kFwd, src, src_stride, src_batch_stride, dst, dst_stride, dst_batch_stride, width, height, batch,
+                   levels, mode, boundary, workspace, workspace_bytes, stream,
+                   scheme == DWT2_SCHEME_SEPARABLE ? kLdsSep : kLdsNonSep);
 }
 
 int dwt2_fwd(const void* src, int64_t src_stride, int64_t src_batch_stride, void* dst, int64_t dst_stride,

@@ -144,6 +144,12 @@ struct TailArgs {
   int32_t W[kTailMaxLevels + 1], H[kTailMaxLevels + 1];  // level sizes from the first tail input
 };
 int launch_tail(int dir, int mode, const TailArgs& a, void* stream);
+// LDS-tiled forward level (comparison kernels): the separable steps of
+// eq. (3) or the spatial steps of eq. (5), a workgroup barrier between steps.
+// Uses src, ll, band and the sizes of a; work is unused.  lds_tiles gives
+// the grid's tile counts (returns 0 if they exceed a launch).
+int lds_tiles(int W, int H, int& tiles_x, int& tiles_y);
+int launch_lds_level(bool separable, int mode, const SepLevel& a, void* stream);
 
 // Kernel launchers (kernels.hip).  Return hipError_t as int.
 int launch_level(int dir, int mode, int chunk, const LevelLaunch& a, void* stream);

@@ -1603,6 +1603,164 @@ __global__ __launch_bounds__(kTailBlock) void tail_bwd(TailArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// LDS-tiled level kernels: the two schemes compared with their data movement
+// held equal (the comparison of §4).  Each workgroup copies a tile of the
+// level input plus a two-pixel halo on every side (through the symmetric
+// fold) into LDS, runs the lifting steps with a workgroup barrier between
+// consecutive steps, and stores its quadruples' four coefficients.
+//   separable (eq. (3)):      HP | VP | HU | VU      four barriers
+//   non-separable (eq. (5)):  spatial predict | spatial update   two barriers
+// Since the fold commutes with lifting (whole-sample symmetry keeps every
+// index's parity), computing on folded halo pixels gives exactly the values
+// the boundary rules give, so each step runs on a fixed local range.
+// ---------------------------------------------------------------------------
+constexpr int kLdsQX = 64, kLdsQY = 16;                              // output quadruples per tile
+constexpr int kLdsPX = 2 * kLdsQX + 4, kLdsPY = 2 * kLdsQY + 4;      // pixel tile incl. halo
+constexpr int kLdsBlock = 256, kLdsWaves = kLdsBlock / kWave;
+constexpr int kLdsQ1 = kLdsQX + 1, kLdsPQ = kLdsQ1 * (kLdsQY + 1);   // predicted quadruples
+
+// Separable 1-D steps: predict x - 1/2 (l + r), update x + 1/4 (l + r);
+// integer: x - floor((l + r) / 2), x + floor((l + r + 2) / 4).
+__device__ __forceinline__ float lp(float x, float l, float r) { return __fmaf_rn(-0.5f, l + r, x); }
+__device__ __forceinline__ float lu(float x, float l, float r) { return __fmaf_rn(0.25f, l + r, x); }
+__device__ __forceinline__ int lp(int x, int l, int r) { return x - ((l + r) >> 1); }
+__device__ __forceinline__ int lu(int x, int l, int r) { return x + ((l + r + 2) >> 2); }
+
+// Runs f(row, q) over quadruple columns q in [0, kLdsQX] and rows
+// [0, nrows): a wave per row for q < kLdsQX, then the last column of every
+// row in one pass of the block.
+template <typename F>
+__device__ __forceinline__ void lds_walk65(int nrows, int lane, int wv, F&& f) {
+  for (int r = wv; r < nrows; r += kLdsWaves) f(r, lane);
+  if ((int)threadIdx.x < nrows) f((int)threadIdx.x, kLdsQX);
+}
+
+template <typename T, bool SEP>
+__global__ __launch_bounds__(kLdsBlock) void lds_level(SepLevel a, int tiles_x) {
+  __shared__ T X[kLdsPX * kLdsPY];
+  __shared__ T PB[SEP ? 1 : 3 * kLdsPQ];
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  const int tile = xcd_remap(blockIdx.x, gridDim.x);
+  const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
+  const int W = a.W, H = a.H;
+  const int ns_w = (W + 1) >> 1, ns_h = (H + 1) >> 1, nd_w = W >> 1, nd_h = H >> 1;
+  const int ox = 2 * kLdsQX * tx - 2, oy = 2 * kLdsQY * ty - 2;  // image position of X[0]
+  // this lane's folded source columns: lane, lane + 64, and 128 + lane % 4
+  // (stored by lanes 0..3 only; the others reload one of those four)
+  const int gc0 = fold_idx(ox + lane, W), gc1 = fold_idx(ox + kWave + lane, W);
+  const int gc2 = fold_idx(ox + 2 * kWave + (lane & 3), W);
+  constexpr int kRowsPerWave = kLdsPY / kLdsWaves;
+  static_assert(kLdsPY % kLdsWaves == 0 && kLdsPX == 2 * kWave + 4, "tile shape");
+  const int gqx = tx * kLdsQX + lane;  // image quadruple column of local column lane + 1
+  for (int img = blockIdx.y; img < a.batch; img += gridDim.y) {
+    const T* src = static_cast<const T*>(a.src) + img * a.src_bstride;
+    T* ll = static_cast<T*>(a.ll) + img * a.ll_bstride;
+    T* band = static_cast<T*>(a.band) + img * a.band_bstride;
+    {
+      T v0[kRowsPerWave], v1[kRowsPerWave], v2[kRowsPerWave];
+#pragma unroll
+      for (int k = 0; k < kRowsPerWave; ++k) {
+        const T* row = src + (int64_t)fold_idx(oy + wv + k * kLdsWaves, H) * a.src_stride;
+        v0[k] = row[gc0];
+        v1[k] = row[gc1];
+        v2[k] = row[gc2];
+      }
+#pragma unroll
+      for (int k = 0; k < kRowsPerWave; ++k) {
+        T* x = X + (wv + k * kLdsWaves) * kLdsPX;
+        x[lane] = v0[k];
+        x[kWave + lane] = v1[k];
+        if (lane < 4) x[2 * kWave + lane] = v2[k];
+      }
+    }
+    __syncthreads();
+    // every step below leaves the quadruples (i, q), i in [1, kLdsQY],
+    // q in [1, kLdsQX], final: LL at X[2i][2q], HL at X[2i][2q+1] (sep.)
+    T ll_v[kLdsQY / kLdsWaves], hl_v[kLdsQY / kLdsWaves], lh_v[kLdsQY / kLdsWaves], hh_v[kLdsQY / kLdsWaves];
+    if constexpr (SEP) {
+      // HP: odd columns, every row
+      lds_walk65(kLdsPY, lane, wv, [&](int r, int q) {
+        T* x = X + r * kLdsPX + 2 * q;
+        x[1] = lp(x[1], x[0], x[2]);
+      });
+      __syncthreads();
+      // VP: odd rows 2i + 1, i in [0, kLdsQY], both columns of quadruple q
+      lds_walk65(kLdsQY + 1, lane, wv, [&](int i, int q) {
+        T* x = X + (2 * i + 1) * kLdsPX + 2 * q;
+        x[0] = lp(x[0], x[-kLdsPX], x[kLdsPX]);
+        x[1] = lp(x[1], x[1 - kLdsPX], x[1 + kLdsPX]);
+      });
+      __syncthreads();
+      // HU: even columns 2q, q in [1, kLdsQX], rows [1, 2 kLdsQY + 1]
+      for (int r = 1 + wv; r <= 2 * kLdsQY + 1; r += kLdsWaves) {
+        T* x = X + r * kLdsPX + 2 * (lane + 1);
+        x[0] = lu(x[0], x[-1], x[1]);
+      }
+      __syncthreads();
+      // VU: even rows 2i, i in [1, kLdsQY]; the odd rows are final
+#pragma unroll
+      for (int k = 0; k < kLdsQY / kLdsWaves; ++k) {
+        const int i = 1 + wv + k * kLdsWaves;
+        const T* x = X + 2 * i * kLdsPX + 2 * (lane + 1);
+        ll_v[k] = lu(x[0], x[-kLdsPX], x[kLdsPX]);
+        hl_v[k] = lu(x[1], x[1 - kLdsPX], x[1 + kLdsPX]);
+        lh_v[k] = x[kLdsPX];
+        hh_v[k] = x[kLdsPX + 1];
+      }
+    } else {
+      // spatial predict over quadruples [0, kLdsQY] x [0, kLdsQX] into PB
+      lds_walk65(kLdsQY + 1, lane, wv, [&](int i, int q) {
+        const T* x0 = X + 2 * i * kLdsPX + 2 * q;
+        const T* x1 = x0 + kLdsPX;
+        const T* x2 = x1 + kLdsPX;
+        const int o = i * kLdsQ1 + q;
+        if constexpr (std::is_same<T, float>::value)
+          f32_predict(x0[0], x0[2], x2[0], x2[2], x0[1], x2[1], x1[0], x1[2], x1[1], PB[o], PB[kLdsPQ + o],
+                      PB[2 * kLdsPQ + o]);
+        else
+          i32_predict(x0[0], x0[2], x2[0], x2[2], x0[1], x2[1], x1[0], x1[2], x1[1], PB[o], PB[kLdsPQ + o],
+                      PB[2 * kLdsPQ + o]);
+      });
+      __syncthreads();
+      // spatial update over [1, kLdsQY] x [1, kLdsQX]
+      const T* P0 = PB;
+      const T* P1 = PB + kLdsPQ;
+      const T* P2 = PB + 2 * kLdsPQ;
+#pragma unroll
+      for (int k = 0; k < kLdsQY / kLdsWaves; ++k) {
+        const int i = 1 + wv + k * kLdsWaves, q = lane + 1;
+        const int o = i * kLdsQ1 + q;
+        const T va = X[2 * i * kLdsPX + 2 * q];
+        if constexpr (std::is_same<T, float>::value) {
+          f32_update(va, P0[o - 1], P0[o], P1[o - kLdsQ1], P1[o], P2[o - kLdsQ1 - 1], P2[o - kLdsQ1], P2[o - 1],
+                     P2[o], ll_v[k], hl_v[k], lh_v[k]);
+        } else {
+          const int c2 = i32_c2(P1[o], P2[o - 1], P2[o]);
+          const int c2U = i32_c2(P1[o - kLdsQ1], P2[o - kLdsQ1 - 1], P2[o - kLdsQ1]);
+          i32_update(va, P0[o - 1], P0[o], c2U, c2, P2[o - kLdsQ1], P2[o], ll_v[k], hl_v[k]);
+          lh_v[k] = c2;
+        }
+        hh_v[k] = P2[o];
+      }
+    }
+    // store this tile's quadruples (rows and columns inside the level)
+#pragma unroll
+    for (int k = 0; k < kLdsQY / kLdsWaves; ++k) {
+      const int gqy = ty * kLdsQY + wv + k * kLdsWaves;
+      if (gqx < ns_w && gqy < ns_h) {
+        ll[(int64_t)gqy * a.ll_stride + gqx] = ll_v[k];
+        if (gqx < nd_w) band[(int64_t)gqy * a.band_stride + ns_w + gqx] = hl_v[k];
+        if (gqy < nd_h) {
+          band[(int64_t)(ns_h + gqy) * a.band_stride + gqx] = lh_v[k];
+          if (gqx < nd_w) band[(int64_t)(ns_h + gqy) * a.band_stride + ns_w + gqx] = hh_v[k];
+        }
+      }
+    }
+    if (img + (int)gridDim.y < a.batch) __syncthreads();  // X and PB are reused for the next image
+  }
+}
+
 __global__ void zero_kernel(uint32_t* p, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     p[i] = 0u;
@@ -1705,6 +1863,27 @@ int launch_tail(int dir, int mode, const TailArgs& a, void* stream) {
   } else {
     if (mode != DWT2_F32) return hipErrorInvalidValue;
     hipLaunchKernelGGL(tail_bwd, grid, dim3(kTailBlock), 0, s, a);
+  }
+  return hipGetLastError();
+}
+
+int lds_tiles(int W, int H, int& tiles_x, int& tiles_y) {
+  tiles_x = (((W + 1) >> 1) + kLdsQX - 1) / kLdsQX;
+  tiles_y = (((H + 1) >> 1) + kLdsQY - 1) / kLdsQY;
+  return (int64_t)tiles_x * tiles_y <= 0x7fffffff;
+}
+
+int launch_lds_level(bool separable, int mode, const SepLevel& a, void* stream) {
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int tx, ty;
+  if (!lds_tiles(a.W, a.H, tx, ty)) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)(tx * ty), (unsigned)(a.batch < 65535 ? a.batch : 65535));
+  if (separable) {
+    if (mode == DWT2_F32) hipLaunchKernelGGL((lds_level<float, true>), grid, dim3(kLdsBlock), 0, s, a, tx);
+    else hipLaunchKernelGGL((lds_level<int, true>), grid, dim3(kLdsBlock), 0, s, a, tx);
+  } else {
+    if (mode == DWT2_F32) hipLaunchKernelGGL((lds_level<float, false>), grid, dim3(kLdsBlock), 0, s, a, tx);
+    else hipLaunchKernelGGL((lds_level<int, false>), grid, dim3(kLdsBlock), 0, s, a, tx);
   }
   return hipGetLastError();
 }

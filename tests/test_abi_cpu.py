@@ -102,6 +102,30 @@ def test_validation_errors(lib, fn, kw, code):
     assert lib.dwt2_last_error().decode() != ""
 
 
+def call_lds(lib, scheme=0, **kw):
+    a = dict(src=FAKE_A, ss=64, sb=0, dst=FAKE_B, ds=64, db=0, w=64, h=64, batch=1, levels=2,
+             mode=0, boundary=0, ws=FAKE_WS, wsb=1 << 30, stream=None)
+    a.update(kw)
+    return lib.dwt2_fwd_lds(a["src"], a["ss"], a["sb"], a["dst"], a["ds"], a["db"], a["w"], a["h"], a["batch"],
+                            a["levels"], a["mode"], a["boundary"], scheme, a["ws"], a["wsb"], a["stream"])
+
+
+@pytest.mark.parametrize("scheme", [0, 1])
+@pytest.mark.parametrize("kw,code", BAD, ids=[str(b[0]) for b in BAD])
+def test_lds_validation_errors(lib, scheme, kw, code):
+    assert call_lds(lib, scheme, **kw) == code
+    assert lib.dwt2_last_error().decode() != ""
+
+
+def test_lds_rejects_unknown_scheme(lib):
+    for scheme in (-1, 2, 7):
+        assert call_lds(lib, scheme) == -1
+        assert "scheme" in lib.dwt2_last_error().decode()
+    # the LDS kernels use the plain workspace
+    need = lib.dwt2_workspace_size(64, 64, 1, 2, 0)
+    assert call_lds(lib, 1, wsb=need - 1) == -4
+
+
 def test_adjoint_rejects_integer_mode(lib):
     assert call(lib, "dwt2_bwd", mode=1) == -3
     assert "F32" in lib.dwt2_last_error().decode()

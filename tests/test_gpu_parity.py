@@ -413,6 +413,63 @@ def test_separable_baseline_batch_strides_and_full_size():
     assert torch.equal(d.fwd_separable(xi, 6), d.fwd(xi, 6))
 
 
+# ----------------------------------------------- LDS-tiled comparison kernels
+
+LDS_SHAPES = [(2, 2), (3, 5), (17, 2), (2, 300), (64, 64), (65, 33), (33, 129), (300, 517), (129, 1030),
+              (97, 258), (260, 131)]
+
+
+@pytest.mark.parametrize("mode", ["f32", "int"])
+def test_lds_tiled_schemes_match_oracle_and_their_counterparts(mode):
+    """The LDS-tiled kernels (128 x 32-pixel tiles, ragged edge tiles and
+    several tiles per axis included) compute the oracle's transform: the
+    non-separable scheme (two barrier-separated steps) reproduces the product
+    path bit for bit, the separable scheme (four steps) the separable-pass
+    baseline bit for bit; integers equal the oracle exactly."""
+    d = D()
+    dt = np.float32 if mode == "f32" else np.int32
+    for idx, (h, w) in enumerate(LDS_SHAPES):
+        x = _img(h, w, 1200 + idx)
+        for levels in sorted({1, 2, max_levels(w, h, 6)}):
+            if max_levels(w, h, 6) < levels:
+                continue
+            xg = to_gpu(x.astype(dt))
+            ns = d.fwd_lds(xg, levels, "nonseparable")
+            sp = d.fwd_lds(xg, levels, "separable")
+            assert torch.equal(ns, d.fwd(xg, levels)), (h, w, levels)
+            assert torch.equal(sp, d.fwd_separable(xg, levels)), (h, w, levels)
+            if mode == "int":
+                ref = oracle.fwd(x, levels, INT)
+                assert np.array_equal(ns.cpu().numpy(), ref), (h, w, levels)
+                assert np.array_equal(sp.cpu().numpy(), ref), (h, w, levels)
+            else:
+                ref = oracle.fwd(x, levels)
+                assert maxdiff(ns.cpu().numpy(), ref) <= TOL, (h, w, levels)
+                assert maxdiff(sp.cpu().numpy(), ref) <= TOL, (h, w, levels)
+
+
+def test_lds_tiled_batch_strides_and_full_size():
+    """Batched strided views, and the 8192^2 6-level workload the benchmark
+    compares on."""
+    d = D()
+    xs = torch.stack([to_gpu(synth.image(333, 250, 1250 + b)) for b in range(3)])
+    base = torch.zeros((3, 250, 340), device="cuda")
+    xv = base[:, :, 2:335]
+    xv.copy_(xs)
+    for scheme in ("separable", "nonseparable"):
+        got = d.fwd_lds(xv, 3, scheme)
+        for b in range(3):
+            assert maxdiff(got[b].cpu().numpy(), oracle.fwd(xs[b].cpu().numpy().astype(np.float64), 3)) <= TOL
+    assert torch.equal(d.fwd_lds(xv, 3, "nonseparable"), d.fwd(xv, 3))
+    x = synth.image_device(8192, 8192, 2)
+    assert torch.equal(d.fwd_lds(x, 6, "nonseparable"), d.fwd(x, 6))
+    assert torch.equal(d.fwd_lds(x, 6, "separable"), d.fwd_separable(x, 6))
+    xi = x.to(torch.int32)
+    ref = d.fwd(xi, 6)
+    assert torch.equal(d.fwd_lds(xi, 6, "nonseparable"), ref)
+    assert torch.equal(d.fwd_lds(xi, 6, "separable"), ref)
+
+
 def test_batched_inverse_and_adjoint_every_schedule():
     """dwt2_inv_batched and dwt2_bwd_batched reproduce per-image dwt2_inv /
     dwt2_bwd bit for bit under both schedules, and the integer batched round
