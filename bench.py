@@ -23,7 +23,14 @@ bandwidth, the separable lifting baseline against the non-separable forward
 256-image batch (one batched call vs 256 plain calls), the 32 x 3 x 1024^2
 autograd forward/backward, and a device-to-device copy ceiling.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+--sweep prints, instead, the two comparisons of the paper's §4 redone on this
+GPU: the forward's time against the image edge (512 .. 16384, 6 levels) for
+the product path, the LDS-tiled non-separable (two barrier steps) and
+separable (four) kernels and the separable-pass baseline; and the level-1
+time of 8192^2 against the work-item shape (segment height x prefetch chunk),
+the counterpart of the paper's tile-size experiment.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--sweep]
 """
 from __future__ import annotations
 
@@ -106,6 +113,8 @@ def main():
     ap.add_argument("--only", choices=["step", "fwd", "fwd1", "inv", "bwd", "copy"], default=None,
                     help="profiling aid: run only this part (fwd1: the level-1 forward kernel alone, "
                          "as a 1-level call with the same grid), untimed JSON omitted")
+    ap.add_argument("--sweep", action="store_true",
+                    help="print the edge-size and work-item-shape sweeps instead of the benchmark line")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -125,6 +134,10 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     timer = Timer(torch)
+
+    if args.sweep:
+        sweep(torch, dwt, synth, dev, timer)
+        return
 
     W = H = 8192
     L = 6
@@ -221,14 +234,30 @@ def main():
             k[0] ^= 1
             fwd(sets[k[0]])
 
+        def lds_fwd(scheme):
+            def f():
+                k[0] ^= 1
+                s_ = sets[k[0]]
+                dwt.fwd_lds(s_["x"], L, scheme, out=s_["c"], workspace=ws)
+            return f
+
         for _ in range(3):
             sep_fwd()
         ts = float(np.median(timer(sep_fwd, 20)))
         tf = float(np.median(timer(fused_fwd, 20)))
+        lds = {}
+        for scheme in ("separable", "nonseparable"):
+            f = lds_fwd(scheme)
+            for _ in range(3):
+                f()
+            lds[scheme] = float(np.median(timer(f, 20)))
         detail["separable_vs_nonseparable_fwd_8192_L6"] = {
             "separable_ms": round(ts, 4), "nonseparable_ms": round(tf, 4),
             "speedup": round(ts / tf, 3),
-            "separable_hbm_passes_per_level": 4, "nonseparable_hbm_passes_per_level": 1}
+            "separable_hbm_passes_per_level": 4, "nonseparable_hbm_passes_per_level": 1,
+            "lds_tiled_separable_ms": round(lds["separable"], 4),
+            "lds_tiled_nonseparable_ms": round(lds["nonseparable"], 4),
+            "lds_tiled_speedup_of_two_steps_over_four": round(lds["separable"] / lds["nonseparable"], 3)}
         del wss
         # copy ceiling: read + write of 1 GiB
         a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
@@ -339,6 +368,58 @@ def main():
                       "width": W, "height": H, "levels": L, "parallelism": "none (1 GPU)"},
            "roofline": roofline, "cpu_baseline": cpu, "detail": detail}
     print(json.dumps(out))
+
+
+def sweep(torch, dwt, synth, dev, timer, reps=20):
+    """The paper's §4 experiments redone on this GPU (see the module doc)."""
+    def med(f):
+        for _ in range(3):
+            f(0)
+        i = [0]
+
+        def g():
+            i[0] ^= 1
+            f(i[0])
+        return float(np.median(timer(g, reps)))
+
+    for edge in (512, 1024, 2048, 4096, 8192, 16384):
+        L = 6
+        xs = [synth.image_device(edge, edge, 2 + 100 * s, device=dev) for s in range(2)]
+        outs = [torch.empty_like(x) for x in xs]
+        ws = torch.empty(dwt.separable_workspace_size(edge, edge, L), dtype=torch.uint8, device=dev)
+        row = {"sweep": "edge", "edge": edge, "levels": L}
+        variants = {
+            "product": lambda s: dwt.fwd(xs[s], L, out=outs[s], workspace=ws),
+            "lds_nonseparable": lambda s: dwt.fwd_lds(xs[s], L, "nonseparable", out=outs[s], workspace=ws),
+            "lds_separable": lambda s: dwt.fwd_lds(xs[s], L, "separable", out=outs[s], workspace=ws),
+            "separable_passes": lambda s: dwt.fwd_separable(xs[s], L, out=outs[s], workspace=ws),
+        }
+        for name, f in variants.items():
+            ms = med(f)
+            row[name + "_us"] = round(ms * 1e3, 2)
+            row[name + "_Gpx_s"] = round(edge * edge / (ms * 1e-3) / 1e9, 1)
+        print(json.dumps(row), flush=True)
+        del xs, outs, ws
+        torch.cuda.empty_cache()
+
+    edge = 8192
+    xs = [synth.image_device(edge, edge, 2 + 100 * s, device=dev) for s in range(2)]
+    outs = [torch.empty_like(x) for x in xs]
+    ws = torch.empty(dwt.workspace_size(edge, edge, 1), dtype=torch.uint8, device=dev)
+    try:
+        for seg in (1, 2, 4, 8, 16, 32, 64, 128, 256, 512, 2048):
+            row = {"sweep": "work_item", "edge": edge, "level": 1, "seg_quad_rows": seg}
+            for ch in (1, 2, 4):
+                dwt.set_tiling(seg, ch)
+                ms = med(lambda s: dwt.fwd(xs[s], 1, out=outs[s], workspace=ws))
+                row[f"chunk{ch}_us"] = round(ms * 1e3, 2)
+            print(json.dumps(row), flush=True)
+        dwt.set_tiling(0, 0)
+        ms = med(lambda s: dwt.fwd(xs[s], 1, out=outs[s], workspace=ws))
+        print(json.dumps({"sweep": "work_item", "edge": edge, "level": 1, "seg_quad_rows": "auto",
+                          "auto_us": round(ms * 1e3, 2)}), flush=True)
+    finally:
+        dwt.set_tiling(0, 0)
 
 
 if __name__ == "__main__":
