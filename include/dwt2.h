@@ -170,6 +170,33 @@ int dwt2_fwd_lds(const void* src, int64_t src_stride, int64_t src_batch_stride,
                  int32_t mode, int32_t boundary, int32_t scheme,
                  void* workspace, size_t workspace_bytes, void* stream);
 
+/* CDF 9/7 (float32 only), computed with the non-separable scheme: the
+ * wavelet's two lifting pairs (§2, eq. (2)) are treated in turn, each as a
+ * spatial predict and a spatial update (§3, eq. (5)), and the quadrants are
+ * then scaled.  The paper prints no 9/7 coefficients, so these are the
+ * Daubechies-Sweldens lifting factorisation with JPEG 2000's normalisation
+ * of the irreversible transform (lowpass gain 1 at DC, highpass gain 2 at
+ * Nyquist): predict -1.586134342059924, update -0.052980118572961, predict
+ * 0.882911075530934, update 0.443506852043971, then L / K and H * K with
+ * K = 1.230174104914001.  Boundary, Mallat layout, level rule, arguments,
+ * ownership and errors are those of dwt2_fwd / dwt2_inv, with the workspace
+ * of dwt2_workspace_size.  mode must be DWT2_F32 (DWT2_ERR_MODE otherwise).
+ * One launch per level; each workgroup lifts a tile of 64 x 16 quadruples
+ * in LDS (two quadruples of halo), with a barrier between the four spatial
+ * steps. */
+int dwt2_fwd_cdf97(const void* src, int64_t src_stride, int64_t src_batch_stride,
+                   void* dst, int64_t dst_stride, int64_t dst_batch_stride,
+                   int32_t width, int32_t height, int32_t batch, int32_t levels,
+                   int32_t mode, int32_t boundary, void* workspace,
+                   size_t workspace_bytes, void* stream);
+/* Inverse of dwt2_fwd_cdf97: src = Mallat-packed 9/7 coefficients, dst =
+ * image. */
+int dwt2_inv_cdf97(const void* src, int64_t src_stride, int64_t src_batch_stride,
+                   void* dst, int64_t dst_stride, int64_t dst_batch_stride,
+                   int32_t width, int32_t height, int32_t batch, int32_t levels,
+                   int32_t mode, int32_t boundary, void* workspace,
+                   size_t workspace_bytes, void* stream);
+
 /* One image of a ragged batch (all pointers device pointers). */
 typedef struct {
   const void* src;

@@ -111,6 +111,18 @@ def fwd_separable(x: torch.Tensor, levels: int, mode=None, out=None, workspace=N
     return _run("dwt2_fwd_separable", x, levels, mode, out, workspace)
 
 
+def fwd_cdf97(x: torch.Tensor, levels: int, out=None, workspace=None) -> torch.Tensor:
+    """Forward multi-level CDF 9/7 transform of float32 (..., H, W) by the
+    non-separable scheme, one spatial predict and update per lifting pair
+    (see dwt2_fwd_cdf97); Mallat-packed result of the same shape."""
+    return _run("dwt2_fwd_cdf97", x, levels, None, out, workspace)
+
+
+def inv_cdf97(c: torch.Tensor, levels: int, out=None, workspace=None) -> torch.Tensor:
+    """Inverse of fwd_cdf97."""
+    return _run("dwt2_inv_cdf97", c, levels, None, out, workspace)
+
+
 SCHEMES = {"separable": 0, "nonseparable": 1}
 
 

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libdwt2.so")
-SOURCES = ["kernels.hip", "separable.hip", "api.cpp", "batched.cpp"]
+SOURCES = ["kernels.hip", "separable.hip", "cdf97.hip", "api.cpp", "batched.cpp"]
 ARCH = os.environ.get("DWT2_ARCH", "gfx950")
 
 FLAGS = [

@@ -439,9 +439,74 @@ static int run_lds(bool separable, const Call& c, const Geo& g, void* stream) {
   return DWT2_OK;
 }
 
-// Which kernels compute a call: the product path, or one of the comparison
-// baselines (separable passes, LDS-tiled separable, LDS-tiled non-separable).
-enum { kProduct = 0, kSepPasses = 1, kLdsSep = 2, kLdsNonSep = 3 };
+// CDF 9/7: one launch per level, LL through the plain workspace's buffers.
+static int run_cdf97(int dir, const Call& c, const Geo& g, void* stream) {
+  const int64_t ws_bs = (int64_t)(ws_per_image(g) / 4);
+  for (int s = 0; s < g.L; ++s) {
+    const int k = dir == kFwd ? s + 1 : g.L - s;  // the inverse runs coarsest first
+    Level97 a;
+    memset(&a, 0, sizeof a);
+    a.W = g.w[k - 1];
+    a.H = g.h[k - 1];
+    a.batch = c.batch;
+    int tx, ty;
+    if (!cdf97_tiles(a.W, a.H, tx, ty)) return fail(DWT2_ERR_SIZE, "level %d needs more tiles than a launch holds", k);
+    if (dir == kFwd) {
+      if (k == 1) {
+        a.in = c.src;
+        a.in_stride = c.src_stride;
+        a.in_bstride = c.src_bs;
+      } else {
+        a.in = ll_buf(c, g, k - 1);
+        a.in_stride = ll_pitch(g.w[k - 1]);
+        a.in_bstride = ws_bs;
+      }
+      if (k == g.L) {
+        a.ll = c.dst;
+        a.ll_stride = c.dst_stride;
+        a.ll_bstride = c.dst_bs;
+      } else {
+        a.ll = ll_buf(c, g, k);
+        a.ll_stride = ll_pitch(g.w[k]);
+        a.ll_bstride = ws_bs;
+      }
+      a.out = c.dst;
+      a.out_stride = c.dst_stride;
+      a.out_bstride = c.dst_bs;
+    } else {
+      if (k == g.L) {
+        a.in = c.src;
+        a.in_stride = c.src_stride;
+        a.in_bstride = c.src_bs;
+      } else {
+        a.in = ll_buf(c, g, k);
+        a.in_stride = ll_pitch(g.w[k]);
+        a.in_bstride = ws_bs;
+      }
+      a.bands = c.src;
+      a.bands_stride = c.src_stride;
+      a.bands_bstride = c.src_bs;
+      if (k == 1) {
+        a.out = c.dst;
+        a.out_stride = c.dst_stride;
+        a.out_bstride = c.dst_bs;
+      } else {
+        a.out = ll_buf(c, g, k - 1);
+        a.out_stride = ll_pitch(g.w[k - 1]);
+        a.out_bstride = ws_bs;
+      }
+    }
+    const int err = launch_cdf97_level(dir, a, stream);
+    if (err != hipSuccess)
+      return fail(DWT2_ERR_HIP, "CDF 9/7 level %d launch failed: %s", k, hipGetErrorString((hipError_t)err));
+  }
+  return DWT2_OK;
+}
+
+// Which kernels compute a call: the product path, one of the comparison
+// baselines (separable passes, LDS-tiled separable, LDS-tiled non-separable),
+// or the CDF 9/7 kernels.
+enum { kProduct = 0, kSepPasses = 1, kLdsSep = 2, kLdsNonSep = 3, kCdf97 = 4 };
 
 static int transform(int dir, const void* src, int64_t src_stride, int64_t src_bs, void* dst, int64_t dst_stride,
                      int64_t dst_bs, int32_t width, int32_t height, int32_t batch, int32_t levels, int32_t mode,
@@ -464,6 +529,7 @@ static int transform(int dir, const void* src, int64_t src_stride, int64_t src_b
     return fail(DWT2_ERR_ARG, "batch stride below stride * height");
   if (mode != DWT2_F32 && mode != DWT2_I32_REV) return fail(DWT2_ERR_MODE, "unknown mode %d", mode);
   if (dir == kBwd && mode != DWT2_F32) return fail(DWT2_ERR_MODE, "the adjoint exists for DWT2_F32 only");
+  if (variant == kCdf97 && mode != DWT2_F32) return fail(DWT2_ERR_MODE, "the CDF 9/7 transform exists for DWT2_F32 only");
   if (src == dst) return fail(DWT2_ERR_ALIAS, "src and dst are the same buffer; the transform is out of place");
   const size_t need =
       sync_bytes(g, batch) + (ws_per_image(g) + (separable ? sep_work_per_image(g) : 0)) * (size_t)batch;
@@ -473,6 +539,7 @@ static int transform(int dir, const void* src, int64_t src_stride, int64_t src_b
          static_cast<char*>(workspace), sync_bytes(g, batch)};
   if (separable) return run_separable(c, g, stream);
   if (variant == kLdsSep || variant == kLdsNonSep) return run_lds(variant == kLdsSep, c, g, stream);
+  if (variant == kCdf97) return run_cdf97(dir, c, g, stream);
   if (g_persistent.load() < 0) g_persistent.store(env_int("DWT2_PERSISTENT") == 1 ? 1 : 0);
   const int path = g_persistent.load();
   if (path == 1 && g.L <= kInlineDescs) return run_job(dir, c, g, stream);
@@ -505,6 +572,20 @@ int dwt2_fwd_separable(const void* src, int64_t src_stride, int64_t src_batch_st
                        int32_t mode, int32_t boundary, void* workspace, size_t workspace_bytes, void* stream) {
   return transform(kFwd, src, src_stride, src_batch_stride, dst, dst_stride, dst_batch_stride, width, height, batch,
                    levels, mode, boundary, workspace, workspace_bytes, stream, kSepPasses);
+}
+
+int dwt2_fwd_cdf97(const void* src, int64_t src_stride, int64_t src_batch_stride, void* dst, int64_t dst_stride,
+                   int64_t dst_batch_stride, int32_t width, int32_t height, int32_t batch, int32_t levels, int32_t mode,
+                   int32_t boundary, void* workspace, size_t workspace_bytes, void* stream) {
+  return transform(kFwd, src, src_stride, src_batch_stride, dst, dst_stride, dst_batch_stride, width, height, batch,
+                   levels, mode, boundary, workspace, workspace_bytes, stream, kCdf97);
+}
+
+int dwt2_inv_cdf97(const void* src, int64_t src_stride, int64_t src_batch_stride, void* dst, int64_t dst_stride,
+                   int64_t dst_batch_stride, int32_t width, int32_t height, int32_t batch, int32_t levels, int32_t mode,
+                   int32_t boundary, void* workspace, size_t workspace_bytes, void* stream) {
+  return transform(kInv, src, src_stride, src_batch_stride, dst, dst_stride, dst_batch_stride, width, height, batch,
+                   levels, mode, boundary, workspace, workspace_bytes, stream, kCdf97);
 }
 
 int dwt2_fwd_lds(const void* src, int64_t src_stride, int64_t src_batch_stride, void* dst, int64_t dst_stride,

@@ -1,0 +1,304 @@
+// CDF 9/7 (float32) with the non-separable lifting scheme, one launch per
+// level.  The wavelet's two lifting pairs (§2, eq. (2)) are treated in turn,
+// each as one spatial predict and one spatial update (§3, eq. (5)), so a
+// level is four spatial steps followed by the scaling of the quadrants.
+// Coefficients: the Daubechies-Sweldens lifting factorisation, normalised as
+// JPEG 2000's irreversible transform (lowpass gain 1 at DC, highpass gain 2
+// at Nyquist), so that the quadrants scale as LL / K^2, HL and LH by 1,
+// HH * K^2.
+//
+// Each 256-thread workgroup owns 64 x 16 output quadruples.  It copies them
+// into LDS with two quadruples of halo on every side, split into the planes
+// a, b, c, d (even/odd row x even/odd column).  Each step reaches one
+// quadruple to one side, so four steps need two on each side.  The copy
+// reads through the symmetric extension: of the pixels (forward), or of the
+// interleaved coefficients (inverse).  The extension keeps every index's
+// parity, so it commutes with lifting, and each step can run on a fixed
+// local range that shrinks by one quadruple per step.  The steps ping-pong
+// between two sets of planes (seven planes in all), with a workgroup
+// barrier between steps, so that no step overwrites a value another thread
+// of the same step still reads.
+#include <hip/hip_runtime.h>
+
+#include "dwt2_internal.h"
+
+namespace dwt2 {
+namespace {
+
+constexpr float kAlpha = -1.586134342059924f, kBeta = -0.052980118572961f;
+constexpr float kGamma = 0.882911075530934f, kDelta = 0.443506852043971f;
+constexpr double kK = 1.230174104914001;
+constexpr float kAlpha2 = (float)(-1.586134342059924 * -1.586134342059924);
+constexpr float kBeta2 = (float)(-0.052980118572961 * -0.052980118572961);
+constexpr float kGamma2 = (float)(0.882911075530934 * 0.882911075530934);
+constexpr float kDelta2 = (float)(0.443506852043971 * 0.443506852043971);
+constexpr float kLLScale = (float)(1.0 / (kK * kK)), kHHScale = (float)(kK * kK);
+
+constexpr int kQX = 64, kQY = 16;                    // output quadruples per tile
+constexpr int kNX = kQX + 4, kNY = kQY + 4, kNP = kNX * kNY;
+constexpr int kBlk = 256, kWv = kBlk / kWave;
+
+// Whole-sample symmetric fold of p onto [0, n), n >= 2.
+__device__ __forceinline__ int fold97(int p, int n) {
+  if ((unsigned)p < (unsigned)n) return p;
+  const int m = 2 * (n - 1);
+  p %= m;
+  if (p < 0) p += m;
+  return p >= n ? m - p : p;
+}
+
+// Consecutive logical tiles on one XCD (workgroups are dealt round-robin
+// over the 8 XCDs), so vertically adjacent tiles share halo rows in one L2.
+__device__ __forceinline__ int tile_remap(int b, int nb) {
+  const int q = nb >> 3, r = nb & 7, x = b & 7, s = b >> 3;
+  return (x < r) ? x * (q + 1) + s : r * (q + 1) + (x - r) * q + s;
+}
+
+// f(i, q) for rows i in [i0, i1) and quadruple columns q in
+// [q0, q0 + 64 + EXTRA): one wave per row for the first 64 columns, then
+// the EXTRA last columns of every row in one pass of the block.
+template <int EXTRA, typename F>
+__device__ __forceinline__ void walk(int i0, int i1, int q0, int lane, int wv, F&& f) {
+  for (int i = i0 + wv; i < i1; i += kWv) f(i, q0 + lane);
+  if constexpr (EXTRA > 0) {
+    const int t = threadIdx.x;
+    if (t < EXTRA * (i1 - i0)) f(i0 + t / EXTRA, q0 + kWave + t % EXTRA);
+  }
+}
+
+// Spatial predict with P = p (1 + z): R / D = next quadruple column / row.
+__device__ __forceinline__ void sp_pred(float p, float pp, float a, float aR, float aD, float aDR, float b, float bD,
+                                        float c, float cR, float d, float& bo, float& co, float& dout) {
+  const float sh = a + aR;
+  bo = __fmaf_rn(p, sh, b);
+  co = __fmaf_rn(p, a + aD, c);
+  dout = __fmaf_rn(pp, sh + (aD + aDR), __fmaf_rn(p, b + bD, __fmaf_rn(p, c + cR, d)));
+}
+
+// Spatial update with U = u (1 + z^-1): L / U = previous column / row.
+__device__ __forceinline__ void sp_upd(float u, float uu, float a, float bL, float b, float cU, float c, float dUL,
+                                       float dU, float dL, float d, float& ao, float& bo, float& co) {
+  bo = __fmaf_rn(u, dU + d, b);
+  co = __fmaf_rn(u, dL + d, c);
+  ao = __fmaf_rn(uu, (dUL + dU) + (dL + d), __fmaf_rn(u, cU + c, __fmaf_rn(u, bL + b, a)));
+}
+
+// Inverse of sp_upd, solved so that it reads only the step's outputs.
+__device__ __forceinline__ void sp_inv_upd(float u, float uu, float ll, float hlL, float hl, float lhU, float lh,
+                                           float dUL, float dU, float dL, float d, float& a, float& b, float& c) {
+  b = __fmaf_rn(-u, dU + d, hl);
+  c = __fmaf_rn(-u, dL + d, lh);
+  a = __fmaf_rn(uu, (dUL + dU) + (dL + d), __fmaf_rn(-u, (hlL + hl) + (lhU + lh), ll));
+}
+
+// Inverse of sp_pred, likewise.
+__device__ __forceinline__ void sp_inv_pred(float p, float pp, float a, float aR, float aD, float aDR, float b1,
+                                            float b1D, float c1, float c1R, float d1, float& b, float& c, float& d) {
+  const float sh = a + aR;
+  b = __fmaf_rn(-p, sh, b1);
+  c = __fmaf_rn(-p, a + aD, c1);
+  d = __fmaf_rn(pp, sh + (aD + aDR), __fmaf_rn(-p, b1 + b1D, __fmaf_rn(-p, c1 + c1R, d1)));
+}
+
+// Forward level: pixels in, LL_k and the three H bands out.
+__global__ __launch_bounds__(kBlk) void fwd97(Level97 a, int tiles_x) {
+  __shared__ float S[7 * kNP];
+  float* A0 = S;
+  float* B0 = S + kNP;
+  float* C0 = S + 2 * kNP;
+  float* D0 = S + 3 * kNP;
+  float* B1 = S + 4 * kNP;
+  float* C1 = S + 5 * kNP;
+  float* D1 = S + 6 * kNP;
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  const int tile = tile_remap(blockIdx.x, gridDim.x);
+  const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
+  const int W = a.W, H = a.H;
+  const int ns_w = (W + 1) >> 1, ns_h = (H + 1) >> 1, nd_w = W >> 1, nd_h = H >> 1;
+  const int px0 = 2 * (tx * kQX - 2), py0 = 2 * (ty * kQY - 2);  // image pixel of local pixel (0, 0)
+  // the tile's 2 kNX = 136 pixel columns: lane, 64 + lane, and 128 + lane % 8
+  // (stored by lanes 0..7; the others reload one of those eight)
+  static_assert(2 * kNX == 2 * kWave + 8, "tile width");
+  const int gc0 = fold97(px0 + lane, W), gc1 = fold97(px0 + kWave + lane, W);
+  const int gc2 = fold97(px0 + 2 * kWave + (lane & 7), W);
+  // plane and quadruple column of those pixel columns (even columns: a / c)
+  const int s0 = (lane & 1) * kNP + (lane >> 1);
+  const int s1 = (lane & 1) * kNP + kWave / 2 + (lane >> 1);
+  const int s2 = (lane & 1) * kNP + kWave + ((lane & 7) >> 1);
+  constexpr int kRowsPerWave = 2 * kNY / kWv;
+  static_assert(2 * kNY % kWv == 0, "tile height");
+  const int gqx = tx * kQX + lane;
+  for (int img = blockIdx.y; img < a.batch; img += gridDim.y) {
+    const float* src = static_cast<const float*>(a.in) + img * a.in_bstride;
+    float* ll = static_cast<float*>(a.ll) + img * a.ll_bstride;
+    float* band = static_cast<float*>(a.out) + img * a.out_bstride;
+    {
+      float v0[kRowsPerWave], v1[kRowsPerWave], v2[kRowsPerWave];
+#pragma unroll
+      for (int k = 0; k < kRowsPerWave; ++k) {
+        const float* row = src + (int64_t)fold97(py0 + wv + k * kWv, H) * a.in_stride;
+        v0[k] = row[gc0];
+        v1[k] = row[gc1];
+        v2[k] = row[gc2];
+      }
+#pragma unroll
+      for (int k = 0; k < kRowsPerWave; ++k) {
+        const int r = wv + k * kWv;
+        float* x = S + (r & 1) * 2 * kNP + (r >> 1) * kNX;  // odd rows: planes c, d
+        x[s0] = v0[k];
+        x[s1] = v1[k];
+        if (lane < 8) x[s2] = v2[k];
+      }
+    }
+    __syncthreads();
+    // pair 1 predict (alpha): rows [0, kNY - 1), columns [0, kNX - 1)
+    walk<3>(0, kNY - 1, 0, lane, wv, [&](int i, int q) {
+      const int o = i * kNX + q;
+      sp_pred(kAlpha, kAlpha2, A0[o], A0[o + 1], A0[o + kNX], A0[o + kNX + 1], B0[o], B0[o + kNX], C0[o],
+              C0[o + 1], D0[o], B1[o], C1[o], D1[o]);
+    });
+    __syncthreads();
+    // pair 1 update (beta): rows [1, kNY - 1), columns [1, kNX - 1)
+    walk<2>(1, kNY - 1, 1, lane, wv, [&](int i, int q) {
+      const int o = i * kNX + q;
+      sp_upd(kBeta, kBeta2, A0[o], B1[o - 1], B1[o], C1[o - kNX], C1[o], D1[o - kNX - 1], D1[o - kNX], D1[o - 1],
+             D1[o], A0[o], B0[o], C0[o]);
+    });
+    __syncthreads();
+    // pair 2 predict (gamma): rows [1, kNY - 2), columns [1, kNX - 2)
+    walk<1>(1, kNY - 2, 1, lane, wv, [&](int i, int q) {
+      const int o = i * kNX + q;
+      sp_pred(kGamma, kGamma2, A0[o], A0[o + 1], A0[o + kNX], A0[o + kNX + 1], B0[o], B0[o + kNX], C0[o],
+              C0[o + 1], D1[o], B1[o], C1[o], D0[o]);
+    });
+    __syncthreads();
+    // pair 2 update (delta) on the tile's own quadruples, scaling, store
+#pragma unroll
+    for (int k = 0; k < kQY / kWv; ++k) {
+      const int i = 2 + wv + k * kWv;
+      const int o = i * kNX + 2 + lane;
+      float vll, vhl, vlh;
+      sp_upd(kDelta, kDelta2, A0[o], B1[o - 1], B1[o], C1[o - kNX], C1[o], D0[o - kNX - 1], D0[o - kNX], D0[o - 1],
+             D0[o], vll, vhl, vlh);
+      const float vhh = D0[o] * kHHScale;
+      vll *= kLLScale;
+      const int gqy = ty * kQY + i - 2;
+      if (gqx < ns_w && gqy < ns_h) {
+        ll[(int64_t)gqy * a.ll_stride + gqx] = vll;
+        if (gqx < nd_w) band[(int64_t)gqy * a.out_stride + ns_w + gqx] = vhl;
+        if (gqy < nd_h) {
+          band[(int64_t)(ns_h + gqy) * a.out_stride + gqx] = vlh;
+          if (gqx < nd_w) band[(int64_t)(ns_h + gqy) * a.out_stride + ns_w + gqx] = vhh;
+        }
+      }
+    }
+    if (img + (int)gridDim.y < a.batch) __syncthreads();  // S is reused for the next image
+  }
+}
+
+// Inverse level: LL_k and the H bands in, the level input's pixels out.
+__global__ __launch_bounds__(kBlk) void inv97(Level97 a, int tiles_x) {
+  __shared__ float S[7 * kNP];
+  float* A0 = S;
+  float* B0 = S + kNP;
+  float* C0 = S + 2 * kNP;
+  float* D0 = S + 3 * kNP;
+  float* B1 = S + 4 * kNP;
+  float* C1 = S + 5 * kNP;
+  float* D1 = S + 6 * kNP;
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  const int tile = tile_remap(blockIdx.x, gridDim.x);
+  const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
+  const int W = a.W, H = a.H;
+  const int ns_w = (W + 1) >> 1, ns_h = (H + 1) >> 1;
+  const int qx0 = tx * kQX - 2, qy0 = ty * kQY - 2;  // image quadruple of local quadruple (0, 0)
+  const int gqx = tx * kQX + lane;
+  for (int img = blockIdx.y; img < a.batch; img += gridDim.y) {
+    const float* lls = static_cast<const float*>(a.in) + img * a.in_bstride;
+    const float* bands = static_cast<const float*>(a.bands) + img * a.bands_bstride;
+    float* out = static_cast<float*>(a.out) + img * a.out_bstride;
+    // coefficients of quadruples [0, kNX) x [0, kNY), through the symmetric
+    // extension of the interleaved array: the L (even) and H (odd) positions
+    // of a quadruple fold onto band indices of their own parity; the scaling
+    // is undone as they are stored
+    walk<4>(0, kNY, 0, lane, wv, [&](int i, int q) {
+      const int gx = qx0 + q, gy = qy0 + i;
+      const int bx0 = fold97(2 * gx, W) >> 1, bx1 = (fold97(2 * gx + 1, W) - 1) >> 1;
+      const int by0 = fold97(2 * gy, H) >> 1, by1 = (fold97(2 * gy + 1, H) - 1) >> 1;
+      const float vll = lls[(int64_t)by0 * a.in_stride + bx0];
+      const float vhl = bands[(int64_t)by0 * a.bands_stride + ns_w + bx1];
+      const float vlh = bands[(int64_t)(ns_h + by1) * a.bands_stride + bx0];
+      const float vhh = bands[(int64_t)(ns_h + by1) * a.bands_stride + ns_w + bx1];
+      const int o = i * kNX + q;
+      A0[o] = vll * kHHScale;
+      B0[o] = vhl;
+      C0[o] = vlh;
+      D0[o] = vhh * kLLScale;
+    });
+    __syncthreads();
+    // undo pair 2 update (delta): rows [1, kNY), columns [1, kNX)
+    walk<3>(1, kNY, 1, lane, wv, [&](int i, int q) {
+      const int o = i * kNX + q;
+      sp_inv_upd(kDelta, kDelta2, A0[o], B0[o - 1], B0[o], C0[o - kNX], C0[o], D0[o - kNX - 1], D0[o - kNX],
+                 D0[o - 1], D0[o], A0[o], B1[o], C1[o]);
+    });
+    __syncthreads();
+    // undo pair 2 predict (gamma): rows [1, kNY - 1), columns [1, kNX - 1)
+    walk<2>(1, kNY - 1, 1, lane, wv, [&](int i, int q) {
+      const int o = i * kNX + q;
+      sp_inv_pred(kGamma, kGamma2, A0[o], A0[o + 1], A0[o + kNX], A0[o + kNX + 1], B1[o], B1[o + kNX], C1[o],
+                  C1[o + 1], D0[o], B0[o], C0[o], D1[o]);
+    });
+    __syncthreads();
+    // undo pair 1 update (beta): rows [2, kNY - 1), columns [2, kNX - 1)
+    walk<1>(2, kNY - 1, 2, lane, wv, [&](int i, int q) {
+      const int o = i * kNX + q;
+      sp_inv_upd(kBeta, kBeta2, A0[o], B0[o - 1], B0[o], C0[o - kNX], C0[o], D1[o - kNX - 1], D1[o - kNX],
+                 D1[o - 1], D1[o], A0[o], B1[o], C1[o]);
+    });
+    __syncthreads();
+    // undo pair 1 predict (alpha) on the tile's own quadruples; store pixels
+#pragma unroll
+    for (int k = 0; k < kQY / kWv; ++k) {
+      const int i = 2 + wv + k * kWv;
+      const int o = i * kNX + 2 + lane;
+      float pb, pc, pd;
+      sp_inv_pred(kAlpha, kAlpha2, A0[o], A0[o + 1], A0[o + kNX], A0[o + kNX + 1], B1[o], B1[o + kNX], C1[o],
+                  C1[o + 1], D1[o], pb, pc, pd);
+      const float pa = A0[o];
+      const int gqy = ty * kQY + i - 2;
+      const int x0 = 2 * gqx, y0 = 2 * gqy;
+      if (x0 < W && y0 < H) {
+        float* r0 = out + (int64_t)y0 * a.out_stride;
+        r0[x0] = pa;
+        if (x0 + 1 < W) r0[x0 + 1] = pb;
+        if (y0 + 1 < H) {
+          float* r1 = r0 + a.out_stride;
+          r1[x0] = pc;
+          if (x0 + 1 < W) r1[x0 + 1] = pd;
+        }
+      }
+    }
+    if (img + (int)gridDim.y < a.batch) __syncthreads();
+  }
+}
+
+}  // namespace
+
+int cdf97_tiles(int W, int H, int& tiles_x, int& tiles_y) {
+  tiles_x = (((W + 1) >> 1) + kQX - 1) / kQX;
+  tiles_y = (((H + 1) >> 1) + kQY - 1) / kQY;
+  return (int64_t)tiles_x * tiles_y <= 0x7fffffff;
+}
+
+int launch_cdf97_level(int dir, const Level97& a, void* stream) {
+  int tx, ty;
+  if (!cdf97_tiles(a.W, a.H, tx, ty)) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)(tx * ty), (unsigned)(a.batch < 65535 ? a.batch : 65535));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (dir == kFwd) hipLaunchKernelGGL(fwd97, grid, dim3(kBlk), 0, s, a, tx);
+  else hipLaunchKernelGGL(inv97, grid, dim3(kBlk), 0, s, a, tx);
+  return hipGetLastError();
+}
+
+}  // namespace dwt2

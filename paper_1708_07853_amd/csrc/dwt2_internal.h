@@ -151,6 +151,21 @@ int launch_tail(int dir, int mode, const TailArgs& a, void* stream);
 int lds_tiles(int W, int H, int& tiles_x, int& tiles_y);
 int launch_lds_level(bool separable, int mode, const SepLevel& a, void* stream);
 
+// One CDF 9/7 level (float32; cdf97.hip).  W, H: the level input's size.
+struct Level97 {
+  const void* in;      // forward: the level input's pixels; inverse: LL_k
+  int64_t in_stride, in_bstride;
+  const void* bands;   // inverse: the packed array holding level k's H bands
+  int64_t bands_stride, bands_bstride;
+  void* ll;            // forward: LL_k
+  int64_t ll_stride, ll_bstride;
+  void* out;           // forward: the packed array (H bands); inverse: the pixels
+  int64_t out_stride, out_bstride;
+  int32_t W, H, batch, pad_;
+};
+int cdf97_tiles(int W, int H, int& tiles_x, int& tiles_y);
+int launch_cdf97_level(int dir, const Level97& a, void* stream);
+
 // Kernel launchers (kernels.hip).  Return hipError_t as int.
 int launch_level(int dir, int mode, int chunk, const LevelLaunch& a, void* stream);
 int job_blocks_per_cu(int dir, int mode, int chunk, bool table);

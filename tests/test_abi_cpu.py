@@ -95,7 +95,8 @@ BAD = [
 ]
 
 
-@pytest.mark.parametrize("fn", ["dwt2_fwd", "dwt2_inv", "dwt2_bwd", "dwt2_fwd_separable"])
+@pytest.mark.parametrize("fn", ["dwt2_fwd", "dwt2_inv", "dwt2_bwd", "dwt2_fwd_separable", "dwt2_fwd_cdf97",
+                                "dwt2_inv_cdf97"])
 @pytest.mark.parametrize("kw,code", BAD, ids=[str(b[0]) for b in BAD])
 def test_validation_errors(lib, fn, kw, code):
     assert call(lib, fn, **kw) == code
@@ -124,6 +125,12 @@ def test_lds_rejects_unknown_scheme(lib):
     # the LDS kernels use the plain workspace
     need = lib.dwt2_workspace_size(64, 64, 1, 2, 0)
     assert call_lds(lib, 1, wsb=need - 1) == -4
+
+
+@pytest.mark.parametrize("fn", ["dwt2_fwd_cdf97", "dwt2_inv_cdf97"])
+def test_cdf97_rejects_integer_mode(lib, fn):
+    assert call(lib, fn, mode=1) == -3
+    assert "9/7" in lib.dwt2_last_error().decode()
 
 
 def test_adjoint_rejects_integer_mode(lib):

@@ -1,0 +1,112 @@
+"""GPU parity of the CDF 9/7 path (dwt2_fwd_cdf97 / dwt2_inv_cdf97, through the
+C ABI) against the float64 9/7 oracle.
+
+Bar: float32 within TOL97 absolute on 8-bit-range data.  The bound is the
+unit roundoff 2^-24, times 2^13 (every intermediate value of a fused level
+on 8-bit input stays below 2^13), times 2^3 (roundings that can reach an
+output at full weight), which is 2^-8 < 4e-3."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import dwt97
+from paper_1708_07853_amd import synth
+
+pytestmark = pytest.mark.gpu
+TOL97 = 4e-3
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def D():
+    import paper_1708_07853_amd as d
+    return d
+
+
+def to_gpu(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def max_levels(w, h, cap=6):
+    lv = 1
+    while lv < cap and -(-w // (1 << lv)) >= 2 and -(-h // (1 << lv)) >= 2:
+        lv += 1
+    return lv
+
+
+def maxdiff(a, b):
+    return float(np.abs(np.asarray(a, dtype=np.float64) - np.asarray(b, dtype=np.float64)).max())
+
+
+# tiles are 128 x 32 pixels: these span several tiles per axis, ragged
+# edges, odd sizes, and inputs narrower than the halo
+SHAPES = [(2, 2), (3, 5), (17, 2), (2, 300), (5, 7), (64, 64), (65, 33), (33, 129), (300, 517), (129, 1030),
+          (97, 258), (260, 131)]
+
+
+def _img(h, w, seed):
+    return np.random.default_rng(seed).integers(0, 256, size=(h, w)).astype(np.float64)
+
+
+def test_cdf97_forward_matches_oracle():
+    d = D()
+    worst = 0.0
+    for idx, (h, w) in enumerate(SHAPES):
+        x = _img(h, w, 9700 + idx)
+        for levels in sorted({1, 2, max_levels(w, h)}):
+            if levels > max_levels(w, h):
+                continue
+            got = d.fwd_cdf97(to_gpu(x), levels).cpu().numpy()
+            err = maxdiff(got, dwt97.fwd(x, levels))
+            worst = max(worst, err)
+            assert err <= TOL97, (h, w, levels, err)
+    print(f"worst forward error {worst:.3g}")
+
+
+def test_cdf97_inverse_matches_oracle_and_round_trips():
+    d = D()
+    for idx, (h, w) in enumerate(SHAPES):
+        x = _img(h, w, 9750 + idx)
+        for levels in sorted({1, max_levels(w, h)}):
+            c32 = dwt97.fwd(x, levels).astype(np.float32)
+            got = d.inv_cdf97(to_gpu(c32), levels).cpu().numpy()
+            assert maxdiff(got, dwt97.inv(c32.astype(np.float64), levels)) <= TOL97, (h, w, levels)
+            xg = to_gpu(x)
+            rt = d.inv_cdf97(d.fwd_cdf97(xg, levels), levels)
+            assert float((rt - xg).abs().max()) <= TOL97, (h, w, levels)
+
+
+def test_cdf97_batch_strides():
+    d = D()
+    xs = torch.stack([to_gpu(_img(250, 333, 9800 + b)) for b in range(3)])
+    base = torch.zeros((3, 250, 340), device="cuda")
+    xv = base[:, :, 2:335]
+    xv.copy_(xs)
+    got = d.fwd_cdf97(xv, 3)
+    for b in range(3):
+        ref = dwt97.fwd(xs[b].cpu().numpy().astype(np.float64), 3)
+        assert maxdiff(got[b].cpu().numpy(), ref) <= TOL97
+    assert float((d.inv_cdf97(got, 3) - xs).abs().max()) <= TOL97
+    # a single image into a strided 2-D view: nothing outside the view is written
+    obase = torch.full((252, 341), -5.0, device="cuda")
+    ov = obase[1:251, 1:334]
+    d.inv_cdf97(got[1].contiguous(), 3, out=ov)
+    assert float((ov - xs[1]).abs().max()) <= TOL97
+    assert torch.all(obase[0] == -5) and torch.all(obase[251] == -5)
+    assert torch.all(obase[:, 0] == -5) and torch.all(obase[:, 334:] == -5)
+
+
+def test_cdf97_full_size():
+    """The 8192^2 6-level workload: the forward against the oracle element
+    by element, the inverse through the round trip."""
+    d = D()
+    x = synth.image_device(8192, 8192, 2)
+    c = d.fwd_cdf97(x, 6)
+    ref = dwt97.fwd(x.cpu().numpy().astype(np.float64), 6)
+    assert maxdiff(c.cpu().numpy(), ref) <= TOL97
+    r = d.inv_cdf97(c, 6)
+    assert float((r - x).abs().max()) <= TOL97
