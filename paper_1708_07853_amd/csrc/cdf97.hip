@@ -213,6 +213,10 @@ __global__ __launch_bounds__(kBlk) void inv97(Level97 a, int tiles_x) {
   const int ns_w = (W + 1) >> 1, ns_h = (H + 1) >> 1;
   const int qx0 = tx * kQX - 2, qy0 = ty * kQY - 2;  // image quadruple of local quadruple (0, 0)
   const int gqx = tx * kQX + lane;
+  // pixel pairs (even column, next column) are 8-byte aligned in every row
+  // and image: store them as one float2
+  const bool pairs = ((reinterpret_cast<uintptr_t>(a.out) | (uintptr_t)(a.out_stride << 2) |
+                       (uintptr_t)(a.out_bstride << 2)) & 7) == 0;
   for (int img = blockIdx.y; img < a.batch; img += gridDim.y) {
     const float* lls = static_cast<const float*>(a.in) + img * a.in_bstride;
     const float* bands = static_cast<const float*>(a.bands) + img * a.bands_bstride;
@@ -221,20 +225,41 @@ __global__ __launch_bounds__(kBlk) void inv97(Level97 a, int tiles_x) {
     // extension of the interleaved array: the L (even) and H (odd) positions
     // of a quadruple fold onto band indices of their own parity; the scaling
     // is undone as they are stored
-    walk<4>(0, kNY, 0, lane, wv, [&](int i, int q) {
-      const int gx = qx0 + q, gy = qy0 + i;
-      const int bx0 = fold97(2 * gx, W) >> 1, bx1 = (fold97(2 * gx + 1, W) - 1) >> 1;
-      const int by0 = fold97(2 * gy, H) >> 1, by1 = (fold97(2 * gy + 1, H) - 1) >> 1;
-      const float vll = lls[(int64_t)by0 * a.in_stride + bx0];
-      const float vhl = bands[(int64_t)by0 * a.bands_stride + ns_w + bx1];
-      const float vlh = bands[(int64_t)(ns_h + by1) * a.bands_stride + bx0];
-      const float vhh = bands[(int64_t)(ns_h + by1) * a.bands_stride + ns_w + bx1];
-      const int o = i * kNX + q;
-      A0[o] = vll * kHHScale;
-      B0[o] = vhl;
-      C0[o] = vlh;
-      D0[o] = vhh * kLLScale;
-    });
+    // (all of a wave's loads are issued before its first LDS store)
+    {
+      constexpr int kR = kNY / kWv;  // rows per wave in the first 64 columns
+      static_assert(kNY % kWv == 0 && (kNX - kWave) * kNY <= kBlk, "inverse load mapping");
+      float vll[kR + 1], vhl[kR + 1], vlh[kR + 1], vhh[kR + 1];
+      int slot[kR + 1];
+#pragma unroll
+      for (int k = 0; k <= kR; ++k) {
+        // k < kR: row wv + k kWv, column lane; k = kR: one of the last
+        // kNX - 64 columns, for threads below (kNX - 64) kNY
+        const bool extra = k == kR;
+        const int t = threadIdx.x;
+        const bool live = !extra || t < (kNX - kWave) * kNY;
+        const int i = extra ? (live ? t / (kNX - kWave) : 0) : wv + k * kWv;
+        const int q = extra ? kWave + t % (kNX - kWave) : lane;
+        const int gx = qx0 + q, gy = qy0 + i;
+        const int bx0 = fold97(2 * gx, W) >> 1, bx1 = (fold97(2 * gx + 1, W) - 1) >> 1;
+        const int by0 = fold97(2 * gy, H) >> 1, by1 = (fold97(2 * gy + 1, H) - 1) >> 1;
+        vll[k] = lls[(int64_t)by0 * a.in_stride + bx0];
+        vhl[k] = bands[(int64_t)by0 * a.bands_stride + ns_w + bx1];
+        vlh[k] = bands[(int64_t)(ns_h + by1) * a.bands_stride + bx0];
+        vhh[k] = bands[(int64_t)(ns_h + by1) * a.bands_stride + ns_w + bx1];
+        slot[k] = live ? i * kNX + q : -1;
+      }
+#pragma unroll
+      for (int k = 0; k <= kR; ++k) {
+        const int o = slot[k];
+        if (o >= 0) {
+          A0[o] = vll[k] * kHHScale;
+          B0[o] = vhl[k];
+          C0[o] = vlh[k];
+          D0[o] = vhh[k] * kLLScale;
+        }
+      }
+    }
     __syncthreads();
     // undo pair 2 update (delta): rows [1, kNY), columns [1, kNX)
     walk<3>(1, kNY, 1, lane, wv, [&](int i, int q) {
@@ -270,12 +295,17 @@ __global__ __launch_bounds__(kBlk) void inv97(Level97 a, int tiles_x) {
       const int x0 = 2 * gqx, y0 = 2 * gqy;
       if (x0 < W && y0 < H) {
         float* r0 = out + (int64_t)y0 * a.out_stride;
-        r0[x0] = pa;
-        if (x0 + 1 < W) r0[x0 + 1] = pb;
-        if (y0 + 1 < H) {
-          float* r1 = r0 + a.out_stride;
-          r1[x0] = pc;
-          if (x0 + 1 < W) r1[x0 + 1] = pd;
+        float* r1 = r0 + a.out_stride;
+        if (pairs && x0 + 1 < W) {
+          *reinterpret_cast<float2*>(r0 + x0) = make_float2(pa, pb);
+          if (y0 + 1 < H) *reinterpret_cast<float2*>(r1 + x0) = make_float2(pc, pd);
+        } else {
+          r0[x0] = pa;
+          if (x0 + 1 < W) r0[x0 + 1] = pb;
+          if (y0 + 1 < H) {
+            r1[x0] = pc;
+            if (x0 + 1 < W) r1[x0 + 1] = pd;
+          }
         }
       }
     }
