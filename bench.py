@@ -18,8 +18,9 @@ call's stream (dwt2_set_probe); achieved = its algorithmic bytes (read the
 8192^2 image once, write as many coefficients) / the mean duration.
 
 Side measurements reported in "detail": per-direction times and effective
-bandwidth, the separable lifting baseline against the non-separable forward
-(the paper's comparison), the integer 16384^2 forward/inverse, the ragged
+bandwidth, the separable lifting baselines (per-step passes and LDS-tiled)
+against the non-separable forward (the paper's comparison), the CDF 9/7
+forward/inverse, the integer 16384^2 forward/inverse, the ragged
 256-image batch (one batched call vs 256 plain calls), the 32 x 3 x 1024^2
 autograd forward/backward, and a device-to-device copy ceiling.
 
@@ -110,7 +111,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-detail", action="store_true", help="skip the side measurements")
-    ap.add_argument("--only", choices=["step", "fwd", "fwd1", "inv", "bwd", "copy"], default=None,
+    ap.add_argument("--only", choices=["step", "fwd", "fwd1", "inv", "bwd", "copy", "fwd97", "inv97"], default=None,
                     help="profiling aid: run only this part (fwd1: the level-1 forward kernel alone, "
                          "as a 1-level call with the same grid), untimed JSON omitted")
     ap.add_argument("--sweep", action="store_true",
@@ -173,6 +174,10 @@ def main():
                 bwd(s)
             if args.only == "copy":
                 s["c"].copy_(s["x"])
+            if args.only == "fwd97":
+                dwt.fwd_cdf97(s["x"], L, out=s["c"], workspace=ws)
+            if args.only == "inv97":
+                dwt.inv_cdf97(s["c"], L, out=s["r"], workspace=ws)
         torch.cuda.synchronize()
         print(json.dumps({"only": args.only, "reps": reps}))
         return
@@ -259,6 +264,24 @@ def main():
             "lds_tiled_nonseparable_ms": round(lds["nonseparable"], 4),
             "lds_tiled_speedup_of_two_steps_over_four": round(lds["separable"] / lds["nonseparable"], 3)}
         del wss
+        # CDF 9/7 (float32), the same image and levels: forward and inverse
+        t97 = {}
+        for name, f in (("fwd", lambda s_: dwt.fwd_cdf97(s_["x"], L, out=s_["c"], workspace=ws)),
+                        ("inv", lambda s_: dwt.inv_cdf97(s_["c"], L, out=s_["r"], workspace=ws))):
+            def g(f=f):
+                k[0] ^= 1
+                f(sets[k[0]])
+            for _ in range(3):
+                g()
+            t97[name] = float(np.median(timer(g, 20)))
+        rt = float((dwt.inv_cdf97(dwt.fwd_cdf97(sets[0]["x"], L), L) - sets[0]["x"]).abs().max())
+        detail["cdf97_8192_L6"] = {
+            "fwd_ms": round(t97["fwd"], 4), "inv_ms": round(t97["inv"], 4),
+            "fwd_Gpx_s": round(npx / (t97["fwd"] * 1e-3) / 1e9, 1),
+            "inv_Gpx_s": round(npx / (t97["inv"] * 1e-3) / 1e9, 1),
+            "fwd_frac_of_8TBps": round(alg_bytes(W, H, L) / (t97["fwd"] * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+            "inv_frac_of_8TBps": round(alg_bytes(W, H, L) / (t97["inv"] * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+            "roundtrip_max_abs_err": rt}
         # copy ceiling: read + write of 1 GiB
         a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
         b = torch.empty_like(a)
