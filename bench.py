@@ -26,8 +26,9 @@ autograd forward/backward, and a device-to-device copy ceiling.
 
 --sweep prints, instead, the two comparisons of the paper's §4 redone on this
 GPU: the forward's time against the image edge (512 .. 16384, 6 levels) for
-the product path, the LDS-tiled non-separable (two barrier steps) and
-separable (four) kernels and the separable-pass baseline; and the level-1
+the product path, the LDS-tiled non-separable (two barrier steps), adapted
+(two, fewer operations) and separable (four) kernels and the separable-pass
+baseline; and the level-1
 time of 8192^2 against the work-item shape (segment height x prefetch chunk),
 the counterpart of the paper's tile-size experiment.
 
@@ -251,7 +252,7 @@ def main():
         ts = float(np.median(timer(sep_fwd, 20)))
         tf = float(np.median(timer(fused_fwd, 20)))
         lds = {}
-        for scheme in ("separable", "nonseparable"):
+        for scheme in ("separable", "nonseparable", "adapted"):
             f = lds_fwd(scheme)
             for _ in range(3):
                 f()
@@ -262,6 +263,7 @@ def main():
             "separable_hbm_passes_per_level": 4, "nonseparable_hbm_passes_per_level": 1,
             "lds_tiled_separable_ms": round(lds["separable"], 4),
             "lds_tiled_nonseparable_ms": round(lds["nonseparable"], 4),
+            "lds_tiled_adapted_ms": round(lds["adapted"], 4),
             "lds_tiled_speedup_of_two_steps_over_four": round(lds["separable"] / lds["nonseparable"], 3)}
         del wss
         # CDF 9/7 (float32), the same image and levels: forward and inverse
@@ -415,6 +417,7 @@ def sweep(torch, dwt, synth, dev, timer, reps=20):
             "product": lambda s: dwt.fwd(xs[s], L, out=outs[s], workspace=ws),
             "lds_nonseparable": lambda s: dwt.fwd_lds(xs[s], L, "nonseparable", out=outs[s], workspace=ws),
             "lds_separable": lambda s: dwt.fwd_lds(xs[s], L, "separable", out=outs[s], workspace=ws),
+            "lds_adapted": lambda s: dwt.fwd_lds(xs[s], L, "adapted", out=outs[s], workspace=ws),
             "separable_passes": lambda s: dwt.fwd_separable(xs[s], L, out=outs[s], workspace=ws),
         }
         for name, f in variants.items():

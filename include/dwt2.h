@@ -157,13 +157,20 @@ int dwt2_fwd_separable(const void* src, int64_t src_stride,
  *   scheme DWT2_SCHEME_SEPARABLE:    horizontal predict, vertical predict,
  *       horizontal update, vertical update (§2, eq. (3)): four steps;
  *   scheme DWT2_SCHEME_NONSEPARABLE: spatial predict, spatial update (§3,
- *       eq. (5)): two steps.
+ *       eq. (5)): two steps;
+ *   scheme DWT2_SCHEME_ADAPTED: the adapted non-separable scheme of §3, float
+ *       only: each filter split into its constant term and the rest
+ *       (P = P0 + P1, U = U0 + U1); the constant terms, which touch only a
+ *       quadruple's own samples, run separably without an exchange, so the
+ *       two steps need fewer operations.
  * Arguments, layout, ownership and errors are those of dwt2_fwd, with the
- * workspace of dwt2_workspace_size; an unknown scheme is DWT2_ERR_ARG.
- * Integer results equal dwt2_fwd's for both schemes.  Float results of the
- * non-separable scheme equal dwt2_fwd's bit for bit; those of the separable
- * scheme equal dwt2_fwd_separable's bit for bit. */
-enum { DWT2_SCHEME_SEPARABLE = 0, DWT2_SCHEME_NONSEPARABLE = 1 };
+ * workspace of dwt2_workspace_size; an unknown scheme is DWT2_ERR_ARG, an
+ * integer mode with the adapted scheme DWT2_ERR_MODE.  Integer results equal
+ * dwt2_fwd's for both other schemes.  Float results of the non-separable
+ * scheme equal dwt2_fwd's bit for bit; those of the separable scheme equal
+ * dwt2_fwd_separable's bit for bit; those of the adapted scheme agree with
+ * both up to rounding. */
+enum { DWT2_SCHEME_SEPARABLE = 0, DWT2_SCHEME_NONSEPARABLE = 1, DWT2_SCHEME_ADAPTED = 2 };
 int dwt2_fwd_lds(const void* src, int64_t src_stride, int64_t src_batch_stride,
                  void* dst, int64_t dst_stride, int64_t dst_batch_stride,
                  int32_t width, int32_t height, int32_t batch, int32_t levels,

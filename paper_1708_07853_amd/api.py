@@ -123,15 +123,16 @@ def inv_cdf97(c: torch.Tensor, levels: int, out=None, workspace=None) -> torch.T
     return _run("dwt2_inv_cdf97", c, levels, None, out, workspace)
 
 
-SCHEMES = {"separable": 0, "nonseparable": 1}
+SCHEMES = {"separable": 0, "nonseparable": 1, "adapted": 2}
 
 
 def fwd_lds(x: torch.Tensor, levels: int, scheme: str = "nonseparable", mode=None, out=None,
             workspace=None) -> torch.Tensor:
     """The same forward transform by the LDS-tiled comparison kernels
     (see dwt2_fwd_lds): scheme "separable" lifts each tile in four
-    barrier-separated steps (eq. (3)), "nonseparable" in two (eq. (5)).
-    For comparisons, not for production use."""
+    barrier-separated steps (eq. (3)), "nonseparable" in two (eq. (5)),
+    "adapted" in two with the filters' constant terms applied separably
+    (§3; float32 only).  For comparisons, not for production use."""
     if scheme not in SCHEMES:
         raise ValueError(f"scheme must be one of {sorted(SCHEMES)}")
     return _run("dwt2_fwd_lds", x, levels, mode, out, workspace, extra=(SCHEMES[scheme],))

@@ -401,7 +401,7 @@ static int run_separable(const Call& c, const Geo& g, void* stream) {
 
 // LDS-tiled comparison kernels: one launch per level, LL through the plain
 // workspace's buffers.
-static int run_lds(bool separable, const Call& c, const Geo& g, void* stream) {
+static int run_lds(int scheme, const Call& c, const Geo& g, void* stream) {
   const int64_t ws_bs = (int64_t)(ws_per_image(g) / 4);
   for (int k = 1; k <= g.L; ++k) {
     SepLevel a;
@@ -432,7 +432,7 @@ static int run_lds(bool separable, const Call& c, const Geo& g, void* stream) {
     a.band = c.dst;
     a.band_stride = c.dst_stride;
     a.band_bstride = c.dst_bs;
-    const int err = launch_lds_level(separable, c.mode, a, stream);
+    const int err = launch_lds_level(scheme, c.mode, a, stream);
     if (err != hipSuccess)
       return fail(DWT2_ERR_HIP, "LDS-tiled level %d launch failed: %s", k, hipGetErrorString((hipError_t)err));
   }
@@ -506,7 +506,7 @@ static int run_cdf97(int dir, const Call& c, const Geo& g, void* stream) {
 // Which kernels compute a call: the product path, one of the comparison
 // baselines (separable passes, LDS-tiled separable, LDS-tiled non-separable),
 // or the CDF 9/7 kernels.
-enum { kProduct = 0, kSepPasses = 1, kLdsSep = 2, kLdsNonSep = 3, kCdf97 = 4 };
+enum { kProduct = 0, kSepPasses = 1, kLdsSep = 2, kLdsNonSep = 3, kCdf97 = 4, kLdsAdapted = 5 };
 
 static int transform(int dir, const void* src, int64_t src_stride, int64_t src_bs, void* dst, int64_t dst_stride,
                      int64_t dst_bs, int32_t width, int32_t height, int32_t batch, int32_t levels, int32_t mode,
@@ -530,6 +530,8 @@ static int transform(int dir, const void* src, int64_t src_stride, int64_t src_b
   if (mode != DWT2_F32 && mode != DWT2_I32_REV) return fail(DWT2_ERR_MODE, "unknown mode %d", mode);
   if (dir == kBwd && mode != DWT2_F32) return fail(DWT2_ERR_MODE, "the adjoint exists for DWT2_F32 only");
   if (variant == kCdf97 && mode != DWT2_F32) return fail(DWT2_ERR_MODE, "the CDF 9/7 transform exists for DWT2_F32 only");
+  if (variant == kLdsAdapted && mode != DWT2_F32)
+    return fail(DWT2_ERR_MODE, "the adapted scheme exists for DWT2_F32 only");
   if (src == dst) return fail(DWT2_ERR_ALIAS, "src and dst are the same buffer; the transform is out of place");
   const size_t need =
       sync_bytes(g, batch) + (ws_per_image(g) + (separable ? sep_work_per_image(g) : 0)) * (size_t)batch;
@@ -538,7 +540,9 @@ static int transform(int dir, const void* src, int64_t src_stride, int64_t src_b
   Call c{static_cast<const char*>(src), src_stride, src_bs, static_cast<char*>(dst), dst_stride, dst_bs, batch, mode,
          static_cast<char*>(workspace), sync_bytes(g, batch)};
   if (separable) return run_separable(c, g, stream);
-  if (variant == kLdsSep || variant == kLdsNonSep) return run_lds(variant == kLdsSep, c, g, stream);
+  if (variant == kLdsSep) return run_lds(DWT2_SCHEME_SEPARABLE, c, g, stream);
+  if (variant == kLdsNonSep) return run_lds(DWT2_SCHEME_NONSEPARABLE, c, g, stream);
+  if (variant == kLdsAdapted) return run_lds(DWT2_SCHEME_ADAPTED, c, g, stream);
   if (variant == kCdf97) return run_cdf97(dir, c, g, stream);
   if (g_persistent.load() < 0) g_persistent.store(env_int("DWT2_PERSISTENT") == 1 ? 1 : 0);
   const int path = g_persistent.load();
@@ -591,13 +595,14 @@ int dwt2_inv_cdf97(const void* src, int64_t src_stride, int64_t src_batch_stride
 int dwt2_fwd_lds(const void* src, int64_t src_stride, int64_t src_batch_stride, void* dst, int64_t dst_stride,
                  int64_t dst_batch_stride, int32_t width, int32_t height, int32_t batch, int32_t levels, int32_t mode,
                  int32_t boundary, int32_t scheme, void* workspace, size_t workspace_bytes, void* stream) {
-  if (scheme != DWT2_SCHEME_SEPARABLE && scheme != DWT2_SCHEME_NONSEPARABLE) {
+  if (scheme != DWT2_SCHEME_SEPARABLE && scheme != DWT2_SCHEME_NONSEPARABLE && scheme != DWT2_SCHEME_ADAPTED) {
     clear_error();
     return fail(DWT2_ERR_ARG, "unknown scheme %d", scheme);
   }
   return transform(kFwd, src, src_stride, src_batch_stride, dst, dst_stride, dst_batch_stride, width, height, batch,
                    levels, mode, boundary, workspace, workspace_bytes, stream,
-                   scheme == DWT2_SCHEME_SEPARABLE ? kLdsSep : kLdsNonSep);
+                   scheme == DWT2_SCHEME_SEPARABLE ? kLdsSep
+                                                   : (scheme == DWT2_SCHEME_NONSEPARABLE ? kLdsNonSep : kLdsAdapted));
 }
 
 int dwt2_fwd(const void* src, int64_t src_stride, int64_t src_batch_stride, void* dst, int64_t dst_stride,

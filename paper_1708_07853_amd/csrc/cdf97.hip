@@ -110,7 +110,9 @@ __global__ __launch_bounds__(kBlk) void fwd97(Level97 a, int tiles_x) {
   float* B1 = S + 4 * kNP;
   float* C1 = S + 5 * kNP;
   float* D1 = S + 6 * kNP;
-  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  // the wave index is uniform: as a scalar, row folds and row pointers are
+  // scalar code, not per-lane branches
+  const int lane = threadIdx.x & (kWave - 1), wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int tile = tile_remap(blockIdx.x, gridDim.x);
   const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
   const int W = a.W, H = a.H;
@@ -206,7 +208,9 @@ __global__ __launch_bounds__(kBlk) void inv97(Level97 a, int tiles_x) {
   float* B1 = S + 4 * kNP;
   float* C1 = S + 5 * kNP;
   float* D1 = S + 6 * kNP;
-  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  // the wave index is uniform: as a scalar, row folds and row pointers are
+  // scalar code, not per-lane branches
+  const int lane = threadIdx.x & (kWave - 1), wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int tile = tile_remap(blockIdx.x, gridDim.x);
   const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
   const int W = a.W, H = a.H;

@@ -144,12 +144,13 @@ struct TailArgs {
   int32_t W[kTailMaxLevels + 1], H[kTailMaxLevels + 1];  // level sizes from the first tail input
 };
 int launch_tail(int dir, int mode, const TailArgs& a, void* stream);
-// LDS-tiled forward level (comparison kernels): the separable steps of
-// eq. (3) or the spatial steps of eq. (5), a workgroup barrier between steps.
-// Uses src, ll, band and the sizes of a; work is unused.  lds_tiles gives
-// the grid's tile counts (returns 0 if they exceed a launch).
+// LDS-tiled forward level (comparison kernels): scheme DWT2_SCHEME_*, the
+// separable steps of eq. (3), the spatial steps of eq. (5) or the adapted
+// scheme of §3 (float only), a workgroup barrier between steps.  Uses src,
+// ll, band and the sizes of a; work is unused.  lds_tiles gives the grid's
+// tile counts (returns 0 if they exceed a launch).
 int lds_tiles(int W, int H, int& tiles_x, int& tiles_y);
-int launch_lds_level(bool separable, int mode, const SepLevel& a, void* stream);
+int launch_lds_level(int scheme, int mode, const SepLevel& a, void* stream);
 
 // One CDF 9/7 level (float32; cdf97.hip).  W, H: the level input's size.
 struct Level97 {

@@ -1640,7 +1640,9 @@ template <typename T, bool SEP>
 __global__ __launch_bounds__(kLdsBlock) void lds_level(SepLevel a, int tiles_x) {
   __shared__ T X[kLdsPX * kLdsPY];
   __shared__ T PB[SEP ? 1 : 3 * kLdsPQ];
-  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  // the wave index is uniform: as a scalar, row folds and row pointers are
+  // scalar code, not per-lane branches
+  const int lane = threadIdx.x & (kWave - 1), wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int tile = xcd_remap(blockIdx.x, gridDim.x);
   const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
   const int W = a.W, H = a.H;
@@ -1761,6 +1763,150 @@ __global__ __launch_bounds__(kLdsBlock) void lds_level(SepLevel a, int tiles_x) 
   }
 }
 
+// The adapted non-separable scheme (§3) on the same tiles, float only.  Each
+// filter splits into its constant term and the rest, P = P0 + P1 and
+// U = U0 + U1 (for the 5/3: P0 = -1/2, P1 = -1/2 z, U0 = 1/4, U1 = 1/4 z^-1).
+// The constant terms touch only a quadruple's own samples, so they run
+// separably without an exchange: P0 as each thread loads its quadruples, U0
+// right after the one-sided predict P1, before the barrier.  The scheme keeps
+// the two barriers of eq. (5) but needs 18 multiply-adds per quadruple
+// instead of 23 operations.  The constant and one-sided parts commute
+// (polynomials commute), so the result equals eq. (5)'s up to rounding.
+constexpr int kLdsQW = kLdsPX / 2, kLdsQH = kLdsPY / 2;  // quadruples of the tile incl. halo
+
+__global__ __launch_bounds__(kLdsBlock) void lds_adapted(SepLevel a, int tiles_x) {
+  constexpr int NQ = kLdsQW * kLdsQH;
+  __shared__ float Q[4 * NQ];        // a, b, c, d after P0
+  __shared__ float R[4 * kLdsPQ];    // a, b', c', d' after P1 and U0
+  const float* Qa = Q;
+  const float* Qb = Q + NQ;
+  const float* Qc = Q + 2 * NQ;
+  const float* Qd = Q + 3 * NQ;
+  float* Ra = R;
+  float* Rb = R + kLdsPQ;
+  float* Rc = R + 2 * kLdsPQ;
+  float* Rd = R + 3 * kLdsPQ;
+  // the wave index is uniform: as a scalar, row folds and row pointers are
+  // scalar code, not per-lane branches
+  const int lane = threadIdx.x & (kWave - 1), wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int tile = xcd_remap(blockIdx.x, gridDim.x);
+  const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
+  const int W = a.W, H = a.H;
+  const int ns_w = (W + 1) >> 1, ns_h = (H + 1) >> 1, nd_w = W >> 1, nd_h = H >> 1;
+  const int ox = 2 * kLdsQX * tx - 2, oy = 2 * kLdsQY * ty - 2;  // image position of the tile's pixel (0, 0)
+  const int cx0 = fold_idx(ox + 2 * lane, W), cx1 = fold_idx(ox + 2 * lane + 1, W);
+  constexpr int kExtraQ = kLdsQW - kWave;                        // quadruple columns past the waves' 64
+  constexpr int kR = (kLdsQH + kLdsWaves - 1) / kLdsWaves;       // quadruple rows per wave
+  static_assert(kExtraQ * kLdsQH <= kLdsBlock, "adapted load mapping");
+  const int gqx = tx * kLdsQX + lane;
+  // rows (and images) start 8-byte aligned: a quadruple row's two pixels
+  // load as one float2
+  const bool pairs = ((reinterpret_cast<uintptr_t>(a.src) | (uintptr_t)(a.src_stride << 2) |
+                       (uintptr_t)(a.src_bstride << 2)) & 7) == 0;
+  const bool interior = pairs && ox >= 0 && ox + kLdsPX <= W;  // ox is even
+  for (int img = blockIdx.y; img < a.batch; img += gridDim.y) {
+    const float* src = static_cast<const float*>(a.src) + img * a.src_bstride;
+    float* ll = static_cast<float*>(a.ll) + img * a.ll_bstride;
+    float* band = static_cast<float*>(a.band) + img * a.band_bstride;
+    {
+      // every quadruple of the tile once: wave rows for columns 0..63, then
+      // the last columns in one pass; all loads before the first LDS store
+      float va[kR + 1], vb[kR + 1], vc[kR + 1], vd[kR + 1];
+      int slot[kR + 1];
+      // VEC: the tile's columns lie inside the image and rows are 8-byte
+      // aligned, so a quadruple row's two pixels load as one float2; the
+      // choice is uniform over the block, so every load is issued at once
+      auto load_all = [&](auto vec_tag) {
+        constexpr bool VEC = decltype(vec_tag)::value;
+#pragma unroll
+        for (int k = 0; k <= kR; ++k) {
+          const bool extra = k == kR;
+          const int t = threadIdx.x;
+          const int row = wv + k * kLdsWaves;
+          const bool live = extra ? t < kExtraQ * kLdsQH : row < kLdsQH;
+          const int i = live ? (extra ? t / kExtraQ : row) : 0;
+          const int q = extra ? kWave + t % kExtraQ : lane;
+          const float* r0 = src + (int64_t)fold_idx(oy + 2 * i, H) * a.src_stride;
+          const float* r1 = src + (int64_t)fold_idx(oy + 2 * i + 1, H) * a.src_stride;
+          if constexpr (VEC) {
+            const int x0 = ox + 2 * q;
+            const float2 p0 = *reinterpret_cast<const float2*>(r0 + x0);
+            const float2 p1 = *reinterpret_cast<const float2*>(r1 + x0);
+            va[k] = p0.x;
+            vb[k] = p0.y;
+            vc[k] = p1.x;
+            vd[k] = p1.y;
+          } else {
+            const int x0 = extra ? fold_idx(ox + 2 * q, W) : cx0, x1 = extra ? fold_idx(ox + 2 * q + 1, W) : cx1;
+            va[k] = r0[x0];
+            vb[k] = r0[x1];
+            vc[k] = r1[x0];
+            vd[k] = r1[x1];
+          }
+          slot[k] = live ? i * kLdsQW + q : -1;
+        }
+      };
+      if (interior) load_all(std::true_type{});
+      else load_all(std::false_type{});
+#pragma unroll
+      for (int k = 0; k <= kR; ++k) {
+        const int o = slot[k];
+        if (o >= 0) {
+          // constant predict parts: horizontal, then vertical
+          const float b = __fmaf_rn(-0.5f, va[k], vb[k]);
+          float d = __fmaf_rn(-0.5f, vc[k], vd[k]);
+          const float c = __fmaf_rn(-0.5f, va[k], vc[k]);
+          d = __fmaf_rn(-0.5f, b, d);
+          Q[o] = va[k];
+          Q[NQ + o] = b;
+          Q[2 * NQ + o] = c;
+          Q[3 * NQ + o] = d;
+        }
+      }
+    }
+    __syncthreads();
+    // step 1 over quadruples [0, kLdsQY] x [0, kLdsQX]: the one-sided predict
+    // (neighbours after P0), then the constant update parts
+    lds_walk65(kLdsQY + 1, lane, wv, [&](int i, int q) {
+      const int o = i * kLdsQW + q;
+      float bp = __fmaf_rn(-0.5f, Qa[o + 1], Qb[o]);
+      float cp = __fmaf_rn(-0.5f, Qa[o + kLdsQW], Qc[o]);
+      const float dp = __fmaf_rn(0.25f, Qa[o + kLdsQW + 1],
+                                 __fmaf_rn(-0.5f, Qb[o + kLdsQW], __fmaf_rn(-0.5f, Qc[o + 1], Qd[o])));
+      float an = __fmaf_rn(0.25f, bp, Qa[o]);
+      cp = __fmaf_rn(0.25f, dp, cp);
+      an = __fmaf_rn(0.25f, cp, an);
+      bp = __fmaf_rn(0.25f, dp, bp);
+      const int p = i * kLdsQ1 + q;
+      Ra[p] = an;
+      Rb[p] = bp;
+      Rc[p] = cp;
+      Rd[p] = dp;
+    });
+    __syncthreads();
+    // step 2 over [1, kLdsQY] x [1, kLdsQX]: the one-sided update
+#pragma unroll
+    for (int k = 0; k < kLdsQY / kLdsWaves; ++k) {
+      const int i = 1 + wv + k * kLdsWaves;
+      const int p = i * kLdsQ1 + lane + 1;
+      const float vll = __fmaf_rn(0.0625f, Rd[p - kLdsQ1 - 1], __fmaf_rn(0.25f, Rc[p - kLdsQ1], __fmaf_rn(0.25f, Rb[p - 1], Ra[p])));
+      const float vhl = __fmaf_rn(0.25f, Rd[p - kLdsQ1], Rb[p]);
+      const float vlh = __fmaf_rn(0.25f, Rd[p - 1], Rc[p]);
+      const float vhh = Rd[p];
+      const int gqy = ty * kLdsQY + wv + k * kLdsWaves;
+      if (gqx < ns_w && gqy < ns_h) {
+        ll[(int64_t)gqy * a.ll_stride + gqx] = vll;
+        if (gqx < nd_w) band[(int64_t)gqy * a.band_stride + ns_w + gqx] = vhl;
+        if (gqy < nd_h) {
+          band[(int64_t)(ns_h + gqy) * a.band_stride + gqx] = vlh;
+          if (gqx < nd_w) band[(int64_t)(ns_h + gqy) * a.band_stride + ns_w + gqx] = vhh;
+        }
+      }
+    }
+    if (img + (int)gridDim.y < a.batch) __syncthreads();
+  }
+}
+
 __global__ void zero_kernel(uint32_t* p, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     p[i] = 0u;
@@ -1873,12 +2019,15 @@ int lds_tiles(int W, int H, int& tiles_x, int& tiles_y) {
   return (int64_t)tiles_x * tiles_y <= 0x7fffffff;
 }
 
-int launch_lds_level(bool separable, int mode, const SepLevel& a, void* stream) {
+int launch_lds_level(int scheme, int mode, const SepLevel& a, void* stream) {
   hipStream_t s = static_cast<hipStream_t>(stream);
   int tx, ty;
   if (!lds_tiles(a.W, a.H, tx, ty)) return hipErrorInvalidValue;
   const dim3 grid((unsigned)(tx * ty), (unsigned)(a.batch < 65535 ? a.batch : 65535));
-  if (separable) {
+  if (scheme == DWT2_SCHEME_ADAPTED) {
+    if (mode != DWT2_F32) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(lds_adapted, grid, dim3(kLdsBlock), 0, s, a, tx);
+  } else if (scheme == DWT2_SCHEME_SEPARABLE) {
     if (mode == DWT2_F32) hipLaunchKernelGGL((lds_level<float, true>), grid, dim3(kLdsBlock), 0, s, a, tx);
     else hipLaunchKernelGGL((lds_level<int, true>), grid, dim3(kLdsBlock), 0, s, a, tx);
   } else {

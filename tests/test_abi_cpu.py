@@ -111,7 +111,7 @@ def call_lds(lib, scheme=0, **kw):
                             a["levels"], a["mode"], a["boundary"], scheme, a["ws"], a["wsb"], a["stream"])
 
 
-@pytest.mark.parametrize("scheme", [0, 1])
+@pytest.mark.parametrize("scheme", [0, 1, 2])
 @pytest.mark.parametrize("kw,code", BAD, ids=[str(b[0]) for b in BAD])
 def test_lds_validation_errors(lib, scheme, kw, code):
     assert call_lds(lib, scheme, **kw) == code
@@ -119,9 +119,12 @@ def test_lds_validation_errors(lib, scheme, kw, code):
 
 
 def test_lds_rejects_unknown_scheme(lib):
-    for scheme in (-1, 2, 7):
+    for scheme in (-1, 3, 7):
         assert call_lds(lib, scheme) == -1
         assert "scheme" in lib.dwt2_last_error().decode()
+    # the adapted scheme splits the filters, which floor rounding does not allow
+    assert call_lds(lib, 2, mode=1) == -3
+    assert "adapted" in lib.dwt2_last_error().decode()
     # the LDS kernels use the plain workspace
     need = lib.dwt2_workspace_size(64, 64, 1, 2, 0)
     assert call_lds(lib, 1, wsb=need - 1) == -4

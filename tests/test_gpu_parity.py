@@ -448,6 +448,26 @@ def test_lds_tiled_schemes_match_oracle_and_their_counterparts(mode):
                 assert maxdiff(sp.cpu().numpy(), ref) <= TOL, (h, w, levels)
 
 
+def test_lds_adapted_scheme_matches_oracle():
+    """The adapted scheme (§3: the filters' constant terms applied separably,
+    the rest non-separably) on the same tiles: within the float tolerance of
+    the oracle and of the non-separable kernels; float32 only."""
+    d = D()
+    for idx, (h, w) in enumerate(LDS_SHAPES):
+        x = _img(h, w, 1300 + idx)
+        for levels in sorted({1, 2, max_levels(w, h, 6)}):
+            if max_levels(w, h, 6) < levels:
+                continue
+            xg = to_gpu(x.astype(np.float32))
+            got = d.fwd_lds(xg, levels, "adapted")
+            assert maxdiff(got.cpu().numpy(), oracle.fwd(x, levels)) <= TOL, (h, w, levels)
+            assert float((got - d.fwd_lds(xg, levels, "nonseparable")).abs().max()) <= TOL, (h, w, levels)
+    x = synth.image_device(8192, 8192, 2)
+    assert float((d.fwd_lds(x, 6, "adapted") - d.fwd(x, 6)).abs().max()) <= TOL
+    with pytest.raises(ValueError):
+        d.fwd_lds(to_gpu(_img(64, 64, 1).astype(np.int32)), 2, "adapted")
+
+
 def test_lds_tiled_batch_strides_and_full_size():
     """Batched strided views, and the 8192^2 6-level workload the benchmark
     compares on."""
