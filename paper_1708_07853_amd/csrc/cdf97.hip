@@ -15,9 +15,10 @@
 // interleaved coefficients (inverse).  The extension keeps every index's
 // parity, so it commutes with lifting, and each step can run on a fixed
 // local range that shrinks by one quadruple per step.  The steps ping-pong
-// between two sets of planes (seven planes in all), with a workgroup
-// barrier between steps, so that no step overwrites a value another thread
-// of the same step still reads.
+// b and c between two sets of planes, with a workgroup barrier between
+// steps, so that no step overwrites a value another thread of the same step
+// still reads.  d needs one plane: a predict step reads it only at its own
+// quadruple.  Six planes (32640 bytes) leave room for five workgroups per CU.
 #include <hip/hip_runtime.h>
 
 #include "dwt2_internal.h"
@@ -101,15 +102,15 @@ __device__ __forceinline__ void sp_inv_pred(float p, float pp, float a, float aR
 }
 
 // Forward level: pixels in, LL_k and the three H bands out.
-__global__ __launch_bounds__(kBlk) void fwd97(Level97 a, int tiles_x) {
-  __shared__ float S[7 * kNP];
+__global__ __launch_bounds__(kBlk, 5) void fwd97(Level97 a, int tiles_x) {
+  __shared__ float S[6 * kNP];
   float* A0 = S;
   float* B0 = S + kNP;
   float* C0 = S + 2 * kNP;
   float* D0 = S + 3 * kNP;
   float* B1 = S + 4 * kNP;
   float* C1 = S + 5 * kNP;
-  float* D1 = S + 6 * kNP;
+  float* D1 = D0;  // d is read only at its own quadruple by the step that rewrites it
   // the wave index is uniform: as a scalar, row folds and row pointers are
   // scalar code, not per-lane branches
   const int lane = threadIdx.x & (kWave - 1), wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
@@ -199,15 +200,15 @@ __global__ __launch_bounds__(kBlk) void fwd97(Level97 a, int tiles_x) {
 }
 
 // Inverse level: LL_k and the H bands in, the level input's pixels out.
-__global__ __launch_bounds__(kBlk) void inv97(Level97 a, int tiles_x) {
-  __shared__ float S[7 * kNP];
+__global__ __launch_bounds__(kBlk, 5) void inv97(Level97 a, int tiles_x) {
+  __shared__ float S[6 * kNP];
   float* A0 = S;
   float* B0 = S + kNP;
   float* C0 = S + 2 * kNP;
   float* D0 = S + 3 * kNP;
   float* B1 = S + 4 * kNP;
   float* C1 = S + 5 * kNP;
-  float* D1 = S + 6 * kNP;
+  float* D1 = D0;  // d is read only at its own quadruple by the step that rewrites it
   // the wave index is uniform: as a scalar, row folds and row pointers are
   // scalar code, not per-lane branches
   const int lane = threadIdx.x & (kWave - 1), wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
