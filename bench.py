@@ -284,6 +284,23 @@ def main():
             "fwd_frac_of_8TBps": round(alg_bytes(W, H, L) / (t97["fwd"] * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
             "inv_frac_of_8TBps": round(alg_bytes(W, H, L) / (t97["inv"] * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
             "roundtrip_max_abs_err": rt}
+        # one GPU's share of a 16384^2 image split into 8 horizontal strips:
+        # 2048 rows plus the one-quadruple (2-row) halo the fused level
+        # needs from each neighbour, level 1 forward
+        xs_ = [synth.image_device(16384, 2048 + 4, 7 + s_, device=dev) for s_ in range(2)]
+        cs_ = [torch.empty_like(x_) for x_ in xs_]
+        wsx = torch.empty(max(1, dwt.workspace_size(16384, 2052, 1)), dtype=torch.uint8, device=dev)
+
+        def strip(i=[0]):
+            i[0] ^= 1
+            dwt.fwd(xs_[i[0]], 1, out=cs_[i[0]], workspace=wsx)
+        for _ in range(3):
+            strip()
+        tsx = float(np.median(timer(strip, 20)))
+        detail["strip_share_16384x2052_L1"] = {
+            "ms": round(tsx, 4), "GBps_alg": round(2 * 4 * 16384 * 2052 / (tsx * 1e-3) / 1e9, 1),
+            "frac_of_8TBps": round(2 * 4 * 16384 * 2052 / (tsx * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)}
+        del xs_, cs_, wsx
         # copy ceiling: read + write of 1 GiB
         a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
         b = torch.empty_like(a)

@@ -15,8 +15,9 @@ import torch
 from . import _lib
 from ._lib import DWT2_EXT_SYMMETRIC, DWT2_F32, DWT2_I32_REV
 
-__all__ = ["fwd", "inv", "bwd", "fwd_batched", "DWT2Function", "workspace_size", "level_sizes", "set_tiling", "set_path",
-           "DWT2_F32", "DWT2_I32_REV"]
+__all__ = ["fwd", "inv", "bwd", "fwd_batched", "inv_batched", "bwd_batched", "DWT2Function", "workspace_size",
+           "batched_workspace_size", "level_sizes", "set_tiling", "set_path", "set_probe", "fwd_separable",
+           "separable_workspace_size", "fwd_lds", "fwd_cdf97", "inv_cdf97", "DWT2_F32", "DWT2_I32_REV"]
 
 
 def level_sizes(w: int, h: int, levels: int):

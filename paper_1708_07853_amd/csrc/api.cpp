@@ -97,9 +97,17 @@ static int device_cus() {
 // filling every resident wave slot: longer walks re-read fewer halo rows at
 // segment starts, and power-of-two heights avoided slow address patterns
 // that other heights hit (8192^2 level 1: 91 us at 64 rows, 105-117 us at
-// 24 or 48).  Below ~1024^2 a level costs the launch latency whatever the
-// tiling.  The persistent job passes its resident capacity as `slots_hint`
-// and keeps one round of items for it, each a whole number of chunk pairs.
+// 24 or 48).  Among the power-of-two heights that give at least that many
+// waves, the choice is the one whose busiest compute unit walks the fewest
+// rows: ceil(waves / CUs) items of height + 1 rows (the +1 is the halo row
+// an item re-reads); ties go to the longer walk.  Rounding a height up
+// instead can leave most CUs with half their waves, and a wave count just
+// above a multiple of the CU count gives some CUs one wave more than the
+// rest (8192 x 4100, level 1: 53 us at 16 rows, 61 us at 32 with 2080
+// waves, 69 us at 64).  Below ~1024^2 a level costs the launch latency
+// whatever the tiling.  The persistent job passes its resident capacity as
+// `slots_hint` and keeps one round of items for it, each a whole number of
+// chunk pairs.
 static std::atomic<int> g_forced_seg{-1}, g_forced_ch{-1}, g_persistent{-1};
 constexpr int kLevelWavesPerCU = 8;
 
@@ -122,10 +130,21 @@ Tiling choose_tiling(int ns_h, int64_t strips_times_batch, int64_t slots_hint) {
     if (forced_ch <= 0 && seg < 2 * t.ch) t.ch = 1;
     seg = (seg + 2 * t.ch - 1) / (2 * t.ch) * (2 * t.ch);
   } else {
-    const int64_t waves = (int64_t)kLevelWavesPerCU * device_cus();
-    const int64_t per_strip = waves / strips_times_batch > 1 ? waves / strips_times_batch : 1;
-    seg = pow2_ceil((int)((ns_h + per_strip - 1) / per_strip));
-    if (seg < 2) seg = 2;
+    const int64_t cus = device_cus();
+    const int64_t min_waves = (int64_t)kLevelWavesPerCU * cus;
+    const int top = pow2_ceil(ns_h > 2 ? ns_h : 2);
+    seg = 0;
+    int64_t best = 0;
+    for (int s = 2; s <= top; s <<= 1) {
+      const int64_t waves = strips_times_batch * ((ns_h + s - 1) / s);
+      if (waves < min_waves) continue;
+      const int64_t cost = (waves + cus - 1) / cus * (s + 1);
+      if (seg == 0 || cost < best || (cost == best && s > seg)) {
+        seg = s;
+        best = cost;
+      }
+    }
+    if (seg == 0) seg = 2;  // no height reaches the wave target: the most waves
     if (forced_ch <= 0 && seg < 2 * t.ch) t.ch = 1;
   }
   t.seg = forced_seg > 0 ? forced_seg : seg;
