@@ -28,7 +28,8 @@ autograd forward/backward, and a device-to-device copy ceiling.
 GPU: the forward's time against the image edge (512 .. 16384, 6 levels) for
 the product path, the LDS-tiled non-separable (two barrier steps), adapted
 (two, fewer operations) and separable (four) kernels and the separable-pass
-baseline; and the level-1
+baseline, and the CDF 9/7 kernels (four steps) against their separable
+counterpart (eight); and the level-1
 time of 8192^2 against the work-item shape (segment height x prefetch chunk),
 the counterpart of the paper's tile-size experiment.
 
@@ -269,7 +270,8 @@ def main():
         # CDF 9/7 (float32), the same image and levels: forward and inverse
         t97 = {}
         for name, f in (("fwd", lambda s_: dwt.fwd_cdf97(s_["x"], L, out=s_["c"], workspace=ws)),
-                        ("inv", lambda s_: dwt.inv_cdf97(s_["c"], L, out=s_["r"], workspace=ws))):
+                        ("inv", lambda s_: dwt.inv_cdf97(s_["c"], L, out=s_["r"], workspace=ws)),
+                        ("fwd_sep", lambda s_: dwt.fwd_cdf97_separable(s_["x"], L, out=s_["r"], workspace=ws))):
             def g(f=f):
                 k[0] ^= 1
                 f(sets[k[0]])
@@ -279,6 +281,8 @@ def main():
         rt = float((dwt.inv_cdf97(dwt.fwd_cdf97(sets[0]["x"], L), L) - sets[0]["x"]).abs().max())
         detail["cdf97_8192_L6"] = {
             "fwd_ms": round(t97["fwd"], 4), "inv_ms": round(t97["inv"], 4),
+            "fwd_separable_8_steps_ms": round(t97["fwd_sep"], 4),
+            "speedup_of_4_steps_over_8": round(t97["fwd_sep"] / t97["fwd"], 3),
             "fwd_Gpx_s": round(npx / (t97["fwd"] * 1e-3) / 1e9, 1),
             "inv_Gpx_s": round(npx / (t97["inv"] * 1e-3) / 1e9, 1),
             "fwd_frac_of_8TBps": round(alg_bytes(W, H, L) / (t97["fwd"] * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
@@ -436,6 +440,8 @@ def sweep(torch, dwt, synth, dev, timer, reps=20):
             "lds_separable": lambda s: dwt.fwd_lds(xs[s], L, "separable", out=outs[s], workspace=ws),
             "lds_adapted": lambda s: dwt.fwd_lds(xs[s], L, "adapted", out=outs[s], workspace=ws),
             "separable_passes": lambda s: dwt.fwd_separable(xs[s], L, out=outs[s], workspace=ws),
+            "cdf97_nonseparable": lambda s: dwt.fwd_cdf97(xs[s], L, out=outs[s], workspace=ws),
+            "cdf97_separable": lambda s: dwt.fwd_cdf97_separable(xs[s], L, out=outs[s], workspace=ws),
         }
         for name, f in variants.items():
             ms = med(f)

@@ -196,6 +196,21 @@ int dwt2_fwd_cdf97(const void* src, int64_t src_stride, int64_t src_batch_stride
                    int32_t width, int32_t height, int32_t batch, int32_t levels,
                    int32_t mode, int32_t boundary, void* workspace,
                    size_t workspace_bytes, void* stream);
+/* Baseline for comparison, not the product path: the same CDF 9/7 forward
+ * with the separable lifting of §2, eq. (3), applied to each pair in turn:
+ * horizontal predict, vertical predict, horizontal update, vertical update,
+ * that is eight steps per level instead of the non-separable scheme's four.
+ * It uses the same tiles and workgroups as dwt2_fwd_cdf97, lifting each
+ * tile in place in LDS with a barrier between steps, so the two differ in
+ * their step count.  Arguments, layout, ownership and errors are those of
+ * dwt2_fwd_cdf97; results agree with it up to rounding. */
+int dwt2_fwd_cdf97_separable(const void* src, int64_t src_stride,
+                             int64_t src_batch_stride, void* dst,
+                             int64_t dst_stride, int64_t dst_batch_stride,
+                             int32_t width, int32_t height, int32_t batch,
+                             int32_t levels, int32_t mode, int32_t boundary,
+                             void* workspace, size_t workspace_bytes,
+                             void* stream);
 /* Inverse of dwt2_fwd_cdf97: src = Mallat-packed 9/7 coefficients, dst =
  * image. */
 int dwt2_inv_cdf97(const void* src, int64_t src_stride, int64_t src_batch_stride,

@@ -26,7 +26,7 @@ EXPORTS = [
     "dwt2_batched_workspace_size", "dwt2_fwd_batched", "dwt2_inv_batched", "dwt2_bwd_batched",
     "dwt2_status_string", "dwt2_last_error", "dwt2_clear_plan_cache", "dwt2_set_tiling", "dwt2_set_path",
     "dwt2_set_probe", "dwt2_separable_workspace_size", "dwt2_fwd_separable", "dwt2_fwd_lds",
-    "dwt2_fwd_cdf97", "dwt2_inv_cdf97",
+    "dwt2_fwd_cdf97", "dwt2_inv_cdf97", "dwt2_fwd_cdf97_separable",
 ]
 
 
@@ -67,7 +67,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dwt2_workspace_size.restype = sz
     lib.dwt2_separable_workspace_size.argtypes = [i32, i32, i32, i32, i32]
     lib.dwt2_separable_workspace_size.restype = sz
-    for name in ("dwt2_fwd", "dwt2_inv", "dwt2_bwd", "dwt2_fwd_separable", "dwt2_fwd_cdf97", "dwt2_inv_cdf97"):
+    for name in ("dwt2_fwd", "dwt2_inv", "dwt2_bwd", "dwt2_fwd_separable", "dwt2_fwd_cdf97", "dwt2_inv_cdf97",
+                 "dwt2_fwd_cdf97_separable"):
         fn = getattr(lib, name)
         fn.argtypes = [vp, i64, i64, vp, i64, i64, i32, i32, i32, i32, i32, i32, vp, sz, vp]
         fn.restype = ctypes.c_int

@@ -17,7 +17,8 @@ from ._lib import DWT2_EXT_SYMMETRIC, DWT2_F32, DWT2_I32_REV
 
 __all__ = ["fwd", "inv", "bwd", "fwd_batched", "inv_batched", "bwd_batched", "DWT2Function", "workspace_size",
            "batched_workspace_size", "level_sizes", "set_tiling", "set_path", "set_probe", "fwd_separable",
-           "separable_workspace_size", "fwd_lds", "fwd_cdf97", "inv_cdf97", "DWT2_F32", "DWT2_I32_REV"]
+           "separable_workspace_size", "fwd_lds", "fwd_cdf97", "inv_cdf97", "fwd_cdf97_separable",
+           "DWT2_F32", "DWT2_I32_REV"]
 
 
 def level_sizes(w: int, h: int, levels: int):
@@ -117,6 +118,13 @@ def fwd_cdf97(x: torch.Tensor, levels: int, out=None, workspace=None) -> torch.T
     non-separable scheme, one spatial predict and update per lifting pair
     (see dwt2_fwd_cdf97); Mallat-packed result of the same shape."""
     return _run("dwt2_fwd_cdf97", x, levels, None, out, workspace)
+
+
+def fwd_cdf97_separable(x: torch.Tensor, levels: int, out=None, workspace=None) -> torch.Tensor:
+    """The same CDF 9/7 forward by the separable comparison kernel (eight
+    barrier-separated steps per level instead of four; see
+    dwt2_fwd_cdf97_separable).  For comparisons, not for production use."""
+    return _run("dwt2_fwd_cdf97_separable", x, levels, None, out, workspace)
 
 
 def inv_cdf97(c: torch.Tensor, levels: int, out=None, workspace=None) -> torch.Tensor:

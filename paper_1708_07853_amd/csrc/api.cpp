@@ -459,7 +459,7 @@ static int run_lds(int scheme, const Call& c, const Geo& g, void* stream) {
 }
 
 // CDF 9/7: one launch per level, LL through the plain workspace's buffers.
-static int run_cdf97(int dir, const Call& c, const Geo& g, void* stream) {
+static int run_cdf97(int dir, bool separable, const Call& c, const Geo& g, void* stream) {
   const int64_t ws_bs = (int64_t)(ws_per_image(g) / 4);
   for (int s = 0; s < g.L; ++s) {
     const int k = dir == kFwd ? s + 1 : g.L - s;  // the inverse runs coarsest first
@@ -515,7 +515,7 @@ static int run_cdf97(int dir, const Call& c, const Geo& g, void* stream) {
         a.out_bstride = ws_bs;
       }
     }
-    const int err = launch_cdf97_level(dir, a, stream);
+    const int err = launch_cdf97_level(dir, separable, a, stream);
     if (err != hipSuccess)
       return fail(DWT2_ERR_HIP, "CDF 9/7 level %d launch failed: %s", k, hipGetErrorString((hipError_t)err));
   }
@@ -525,7 +525,7 @@ static int run_cdf97(int dir, const Call& c, const Geo& g, void* stream) {
 // Which kernels compute a call: the product path, one of the comparison
 // baselines (separable passes, LDS-tiled separable, LDS-tiled non-separable),
 // or the CDF 9/7 kernels.
-enum { kProduct = 0, kSepPasses = 1, kLdsSep = 2, kLdsNonSep = 3, kCdf97 = 4, kLdsAdapted = 5 };
+enum { kProduct = 0, kSepPasses = 1, kLdsSep = 2, kLdsNonSep = 3, kCdf97 = 4, kLdsAdapted = 5, kCdf97Sep = 6 };
 
 static int transform(int dir, const void* src, int64_t src_stride, int64_t src_bs, void* dst, int64_t dst_stride,
                      int64_t dst_bs, int32_t width, int32_t height, int32_t batch, int32_t levels, int32_t mode,
@@ -548,7 +548,8 @@ static int transform(int dir, const void* src, int64_t src_stride, int64_t src_b
     return fail(DWT2_ERR_ARG, "batch stride below stride * height");
   if (mode != DWT2_F32 && mode != DWT2_I32_REV) return fail(DWT2_ERR_MODE, "unknown mode %d", mode);
   if (dir == kBwd && mode != DWT2_F32) return fail(DWT2_ERR_MODE, "the adjoint exists for DWT2_F32 only");
-  if (variant == kCdf97 && mode != DWT2_F32) return fail(DWT2_ERR_MODE, "the CDF 9/7 transform exists for DWT2_F32 only");
+  if ((variant == kCdf97 || variant == kCdf97Sep) && mode != DWT2_F32)
+    return fail(DWT2_ERR_MODE, "the CDF 9/7 transform exists for DWT2_F32 only");
   if (variant == kLdsAdapted && mode != DWT2_F32)
     return fail(DWT2_ERR_MODE, "the adapted scheme exists for DWT2_F32 only");
   if (src == dst) return fail(DWT2_ERR_ALIAS, "src and dst are the same buffer; the transform is out of place");
@@ -562,7 +563,7 @@ static int transform(int dir, const void* src, int64_t src_stride, int64_t src_b
   if (variant == kLdsSep) return run_lds(DWT2_SCHEME_SEPARABLE, c, g, stream);
   if (variant == kLdsNonSep) return run_lds(DWT2_SCHEME_NONSEPARABLE, c, g, stream);
   if (variant == kLdsAdapted) return run_lds(DWT2_SCHEME_ADAPTED, c, g, stream);
-  if (variant == kCdf97) return run_cdf97(dir, c, g, stream);
+  if (variant == kCdf97 || variant == kCdf97Sep) return run_cdf97(dir, variant == kCdf97Sep, c, g, stream);
   if (g_persistent.load() < 0) g_persistent.store(env_int("DWT2_PERSISTENT") == 1 ? 1 : 0);
   const int path = g_persistent.load();
   if (path == 1 && g.L <= kInlineDescs) return run_job(dir, c, g, stream);
@@ -602,6 +603,14 @@ int dwt2_fwd_cdf97(const void* src, int64_t src_stride, int64_t src_batch_stride
                    int32_t boundary, void* workspace, size_t workspace_bytes, void* stream) {
   return transform(kFwd, src, src_stride, src_batch_stride, dst, dst_stride, dst_batch_stride, width, height, batch,
                    levels, mode, boundary, workspace, workspace_bytes, stream, kCdf97);
+}
+
+int dwt2_fwd_cdf97_separable(const void* src, int64_t src_stride, int64_t src_batch_stride, void* dst,
+                             int64_t dst_stride, int64_t dst_batch_stride, int32_t width, int32_t height,
+                             int32_t batch, int32_t levels, int32_t mode, int32_t boundary, void* workspace,
+                             size_t workspace_bytes, void* stream) {
+  return transform(kFwd, src, src_stride, src_batch_stride, dst, dst_stride, dst_batch_stride, width, height, batch,
+                   levels, mode, boundary, workspace, workspace_bytes, stream, kCdf97Sep);
 }
 
 int dwt2_inv_cdf97(const void* src, int64_t src_stride, int64_t src_batch_stride, void* dst, int64_t dst_stride,

@@ -318,6 +318,91 @@ __global__ __launch_bounds__(kBlk, 5) void inv97(Level97 a, int tiles_x) {
   }
 }
 
+// Separable comparison kernel on the same tiles: per level and per pair,
+// horizontal predict, vertical predict, horizontal update, vertical update
+// (eq. (3)), eight steps with a workgroup barrier between steps, then the
+// scaling.  The 136 x 40-pixel tile (a 4-pixel halo around the 128 x 32
+// output pixels) is lifted in place: a step changes one parity class and
+// reads only the other.  Each step reads one pixel to each side on its
+// axis, so the valid region shrinks by one pixel per step and four steps per
+// axis use up the halo exactly; steps run on every position whose
+// neighbours lie in the tile.
+constexpr int kSX = 2 * kNX, kSY = 2 * kNY;  // 136 x 40
+
+__global__ __launch_bounds__(kBlk) void fwd97_sep(Level97 a, int tiles_x) {
+  __shared__ float X[kSX * kSY];
+  const int lane = threadIdx.x & (kWave - 1), wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int tile = tile_remap(blockIdx.x, gridDim.x);
+  const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
+  const int W = a.W, H = a.H;
+  const int ns_w = (W + 1) >> 1, ns_h = (H + 1) >> 1, nd_w = W >> 1, nd_h = H >> 1;
+  const int px0 = 2 * (tx * kQX - 2), py0 = 2 * (ty * kQY - 2);
+  const int gc0 = fold97(px0 + lane, W), gc1 = fold97(px0 + kWave + lane, W);
+  const int gc2 = fold97(px0 + 2 * kWave + (lane & 7), W);
+  constexpr int kRowsPerWave = kSY / kWv;
+  const int gqx = tx * kQX + lane;
+  constexpr float kCoef[4] = {kAlpha, kBeta, kGamma, kDelta};
+  for (int img = blockIdx.y; img < a.batch; img += gridDim.y) {
+    const float* src = static_cast<const float*>(a.in) + img * a.in_bstride;
+    float* ll = static_cast<float*>(a.ll) + img * a.ll_bstride;
+    float* band = static_cast<float*>(a.out) + img * a.out_bstride;
+    {
+      float v0[kRowsPerWave], v1[kRowsPerWave], v2[kRowsPerWave];
+#pragma unroll
+      for (int k = 0; k < kRowsPerWave; ++k) {
+        const float* row = src + (int64_t)fold97(py0 + wv + k * kWv, H) * a.in_stride;
+        v0[k] = row[gc0];
+        v1[k] = row[gc1];
+        v2[k] = row[gc2];
+      }
+#pragma unroll
+      for (int k = 0; k < kRowsPerWave; ++k) {
+        float* x = X + (wv + k * kWv) * kSX;
+        x[lane] = v0[k];
+        x[kWave + lane] = v1[k];
+        if (lane < 8) x[2 * kWave + lane] = v2[k];
+      }
+    }
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      const float cf = kCoef[st];
+      const int par = (st & 1) ? 0 : 1;  // predicts change odd samples, updates even ones
+      __syncthreads();
+      // horizontal: columns of parity `par` in [1, kSX - 1), every row
+      for (int e = threadIdx.x; e < kSY * (kSX / 2 - 1); e += kBlk) {
+        const int r = e / (kSX / 2 - 1), k = e - r * (kSX / 2 - 1);
+        float* x = X + r * kSX + 2 * k + par + (par ? 0 : 2);
+        x[0] = __fmaf_rn(cf, x[-1] + x[1], x[0]);
+      }
+      __syncthreads();
+      // vertical: rows of parity `par` in [1, kSY - 1), every column
+      for (int e = threadIdx.x; e < (kSY / 2 - 1) * kSX; e += kBlk) {
+        const int j = e / kSX, c = e - j * kSX;
+        float* x = X + (2 * j + par + (par ? 0 : 2)) * kSX + c;
+        x[0] = __fmaf_rn(cf, x[-kSX] + x[kSX], x[0]);
+      }
+    }
+    __syncthreads();
+    // scaling and store of the tile's own quadruples (local pixels [4, 132) x [4, 36))
+#pragma unroll
+    for (int k = 0; k < kQY / kWv; ++k) {
+      const int i = wv + k * kWv;
+      const float* x = X + (2 * i + 4) * kSX + 2 * lane + 4;
+      const float vll = x[0] * kLLScale, vhl = x[1], vlh = x[kSX], vhh = x[kSX + 1] * kHHScale;
+      const int gqy = ty * kQY + i;
+      if (gqx < ns_w && gqy < ns_h) {
+        ll[(int64_t)gqy * a.ll_stride + gqx] = vll;
+        if (gqx < nd_w) band[(int64_t)gqy * a.out_stride + ns_w + gqx] = vhl;
+        if (gqy < nd_h) {
+          band[(int64_t)(ns_h + gqy) * a.out_stride + gqx] = vlh;
+          if (gqx < nd_w) band[(int64_t)(ns_h + gqy) * a.out_stride + ns_w + gqx] = vhh;
+        }
+      }
+    }
+    if (img + (int)gridDim.y < a.batch) __syncthreads();
+  }
+}
+
 }  // namespace
 
 int cdf97_tiles(int W, int H, int& tiles_x, int& tiles_y) {
@@ -326,13 +411,15 @@ int cdf97_tiles(int W, int H, int& tiles_x, int& tiles_y) {
   return (int64_t)tiles_x * tiles_y <= 0x7fffffff;
 }
 
-int launch_cdf97_level(int dir, const Level97& a, void* stream) {
+int launch_cdf97_level(int dir, bool separable, const Level97& a, void* stream) {
   int tx, ty;
   if (!cdf97_tiles(a.W, a.H, tx, ty)) return hipErrorInvalidValue;
   const dim3 grid((unsigned)(tx * ty), (unsigned)(a.batch < 65535 ? a.batch : 65535));
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (dir == kFwd) hipLaunchKernelGGL(fwd97, grid, dim3(kBlk), 0, s, a, tx);
-  else hipLaunchKernelGGL(inv97, grid, dim3(kBlk), 0, s, a, tx);
+  if (dir == kFwd && separable) hipLaunchKernelGGL(fwd97_sep, grid, dim3(kBlk), 0, s, a, tx);
+  else if (dir == kFwd) hipLaunchKernelGGL(fwd97, grid, dim3(kBlk), 0, s, a, tx);
+  else if (!separable) hipLaunchKernelGGL(inv97, grid, dim3(kBlk), 0, s, a, tx);
+  else return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

@@ -165,7 +165,8 @@ struct Level97 {
   int32_t W, H, batch, pad_;
 };
 int cdf97_tiles(int W, int H, int& tiles_x, int& tiles_y);
-int launch_cdf97_level(int dir, const Level97& a, void* stream);
+// separable: the comparison kernel with the eight separable steps (forward only)
+int launch_cdf97_level(int dir, bool separable, const Level97& a, void* stream);
 
 // Kernel launchers (kernels.hip).  Return hipError_t as int.
 int launch_level(int dir, int mode, int chunk, const LevelLaunch& a, void* stream);

@@ -96,7 +96,7 @@ BAD = [
 
 
 @pytest.mark.parametrize("fn", ["dwt2_fwd", "dwt2_inv", "dwt2_bwd", "dwt2_fwd_separable", "dwt2_fwd_cdf97",
-                                "dwt2_inv_cdf97"])
+                                "dwt2_inv_cdf97", "dwt2_fwd_cdf97_separable"])
 @pytest.mark.parametrize("kw,code", BAD, ids=[str(b[0]) for b in BAD])
 def test_validation_errors(lib, fn, kw, code):
     assert call(lib, fn, **kw) == code
@@ -130,7 +130,7 @@ def test_lds_rejects_unknown_scheme(lib):
     assert call_lds(lib, 1, wsb=need - 1) == -4
 
 
-@pytest.mark.parametrize("fn", ["dwt2_fwd_cdf97", "dwt2_inv_cdf97"])
+@pytest.mark.parametrize("fn", ["dwt2_fwd_cdf97", "dwt2_inv_cdf97", "dwt2_fwd_cdf97_separable"])
 def test_cdf97_rejects_integer_mode(lib, fn):
     assert call(lib, fn, mode=1) == -3
     assert "9/7" in lib.dwt2_last_error().decode()

@@ -80,6 +80,24 @@ def test_cdf97_inverse_matches_oracle_and_round_trips():
             assert float((rt - xg).abs().max()) <= TOL97, (h, w, levels)
 
 
+def test_cdf97_separable_comparison_kernel():
+    """The separable comparison kernel (eight barrier-separated steps per
+    level) computes the same transform: within the bound of the oracle and of
+    the non-separable kernels, on the size sweep, a batch and 8192^2."""
+    d = D()
+    for idx, (h, w) in enumerate(SHAPES):
+        x = _img(h, w, 9900 + idx)
+        for levels in sorted({1, max_levels(w, h)}):
+            xg = to_gpu(x)
+            got = d.fwd_cdf97_separable(xg, levels)
+            assert maxdiff(got.cpu().numpy(), dwt97.fwd(x, levels)) <= TOL97, (h, w, levels)
+            assert float((got - d.fwd_cdf97(xg, levels)).abs().max()) <= TOL97, (h, w, levels)
+    xs = torch.stack([to_gpu(_img(250, 333, 9950 + b)) for b in range(2)])
+    assert float((d.fwd_cdf97_separable(xs, 3) - d.fwd_cdf97(xs, 3)).abs().max()) <= TOL97
+    x = synth.image_device(8192, 8192, 2)
+    assert float((d.fwd_cdf97_separable(x, 6) - d.fwd_cdf97(x, 6)).abs().max()) <= TOL97
+
+
 def test_cdf97_batch_strides():
     d = D()
     xs = torch.stack([to_gpu(_img(250, 333, 9800 + b)) for b in range(3)])
