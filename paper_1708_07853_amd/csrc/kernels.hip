@@ -290,28 +290,45 @@ __device__ __forceinline__ AxisW axis_weights(int m, int n) {
   return w;
 }
 
+// Weighted pair sum wa a + wb b.  UNIT: every weight is 1 (a quadruple away
+// from the borders); the plain sum then rounds exactly as the weighted one
+// (products by 1 are exact and nothing is contracted), so both forms give
+// the same bits.
+template <bool UNIT>
+__device__ __forceinline__ float wsum(float wa, float a, float wb, float b) {
+  if constexpr (UNIT) return a + b;
+  else return wa * a + wb * b;
+}
+__device__ __forceinline__ bool unit_weights(const AxisW& w) {
+  return w.alpha == 1.f && w.beta == 1.f && w.gamma == 1.f && w.delta == 1.f;
+}
+
 // Transposed spatial update (M_U^T, predict-shaped).
+template <bool UNIT = false>
 __device__ __forceinline__ void f32_adj_a(float ga, float gaR, float gaD, float gaDR, float gb, float gbD,
                                           float gc, float gcR, float gd, AxisW h, AxisW v, float& gb1, float& gc1,
                                           float& gd1) {
-  const float th = h.alpha * ga + h.beta * gaR;  // U^T_h ga (x4)
-  const float thD = h.alpha * gaD + h.beta * gaDR;
+  const float th = wsum<UNIT>(h.alpha, ga, h.beta, gaR);  // U^T_h ga (x4)
+  const float thD = wsum<UNIT>(h.alpha, gaD, h.beta, gaDR);
   gb1 = __fmaf_rn(0.25f, th, gb);
-  gc1 = __fmaf_rn(0.25f, v.alpha * ga + v.beta * gaD, gc);
-  gd1 = __fmaf_rn(0.0625f, v.alpha * th + v.beta * thD,
-                  __fmaf_rn(0.25f, h.alpha * gc + h.beta * gcR, __fmaf_rn(0.25f, v.alpha * gb + v.beta * gbD, gd)));
+  gc1 = __fmaf_rn(0.25f, wsum<UNIT>(v.alpha, ga, v.beta, gaD), gc);
+  gd1 = __fmaf_rn(0.0625f, wsum<UNIT>(v.alpha, th, v.beta, thD),
+                  __fmaf_rn(0.25f, wsum<UNIT>(h.alpha, gc, h.beta, gcR),
+                            __fmaf_rn(0.25f, wsum<UNIT>(v.alpha, gb, v.beta, gbD), gd)));
 }
 
 // Transposed spatial predict (M_P^T, update-shaped).
+template <bool UNIT = false>
 __device__ __forceinline__ void f32_adj_b(float ga, float gb1L, float gb1, float gc1U, float gc1, float gd1UL,
                                           float gd1U, float gd1L, float gd1, AxisW h, AxisW v, float& ga2,
                                           float& gb2, float& gc2) {
-  gb2 = __fmaf_rn(-0.5f, v.gamma * gd1U + v.delta * gd1, gb1);
-  gc2 = __fmaf_rn(-0.5f, h.gamma * gd1L + h.delta * gd1, gc1);
-  const float tU = h.gamma * gd1UL + h.delta * gd1U;
-  const float t0 = h.gamma * gd1L + h.delta * gd1;
-  ga2 = __fmaf_rn(0.25f, v.gamma * tU + v.delta * t0,
-                  __fmaf_rn(-0.5f, v.gamma * gc1U + v.delta * gc1, __fmaf_rn(-0.5f, h.gamma * gb1L + h.delta * gb1, ga)));
+  gb2 = __fmaf_rn(-0.5f, wsum<UNIT>(v.gamma, gd1U, v.delta, gd1), gb1);
+  gc2 = __fmaf_rn(-0.5f, wsum<UNIT>(h.gamma, gd1L, h.delta, gd1), gc1);
+  const float tU = wsum<UNIT>(h.gamma, gd1UL, h.delta, gd1U);
+  const float t0 = wsum<UNIT>(h.gamma, gd1L, h.delta, gd1);
+  ga2 = __fmaf_rn(0.25f, wsum<UNIT>(v.gamma, tU, v.delta, t0),
+                  __fmaf_rn(-0.5f, wsum<UNIT>(v.gamma, gc1U, v.delta, gc1),
+                            __fmaf_rn(-0.5f, wsum<UNIT>(h.gamma, gb1L, h.delta, gb1), ga)));
 }
 
 // ---------------------------------------------------------------------------
@@ -900,6 +917,9 @@ __device__ void bwd_f32(const LevelDesc& d, const float* __restrict__ ll, const 
   const PxStore<float, EDGE, CO> S{px, d.pix_stride, it.W, it.H, 2 * it.qL, min(2 * it.I1, it.H)};
   const bool first = it.first, last = it.last;
   const AxisW hL = axis_weights(it.qL, it.W), hR = axis_weights(it.qL + 1, it.W), hH = axis_weights(it.qL - 1, it.W);
+  // whole item away from the left and right borders: the horizontal weights
+  // are all 1 (then rows away from the top and bottom take the plain sums)
+  const bool unit_h = __all(unit_weights(hL) && unit_weights(hR) && unit_weights(hH));
   using Buf = QBuf<float, CH>;
   auto load_chunk = [&](Buf& b, int i0) {
 #pragma unroll
@@ -940,10 +960,16 @@ __device__ void bwd_f32(const LevelDesc& d, const float* __restrict__ ll, const 
     const AxisW v = axis_weights(i, it.H);
     const float gaN = nxt(last, ge0, ga_L), gaDN = nxt(last, ne0, nL);
     const float gcN = nxt(last, go0, gc_L);
-    f32_adj_a(ga_L, ga_R, nL, nR, gb_L, nbL, gc_L, gc_R, gd_L, hL, v, gb1L, gc1L, gd1L);
-    f32_adj_a(ga_R, gaN, nR, gaDN, gb_R, nbR, gc_R, gcN, gd_R, hR, v, gb1R, gc1R, gd1R);
     float gc1H;
-    f32_adj_a(ge0, ga_L, ne0, nL, ge1, ne1, go0, gc_L, go1, hH, v, gb1H, gc1H, gd1H);
+    if (unit_h && unit_weights(v)) {
+      f32_adj_a<true>(ga_L, ga_R, nL, nR, gb_L, nbL, gc_L, gc_R, gd_L, hL, v, gb1L, gc1L, gd1L);
+      f32_adj_a<true>(ga_R, gaN, nR, gaDN, gb_R, nbR, gc_R, gcN, gd_R, hR, v, gb1R, gc1R, gd1R);
+      f32_adj_a<true>(ge0, ga_L, ne0, nL, ge1, ne1, go0, gc_L, go1, hH, v, gb1H, gc1H, gd1H);
+    } else {
+      f32_adj_a(ga_L, ga_R, nL, nR, gb_L, nbL, gc_L, gc_R, gd_L, hL, v, gb1L, gc1L, gd1L);
+      f32_adj_a(ga_R, gaN, nR, gaDN, gb_R, nbR, gc_R, gcN, gd_R, hR, v, gb1R, gc1R, gd1R);
+      f32_adj_a(ge0, ga_L, ne0, nL, ge1, ne1, go0, gc_L, go1, hH, v, gb1H, gc1H, gd1H);
+    }
   };
   float gc1U_L, gc1U_R, gd1U_L, gd1U_R, gd1UL_L;
   {
@@ -967,8 +993,13 @@ __device__ void bwd_f32(const LevelDesc& d, const float* __restrict__ ll, const 
     const float gd1P = prv(first, gd1H, gd1_R);
     const AxisW v = axis_weights(i, it.H);
     V4<float> e, o;
-    f32_adj_b(ga_L, gb1P, gb1_L, gc1U_L, gc1_L, gd1UL_L, gd1U_L, gd1P, gd1_L, hL, v, e.x, e.y, o.x);
-    f32_adj_b(ga_R, gb1_L, gb1_R, gc1U_R, gc1_R, gd1U_L, gd1U_R, gd1_L, gd1_R, hR, v, e.z, e.w, o.z);
+    if (unit_h && unit_weights(v)) {
+      f32_adj_b<true>(ga_L, gb1P, gb1_L, gc1U_L, gc1_L, gd1UL_L, gd1U_L, gd1P, gd1_L, hL, v, e.x, e.y, o.x);
+      f32_adj_b<true>(ga_R, gb1_L, gb1_R, gc1U_R, gc1_R, gd1U_L, gd1U_R, gd1_L, gd1_R, hR, v, e.z, e.w, o.z);
+    } else {
+      f32_adj_b(ga_L, gb1P, gb1_L, gc1U_L, gc1_L, gd1UL_L, gd1U_L, gd1P, gd1_L, hL, v, e.x, e.y, o.x);
+      f32_adj_b(ga_R, gb1_L, gb1_R, gc1U_R, gc1_R, gd1U_L, gd1U_R, gd1_L, gd1_R, hR, v, e.z, e.w, o.z);
+    }
     o.y = gd1_L;
     o.w = gd1_R;
     S.row(2 * i, e);
