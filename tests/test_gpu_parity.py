@@ -282,6 +282,28 @@ def test_results_do_not_depend_on_tiling_or_path(mode):
         d.set_path("levels")
 
 
+@pytest.mark.parametrize("mode", ["f32", "int"])
+def test_strip_share_shape_matches_oracle(mode):
+    """The shape the benchmark times as one GPU's share of a 16384^2 image
+    split eight ways (16384 x 2052, level 1), in the automatic tiling it is
+    timed with: integers bit-exact and floats within the tolerance of the
+    oracle, and bit-identical to a forced tiling."""
+    d = D()
+    dt = np.float32 if mode == "f32" else np.int32
+    x = _img(2052, 16384, 4242)
+    xg = to_gpu(x.astype(dt))
+    got = d.fwd(xg, 1)
+    if mode == "int":
+        assert np.array_equal(got.cpu().numpy(), oracle.fwd(x, 1, INT))
+    else:
+        assert maxdiff(got.cpu().numpy(), oracle.fwd(x, 1)) <= TOL
+    try:
+        d.set_tiling(64, 2)
+        assert torch.equal(d.fwd(xg, 1), got)
+    finally:
+        d.set_tiling(0, 0)
+
+
 def test_batched_equals_plain_on_ragged_set():
     """A ragged set like the benchmark's (uneven, odd sizes), smaller: the
     one-launch batched path reproduces per-image calls bit for bit, on the
