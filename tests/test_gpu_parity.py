@@ -304,6 +304,43 @@ def test_strip_share_shape_matches_oracle(mode):
         d.set_tiling(0, 0)
 
 
+def test_benchmark_ragged_set_full_size():
+    """The benchmark's ragged set itself (256 images, widths and heights in
+    64..4096, 3 levels, float and integer): the batched forward equals the
+    per-image calls bit for bit, the batched inverse and adjoint too (float),
+    the integer round trip is exact, and the smallest images and every
+    odd-sized one up to 2^20 pixels match the oracle."""
+    d = D()
+    sizes = synth.ragged_sizes(256, 4)
+    for dt in (torch.float32, torch.int32):
+        imgs = [synth.image_device(w, h, 4000 + i, dtype=dt) for i, (w, h) in enumerate(sizes)]
+        outs = d.fwd_batched(imgs, 3)
+        for im, o in zip(imgs, outs):
+            assert torch.equal(o, d.fwd(im, 3))
+        checked = 0
+        for (w, h), im, o in sorted(zip(sizes, imgs, outs), key=lambda t: t[0][0] * t[0][1]):
+            if checked < 4 or ((w * h) % 2 and w * h <= 1 << 20 and checked < 12):
+                x = im.cpu().numpy().astype(np.int64 if dt == torch.int32 else np.float64)
+                ref = oracle.fwd(x, 3, INT) if dt == torch.int32 else oracle.fwd(x, 3)
+                got = o.cpu().numpy()
+                if dt == torch.int32:
+                    assert np.array_equal(got, ref), (w, h)
+                else:
+                    assert maxdiff(got, ref) <= TOL, (w, h)
+                checked += 1
+        back = d.inv_batched(outs, 3)
+        if dt == torch.int32:
+            for im, r in zip(imgs, back):
+                assert torch.equal(im, r)
+        else:
+            for o, r in zip(outs, back):
+                assert torch.equal(r, d.inv(o, 3))
+            adj = d.bwd_batched(outs, 3)
+            for o, g in zip(outs, adj):
+                assert torch.equal(g, d.bwd(o, 3))
+        del imgs, outs, back
+
+
 def test_batched_equals_plain_on_ragged_set():
     """A ragged set like the benchmark's (uneven, odd sizes), smaller: the
     one-launch batched path reproduces per-image calls bit for bit, on the
