@@ -66,9 +66,11 @@ def alg_bytes(w, h, levels, elem=4):
 
 def kernel_sources_digest():
     h = hashlib.sha256()
-    for name in ("kernels.hip", "dwt2_internal.h"):
-        with open(os.path.join(ROOT, "paper_1708_07853_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
+    csrc = os.path.join(ROOT, "paper_1708_07853_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".h")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(f.read())
     return h.hexdigest()[:16]
 
 

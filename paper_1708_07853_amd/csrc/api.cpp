@@ -311,16 +311,15 @@ int run_levels(int dir, const Call& c, const Geo& g, void* stream, bool tail) {
   return DWT2_OK;
 }
 
-int64_t job_slots(int dir, int mode, int ch) {
+int64_t job_slots(int dir, int mode) {
   static std::mutex mu;
-  static int cache[3][2][3] = {};
-  const int ci = ch >= 4 ? 2 : (ch >= 2 ? 1 : 0);
+  static int cache[3][2] = {};
   int blocks;
   {
     std::lock_guard<std::mutex> lock(mu);
-    int& c = cache[dir][mode][ci];
+    int& c = cache[dir][mode];
     if (!c) {
-      c = job_blocks_per_cu(dir, mode, ch, false);
+      c = job_blocks_per_cu(dir, mode, false);
       if (c <= 0) c = 1;
     }
     blocks = c;
@@ -331,10 +330,7 @@ int64_t job_slots(int dir, int mode, int ch) {
 // All levels in one persistent launch (after a small kernel that clears the
 // synchronisation words).
 int run_job(int dir, const Call& c, const Geo& g, void* stream) {
-  if (g_forced_ch.load() < 0) g_forced_ch.store(env_int("DWT2_CH") > 0 ? env_int("DWT2_CH") : 0);
-  const int forced_ch = g_forced_ch.load();
-  const int ch = forced_ch > 0 ? (forced_ch >= 4 ? 4 : (forced_ch >= 2 ? 2 : 1)) : 2;
-  const int64_t blocks_per_cu = job_slots(dir, c.mode, ch);
+  const int64_t blocks_per_cu = job_slots(dir, c.mode);
   const int64_t slots = blocks_per_cu * kWavesPerBlock * device_cus();
   static JobArgs args;  // large; filled per call under the lock below
   static std::mutex mu;
@@ -368,7 +364,7 @@ int run_job(int dir, const Call& c, const Geo& g, void* stream) {
     const int64_t want = (items + kWavesPerBlock - 1) / kWavesPerBlock;
     const int64_t cap = blocks_per_cu * device_cus();
     const int blocks = (int)(want < cap ? want : cap);
-    err = launch_job(dir, c.mode, ch, args, blocks, stream);
+    err = launch_job(dir, c.mode, args, blocks, stream);
   }
   if (err != hipSuccess) return fail(DWT2_ERR_HIP, "persistent launch failed: %s", hipGetErrorString((hipError_t)err));
   return DWT2_OK;

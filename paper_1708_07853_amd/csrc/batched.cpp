@@ -272,14 +272,14 @@ hipError_t enqueue(const Plan& p, hipStream_t s) {
       a.item_desc = reinterpret_cast<const uint32_t*>(p.ws + p.lay.items);
       a.item_begin = p.step_begin[t];
       a.items = p.step_begin[t + 1] - p.step_begin[t];
-      const int err = launch_table(p.dir, p.mode, kBatchCh, a, s);
+      const int err = launch_table(p.dir, p.mode, a, s);
       if (err != hipSuccess) return (hipError_t)err;
     }
     return hipSuccess;
   }
   int err = launch_zero(reinterpret_cast<uint32_t*>(p.ws + p.lay.sync), kSyncCounters + (int64_t)kCounterStride * p.counters, s);
   if (err != hipSuccess) return (hipError_t)err;
-  return (hipError_t)launch_job(p.dir, p.mode, kBatchCh, job_args(p), p.blocks, s);
+  return (hipError_t)launch_job(p.dir, p.mode, job_args(p), p.blocks, s);
 }
 
 void write_staging(Plan& p, const dwt2_image_t* images) {
@@ -382,7 +382,7 @@ int build_plan(Plan& p, int dir, const dwt2_image_t* images, int n, int levels, 
   });
   int dev = 0, cus = 256;
   if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  int bpc = job_blocks_per_cu(dir, mode, kBatchCh, true);
+  int bpc = job_blocks_per_cu(dir, mode, true);
   p.blocks = (bpc > 0 ? bpc : 1) * (cus > 0 ? cus : 256);
   load_tune_cache();
   int st = autotune(p, images, s, hash_key(key));

@@ -1,5 +1,6 @@
-// Internal types shared by the host API (api.cpp) and the HIP kernels
-// (kernels.hip).  Not part of the public interface.
+// Internal types shared by the host API (api.cpp, batched.cpp) and the HIP
+// kernels (strip_*.hip, tail_kernels.hip, lds_kernels.hip, separable.hip,
+// cdf97.hip).  Not part of the public interface.
 #pragma once
 
 #include <stddef.h>
@@ -168,11 +169,39 @@ int cdf97_tiles(int W, int H, int& tiles_x, int& tiles_y);
 // separable: the comparison kernel with the eight separable steps (forward only)
 int launch_cdf97_level(int dir, bool separable, const Level97& a, void* stream);
 
-// Kernel launchers (kernels.hip).  Return hipError_t as int.
-int launch_level(int dir, int mode, int chunk, const LevelLaunch& a, void* stream);
-int job_blocks_per_cu(int dir, int mode, int chunk, bool table);
-int launch_job(int dir, int mode, int chunk, const JobArgs& a, int blocks, void* stream);
+// Strip-kernel launchers, instantiated per direction (level kernels in
+// strip_fwd.hip, strip_inv.hip, strip_bwd.hip; job and table kernels in
+// job_fwd.hip, job_inv.hip, job_bwd.hip).  Return hipError_t as int.
+template <int DIR> int launch_level_dir(int mode, int chunk, const LevelLaunch& a, void* stream);
+template <int DIR> int launch_job_dir(int mode, const JobArgs& a, int blocks, void* stream);
+template <int DIR> int job_blocks_per_cu_dir(int mode, bool table);
+template <int DIR> int launch_table_dir(int mode, const TableArgs& a, void* stream);
+
+// One level of a plain call; `chunk`: prefetch chunk (1, 2 or 4 quadruple rows).
+inline int launch_level(int dir, int mode, int chunk, const LevelLaunch& a, void* stream) {
+  if (dir == kFwd) return launch_level_dir<kFwd>(mode, chunk, a, stream);
+  if (dir == kInv) return launch_level_dir<kInv>(mode, chunk, a, stream);
+  return launch_level_dir<kBwd>(mode, chunk, a, stream);
+}
+// Resident blocks per CU of the persistent job kernel (TABLE variant or not).
+inline int job_blocks_per_cu(int dir, int mode, bool table) {
+  if (dir == kFwd) return job_blocks_per_cu_dir<kFwd>(mode, table);
+  if (dir == kInv) return job_blocks_per_cu_dir<kInv>(mode, table);
+  return job_blocks_per_cu_dir<kBwd>(mode, table);
+}
+// The persistent job (cooperative launch of `blocks` blocks).
+inline int launch_job(int dir, int mode, const JobArgs& a, int blocks, void* stream) {
+  if (dir == kFwd) return launch_job_dir<kFwd>(mode, a, blocks, stream);
+  if (dir == kInv) return launch_job_dir<kInv>(mode, a, blocks, stream);
+  return launch_job_dir<kBwd>(mode, a, blocks, stream);
+}
+// One level-synchronous launch over a ragged batch's item range.
+inline int launch_table(int dir, int mode, const TableArgs& a, void* stream) {
+  if (dir == kFwd) return launch_table_dir<kFwd>(mode, a, stream);
+  if (dir == kInv) return launch_table_dir<kInv>(mode, a, stream);
+  return launch_table_dir<kBwd>(mode, a, stream);
+}
+// Clears n synchronisation words with a fill kernel (tail_kernels.hip).
 int launch_zero(uint32_t* p, int64_t n, void* stream);
-int launch_table(int dir, int mode, int chunk, const TableArgs& a, void* stream);
 
 }  // namespace dwt2

@@ -1,5 +1,7 @@
-// HIP kernels for gfx950: one level of the 2-D CDF 5/3 transform with the
-// non-separable lifting scheme (§3, eq. (5)) -- forward, inverse, adjoint.
+// Device code shared by the HIP kernels for gfx950: the per-quadruple
+// arithmetic of the 2-D CDF 5/3 transform with the non-separable lifting
+// scheme (§3, eq. (5)) -- forward, inverse, adjoint -- and the strip work
+// items that one level's kernels run.
 //
 // Mapping.  A wave owns a strip of 128 quadruple columns (lane l holds the
 // quadruples 2l and 2l+1, i.e. one 16-byte vector of each pixel row) and walks
@@ -25,6 +27,8 @@
 // interior formulas hold everywhere.  The adjoint transposes that extension
 // with explicit boundary weights instead (zero outside, doubled where the
 // mirror folds two taps onto one sample).
+#pragma once
+
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -1086,1000 +1090,5 @@ __device__ __forceinline__ void run_item(const LevelDesc& d, int coh, int64_t pi
   }
 }
 
-// One launch per level: one wave per work item.
-template <int DIR, typename T, int CH>
-__global__ __launch_bounds__(kBlock) void level_kernel(LevelLaunch a) {
-  const int lane = threadIdx.x & (kWave - 1);
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
-  const int64_t item = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + wave;
-  if (item >= a.items) return;
-  const int img = (int)(item / a.items_per_image);
-  const int rem = (int)(item - (int64_t)img * a.items_per_image);
-  const int seg = rem / a.d.nstrips;
-  const int strip = rem - seg * a.d.nstrips;
-  run_item<DIR, T, CH, false>(a.d, 0, img * a.pix_bstride, img * a.ll_bstride, img * a.band_bstride, strip, seg, lane);
-}
-
-// ---------------------------------------------------------------------------
-// Persistent job: all levels of a transform (of one or many images) in one
-// cooperative launch.  Work items are numbered step by step (a step is one
-// level of one image, or of a batch of images); wave w takes items w,
-// w + N, w + 2N, ... (N waves, all co-resident by the cooperative launch).
-// An item of step t first waits until the items of step t-1 that produced
-// the rows it reads have finished (per-segment completion counters), so
-// levels overlap instead of meeting at a grid-wide barrier.  An item waits
-// only for items with smaller numbers, each owned by a running wave that
-// reaches it after finishing its own smaller items, so the schedule cannot
-// deadlock; a wait that exceeds a fixed poll budget sets the error word and
-// gives up rather than hang.
-// ---------------------------------------------------------------------------
-// s_sleep(16) pauses about 16 * 64 clocks (~0.43 us at 2.4 GHz); a poll
-// backs off to at most kNapCap of them (~1.7 us), so a waiter sees a finished
-// producer within about that time, and gives up after kSpinLimit polls (~2 s).
-constexpr uint32_t kNapCap = 4;
-constexpr uint32_t kSpinLimit = 1u << 20;
-
-// Wait until rows [r_lo, r_hi] of the output of step p (image img) exist.
-// `pixels`: the rows are pixel rows of p's output (inverse / adjoint, two per
-// quadruple row); otherwise they are p's LL rows (forward, one per row).
-__device__ __forceinline__ void wait_rows(const JobDesc& p, uint32_t* sync, int img, int r_lo, int r_hi,
-                                          bool pixels) {
-  const int ns_h = (p.d.H + 1) >> 1;
-  int q_lo = pixels ? (r_lo >> 1) : r_lo, q_hi = pixels ? (r_hi >> 1) : r_hi;
-  q_lo = q_lo < 0 ? 0 : q_lo;
-  q_hi = q_hi > ns_h - 1 ? ns_h - 1 : q_hi;
-  const int g_lo = q_lo / p.d.seg, g_hi = q_hi / p.d.seg;
-  uint32_t* ctr = sync + kSyncCounters + (int64_t)kCounterStride * (p.cbase + img * p.d.nsegs);
-  for (int g = g_lo; g <= g_hi; ++g) {
-    uint32_t spins = 0, nap = 1;
-    // every lane reads the same word; readfirstlane makes the loop wave-uniform
-    while (__builtin_amdgcn_readfirstlane(__hip_atomic_load(ctr + (int64_t)kCounterStride * g, __ATOMIC_RELAXED,
-                                                            __HIP_MEMORY_SCOPE_AGENT)) < (uint32_t)p.d.nstrips) {
-      if (++spins > kSpinLimit) {
-        __hip_atomic_store(sync + kSyncError, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        break;
-      }
-      for (uint32_t k = 0; k < nap; ++k) __builtin_amdgcn_s_sleep(16);
-      nap = nap < kNapCap ? 2 * nap : kNapCap;
-    }
-  }
-  // the item's loads of the producers' rows are coherent (sc0 sc1) and are
-  // issued only after the counters were seen; the fence keeps the compiler
-  // from moving them above the wait
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-}
-
-// TABLE: descriptors and the slot -> descriptor map live in device memory
-// (ragged batches); otherwise the descriptors are kernel arguments and the
-// descriptor of a slot is found by a scan (at most kInlineDescs steps).
-// Either way they are wave-uniform and stay in scalar registers.
-template <int DIR, typename T, int CH, bool TABLE>
-__global__ __launch_bounds__(kBlock) void job_kernel(JobArgs a) {
-  const int lane = threadIdx.x & (kWave - 1);
-  const JobDesc* __restrict__ D = TABLE ? a.descs : a.inl;
-  uint32_t* sync = a.sync;
-  const uint32_t one = lane == 0 ? 1u : 0u;  // wave-uniform atomic: lane 0 adds 1, the rest add 0
-  const uint32_t wave = (uint32_t)xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock +
-                        __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  const uint32_t nwaves = gridDim.x * kWavesPerBlock;
-  int j = 0;
-  for (uint32_t q = wave; q < (uint32_t)a.total_items; q += nwaves) {
-    if constexpr (TABLE) {
-      j = __builtin_amdgcn_readfirstlane(((const uint32_t* __restrict__)a.item_desc)[q]);
-    } else {
-      while (j + 1 < a.ndesc && a.inl[j + 1].item_start <= (int)q) ++j;  // items only move forward
-    }
-    const JobDesc jd = D[j];
-    const int item = (int)q - jd.item_start;
-    const int per_img = jd.d.nsegs * jd.d.nstrips;
-    const int img = item / per_img;
-    const int rem = item - img * per_img;
-    const int seg = rem / jd.d.nstrips;
-    const int strip = rem - seg * jd.d.nstrips;
-    if (jd.prev >= 0) {
-      const JobDesc p = D[jd.prev];
-      const int I0 = seg * jd.d.seg;
-      const int I1 = min(I0 + jd.d.seg, (jd.d.H + 1) >> 1);
-      // rows this item reads from p's output, with a margin that covers the
-      // symmetric folds at the image edges
-      if (DIR == kFwd) wait_rows(p, sync, img, 2 * I0 - 4, 2 * I1 + 2, false);
-      else wait_rows(p, sync, img, I0 - 3, I1 + 2, true);
-    }
-    run_item<DIR, T, CH, true>(jd.d, jd.coh, img * jd.pix_bstride, img * jd.ll_bstride, img * jd.band_bstride, strip,
-                               seg, lane);
-    // publish: the item's stores write through (sc1); once they have
-    // completed (s_waitcnt 0) the count makes them visible to every XCD
-    __builtin_amdgcn_s_waitcnt(0);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __hip_atomic_fetch_add(sync + kSyncCounters + (int64_t)kCounterStride * (jd.cbase + img * jd.d.nsegs + seg), one,
-                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-}
-
-// One step range of a ragged batch per launch (level-synchronous schedule,
-// any direction):
-// one wave per work item, the item's step found through the device
-// item -> step table.  Steps of one launch never depend on each other.
-template <int DIR, typename T, int CH>
-__global__ __launch_bounds__(kBlock) void table_kernel(TableArgs a) {
-  const int lane = threadIdx.x & (kWave - 1);
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  const int64_t w = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + wave;
-  if (w >= a.items) return;
-  const int q = a.item_begin + (int)w;
-  const int j = __builtin_amdgcn_readfirstlane(((const uint32_t* __restrict__)a.item_desc)[q]);
-  const JobDesc jd = ((const JobDesc* __restrict__)a.descs)[j];
-  const int item = q - jd.item_start;
-  const int per_img = jd.d.nsegs * jd.d.nstrips;
-  const int img = item / per_img;
-  const int rem = item - img * per_img;
-  const int seg = rem / jd.d.nstrips;
-  const int strip = rem - seg * jd.d.nstrips;
-  run_item<DIR, T, CH, false>(jd.d, 0, img * jd.pix_bstride, img * jd.ll_bstride, img * jd.band_bstride, strip, seg,
-                              lane);
-}
-
-// ---------------------------------------------------------------------------
-// Tail kernel: the last n (2 or 3) levels of a transform, whose inputs are
-// small, in one launch.  Each workgroup owns a kTailS x kTailS tile of the
-// first tail level's input and runs every remaining level in LDS on that
-// tile plus a recompute halo of 2^(n+1) - 2 pixels (a 5/3 level reads two
-// pixels on each side of a quadruple, so each coarser level doubles the
-// halo and adds two), then writes the coefficients of its own tile.  Every
-// read goes through the symmetric fold of its level, so values past an
-// edge are the ones the strip kernels see, and the per-quadruple arithmetic
-// is the strip kernels' own: results are bit-identical.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ int tail_halo(int n, int m) { return (2 << (n - m)) - 2; }
-
-// The symmetric fold for positions in [-2, n + 1] (all that the tail reads,
-// n >= 2), without the division of the general fold: one reflection at 0,
-// one at n - 1, and a last one at 0 for n = 2.
-__device__ __forceinline__ int fold_near(int p, int n) {
-  int q = p < 0 ? -p : p;
-  q = q > n - 1 ? 2 * (n - 1) - q : q;
-  return q < 0 ? -q : q;
-}
-
-// Threads walk 2-D ranges in rows of 64 (one wave per row), so that no
-// division is needed and a wave touches consecutive columns.
-constexpr int kTailRowT = 64, kTailRows = kTailBlock / kTailRowT;
-// loads per thread that cover the largest level-0 region (n = 3)
-constexpr int kTailLoads = ((kTailS + 2 * 14) * (kTailS + 2 * 14) + kTailBlock - 1) / kTailBlock;
-
-template <typename T>
-__global__ __launch_bounds__(kTailBlock) void tail_fwd(TailArgs a) {
-  __shared__ T lds[kTailLds];
-  const int lx = threadIdx.x & (kTailRowT - 1), ly = threadIdx.x / kTailRowT;
-  const int tx = blockIdx.x % a.tiles_x, ty = blockIdx.x / a.tiles_x;
-  const int n = a.n;
-  // region arrays, one per level, then the three predict arrays
-  int base[kTailMaxLevels];
-  int acc = 0;
-  for (int m = 0; m < n; ++m) {
-    base[m] = acc;
-    const int N = (kTailS >> m) + 2 * tail_halo(n, m);
-    acc += N * N;
-  }
-  const int NP = (kTailS >> 1) + 2 * tail_halo(n, 1) + 1;
-  T* P0 = lds + acc;
-  T* P1 = P0 + NP * NP;
-  T* P2 = P1 + NP * NP;
-  for (int img = blockIdx.y; img < a.batch; img += gridDim.y) {
-    const T* in = static_cast<const T*>(a.in) + img * a.in_bstride;
-    T* dst = static_cast<T*>(a.out) + img * a.out_bstride;
-    // level 0 input: the in-image part of the region.  Every thread issues
-    // all its loads before the first LDS store, so they are in flight
-    // together; surplus lanes load a valid element and discard it.
-    {
-      const int r = tail_halo(n, 0), N = kTailS + 2 * r;
-      const int ox = tx * kTailS - r, oy = ty * kTailS - r;
-      const int x0 = max(ox, 0), x1 = min(ox + N, a.W[0]), y0 = max(oy, 0), y1 = min(oy + N, a.H[0]);
-      const int w = x1 - x0, cnt = w * (y1 - y0);
-      // element e = threadIdx.x + k * kTailBlock sits at (y0 + e / w, x0 + e % w);
-      // one division, then steps of kTailBlock elements
-      const int dq = kTailBlock / w, dr = kTailBlock - dq * w;
-      int ey = (int)threadIdx.x / w, ex = (int)threadIdx.x - ey * w;
-      T v[kTailLoads];
-      int slot[kTailLoads];
-#pragma unroll
-      for (int k = 0; k < kTailLoads; ++k) {
-        const bool ok = (int)threadIdx.x + k * kTailBlock < cnt;
-        const int gy = ok ? y0 + ey : y0, gx = ok ? x0 + ex : x0;  // surplus lanes reload a valid element
-        v[k] = in[(int64_t)gy * a.in_stride + gx];
-        slot[k] = ok ? base[0] + (gy - oy) * N + (gx - ox) : -1;
-        ex += dr;
-        ey += dq;
-        if (ex >= w) {
-          ex -= w;
-          ++ey;
-        }
-      }
-#pragma unroll
-      for (int k = 0; k < kTailLoads; ++k)
-        if (slot[k] >= 0) lds[slot[k]] = v[k];
-    }
-    __syncthreads();
-    for (int m = 0; m < n; ++m) {
-      const int Wm = a.W[m], Hm = a.H[m];
-      const int r = tail_halo(n, m);
-      const int N = (kTailS >> m) + 2 * r, ox = tx * (kTailS >> m) - r, oy = ty * (kTailS >> m) - r;
-      const T* A = lds + base[m];
-      // quadruples this level produces: the next region (or, at the last
-      // level, the core), inside the image
-      const int rn = m + 1 < n ? tail_halo(n, m + 1) : 0;
-      const int S1 = kTailS >> (m + 1), cx = tx * S1, cy = ty * S1;
-      const int ns_w = (Wm + 1) >> 1, ns_h = (Hm + 1) >> 1, nd_w = Wm >> 1, nd_h = Hm >> 1;
-      const int ux0 = max(cx - rn, 0), ux1 = min(cx + S1 + rn, ns_w);
-      const int uy0 = max(cy - rn, 0), uy1 = min(cy + S1 + rn, ns_h);
-      // predict over the produced quadruples and one more on the left and top
-      const int px0 = ux0 - 1, py0 = uy0 - 1;
-      // the ranges are at most NP <= kTailRowT quadruples wide, so each
-      // thread owns one column: its folded LDS columns are fixed per level
-      const int qx = px0 + lx;
-      const int c0 = fold_near(2 * qx, Wm) - ox, c1 = fold_near(2 * qx + 1, Wm) - ox;
-      const int c2 = fold_near(2 * qx + 2, Wm) - ox;
-      for (int qy = py0 + ly; qy < uy1; qy += kTailRows) {
-        // folded rows 2qy .. 2qy+2 as LDS offsets
-        const int r0 = (fold_near(2 * qy, Hm) - oy) * N, r1 = (fold_near(2 * qy + 1, Hm) - oy) * N;
-        const int r2 = (fold_near(2 * qy + 2, Hm) - oy) * N;
-        if (qx < ux1) {
-          const int o = (qy - py0) * NP + (qx - px0);
-          if constexpr (std::is_same<T, float>::value)
-            f32_predict(A[r0 + c0], A[r0 + c2], A[r2 + c0], A[r2 + c2], A[r0 + c1], A[r2 + c1], A[r1 + c0],
-                        A[r1 + c2], A[r1 + c1], P0[o], P1[o], P2[o]);
-          else
-            i32_predict(A[r0 + c0], A[r0 + c2], A[r2 + c0], A[r2 + c2], A[r0 + c1], A[r2 + c1], A[r1 + c0],
-                        A[r1 + c2], A[r1 + c1], P0[o], P1[o], P2[o]);
-        }
-      }
-      __syncthreads();
-      const bool last = m + 1 == n;
-      const int rn_base = last ? 0 : base[m + 1];
-      const int Nn = S1 + 2 * rn, oxn = cx - rn, oyn = cy - rn;
-      const int ux = ux0 + lx;
-      const int cu = fold_near(2 * ux, Wm) - ox;
-      const bool own_col = ux >= cx && ux < cx + S1;
-      for (int qy = uy0 + ly; qy < uy1; qy += kTailRows) {
-        const int r0 = (fold_near(2 * qy, Hm) - oy) * N;
-        const bool own_row = qy >= cy && qy < cy + S1;
-        if (ux < ux1) {
-          const int qx = ux;
-          const int o = (qy - py0) * NP + (qx - px0);
-          const T va = A[r0 + cu];
-          T ll, hl, lh, hh;
-          if constexpr (std::is_same<T, float>::value) {
-            f32_update(va, P0[o - 1], P0[o], P1[o - NP], P1[o], P2[o - NP - 1], P2[o - NP], P2[o - 1], P2[o], ll, hl,
-                       lh);
-            hh = P2[o];
-          } else {
-            const int c2 = i32_c2(P1[o], P2[o - 1], P2[o]);
-            const int c2U = i32_c2(P1[o - NP], P2[o - NP - 1], P2[o - NP]);
-            i32_update(va, P0[o - 1], P0[o], c2U, c2, P2[o - NP], P2[o], ll, hl);
-            lh = c2;
-            hh = P2[o];
-          }
-          if (!last) lds[rn_base + (qy - oyn) * Nn + (qx - oxn)] = ll;
-          if (own_row && own_col) {  // this tile's own quadruples
-            if (last) dst[(int64_t)qy * a.out_stride + qx] = ll;
-            if (qx < nd_w) dst[(int64_t)qy * a.out_stride + ns_w + qx] = hl;
-            if (qy < nd_h) {
-              dst[(int64_t)(ns_h + qy) * a.out_stride + qx] = lh;
-              if (qx < nd_w) dst[(int64_t)(ns_h + qy) * a.out_stride + ns_w + qx] = hh;
-            }
-          }
-        }
-      }
-      __syncthreads();
-    }
-  }
-}
-
-// Inverse tail: the last n levels of an inverse (coarsest first) in one
-// launch.  Each workgroup owns a kTailS x kTailS tile of the finest tail
-// output and works back through the coarser levels: output pixels [d0, d1)
-// of a level need its quadruples q0..q1, their coefficients one quadruple
-// around (read through the symmetric extension of the interleaved array, as
-// the strip kernels read them), and the LL pixels the update at q0..q1+1
-// reads, which the coarser level produces (the coarsest reads them from the
-// packed array).  Every array is kTailInvE wide; the index facts are walked
-// on the CPU for many sizes.
-constexpr int kTailInvE = kTailS / 2 + 2;
-constexpr int kTailInvPasses = (kTailInvE + kTailRows - 1) / kTailRows;
-
-__device__ __forceinline__ int band_near(int q, int n, int par) { return (fold_near(2 * q + par, n) - par) >> 1; }
-
-template <typename T>
-__global__ __launch_bounds__(kTailBlock) void tail_inv(TailArgs a) {
-  __shared__ T lds[8 * kTailInvE * kTailInvE];
-  constexpr int E = kTailInvE, EE = E * E;
-  T* CHL = lds;           // coefficients over quadruples [q0 - 1, q1 + 1]
-  T* CLH = CHL + EE;
-  T* CHH = CLH + EE;
-  T* U0 = CHH + EE;       // undone update (float: a, b', c'; int: b1, a, c1)
-  T* U1 = U0 + EE;
-  T* U2 = U1 + EE;
-  T* XB[2] = {U2 + EE, U2 + 2 * EE};  // LL input of a level / its output
-  const int lx = threadIdx.x & (kTailRowT - 1), ly = threadIdx.x / kTailRowT;
-  const int tx = blockIdx.x % a.tiles_x, ty = blockIdx.x / a.tiles_x;
-  const int n = a.n;
-  // ranges per level (x, y): output pixels [d0, d1), quadruples [q0, q1]
-  int d0x[kTailMaxLevels + 1], d1x[kTailMaxLevels + 1], d0y[kTailMaxLevels + 1], d1y[kTailMaxLevels + 1];
-  d0x[0] = tx * kTailS;
-  d1x[0] = min(tx * kTailS + kTailS, a.W[0]);
-  d0y[0] = ty * kTailS;
-  d1y[0] = min(ty * kTailS + kTailS, a.H[0]);
-  for (int m = 0; m < n; ++m) {
-    const int q0x = d0x[m] >> 1, q1x = (d1x[m] - 1) >> 1, q0y = d0y[m] >> 1, q1y = (d1y[m] - 1) >> 1;
-    d0x[m + 1] = min(q0x, band_near(q1x + 1, a.W[m], 0));
-    d1x[m + 1] = min(q1x + 2, a.W[m + 1]);
-    d0y[m + 1] = min(q0y, band_near(q1y + 1, a.H[m], 0));
-    d1y[m + 1] = min(q1y + 2, a.H[m + 1]);
-  }
-  for (int img = blockIdx.y; img < a.batch; img += gridDim.y) {
-    const T* src = static_cast<const T*>(a.in) + img * a.in_bstride;
-    T* out = static_cast<T*>(a.out) + img * a.out_bstride;
-    int cur = 0;  // XB[cur]: LL input of the level being inverted
-    // the coarsest level's LL from the packed array
-    {
-      const int x0 = d0x[n], y0 = d0y[n], w = d1x[n] - x0, h = d1y[n] - y0;
-      T v[kTailInvPasses];
-#pragma unroll
-      for (int k = 0; k < kTailInvPasses; ++k) {
-        const int y = min(ly + k * kTailRows, h - 1), x = min(lx, w - 1);
-        v[k] = src[(int64_t)(y0 + y) * a.in_stride + x0 + x];
-      }
-#pragma unroll
-      for (int k = 0; k < kTailInvPasses; ++k)
-        if (lx < w && ly + k * kTailRows < h) XB[cur][(ly + k * kTailRows) * E + lx] = v[k];
-    }
-    for (int m = n - 1; m >= 0; --m) {
-      const int Wm = a.W[m], Hm = a.H[m];
-      const int ns_w = (Wm + 1) >> 1, ns_h = (Hm + 1) >> 1;
-      const int q0x = d0x[m] >> 1, q1x = (d1x[m] - 1) >> 1, q0y = d0y[m] >> 1, q1y = (d1y[m] - 1) >> 1;
-      const int bx = q0x - 1, by = q0y - 1;  // array origin (quadruples)
-      // this thread's column: quadruple bx + lx, with its folded band columns
-      const int qx = bx + lx;
-      const bool col_c = qx <= q1x + 1;  // inside the coefficient range
-      const int cl = band_near(qx, Wm, 0), ch = ns_w + band_near(qx, Wm, 1);
-      // coefficients HL, LH, HH over [q0 - 1, q1 + 1]
-      {
-        const int h = q1y - q0y + 3;
-        T vhl[kTailInvPasses], vlh[kTailInvPasses], vhh[kTailInvPasses];
-#pragma unroll
-        for (int k = 0; k < kTailInvPasses; ++k) {
-          const int qy = by + min(ly + k * kTailRows, h - 1);
-          const int re = band_near(qy, Hm, 0), ro = ns_h + band_near(qy, Hm, 1);
-          const int c0 = col_c ? cl : 0, c1 = col_c ? ch : 0;
-          vhl[k] = src[(int64_t)re * a.in_stride + c1];
-          vlh[k] = src[(int64_t)ro * a.in_stride + c0];
-          vhh[k] = src[(int64_t)ro * a.in_stride + c1];
-        }
-#pragma unroll
-        for (int k = 0; k < kTailInvPasses; ++k) {
-          const int row = ly + k * kTailRows;
-          if (col_c && row < h) {
-            CHL[row * E + lx] = vhl[k];
-            CLH[row * E + lx] = vlh[k];
-            CHH[row * E + lx] = vhh[k];
-          }
-        }
-      }
-      __syncthreads();
-      const T* LL = XB[cur];
-      const int lx0 = d0x[m + 1], ly0 = d0y[m + 1];
-      const int llc = band_near(qx, Wm, 0) - lx0;  // this column's LL position in XB[cur]
-      if constexpr (std::is_same<T, float>::value) {
-        // undo the update at [q0, q1 + 1]
-        for (int qy = q0y + ly; qy <= q1y + 1; qy += kTailRows) {
-          if (qx < q0x || qx > q1x + 1) continue;
-          const int o = (qy - by) * E + lx;
-          const T ll = LL[(band_near(qy, Hm, 0) - ly0) * E + llc];
-          f32_inv_update(ll, CHL[o - 1], CHL[o], CLH[o - E], CLH[o], CHH[o - E - 1], CHH[o - E], CHH[o - 1], CHH[o],
-                         U0[o], U1[o], U2[o]);
-        }
-      } else {
-        // b1 over columns [q0 - 1, q1 + 1], rows [q0, q1 + 1]
-        for (int qy = q0y + ly; qy <= q1y + 1; qy += kTailRows) {
-          if (!col_c) continue;
-          const int o = (qy - by) * E + lx;
-          U0[o] = i32_inv_b1(CHL[o], CHH[o - E], CHH[o]);
-        }
-        __syncthreads();
-        for (int qy = q0y + ly; qy <= q1y + 1; qy += kTailRows) {
-          if (qx < q0x || qx > q1x + 1) continue;
-          const int o = (qy - by) * E + lx;
-          const T ll = LL[(band_near(qy, Hm, 0) - ly0) * E + llc];
-          i32_inv_update(ll, CLH[o - E], CLH[o], U0[o - 1], U0[o], CHH[o - 1], CHH[o], U1[o], U2[o]);
-        }
-      }
-      __syncthreads();
-      // undo the predict at [q0, q1]: pixels of quadruple (qx, qy)
-      T* X = m > 0 ? XB[cur ^ 1] : nullptr;
-      const int ox = d0x[m], oy = d0y[m];
-      for (int qy = q0y + ly; qy <= q1y; qy += kTailRows) {
-        if (qx < q0x || qx > q1x) continue;
-        const int o = (qy - by) * E + lx;
-        T va, vb, vc, vd;
-        if constexpr (std::is_same<T, float>::value) {
-          va = U0[o];
-          f32_inv_predict(U0[o], U0[o + 1], U0[o + E], U0[o + E + 1], U1[o], U1[o + E], U2[o], U2[o + 1], CHH[o], vb,
-                          vc, vd);
-        } else {
-          va = U1[o];
-          vc = i32_inv_c(U2[o], U1[o], U1[o + E]);
-          const int cR = i32_inv_c(U2[o + 1], U1[o + 1], U1[o + E + 1]);
-          i32_inv_predict(U1[o], U1[o + 1], U0[o], U0[o + E], vc, cR, CHH[o], vb, vd);
-        }
-        const int px = 2 * qx, py = 2 * qy;
-        const T vals[4] = {va, vb, vc, vd};
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const int x = px + (k & 1), y = py + (k >> 1);
-          if (x < d0x[m] || x >= d1x[m] || y < d0y[m] || y >= d1y[m]) continue;
-          if (m > 0) X[(y - oy) * E + (x - ox)] = vals[k];
-          else out[(int64_t)y * a.out_stride + x] = vals[k];
-        }
-      }
-      __syncthreads();
-      cur ^= 1;
-    }
-  }
-}
-
-// Adjoint tail: the last n levels of W^T (coarsest first) in one launch, on
-// the inverse tail's tiles.  The adjoint reads no symmetric extension:
-// coefficients outside their bands are zero and the transposed boundary
-// weights of the axis carry the edges, exactly as in the strip kernel.
-// Output pixels [d0, d1) of a level need its quadruples q0..q1, the
-// transposed update at q0-1..q1, coefficients at q0-1..q1+1, and LL pixels
-// [max(q0 - 1, 0), min(q1 + 2, size)) from the coarser level.
-__global__ __launch_bounds__(kTailBlock) void tail_bwd(TailArgs a) {
-  __shared__ float lds[8 * kTailInvE * kTailInvE];
-  constexpr int E = kTailInvE, EE = E * E;
-  float* CLL = lds;          // coefficients over quadruples [q0 - 1, q1 + 1]
-  float* CHL = CLL + EE;
-  float* CLH = CHL + EE;
-  float* CHH = CLH + EE;
-  float* GB = CHH + EE;      // transposed update over [q0 - 1, q1]
-  float* GC = GB + EE;
-  float* GD = GC + EE;
-  float* XO = GD + EE;       // a level's output pixels (the finer level's LL)
-  const int lx = threadIdx.x & (kTailRowT - 1), ly = threadIdx.x / kTailRowT;
-  const int tx = blockIdx.x % a.tiles_x, ty = blockIdx.x / a.tiles_x;
-  const int n = a.n;
-  int d0x[kTailMaxLevels + 1], d1x[kTailMaxLevels + 1], d0y[kTailMaxLevels + 1], d1y[kTailMaxLevels + 1];
-  d0x[0] = tx * kTailS;
-  d1x[0] = min(tx * kTailS + kTailS, a.W[0]);
-  d0y[0] = ty * kTailS;
-  d1y[0] = min(ty * kTailS + kTailS, a.H[0]);
-  for (int m = 0; m < n; ++m) {
-    const int q0x = d0x[m] >> 1, q1x = (d1x[m] - 1) >> 1, q0y = d0y[m] >> 1, q1y = (d1y[m] - 1) >> 1;
-    d0x[m + 1] = max(q0x - 1, 0);
-    d1x[m + 1] = min(q1x + 2, a.W[m + 1]);
-    d0y[m + 1] = max(q0y - 1, 0);
-    d1y[m + 1] = min(q1y + 2, a.H[m + 1]);
-  }
-  for (int img = blockIdx.y; img < a.batch; img += gridDim.y) {
-    const float* src = static_cast<const float*>(a.in) + img * a.in_bstride;
-    float* out = static_cast<float*>(a.out) + img * a.out_bstride;
-    for (int m = n - 1; m >= 0; --m) {
-      const int Wm = a.W[m], Hm = a.H[m];
-      const int ns_w = (Wm + 1) >> 1, ns_h = (Hm + 1) >> 1, nd_w = Wm >> 1, nd_h = Hm >> 1;
-      const int q0x = d0x[m] >> 1, q1x = (d1x[m] - 1) >> 1, q0y = d0y[m] >> 1, q1y = (d1y[m] - 1) >> 1;
-      const int bx = q0x - 1, by = q0y - 1;
-      const int qx = bx + lx;
-      const bool col_c = qx <= q1x + 1;
-      // coefficients over [q0 - 1, q1 + 1]; zero outside their bands.  LL
-      // comes from the packed array at the coarsest level, else from the
-      // coarser level's output in XO (LDS).
-      {
-        const int h = q1y - q0y + 3;
-        const int lxo = d0x[m + 1], lyo = d0y[m + 1];
-        float vll[kTailInvPasses], vhl[kTailInvPasses], vlh[kTailInvPasses], vhh[kTailInvPasses];
-#pragma unroll
-        for (int k = 0; k < kTailInvPasses; ++k) {
-          const int qy = by + min(ly + k * kTailRows, h - 1);
-          const bool rl = qy >= 0 && qy < ns_h, rh = qy >= 0 && qy < nd_h;
-          const bool cl = qx >= 0 && qx < ns_w, chh = qx >= 0 && qx < nd_w;
-          const int ry = rl ? qy : 0, ryo = ns_h + (rh ? qy : 0), cx = cl ? qx : 0, cxh = ns_w + (chh ? qx : 0);
-          const bool ok = col_c;
-          vhl[k] = (ok && rl && chh) ? src[(int64_t)ry * a.in_stride + cxh] : 0.f;
-          vlh[k] = (ok && rh && cl) ? src[(int64_t)ryo * a.in_stride + cx] : 0.f;
-          vhh[k] = (ok && rh && chh) ? src[(int64_t)ryo * a.in_stride + cxh] : 0.f;
-          if (m == n - 1) vll[k] = (ok && rl && cl) ? src[(int64_t)ry * a.in_stride + cx] : 0.f;
-          else vll[k] = (ok && rl && cl) ? XO[(ry - lyo) * E + (cx - lxo)] : 0.f;
-        }
-#pragma unroll
-        for (int k = 0; k < kTailInvPasses; ++k) {
-          const int row = ly + k * kTailRows;
-          if (col_c && row < h) {
-            CLL[row * E + lx] = vll[k];
-            CHL[row * E + lx] = vhl[k];
-            CLH[row * E + lx] = vlh[k];
-            CHH[row * E + lx] = vhh[k];
-          }
-        }
-      }
-      __syncthreads();
-      // transposed update at [q0 - 1, q1]
-      const AxisW h0 = axis_weights(qx, Wm);
-      for (int qy = by + ly; qy <= q1y; qy += kTailRows) {
-        if (qx > q1x) continue;
-        const int o = (qy - by) * E + lx;
-        f32_adj_a(CLL[o], CLL[o + 1], CLL[o + E], CLL[o + E + 1], CHL[o], CHL[o + E], CLH[o], CLH[o + 1], CHH[o], h0,
-                  axis_weights(qy, Hm), GB[o], GC[o], GD[o]);
-      }
-      __syncthreads();
-      // transposed predict at [q0, q1]: pixels of quadruple (qx, qy)
-      const int ox = d0x[m], oy = d0y[m];
-      for (int qy = q0y + ly; qy <= q1y; qy += kTailRows) {
-        if (qx < q0x || qx > q1x) continue;
-        const int o = (qy - by) * E + lx;
-        float ga2, gb2, gc2;
-        f32_adj_b(CLL[o], GB[o - 1], GB[o], GC[o - E], GC[o], GD[o - E - 1], GD[o - E], GD[o - 1], GD[o], h0,
-                  axis_weights(qy, Hm), ga2, gb2, gc2);
-        const float vals[4] = {ga2, gb2, gc2, GD[o]};
-        const int px = 2 * qx, py = 2 * qy;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const int x = px + (k & 1), y = py + (k >> 1);
-          if (x < d0x[m] || x >= d1x[m] || y < d0y[m] || y >= d1y[m]) continue;
-          if (m > 0) XO[(y - oy) * E + (x - ox)] = vals[k];
-          else out[(int64_t)y * a.out_stride + x] = vals[k];
-        }
-      }
-      __syncthreads();
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// LDS-tiled level kernels: the two schemes compared with their data movement
-// held equal (the comparison of §4).  Each workgroup copies a tile of the
-// level input plus a two-pixel halo on every side (through the symmetric
-// fold) into LDS, runs the lifting steps with a workgroup barrier between
-// consecutive steps, and stores its quadruples' four coefficients.
-//   separable (eq. (3)):      HP | VP | HU | VU      four barriers
-//   non-separable (eq. (5)):  spatial predict | spatial update   two barriers
-// Since the fold commutes with lifting (whole-sample symmetry keeps every
-// index's parity), computing on folded halo pixels gives exactly the values
-// the boundary rules give, so each step runs on a fixed local range.
-// ---------------------------------------------------------------------------
-constexpr int kLdsQX = 64, kLdsQY = 16;                              // output quadruples per tile
-constexpr int kLdsPX = 2 * kLdsQX + 4, kLdsPY = 2 * kLdsQY + 4;      // pixel tile incl. halo
-constexpr int kLdsBlock = 256, kLdsWaves = kLdsBlock / kWave;
-constexpr int kLdsQ1 = kLdsQX + 1, kLdsPQ = kLdsQ1 * (kLdsQY + 1);   // predicted quadruples
-
-// Separable 1-D steps: predict x - 1/2 (l + r), update x + 1/4 (l + r);
-// integer: x - floor((l + r) / 2), x + floor((l + r + 2) / 4).
-__device__ __forceinline__ float lp(float x, float l, float r) { return __fmaf_rn(-0.5f, l + r, x); }
-__device__ __forceinline__ float lu(float x, float l, float r) { return __fmaf_rn(0.25f, l + r, x); }
-__device__ __forceinline__ int lp(int x, int l, int r) { return x - ((l + r) >> 1); }
-__device__ __forceinline__ int lu(int x, int l, int r) { return x + ((l + r + 2) >> 2); }
-
-// Runs f(row, q) over quadruple columns q in [0, kLdsQX] and rows
-// [0, nrows): a wave per row for q < kLdsQX, then the last column of every
-// row in one pass of the block.
-template <typename F>
-__device__ __forceinline__ void lds_walk65(int nrows, int lane, int wv, F&& f) {
-  for (int r = wv; r < nrows; r += kLdsWaves) f(r, lane);
-  if ((int)threadIdx.x < nrows) f((int)threadIdx.x, kLdsQX);
-}
-
-template <typename T, bool SEP>
-__global__ __launch_bounds__(kLdsBlock) void lds_level(SepLevel a, int tiles_x) {
-  __shared__ T X[kLdsPX * kLdsPY];
-  __shared__ T PB[SEP ? 1 : 3 * kLdsPQ];
-  // the wave index is uniform: as a scalar, row folds and row pointers are
-  // scalar code, not per-lane branches
-  const int lane = threadIdx.x & (kWave - 1), wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  const int tile = xcd_remap(blockIdx.x, gridDim.x);
-  const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
-  const int W = a.W, H = a.H;
-  const int ns_w = (W + 1) >> 1, ns_h = (H + 1) >> 1, nd_w = W >> 1, nd_h = H >> 1;
-  const int ox = 2 * kLdsQX * tx - 2, oy = 2 * kLdsQY * ty - 2;  // image position of X[0]
-  // this lane's folded source columns: lane, lane + 64, and 128 + lane % 4
-  // (stored by lanes 0..3 only; the others reload one of those four)
-  const int gc0 = fold_idx(ox + lane, W), gc1 = fold_idx(ox + kWave + lane, W);
-  const int gc2 = fold_idx(ox + 2 * kWave + (lane & 3), W);
-  constexpr int kRowsPerWave = kLdsPY / kLdsWaves;
-  static_assert(kLdsPY % kLdsWaves == 0 && kLdsPX == 2 * kWave + 4, "tile shape");
-  const int gqx = tx * kLdsQX + lane;  // image quadruple column of local column lane + 1
-  for (int img = blockIdx.y; img < a.batch; img += gridDim.y) {
-    const T* src = static_cast<const T*>(a.src) + img * a.src_bstride;
-    T* ll = static_cast<T*>(a.ll) + img * a.ll_bstride;
-    T* band = static_cast<T*>(a.band) + img * a.band_bstride;
-    {
-      T v0[kRowsPerWave], v1[kRowsPerWave], v2[kRowsPerWave];
-#pragma unroll
-      for (int k = 0; k < kRowsPerWave; ++k) {
-        const T* row = src + (int64_t)fold_idx(oy + wv + k * kLdsWaves, H) * a.src_stride;
-        v0[k] = row[gc0];
-        v1[k] = row[gc1];
-        v2[k] = row[gc2];
-      }
-#pragma unroll
-      for (int k = 0; k < kRowsPerWave; ++k) {
-        T* x = X + (wv + k * kLdsWaves) * kLdsPX;
-        x[lane] = v0[k];
-        x[kWave + lane] = v1[k];
-        if (lane < 4) x[2 * kWave + lane] = v2[k];
-      }
-    }
-    __syncthreads();
-    // every step below leaves the quadruples (i, q), i in [1, kLdsQY],
-    // q in [1, kLdsQX], final: LL at X[2i][2q], HL at X[2i][2q+1] (sep.)
-    T ll_v[kLdsQY / kLdsWaves], hl_v[kLdsQY / kLdsWaves], lh_v[kLdsQY / kLdsWaves], hh_v[kLdsQY / kLdsWaves];
-    if constexpr (SEP) {
-      // HP: odd columns, every row
-      lds_walk65(kLdsPY, lane, wv, [&](int r, int q) {
-        T* x = X + r * kLdsPX + 2 * q;
-        x[1] = lp(x[1], x[0], x[2]);
-      });
-      __syncthreads();
-      // VP: odd rows 2i + 1, i in [0, kLdsQY], both columns of quadruple q
-      lds_walk65(kLdsQY + 1, lane, wv, [&](int i, int q) {
-        T* x = X + (2 * i + 1) * kLdsPX + 2 * q;
-        x[0] = lp(x[0], x[-kLdsPX], x[kLdsPX]);
-        x[1] = lp(x[1], x[1 - kLdsPX], x[1 + kLdsPX]);
-      });
-      __syncthreads();
-      // HU: even columns 2q, q in [1, kLdsQX], rows [1, 2 kLdsQY + 1]
-      for (int r = 1 + wv; r <= 2 * kLdsQY + 1; r += kLdsWaves) {
-        T* x = X + r * kLdsPX + 2 * (lane + 1);
-        x[0] = lu(x[0], x[-1], x[1]);
-      }
-      __syncthreads();
-      // VU: even rows 2i, i in [1, kLdsQY]; the odd rows are final
-#pragma unroll
-      for (int k = 0; k < kLdsQY / kLdsWaves; ++k) {
-        const int i = 1 + wv + k * kLdsWaves;
-        const T* x = X + 2 * i * kLdsPX + 2 * (lane + 1);
-        ll_v[k] = lu(x[0], x[-kLdsPX], x[kLdsPX]);
-        hl_v[k] = lu(x[1], x[1 - kLdsPX], x[1 + kLdsPX]);
-        lh_v[k] = x[kLdsPX];
-        hh_v[k] = x[kLdsPX + 1];
-      }
-    } else {
-      // spatial predict over quadruples [0, kLdsQY] x [0, kLdsQX] into PB
-      lds_walk65(kLdsQY + 1, lane, wv, [&](int i, int q) {
-        const T* x0 = X + 2 * i * kLdsPX + 2 * q;
-        const T* x1 = x0 + kLdsPX;
-        const T* x2 = x1 + kLdsPX;
-        const int o = i * kLdsQ1 + q;
-        if constexpr (std::is_same<T, float>::value)
-          f32_predict(x0[0], x0[2], x2[0], x2[2], x0[1], x2[1], x1[0], x1[2], x1[1], PB[o], PB[kLdsPQ + o],
-                      PB[2 * kLdsPQ + o]);
-        else
-          i32_predict(x0[0], x0[2], x2[0], x2[2], x0[1], x2[1], x1[0], x1[2], x1[1], PB[o], PB[kLdsPQ + o],
-                      PB[2 * kLdsPQ + o]);
-      });
-      __syncthreads();
-      // spatial update over [1, kLdsQY] x [1, kLdsQX]
-      const T* P0 = PB;
-      const T* P1 = PB + kLdsPQ;
-      const T* P2 = PB + 2 * kLdsPQ;
-#pragma unroll
-      for (int k = 0; k < kLdsQY / kLdsWaves; ++k) {
-        const int i = 1 + wv + k * kLdsWaves, q = lane + 1;
-        const int o = i * kLdsQ1 + q;
-        const T va = X[2 * i * kLdsPX + 2 * q];
-        if constexpr (std::is_same<T, float>::value) {
-          f32_update(va, P0[o - 1], P0[o], P1[o - kLdsQ1], P1[o], P2[o - kLdsQ1 - 1], P2[o - kLdsQ1], P2[o - 1],
-                     P2[o], ll_v[k], hl_v[k], lh_v[k]);
-        } else {
-          const int c2 = i32_c2(P1[o], P2[o - 1], P2[o]);
-          const int c2U = i32_c2(P1[o - kLdsQ1], P2[o - kLdsQ1 - 1], P2[o - kLdsQ1]);
-          i32_update(va, P0[o - 1], P0[o], c2U, c2, P2[o - kLdsQ1], P2[o], ll_v[k], hl_v[k]);
-          lh_v[k] = c2;
-        }
-        hh_v[k] = P2[o];
-      }
-    }
-    // store this tile's quadruples (rows and columns inside the level)
-#pragma unroll
-    for (int k = 0; k < kLdsQY / kLdsWaves; ++k) {
-      const int gqy = ty * kLdsQY + wv + k * kLdsWaves;
-      if (gqx < ns_w && gqy < ns_h) {
-        ll[(int64_t)gqy * a.ll_stride + gqx] = ll_v[k];
-        if (gqx < nd_w) band[(int64_t)gqy * a.band_stride + ns_w + gqx] = hl_v[k];
-        if (gqy < nd_h) {
-          band[(int64_t)(ns_h + gqy) * a.band_stride + gqx] = lh_v[k];
-          if (gqx < nd_w) band[(int64_t)(ns_h + gqy) * a.band_stride + ns_w + gqx] = hh_v[k];
-        }
-      }
-    }
-    if (img + (int)gridDim.y < a.batch) __syncthreads();  // X and PB are reused for the next image
-  }
-}
-
-// The adapted non-separable scheme (§3) on the same tiles, float only.  Each
-// filter splits into its constant term and the rest, P = P0 + P1 and
-// U = U0 + U1 (for the 5/3: P0 = -1/2, P1 = -1/2 z, U0 = 1/4, U1 = 1/4 z^-1).
-// The constant terms touch only a quadruple's own samples, so they run
-// separably without an exchange: P0 as each thread loads its quadruples, U0
-// right after the one-sided predict P1, before the barrier.  The scheme keeps
-// the two barriers of eq. (5) but needs 18 multiply-adds per quadruple
-// instead of 23 operations.  The constant and one-sided parts commute
-// (polynomials commute), so the result equals eq. (5)'s up to rounding.
-constexpr int kLdsQW = kLdsPX / 2, kLdsQH = kLdsPY / 2;  // quadruples of the tile incl. halo
-
-__global__ __launch_bounds__(kLdsBlock) void lds_adapted(SepLevel a, int tiles_x) {
-  constexpr int NQ = kLdsQW * kLdsQH;
-  __shared__ float Q[4 * NQ];        // a, b, c, d after P0
-  __shared__ float R[4 * kLdsPQ];    // a, b', c', d' after P1 and U0
-  const float* Qa = Q;
-  const float* Qb = Q + NQ;
-  const float* Qc = Q + 2 * NQ;
-  const float* Qd = Q + 3 * NQ;
-  float* Ra = R;
-  float* Rb = R + kLdsPQ;
-  float* Rc = R + 2 * kLdsPQ;
-  float* Rd = R + 3 * kLdsPQ;
-  // the wave index is uniform: as a scalar, row folds and row pointers are
-  // scalar code, not per-lane branches
-  const int lane = threadIdx.x & (kWave - 1), wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  const int tile = xcd_remap(blockIdx.x, gridDim.x);
-  const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
-  const int W = a.W, H = a.H;
-  const int ns_w = (W + 1) >> 1, ns_h = (H + 1) >> 1, nd_w = W >> 1, nd_h = H >> 1;
-  const int ox = 2 * kLdsQX * tx - 2, oy = 2 * kLdsQY * ty - 2;  // image position of the tile's pixel (0, 0)
-  const int cx0 = fold_idx(ox + 2 * lane, W), cx1 = fold_idx(ox + 2 * lane + 1, W);
-  constexpr int kExtraQ = kLdsQW - kWave;                        // quadruple columns past the waves' 64
-  constexpr int kR = (kLdsQH + kLdsWaves - 1) / kLdsWaves;       // quadruple rows per wave
-  static_assert(kExtraQ * kLdsQH <= kLdsBlock, "adapted load mapping");
-  const int gqx = tx * kLdsQX + lane;
-  // rows (and images) start 8-byte aligned: a quadruple row's two pixels
-  // load as one float2
-  const bool pairs = ((reinterpret_cast<uintptr_t>(a.src) | (uintptr_t)(a.src_stride << 2) |
-                       (uintptr_t)(a.src_bstride << 2)) & 7) == 0;
-  const bool interior = pairs && ox >= 0 && ox + kLdsPX <= W;  // ox is even
-  for (int img = blockIdx.y; img < a.batch; img += gridDim.y) {
-    const float* src = static_cast<const float*>(a.src) + img * a.src_bstride;
-    float* ll = static_cast<float*>(a.ll) + img * a.ll_bstride;
-    float* band = static_cast<float*>(a.band) + img * a.band_bstride;
-    {
-      // every quadruple of the tile once: wave rows for columns 0..63, then
-      // the last columns in one pass; all loads before the first LDS store
-      float va[kR + 1], vb[kR + 1], vc[kR + 1], vd[kR + 1];
-      int slot[kR + 1];
-      // VEC: the tile's columns lie inside the image and rows are 8-byte
-      // aligned, so a quadruple row's two pixels load as one float2; the
-      // choice is uniform over the block, so every load is issued at once
-      auto load_all = [&](auto vec_tag) {
-        constexpr bool VEC = decltype(vec_tag)::value;
-#pragma unroll
-        for (int k = 0; k <= kR; ++k) {
-          const bool extra = k == kR;
-          const int t = threadIdx.x;
-          const int row = wv + k * kLdsWaves;
-          const bool live = extra ? t < kExtraQ * kLdsQH : row < kLdsQH;
-          const int i = live ? (extra ? t / kExtraQ : row) : 0;
-          const int q = extra ? kWave + t % kExtraQ : lane;
-          const float* r0 = src + (int64_t)fold_idx(oy + 2 * i, H) * a.src_stride;
-          const float* r1 = src + (int64_t)fold_idx(oy + 2 * i + 1, H) * a.src_stride;
-          if constexpr (VEC) {
-            const int x0 = ox + 2 * q;
-            const float2 p0 = *reinterpret_cast<const float2*>(r0 + x0);
-            const float2 p1 = *reinterpret_cast<const float2*>(r1 + x0);
-            va[k] = p0.x;
-            vb[k] = p0.y;
-            vc[k] = p1.x;
-            vd[k] = p1.y;
-          } else {
-            const int x0 = extra ? fold_idx(ox + 2 * q, W) : cx0, x1 = extra ? fold_idx(ox + 2 * q + 1, W) : cx1;
-            va[k] = r0[x0];
-            vb[k] = r0[x1];
-            vc[k] = r1[x0];
-            vd[k] = r1[x1];
-          }
-          slot[k] = live ? i * kLdsQW + q : -1;
-        }
-      };
-      if (interior) load_all(std::true_type{});
-      else load_all(std::false_type{});
-#pragma unroll
-      for (int k = 0; k <= kR; ++k) {
-        const int o = slot[k];
-        if (o >= 0) {
-          // constant predict parts: horizontal, then vertical
-          const float b = __fmaf_rn(-0.5f, va[k], vb[k]);
-          float d = __fmaf_rn(-0.5f, vc[k], vd[k]);
-          const float c = __fmaf_rn(-0.5f, va[k], vc[k]);
-          d = __fmaf_rn(-0.5f, b, d);
-          Q[o] = va[k];
-          Q[NQ + o] = b;
-          Q[2 * NQ + o] = c;
-          Q[3 * NQ + o] = d;
-        }
-      }
-    }
-    __syncthreads();
-    // step 1 over quadruples [0, kLdsQY] x [0, kLdsQX]: the one-sided predict
-    // (neighbours after P0), then the constant update parts
-    lds_walk65(kLdsQY + 1, lane, wv, [&](int i, int q) {
-      const int o = i * kLdsQW + q;
-      float bp = __fmaf_rn(-0.5f, Qa[o + 1], Qb[o]);
-      float cp = __fmaf_rn(-0.5f, Qa[o + kLdsQW], Qc[o]);
-      const float dp = __fmaf_rn(0.25f, Qa[o + kLdsQW + 1],
-                                 __fmaf_rn(-0.5f, Qb[o + kLdsQW], __fmaf_rn(-0.5f, Qc[o + 1], Qd[o])));
-      float an = __fmaf_rn(0.25f, bp, Qa[o]);
-      cp = __fmaf_rn(0.25f, dp, cp);
-      an = __fmaf_rn(0.25f, cp, an);
-      bp = __fmaf_rn(0.25f, dp, bp);
-      const int p = i * kLdsQ1 + q;
-      Ra[p] = an;
-      Rb[p] = bp;
-      Rc[p] = cp;
-      Rd[p] = dp;
-    });
-    __syncthreads();
-    // step 2 over [1, kLdsQY] x [1, kLdsQX]: the one-sided update
-#pragma unroll
-    for (int k = 0; k < kLdsQY / kLdsWaves; ++k) {
-      const int i = 1 + wv + k * kLdsWaves;
-      const int p = i * kLdsQ1 + lane + 1;
-      const float vll = __fmaf_rn(0.0625f, Rd[p - kLdsQ1 - 1], __fmaf_rn(0.25f, Rc[p - kLdsQ1], __fmaf_rn(0.25f, Rb[p - 1], Ra[p])));
-      const float vhl = __fmaf_rn(0.25f, Rd[p - kLdsQ1], Rb[p]);
-      const float vlh = __fmaf_rn(0.25f, Rd[p - 1], Rc[p]);
-      const float vhh = Rd[p];
-      const int gqy = ty * kLdsQY + wv + k * kLdsWaves;
-      if (gqx < ns_w && gqy < ns_h) {
-        ll[(int64_t)gqy * a.ll_stride + gqx] = vll;
-        if (gqx < nd_w) band[(int64_t)gqy * a.band_stride + ns_w + gqx] = vhl;
-        if (gqy < nd_h) {
-          band[(int64_t)(ns_h + gqy) * a.band_stride + gqx] = vlh;
-          if (gqx < nd_w) band[(int64_t)(ns_h + gqy) * a.band_stride + ns_w + gqx] = vhh;
-        }
-      }
-    }
-    if (img + (int)gridDim.y < a.batch) __syncthreads();
-  }
-}
-
-__global__ void zero_kernel(uint32_t* p, int64_t n) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    p[i] = 0u;
-}
-
-template <int DIR, typename T, int CH>
-hipError_t launch_t(const LevelLaunch& a, hipStream_t s) {
-  const int64_t blocks = (a.items + kWavesPerBlock - 1) / kWavesPerBlock;
-  hipLaunchKernelGGL((level_kernel<DIR, T, CH>), dim3((unsigned)blocks), dim3(kBlock), 0, s, a);
-  return hipGetLastError();
-}
-
-template <int DIR, typename T>
-hipError_t launch_ch(int chunk, const LevelLaunch& a, hipStream_t s) {
-  if (chunk >= 4) return launch_t<DIR, T, 4>(a, s);
-  if (chunk >= 2) return launch_t<DIR, T, 2>(a, s);
-  return launch_t<DIR, T, 1>(a, s);
-}
-
-
-// Cooperative launch: the runtime places every block at once or fails.
-template <int DIR, typename T, int CH>
-hipError_t launch_job_t(const JobArgs& a, int blocks, hipStream_t s) {
-  void* args[] = {const_cast<JobArgs*>(&a)};
-  const void* f = a.descs ? reinterpret_cast<const void*>(&job_kernel<DIR, T, CH, true>)
-                          : reinterpret_cast<const void*>(&job_kernel<DIR, T, CH, false>);
-  return hipLaunchCooperativeKernel(f, dim3((unsigned)blocks), dim3(kBlock), args, 0, s);
-}
-
-template <int DIR, typename T>
-hipError_t launch_job_ch(int chunk, const JobArgs& a, int blocks, hipStream_t s) {
-  if (chunk >= 4) return launch_job_t<DIR, T, 4>(a, blocks, s);
-  if (chunk >= 2) return launch_job_t<DIR, T, 2>(a, blocks, s);
-  return launch_job_t<DIR, T, 1>(a, blocks, s);
-}
-
-// Resident blocks per CU of the job kernel variant that a launch uses
-// (TABLE: descriptors in device memory); the cooperative launch fails if
-// the grid exceeds what this variant can hold at once.
-template <int DIR, typename T, int CH>
-int occ_job(bool table) {
-  int n = 0;
-  const void* f = table ? reinterpret_cast<const void*>(&job_kernel<DIR, T, CH, true>)
-                        : reinterpret_cast<const void*>(&job_kernel<DIR, T, CH, false>);
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, kBlock, 0) != hipSuccess) n = 0;
-  return n;
-}
-
-template <int CH>
-int occ_job_dir(int dir, int mode, bool table) {
-  if (dir == kFwd) return mode == DWT2_F32 ? occ_job<kFwd, float, CH>(table) : occ_job<kFwd, int, CH>(table);
-  if (dir == kInv) return mode == DWT2_F32 ? occ_job<kInv, float, CH>(table) : occ_job<kInv, int, CH>(table);
-  return occ_job<kBwd, float, CH>(table);
-}
-
 }  // namespace
-
-int launch_job(int dir, int mode, int chunk, const JobArgs& a, int blocks, void* stream) {
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  if (dir == kFwd)
-    return mode == DWT2_F32 ? launch_job_ch<kFwd, float>(chunk, a, blocks, s) : launch_job_ch<kFwd, int>(chunk, a, blocks, s);
-  if (dir == kInv)
-    return mode == DWT2_F32 ? launch_job_ch<kInv, float>(chunk, a, blocks, s) : launch_job_ch<kInv, int>(chunk, a, blocks, s);
-  return launch_job_ch<kBwd, float>(chunk, a, blocks, s);
-}
-
-int job_blocks_per_cu(int dir, int mode, int chunk, bool table) {
-  if (chunk >= 4) return occ_job_dir<4>(dir, mode, table);
-  if (chunk >= 2) return occ_job_dir<2>(dir, mode, table);
-  return occ_job_dir<1>(dir, mode, table);
-}
-
-template <int DIR, typename T>
-hipError_t launch_table_t(int chunk, const TableArgs& a, hipStream_t s) {
-  const dim3 grid((unsigned)((a.items + kWavesPerBlock - 1) / kWavesPerBlock));
-  if (chunk >= 2) hipLaunchKernelGGL((table_kernel<DIR, T, 2>), grid, dim3(kBlock), 0, s, a);
-  else hipLaunchKernelGGL((table_kernel<DIR, T, 1>), grid, dim3(kBlock), 0, s, a);
-  return hipGetLastError();
-}
-
-int launch_table(int dir, int mode, int chunk, const TableArgs& a, void* stream) {
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  if (a.items <= 0) return hipSuccess;
-  if (dir == kFwd)
-    return mode == DWT2_F32 ? launch_table_t<kFwd, float>(chunk, a, s) : launch_table_t<kFwd, int>(chunk, a, s);
-  if (dir == kInv)
-    return mode == DWT2_F32 ? launch_table_t<kInv, float>(chunk, a, s) : launch_table_t<kInv, int>(chunk, a, s);
-  return launch_table_t<kBwd, float>(chunk, a, s);
-}
-
-int launch_tail(int dir, int mode, const TailArgs& a, void* stream) {
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  const dim3 grid((unsigned)(a.tiles_x * a.tiles_y), (unsigned)(a.batch < 65535 ? a.batch : 65535));
-  if (dir == kFwd) {
-    if (mode == DWT2_F32) hipLaunchKernelGGL(tail_fwd<float>, grid, dim3(kTailBlock), 0, s, a);
-    else hipLaunchKernelGGL(tail_fwd<int>, grid, dim3(kTailBlock), 0, s, a);
-  } else if (dir == kInv) {
-    if (mode == DWT2_F32) hipLaunchKernelGGL(tail_inv<float>, grid, dim3(kTailBlock), 0, s, a);
-    else hipLaunchKernelGGL(tail_inv<int>, grid, dim3(kTailBlock), 0, s, a);
-  } else {
-    if (mode != DWT2_F32) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(tail_bwd, grid, dim3(kTailBlock), 0, s, a);
-  }
-  return hipGetLastError();
-}
-
-int lds_tiles(int W, int H, int& tiles_x, int& tiles_y) {
-  tiles_x = (((W + 1) >> 1) + kLdsQX - 1) / kLdsQX;
-  tiles_y = (((H + 1) >> 1) + kLdsQY - 1) / kLdsQY;
-  return (int64_t)tiles_x * tiles_y <= 0x7fffffff;
-}
-
-int launch_lds_level(int scheme, int mode, const SepLevel& a, void* stream) {
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  int tx, ty;
-  if (!lds_tiles(a.W, a.H, tx, ty)) return hipErrorInvalidValue;
-  const dim3 grid((unsigned)(tx * ty), (unsigned)(a.batch < 65535 ? a.batch : 65535));
-  if (scheme == DWT2_SCHEME_ADAPTED) {
-    if (mode != DWT2_F32) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(lds_adapted, grid, dim3(kLdsBlock), 0, s, a, tx);
-  } else if (scheme == DWT2_SCHEME_SEPARABLE) {
-    if (mode == DWT2_F32) hipLaunchKernelGGL((lds_level<float, true>), grid, dim3(kLdsBlock), 0, s, a, tx);
-    else hipLaunchKernelGGL((lds_level<int, true>), grid, dim3(kLdsBlock), 0, s, a, tx);
-  } else {
-    if (mode == DWT2_F32) hipLaunchKernelGGL((lds_level<float, false>), grid, dim3(kLdsBlock), 0, s, a, tx);
-    else hipLaunchKernelGGL((lds_level<int, false>), grid, dim3(kLdsBlock), 0, s, a, tx);
-  }
-  return hipGetLastError();
-}
-
-int launch_zero(uint32_t* p, int64_t n, void* stream) {
-  const int64_t blocks = n < 256 * 256 ? (n + 255) / 256 : 256;
-  hipLaunchKernelGGL(zero_kernel, dim3((unsigned)(blocks > 0 ? blocks : 1)), dim3(256), 0,
-                     static_cast<hipStream_t>(stream), p, n);
-  return hipGetLastError();
-}
-
-int launch_level(int dir, int mode, int chunk, const LevelLaunch& a, void* stream) {
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  if (dir == kFwd) return mode == DWT2_F32 ? launch_ch<kFwd, float>(chunk, a, s) : launch_ch<kFwd, int>(chunk, a, s);
-  if (dir == kInv) return mode == DWT2_F32 ? launch_ch<kInv, float>(chunk, a, s) : launch_ch<kInv, int>(chunk, a, s);
-  return launch_ch<kBwd, float>(chunk, a, s);
-}
-
 }  // namespace dwt2

@@ -1,0 +1,6 @@
+// Per-level strip kernels of the forward (float32 and int32).
+#include "strip_kernels.h"
+
+namespace dwt2 {
+DWT2_INSTANTIATE_LEVEL(kFwd)
+}  // namespace dwt2

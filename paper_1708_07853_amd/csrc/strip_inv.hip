@@ -1,0 +1,6 @@
+// Per-level strip kernels of the inverse (float32 and int32).
+#include "strip_kernels.h"
+
+namespace dwt2 {
+DWT2_INSTANTIATE_LEVEL(kInv)
+}  // namespace dwt2
