@@ -76,7 +76,7 @@ enum {
                               dimension above DWT2_MAX_DIM */
   DWT2_ERR_MODE = -3,      /* unknown mode, or integer mode in dwt2_bwd */
   DWT2_ERR_WORKSPACE = -4, /* workspace smaller than the queried size */
-  DWT2_ERR_ALIAS = -5,     /* src == dst */
+  DWT2_ERR_ALIAS = -5,     /* src, dst and workspace byte ranges overlap */
   DWT2_ERR_HIP = -6,       /* HIP runtime / launch failure (detail in last_error) */
   DWT2_ERR_NOMEM = -7      /* host or plan-cache allocation failed */
 };
@@ -249,8 +249,12 @@ size_t dwt2_batched_workspace_size(const dwt2_image_t* images, int32_t n,
  * and DWT2_TUNE_CACHE names a file that keeps tuning results.
  * Results are bit-identical to n separate dwt2_fwd calls under every
  * policy.  The first call for a new shape set builds the plan (tuning,
- * schedule, graph) and is therefore not capture-safe; later calls only
- * update the descriptor table and launch the graph on `stream`.  Calls
+ * schedule, graph); later calls with the same shapes and workspace only
+ * rewrite the descriptor table in pinned staging memory and launch the
+ * graph on `stream`.  Batched calls are not capture-safe: the graph copies
+ * the staging memory when it runs, and the next eager call rewrites it.
+ * The library keeps at most 16 plans and evicts the least recently used
+ * one; reusing one workspace per shape set avoids rebuilding plans.  Calls
  * sharing a workspace must be stream-ordered. */
 int dwt2_fwd_batched(const dwt2_image_t* images, int32_t n, int32_t levels,
                      int32_t mode, int32_t boundary, void* workspace,
@@ -301,6 +305,27 @@ int dwt2_set_path(int32_t path);
  * 1..DWT2_MAX_LEVELS or a null event. */
 int dwt2_set_probe(int32_t dir, int32_t level, void* ev_begin, void* ev_end);
 
+/* Persistent-launch wait settings, for tests of the failure path: every
+ * later persistent launch (path 1 of dwt2_set_path, and batched plans built
+ * afterwards with the persistent schedule) gives a dependency wait at most
+ * max_polls polls (0 = the default budget, about 2 s), and with
+ * unreachable = 1 every wait asks for one completion more than can happen,
+ * so each one runs out its budget.  A wait that gives up never hangs the
+ * GPU: its work item skips its arithmetic, the launch finishes, and the
+ * library records the failure for the device (see dwt2_synchronize).  Must
+ * not race with running calls.  Returns DWT2_OK, or DWT2_ERR_ARG for
+ * max_polls < 0 or unreachable other than 0 or 1. */
+int dwt2_set_job_wait(int32_t max_polls, int32_t unreachable);
+
+/* Waits for the work on `stream` (a hipStream_t as void*, NULL = the null
+ * stream) and reports failures that surfaced while it ran: DWT2_ERR_HIP if
+ * the synchronisation fails, or if a persistent launch on the current
+ * device gave up a dependency wait since the last report (its results are
+ * then invalid); DWT2_OK otherwise.  Such a give-up is also reported, once,
+ * by the next transform call on the device (dwt2_fwd ... dwt2_bwd_batched),
+ * which then returns DWT2_ERR_HIP without running. */
+int dwt2_synchronize(void* stream);
+
 /* Static description of a status code. */
 const char* dwt2_status_string(int status);
 /* Thread-local detail of the last failing call on this thread ("" if none). */
@@ -308,6 +333,8 @@ const char* dwt2_last_error(void);
 /* Releases every cached batched plan (graphs, device tables, pinned staging).
  * Must not race with dwt2_fwd_batched calls. */
 void dwt2_clear_plan_cache(void);
+/* Number of batched plans currently cached (at most 16). */
+int32_t dwt2_plan_cache_size(void);
 
 #ifdef __cplusplus
 }

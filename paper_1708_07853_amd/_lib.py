@@ -26,7 +26,8 @@ EXPORTS = [
     "dwt2_batched_workspace_size", "dwt2_fwd_batched", "dwt2_inv_batched", "dwt2_bwd_batched",
     "dwt2_status_string", "dwt2_last_error", "dwt2_clear_plan_cache", "dwt2_set_tiling", "dwt2_set_path",
     "dwt2_set_probe", "dwt2_separable_workspace_size", "dwt2_fwd_separable", "dwt2_fwd_lds",
-    "dwt2_fwd_cdf97", "dwt2_inv_cdf97", "dwt2_fwd_cdf97_separable",
+    "dwt2_fwd_cdf97", "dwt2_inv_cdf97", "dwt2_fwd_cdf97_separable", "dwt2_set_job_wait", "dwt2_synchronize",
+    "dwt2_plan_cache_size",
 ]
 
 
@@ -92,6 +93,12 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dwt2_set_probe.restype = ctypes.c_int
     lib.dwt2_clear_plan_cache.argtypes = []
     lib.dwt2_clear_plan_cache.restype = None
+    lib.dwt2_plan_cache_size.argtypes = []
+    lib.dwt2_plan_cache_size.restype = i32
+    lib.dwt2_set_job_wait.argtypes = [i32, i32]
+    lib.dwt2_set_job_wait.restype = ctypes.c_int
+    lib.dwt2_synchronize.argtypes = [vp]
+    lib.dwt2_synchronize.restype = ctypes.c_int
     _lib = lib
     return lib
 

@@ -8,6 +8,7 @@ unit stride along the last (width) axis.
 from __future__ import annotations
 
 import ctypes
+from collections import OrderedDict
 from typing import List, Sequence
 
 import torch
@@ -18,7 +19,7 @@ from ._lib import DWT2_EXT_SYMMETRIC, DWT2_F32, DWT2_I32_REV
 __all__ = ["fwd", "inv", "bwd", "fwd_batched", "inv_batched", "bwd_batched", "DWT2Function", "workspace_size",
            "batched_workspace_size", "level_sizes", "set_tiling", "set_path", "set_probe", "fwd_separable",
            "separable_workspace_size", "fwd_lds", "fwd_cdf97", "inv_cdf97", "fwd_cdf97_separable",
-           "DWT2_F32", "DWT2_I32_REV"]
+           "synchronize", "set_job_wait", "plan_cache_size", "clear_plan_cache", "DWT2_F32", "DWT2_I32_REV"]
 
 
 def level_sizes(w: int, h: int, levels: int):
@@ -219,6 +220,50 @@ def batched_workspace_size(images: Sequence[torch.Tensor], levels: int, mode=Non
     return int(_lib.load().dwt2_batched_workspace_size(arr, len(images), levels, mode))
 
 
+# Workspaces of batched calls made without one, one per (device, shape set,
+# levels, mode), at most _WS_CACHE_MAX of them: the library caches a plan
+# per shape set and workspace address, so a stable workspace lets repeated
+# calls replay their plan instead of building a new one.
+_WS_CACHE_MAX = 4
+_ws_cache: "OrderedDict[tuple, torch.Tensor]" = OrderedDict()
+
+
+def _batched_workspace(images: Sequence[torch.Tensor], levels: int, mode: int, nbytes: int) -> torch.Tensor:
+    dev = images[0].device
+    key = (str(dev), levels, mode, tuple(tuple(t.shape) for t in images))
+    ws = _ws_cache.get(key)
+    if ws is None or ws.numel() < nbytes:
+        ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
+        _ws_cache[key] = ws
+        while len(_ws_cache) > _WS_CACHE_MAX:
+            _ws_cache.popitem(last=False)
+    _ws_cache.move_to_end(key)
+    return ws
+
+
+def synchronize() -> None:
+    """Wait for the current stream and raise if a persistent launch on this
+    device gave up a dependency wait (see dwt2_synchronize)."""
+    _lib.check(_lib.load().dwt2_synchronize(_stream()))
+
+
+def set_job_wait(max_polls: int = 0, unreachable: bool = False) -> None:
+    """Poll budget of the persistent launches' dependency waits, for tests of
+    the failure path (see dwt2_set_job_wait); (0, False) restores the default."""
+    _lib.check(_lib.load().dwt2_set_job_wait(max_polls, 1 if unreachable else 0))
+
+
+def plan_cache_size() -> int:
+    """Number of batched plans the library holds (at most 16)."""
+    return int(_lib.load().dwt2_plan_cache_size())
+
+
+def clear_plan_cache() -> None:
+    """Release every batched plan, and the workspaces kept for them here."""
+    _ws_cache.clear()
+    _lib.load().dwt2_clear_plan_cache()
+
+
 def _batched(name: str, images: Sequence[torch.Tensor], levels: int, mode, outs, workspace) -> List[torch.Tensor]:
     lib = _lib.load()
     if not images:
@@ -234,7 +279,7 @@ def _batched(name: str, images: Sequence[torch.Tensor], levels: int, mode, outs,
     n = len(images)
     nbytes = int(lib.dwt2_batched_workspace_size(arr, n, levels, mode))
     if workspace is None:
-        ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=images[0].device)
+        ws = _batched_workspace(images, levels, mode, nbytes)
     else:
         if workspace.device != images[0].device or workspace.numel() * workspace.element_size() < nbytes:
             raise ValueError(f"workspace must be a tensor of at least {nbytes} bytes on {images[0].device}")
@@ -250,7 +295,7 @@ def fwd_batched(images: Sequence[torch.Tensor], levels: int, mode=None,
                 workspace: torch.Tensor | None = None) -> List[torch.Tensor]:
     """Forward transform of a ragged list of 2-D images in one batched call
     (see dwt2_fwd_batched).  Plans are cached per image geometry and
-    workspace address: pass the same `workspace` on repeated calls."""
+    workspace address; without a `workspace`, one is kept per shape set."""
     return _batched("dwt2_fwd_batched", images, levels, mode, outs, workspace)
 
 

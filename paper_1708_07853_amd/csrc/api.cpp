@@ -109,6 +109,58 @@ static int device_cus() {
 // `slots_hint` and keeps one round of items for it, each a whole number of
 // chunk pairs.
 static std::atomic<int> g_forced_seg{-1}, g_forced_ch{-1}, g_persistent{-1};
+
+// Wait settings of the persistent job (dwt2_set_job_wait).
+static std::atomic<uint32_t> g_max_polls{0}, g_unreachable{0};
+void job_wait_settings(uint32_t& max_polls, uint32_t& unreachable) {
+  max_polls = g_max_polls.load();
+  unreachable = g_unreachable.load();
+}
+
+// One pinned host word per device that a persistent launch sets when one of
+// its waits gives up.  It is allocated on first use and kept for the
+// process's lifetime (no exit-time HIP calls); the host reads it with plain
+// loads, because the kernel's store to it is a system-scope store.
+static std::mutex g_err_mu;
+static uint32_t* g_err_host[64];
+static uint32_t* g_err_dev[64];
+
+uint32_t* host_error_word() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  std::lock_guard<std::mutex> lock(g_err_mu);
+  if (!g_err_host[dev]) {
+    void* h = nullptr;
+    void* d = nullptr;
+    if (hipHostMalloc(&h, 256, hipHostMallocDefault) != hipSuccess || !h) return nullptr;
+    if (hipHostGetDevicePointer(&d, h, 0) != hipSuccess || !d) {
+      (void)hipHostFree(h);
+      return nullptr;
+    }
+    *static_cast<volatile uint32_t*>(h) = 0;
+    g_err_host[dev] = static_cast<uint32_t*>(h);
+    g_err_dev[dev] = static_cast<uint32_t*>(d);
+  }
+  return g_err_dev[dev];
+}
+
+// Reports (once) a give-up that a persistent launch on the current device
+// recorded since the last report.
+static int take_async_error() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return DWT2_OK;
+  uint32_t* h;
+  {
+    std::lock_guard<std::mutex> lock(g_err_mu);
+    h = g_err_host[dev];
+  }
+  if (!h || *static_cast<volatile uint32_t*>(h) == 0) return DWT2_OK;
+  *static_cast<volatile uint32_t*>(h) = 0;
+  return fail(DWT2_ERR_HIP,
+              "a persistent launch on device %d gave up waiting for rows it depends on; the results of that "
+              "call are invalid", dev);
+}
+int report_async_error() { return take_async_error(); }
 constexpr int kLevelWavesPerCU = 8;
 
 static int pow2_ceil(int v) {
@@ -359,6 +411,8 @@ int run_job(int dir, const Call& c, const Geo& g, void* stream) {
   args.ndesc = g.L;
   args.total_items = items;
   args.sync = reinterpret_cast<uint32_t*>(c.ws);
+  args.host_err = host_error_word();
+  job_wait_settings(args.max_polls, args.unreachable);
   int err = launch_zero(args.sync, kSyncCounters + (int64_t)kCounterStride * counters, stream);
   if (err == hipSuccess) {
     const int64_t want = (items + kWavesPerBlock - 1) / kWavesPerBlock;
@@ -529,6 +583,7 @@ static int transform(int dir, const void* src, int64_t src_stride, int64_t src_b
                      int variant = kProduct) {
   const bool separable = variant == kSepPasses;
   clear_error();
+  if (int st = take_async_error()) return st;
   if (!src || !dst) return fail(DWT2_ERR_ARG, "null src or dst");
   if (((uintptr_t)src | (uintptr_t)dst | (uintptr_t)workspace) & 3)
     return fail(DWT2_ERR_ARG, "src, dst and workspace must be 4-byte aligned");
@@ -548,11 +603,15 @@ static int transform(int dir, const void* src, int64_t src_stride, int64_t src_b
     return fail(DWT2_ERR_MODE, "the CDF 9/7 transform exists for DWT2_F32 only");
   if (variant == kLdsAdapted && mode != DWT2_F32)
     return fail(DWT2_ERR_MODE, "the adapted scheme exists for DWT2_F32 only");
-  if (src == dst) return fail(DWT2_ERR_ALIAS, "src and dst are the same buffer; the transform is out of place");
   const size_t need =
       sync_bytes(g, batch) + (ws_per_image(g) + (separable ? sep_work_per_image(g) : 0)) * (size_t)batch;
+  const Span ss = image_span(src, src_stride, src_bs, width, height, batch);
+  const Span ds = image_span(dst, dst_stride, dst_bs, width, height, batch);
+  if (overlap(ss, ds)) return fail(DWT2_ERR_ALIAS, "src and dst overlap; the transform is out of place");
   if (!workspace || workspace_bytes < need)
     return fail(DWT2_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, workspace ? workspace_bytes : 0);
+  const Span ws{reinterpret_cast<uintptr_t>(workspace), reinterpret_cast<uintptr_t>(workspace) + need};
+  if (overlap(ws, ss) || overlap(ws, ds)) return fail(DWT2_ERR_ALIAS, "the workspace overlaps src or dst");
   Call c{static_cast<const char*>(src), src_stride, src_bs, static_cast<char*>(dst), dst_stride, dst_bs, batch, mode,
          static_cast<char*>(workspace), sync_bytes(g, batch)};
   if (separable) return run_separable(c, g, stream);
@@ -687,6 +746,22 @@ int dwt2_set_path(int32_t path) {
   if (path < 0 || path > 2) return fail(DWT2_ERR_ARG, "path must be 0, 1 or 2");
   g_persistent.store(path);
   return DWT2_OK;
+}
+
+int dwt2_set_job_wait(int32_t max_polls, int32_t unreachable) {
+  clear_error();
+  if (max_polls < 0 || (unreachable != 0 && unreachable != 1))
+    return fail(DWT2_ERR_ARG, "max_polls must be >= 0 and unreachable 0 or 1");
+  g_max_polls.store((uint32_t)max_polls);
+  g_unreachable.store((uint32_t)unreachable);
+  return DWT2_OK;
+}
+
+int dwt2_synchronize(void* stream) {
+  clear_error();
+  const hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return fail(DWT2_ERR_HIP, "stream synchronisation failed: %s", hipGetErrorString(e));
+  return take_async_error();
 }
 
 int dwt2_set_tiling(int32_t seg, int32_t chunk) {

@@ -1,6 +1,6 @@
 // dwt2_fwd_batched: a ragged list of images in one persistent launch.
 //
-// Plan (cached per shape set and workspace): every (level, image) becomes one
+// Plan (cached per shape set and workspace, at most 16): every (level, image) becomes one
 // step of a persistent job; the queue holds level 1 of all images (largest
 // first), then level 2, and so on, so an image's next level starts as soon
 // as the rows it reads exist while other images are still at the previous
@@ -54,7 +54,47 @@ int validate_images(const dwt2_image_t* images, int32_t n, int32_t levels, int32
       const std::string why = dwt2_last_error();
       return fail(st, "image %d: %s", i, why.c_str());
     }
-    if (pointers && im.src == im.dst) return fail(DWT2_ERR_ALIAS, "image %d: src == dst", i);
+  }
+  return DWT2_OK;
+}
+
+// Every output range must be disjoint from every other output, every input
+// and the workspace (inputs may overlap each other: they are only read).
+int check_aliasing(const dwt2_image_t* images, int32_t n, const void* workspace, size_t ws_bytes) {
+  struct Out {
+    Span s;
+    int img;  // -1: the workspace
+  };
+  std::vector<Out> outs;
+  outs.reserve(n + 1);
+  for (int i = 0; i < n; ++i) {
+    const dwt2_image_t& im = images[i];
+    outs.push_back({image_span(im.dst, im.dst_stride, 0, im.width, im.height, 1), i});
+  }
+  const uintptr_t w0 = reinterpret_cast<uintptr_t>(workspace);
+  outs.push_back({Span{w0, w0 + ws_bytes}, -1});
+  std::sort(outs.begin(), outs.end(), [](const Out& a, const Out& b) { return a.s.lo < b.s.lo; });
+  auto name = [](int i, char* buf, size_t len) {
+    if (i < 0) snprintf(buf, len, "the workspace");
+    else snprintf(buf, len, "image %d's dst", i);
+  };
+  char b1[48], b2[48];
+  for (size_t k = 1; k < outs.size(); ++k)
+    if (overlap(outs[k - 1].s, outs[k].s)) {
+      name(outs[k - 1].img, b1, sizeof b1);
+      name(outs[k].img, b2, sizeof b2);
+      return fail(DWT2_ERR_ALIAS, "%s overlaps %s", b1, b2);
+    }
+  // the outputs are disjoint and sorted, so their ends are sorted too: the
+  // first output ending past an input's start is the only candidate
+  for (int i = 0; i < n; ++i) {
+    const dwt2_image_t& im = images[i];
+    const Span in = image_span(im.src, im.src_stride, 0, im.width, im.height, 1);
+    auto it = std::upper_bound(outs.begin(), outs.end(), in.lo, [](uintptr_t v, const Out& o) { return v < o.s.hi; });
+    if (it != outs.end() && overlap(it->s, in)) {
+      name(it->img, b1, sizeof b1);
+      return fail(DWT2_ERR_ALIAS, "image %d's src overlaps %s", i, b1);
+    }
   }
   return DWT2_OK;
 }
@@ -133,10 +173,32 @@ struct Plan {
   }
 };
 
+// The plan cache and the tuning results live for the whole process and are
+// never destroyed at exit (no HIP calls from static destructors, which
+// would run after the runtime has gone); dwt2_clear_plan_cache and the LRU
+// eviction below release plans explicitly.  At most kMaxPlans plans are
+// kept: a plan holds a graph and pinned staging, and callers that pass a new
+// workspace each time would otherwise add one per call.
+constexpr size_t kMaxPlans = 16;
+struct CachedPlan {
+  std::unique_ptr<Plan> plan;
+  uint64_t last_use = 0;
+};
 std::mutex g_mu;
-std::map<std::string, std::unique_ptr<Plan>> g_plans;
-std::map<std::string, int> g_tuned;  // shape set -> policy code (kind * kPolicyKind + base)
+std::map<std::string, CachedPlan>& g_plans = *new std::map<std::string, CachedPlan>;
+std::map<std::string, int>& g_tuned = *new std::map<std::string, int>;  // shape set -> policy code
+uint64_t g_use_clock = 0;
 bool g_tune_loaded = false;
+
+// A policy is usable if its schedule is one of the two and its level-1
+// segment height lies in [kMinSeg, kMaxSeg]; anything else (a stale or
+// edited tuning file, an out-of-range environment override) is ignored.
+constexpr int kMaxSeg = 4096;
+bool valid_policy(int policy) {
+  if (policy < 0) return false;
+  const int kind = policy / kPolicyKind, base = policy % kPolicyKind;
+  return (kind == kChained || kind == kLevelSync) && base >= kMinSeg && base <= kMaxSeg;
+}
 
 std::string shape_key(int dir, const dwt2_image_t* images, int n, int levels, int mode) {
   std::string k;
@@ -167,7 +229,8 @@ void load_tune_cache() {
   if (!f) return;
   char key[64];
   int base;
-  while (fscanf(f, "%63s %d", key, &base) == 2) g_tuned[key] = base;
+  while (fscanf(f, "%63s %d", key, &base) == 2)
+    if (valid_policy(base)) g_tuned[key] = base;
   fclose(f);
 }
 
@@ -236,7 +299,7 @@ void fill_descs(Plan& p, const dwt2_image_t* images, JobDesc* out) {
       jd.items = d.nsegs * d.nstrips;
       jd.cbase = cbase;
       jd.prev = t > 0 ? (t - 1) * p.n + oi : -1;
-      jd.coh = p.kind == kChained ? ((t > 0 ? 1 : 0) | (t + 1 < p.levels ? 2 : 0)) : 0;
+      jd.coh = p.kind != kLevelSync ? ((t > 0 ? 1 : 0) | (t + 1 < p.levels ? 2 : 0)) : 0;
       d.keep_out = p.kind == kLevelSync && t + 1 < p.levels && p.step_ll_bytes[t] <= kKeepBytes;
       start += jd.items;
       cbase += d.nsegs;
@@ -252,6 +315,8 @@ JobArgs job_args(const Plan& p) {
   a.sync = reinterpret_cast<uint32_t*>(p.ws + p.lay.sync);
   a.ndesc = p.ndesc;
   a.total_items = p.total_items;
+  a.host_err = host_error_word();
+  job_wait_settings(a.max_polls, a.unreachable);
   return a;
 }
 
@@ -313,7 +378,10 @@ int autotune(Plan& p, const dwt2_image_t* images, hipStream_t s, const std::stri
   const int forced_kind = fk ? atoi(fk) : -1;
   const int forced_seg = fs ? atoi(fs) : 0;
   if (forced_kind == kChained || forced_kind == kLevelSync) {
-    build_schedule(p, forced_kind * kPolicyKind + (forced_seg > 0 ? forced_seg : 32));
+    const int policy = forced_kind * kPolicyKind + (forced_seg > 0 ? forced_seg : 32);
+    if (!valid_policy(policy))
+      return fail(DWT2_ERR_ARG, "DWT2_BATCH_SEG must lie in [%d, %d] (got %d)", kMinSeg, kMaxSeg, forced_seg);
+    build_schedule(p, policy);
     return DWT2_OK;
   }
   auto it = g_tuned.find(hk);
@@ -360,6 +428,8 @@ int autotune(Plan& p, const dwt2_image_t* images, hipStream_t s, const std::stri
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  // a persistent candidate that gave up a wait invalidates the tuning run
+  if (int e = report_async_error()) return e;
   build_schedule(p, best_policy);
   g_tuned[hk] = best_policy;
   save_tune(hk, best_policy);
@@ -426,6 +496,7 @@ int build_plan(Plan& p, int dir, const dwt2_image_t* images, int n, int levels, 
 static int batched(int dir, const dwt2_image_t* images, int32_t n, int32_t levels, int32_t mode, int32_t boundary,
                    void* workspace, size_t workspace_bytes, void* stream) {
   clear_error();
+  if (int e = report_async_error()) return e;
   if (boundary != DWT2_EXT_SYMMETRIC) return fail(DWT2_ERR_ARG, "unknown boundary %d", boundary);
   std::vector<Geo> geos;
   int st = validate_images(images, n, levels, mode, geos);
@@ -434,6 +505,8 @@ static int batched(int dir, const dwt2_image_t* images, int32_t n, int32_t level
   const size_t total = layout(geos).total;
   if (!workspace || workspace_bytes < total)
     return fail(DWT2_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", total, workspace ? workspace_bytes : 0);
+  st = check_aliasing(images, n, workspace, total);
+  if (st) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return fail(DWT2_ERR_HIP, "no current device");
@@ -445,12 +518,20 @@ static int batched(int dir, const dwt2_image_t* images, int32_t n, int32_t level
   std::lock_guard<std::mutex> lock(g_mu);
   auto it = g_plans.find(plan_key);
   if (it == g_plans.end()) {
+    if (g_plans.size() >= kMaxPlans) {  // evict the least recently used plan
+      auto lru = g_plans.begin();
+      for (auto j = g_plans.begin(); j != g_plans.end(); ++j)
+        if (j->second.last_use < lru->second.last_use) lru = j;
+      if (lru->second.plan->pending) (void)hipEventSynchronize(lru->second.plan->done);
+      g_plans.erase(lru);
+    }
     std::unique_ptr<Plan> p(new Plan);
     st = build_plan(*p, dir, images, n, levels, mode, std::move(geos), static_cast<char*>(workspace), s, key);
     if (st) return st;
-    it = g_plans.emplace(plan_key, std::move(p)).first;
+    it = g_plans.emplace(plan_key, CachedPlan{std::move(p), 0}).first;
   }
-  Plan& p = *it->second;
+  it->second.last_use = ++g_use_clock;
+  Plan& p = *it->second.plan;
   // the previous call of this plan must have consumed the staging buffer
   if (p.pending && hipEventSynchronize(p.done) != hipSuccess) return fail(DWT2_ERR_HIP, "event wait failed");
   write_staging(p, images);
@@ -486,10 +567,15 @@ int dwt2_bwd_batched(const dwt2_image_t* images, int32_t n, int32_t levels, int3
   return batched(kBwd, images, n, levels, mode, boundary, workspace, workspace_bytes, stream);
 }
 
+int32_t dwt2_plan_cache_size(void) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  return (int32_t)g_plans.size();
+}
+
 void dwt2_clear_plan_cache(void) {
   std::lock_guard<std::mutex> lock(g_mu);
   for (auto& kv : g_plans)
-    if (kv.second->pending) (void)hipEventSynchronize(kv.second->done);
+    if (kv.second.plan->pending) (void)hipEventSynchronize(kv.second.plan->done);
   g_plans.clear();
 }
 

@@ -95,11 +95,18 @@ struct JobArgs {
   const JobDesc* descs;       // device table, or null: use inl[]
   const uint32_t* item_desc;  // device queue-slot -> desc table, or null: scan
   uint32_t* sync;             // zeroed before every launch
+  uint32_t* host_err;         // pinned host word set when a wait gives up (may be null)
   int32_t ndesc;
   int32_t total_items;
-  int32_t pad_[2];
+  uint32_t max_polls;         // poll budget of one wait (0: kSpinLimit, about 2 s)
+  uint32_t unreachable;       // test setting: every wait runs out its budget
   JobDesc inl[kInlineDescs];
 };
+
+// Wait settings of later persistent launches (dwt2_set_job_wait) and the
+// device's host-visible error word (api.cpp).
+void job_wait_settings(uint32_t& max_polls, uint32_t& unreachable);
+uint32_t* host_error_word();  // device pointer of the current device's word, or null
 
 // One level-synchronous launch over items [item_begin, item_begin + items)
 // of a ragged batch's item table.

@@ -28,6 +28,17 @@ struct Call {
 };
 
 int fail(int code, const char* fmt, ...);
+// Byte range [lo, hi) from the first to one past the last element of a
+// (batch of) w x h images of 4-byte samples; the alias checks compare these.
+struct Span {
+  uintptr_t lo, hi;
+};
+inline Span image_span(const void* p, int64_t stride, int64_t bstride, int w, int h, int batch) {
+  const uintptr_t lo = reinterpret_cast<uintptr_t>(p);
+  const int64_t last = (int64_t)(batch - 1) * bstride + (int64_t)(h - 1) * stride + w;
+  return Span{lo, lo + (uintptr_t)last * 4u};
+}
+inline bool overlap(const Span& a, const Span& b) { return a.lo < b.hi && b.lo < a.hi; }
 void clear_error();
 int check_geometry(int32_t width, int32_t height, int32_t levels, Geo& g);
 size_t round256(size_t b);
@@ -44,5 +55,7 @@ void level_pointers(int dir, const Call& c, const Geo& g, int k, LevelDesc& d, i
                     int64_t& band_bs);
 int run_levels(int dir, const Call& c, const Geo& g, void* stream, bool tail);
 int run_job(int dir, const Call& c, const Geo& g, void* stream);
+// DWT2_ERR_HIP (once) if a persistent launch gave up a wait since the last report.
+int report_async_error();
 
 }  // namespace dwt2

@@ -35,43 +35,57 @@ __global__ __launch_bounds__(kBlock) void level_kernel(LevelLaunch a) {
 // levels overlap instead of meeting at a grid-wide barrier.  An item waits
 // only for items with smaller numbers, each owned by a running wave that
 // reaches it after finishing its own smaller items, so the schedule cannot
-// deadlock; a wait that exceeds a fixed poll budget sets the error word and
-// gives up rather than hang.
+// deadlock.  A wait that exceeds its poll budget gives up rather than hang:
+// it sets the error word in the workspace and the library's host-visible
+// error word (pinned host memory, read by the next library call on the
+// host), and the item skips its arithmetic -- its inputs may not exist -- but
+// still publishes its counter so that its dependants do not wait in turn.
 // ---------------------------------------------------------------------------
 // s_sleep(16) pauses about 16 * 64 clocks (~0.43 us at 2.4 GHz); a poll
 // backs off to at most kNapCap of them (~1.7 us), so a waiter sees a finished
-// producer within about that time, and gives up after kSpinLimit polls (~2 s).
+// producer within about that time, and gives up after kSpinLimit polls (~2 s)
+// unless the launch sets a smaller budget.
 constexpr uint32_t kNapCap = 4;
 constexpr uint32_t kSpinLimit = 1u << 20;
 
-// Wait until rows [r_lo, r_hi] of the output of step p (image img) exist.
-// `pixels`: the rows are pixel rows of p's output (inverse / adjoint, two per
-// quadruple row); otherwise they are p's LL rows (forward, one per row).
-__device__ __forceinline__ void wait_rows(const JobDesc& p, uint32_t* sync, int img, int r_lo, int r_hi,
+// Wait until rows [r_lo, r_hi] of the output of step p (image img) exist;
+// false if the wait gave up.  `pixels`: the rows are pixel rows of p's output
+// (inverse / adjoint, two per quadruple row); otherwise they are p's LL rows
+// (forward, one per row).  `unreachable` (a test setting) asks for one
+// completion more than a segment has, so every wait runs out its budget.
+__device__ __forceinline__ bool wait_rows(const JobDesc& p, const JobArgs& a, int img, int r_lo, int r_hi,
                                           bool pixels) {
   const int ns_h = (p.d.H + 1) >> 1;
   int q_lo = pixels ? (r_lo >> 1) : r_lo, q_hi = pixels ? (r_hi >> 1) : r_hi;
   q_lo = q_lo < 0 ? 0 : q_lo;
   q_hi = q_hi > ns_h - 1 ? ns_h - 1 : q_hi;
   const int g_lo = q_lo / p.d.seg, g_hi = q_hi / p.d.seg;
-  uint32_t* ctr = sync + kSyncCounters + (int64_t)kCounterStride * (p.cbase + img * p.d.nsegs);
-  for (int g = g_lo; g <= g_hi; ++g) {
+  uint32_t* ctr = a.sync + kSyncCounters + (int64_t)kCounterStride * (p.cbase + img * p.d.nsegs);
+  const uint32_t limit = a.max_polls ? a.max_polls : kSpinLimit;
+  const uint32_t need = (uint32_t)p.d.nstrips + (a.unreachable ? 1u : 0u);
+  bool ok = true;
+  for (int g = g_lo; g <= g_hi && ok; ++g) {
     uint32_t spins = 0, nap = 1;
     // every lane reads the same word; readfirstlane makes the loop wave-uniform
     while (__builtin_amdgcn_readfirstlane(__hip_atomic_load(ctr + (int64_t)kCounterStride * g, __ATOMIC_RELAXED,
-                                                            __HIP_MEMORY_SCOPE_AGENT)) < (uint32_t)p.d.nstrips) {
-      if (++spins > kSpinLimit) {
-        __hip_atomic_store(sync + kSyncError, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                                                            __HIP_MEMORY_SCOPE_AGENT)) < need) {
+      if (++spins > limit) {
+        ok = false;
         break;
       }
       for (uint32_t k = 0; k < nap; ++k) __builtin_amdgcn_s_sleep(16);
       nap = nap < kNapCap ? 2 * nap : kNapCap;
     }
   }
+  if (!ok) {
+    __hip_atomic_store(a.sync + kSyncError, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (a.host_err) __hip_atomic_store(a.host_err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
   // the item's loads of the producers' rows are coherent (sc0 sc1) and are
   // issued only after the counters were seen; the fence keeps the compiler
   // from moving them above the wait
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  return ok;
 }
 
 // TABLE: descriptors and the slot -> descriptor map live in device memory
@@ -101,17 +115,19 @@ __global__ __launch_bounds__(kBlock) void job_kernel(JobArgs a) {
     const int rem = item - img * per_img;
     const int seg = rem / jd.d.nstrips;
     const int strip = rem - seg * jd.d.nstrips;
+    bool ready = true;
     if (jd.prev >= 0) {
       const JobDesc p = D[jd.prev];
       const int I0 = seg * jd.d.seg;
       const int I1 = min(I0 + jd.d.seg, (jd.d.H + 1) >> 1);
       // rows this item reads from p's output, with a margin that covers the
       // symmetric folds at the image edges
-      if (DIR == kFwd) wait_rows(p, sync, img, 2 * I0 - 4, 2 * I1 + 2, false);
-      else wait_rows(p, sync, img, I0 - 3, I1 + 2, true);
+      if (DIR == kFwd) ready = wait_rows(p, a, img, 2 * I0 - 4, 2 * I1 + 2, false);
+      else ready = wait_rows(p, a, img, I0 - 3, I1 + 2, true);
     }
-    run_item<DIR, T, CH, true>(jd.d, jd.coh, img * jd.pix_bstride, img * jd.ll_bstride, img * jd.band_bstride, strip,
-                               seg, lane);
+    if (ready)
+      run_item<DIR, T, CH, true>(jd.d, jd.coh, img * jd.pix_bstride, img * jd.ll_bstride, img * jd.band_bstride,
+                                 strip, seg, lane);
     // publish: the item's stores write through (sc1); once they have
     // completed (s_waitcnt 0) the count makes them visible to every XCD
     __builtin_amdgcn_s_waitcnt(0);

@@ -204,3 +204,68 @@ def test_set_tiling_validation(lib):
     assert lib.dwt2_set_tiling(-1, 0) == -1
     assert lib.dwt2_set_tiling(8, 3) == -1
     assert lib.dwt2_set_tiling(0, 0) == 0
+
+
+# Byte ranges from the first to one past the last element: a 64 x 64 float
+# image with stride 64 spans 16 KiB.
+SPAN = 64 * 64 * 4
+ALIAS = [
+    dict(dst=FAKE_A + 4 * 64 * 10),                 # dst starts inside src
+    dict(src=FAKE_B + SPAN - 4),                    # src's first element is dst's last
+    dict(dst=FAKE_A - SPAN + 4),                    # dst's last element is src's first
+    dict(ws=FAKE_A + 64),                           # workspace inside src
+    dict(ws=FAKE_B - 256),                          # workspace runs into dst
+    dict(batch=2, sb=64 * 64, db=64 * 64, dst=FAKE_A + 2 * SPAN - 4),  # second image of src meets dst
+]
+
+
+@pytest.mark.parametrize("fn", ["dwt2_fwd", "dwt2_inv", "dwt2_bwd", "dwt2_fwd_separable", "dwt2_fwd_cdf97"])
+@pytest.mark.parametrize("kw", ALIAS, ids=[str(k) for k in ALIAS])
+def test_overlapping_ranges_are_rejected(lib, fn, kw):
+    assert call(lib, fn, **kw) == -5
+    assert "overlap" in lib.dwt2_last_error().decode()
+
+
+def test_adjacent_ranges_pass_validation(lib):
+    # touching but not overlapping ranges pass every check; with no GPU the
+    # call then fails at the first HIP call, not in validation
+    st = call(lib, "dwt2_fwd", dst=FAKE_A + SPAN)
+    assert st in (0, -6)
+    assert "overlap" not in lib.dwt2_last_error().decode()
+
+
+@pytest.mark.parametrize("fn", ["dwt2_fwd_batched", "dwt2_inv_batched", "dwt2_bwd_batched"])
+def test_batched_overlapping_ranges_are_rejected(lib, fn):
+    call_b = getattr(lib, fn)
+    imgs = _images([(64, 64, 64), (64, 64, 64)])
+    imgs[1].dst = imgs[0].dst + 4 * 64 * 63            # two outputs overlap
+    assert call_b(imgs, 2, 2, 0, 0, FAKE_WS, 1 << 30, None) == -5
+    assert "overlaps" in lib.dwt2_last_error().decode()
+    imgs = _images([(64, 64, 64), (64, 64, 64)])
+    imgs[1].src = imgs[0].dst + 4                      # an input overlaps another image's output
+    assert call_b(imgs, 2, 2, 0, 0, FAKE_WS, 1 << 30, None) == -5
+    assert "image 1's src" in lib.dwt2_last_error().decode()
+    imgs = _images([(64, 64, 64), (64, 64, 64)])
+    ws = imgs[1].dst - 64                              # the workspace runs into an output
+    assert call_b(imgs, 2, 2, 0, 0, ws, 1 << 30, None) == -5
+    assert "workspace" in lib.dwt2_last_error().decode()
+    imgs = _images([(64, 64, 64), (64, 64, 64)])
+    imgs[0].src = imgs[0].dst                          # an image's own input and output
+    assert call_b(imgs, 2, 2, 0, 0, FAKE_WS, 1 << 30, None) == -5
+    # inputs may overlap each other: they are only read
+    imgs = _images([(64, 64, 64), (64, 64, 64)])
+    imgs[1].src = imgs[0].src
+    assert call_b(imgs, 2, 2, 0, 0, FAKE_WS, 1 << 30, None) in (0, -6)
+    assert "overlap" not in lib.dwt2_last_error().decode()
+
+
+def test_set_job_wait_validation(lib):
+    assert lib.dwt2_set_job_wait(-1, 0) == -1
+    assert lib.dwt2_set_job_wait(8, 2) == -1
+    assert lib.dwt2_set_job_wait(8, 1) == 0
+    assert lib.dwt2_set_job_wait(0, 0) == 0
+
+
+def test_plan_cache_starts_empty_and_clears(lib):
+    lib.dwt2_clear_plan_cache()
+    assert lib.dwt2_plan_cache_size() == 0
