@@ -96,6 +96,36 @@ def test_perfect_reconstruction(h, w, levels):
     assert np.abs(dwt97.inv(c, levels) - x).max() < 1e-9
 
 
+def _dense97(n):
+    """n x n analysis matrix, rows [s; d], from the published taps applied to
+    the reflect-padded unit impulses (no lifting involved)."""
+    eye = np.eye(n)
+    return np.array([_conv_reference(eye[j]) for j in range(n)]).T
+
+
+def _dense97_multilevel(x, levels):
+    """Dyadic recursion on the LL corner (Mallat), each level the tensor
+    product A_h X A_w^T of the dense matrices: the rows [s; d] of A put the
+    quadrants in Mallat order."""
+    out = np.array(x, dtype=np.float64)
+    h, w = out.shape
+    for _ in range(levels):
+        out[:h, :w] = _dense97(h) @ out[:h, :w] @ _dense97(w).T
+        h, w = (h + 1) // 2, (w + 1) // 2
+    return out
+
+
+@pytest.mark.parametrize("h,w,levels", [(16, 16, 3), (37, 29, 3), (64, 65, 5), (9, 130, 3), (2, 2, 1),
+                                        (5, 3, 2), (130, 40, 6)])
+def test_multilevel_equals_recursive_dense(h, w, levels):
+    """The oracle's multi-level forward equals the recursive dense form built
+    from the published taps, at every level; its inverse undoes it."""
+    x = np.random.default_rng(h * 31 + w).uniform(0, 255, (h, w))
+    want = _dense97_multilevel(x, levels)
+    assert np.allclose(dwt97.fwd(x, levels), want, atol=1e-8, rtol=0)
+    assert np.allclose(dwt97.inv(want, levels), x, atol=1e-8, rtol=0)
+
+
 @pytest.mark.parametrize("h,w", [(2, 2), (7, 12), (33, 65), (64, 31)])
 def test_2d_level_is_the_tensor_product(h, w):
     rng = np.random.default_rng(h + 7 * w)

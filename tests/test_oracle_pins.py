@@ -123,6 +123,28 @@ def test_hand_derived_golden(case):
     assert len(GOLDEN) >= 7
 
 
+@pytest.mark.parametrize("case", [c for c in GOLDEN if c["kind"] == "1d"], ids=lambda c: c["case"])
+def test_inv_1d_rebuilds_hand_derived_inputs(case):
+    """inv_1d applied to the hand-derived coefficients gives back the hand
+    example's input, in both modes (an inverse that undid the steps in the
+    wrong order, or with a wrong sign, would not)."""
+    x = _parse(case["input"])[0]
+    got = oracle.inv_1d(_parse(case["f64_s"])[0], _parse(case["f64_d"])[0], FLOAT)
+    np.testing.assert_array_equal(got, x)
+    got = oracle.inv_1d(_parse(case["int_s"])[0].astype(np.int64), _parse(case["int_d"])[0].astype(np.int64), INT)
+    np.testing.assert_array_equal(got, x.astype(np.int64))
+
+
+@pytest.mark.parametrize("n", range(2, 34))
+def test_inv_1d_equals_dense_inverse(n):
+    """inv_1d is the inverse of the dense convolution matrix built from the
+    taps (not of the oracle's own forward)."""
+    c = np.random.default_rng(500 + n).normal(size=n) * 30
+    ns = (n + 1) // 2
+    want = np.linalg.solve(dense_1d(n), c)
+    np.testing.assert_allclose(oracle.inv_1d(c[:ns], c[ns:], FLOAT), want, atol=1e-9, rtol=0)
+
+
 # ---------------------------------------------------------------- integer mode
 
 def _int_predict_rows(x):
