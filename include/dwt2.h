@@ -298,9 +298,9 @@ int dwt2_set_path(int32_t path);
  * level `level` (1 = finest) and ev_end just after it, so hipEventElapsedTime
  * of the pair is that one kernel's duration.  ev_begin / ev_end are
  * hipEvent_t handles owned by the caller, created on the device of the
- * calls.  Levels that share the fused tail launch record around that
- * launch; the persistent path has no per-level launches and records
- * nothing.  dir < 0 clears the probe.  Must not race with running calls.
+ * calls.  A probe on any level of a launch that covers several levels
+ * (see dwt2_launch_levels) records around that launch; the persistent path
+ * has no per-level launches and records nothing.  dir < 0 clears the probe.  Must not race with running calls.
  * Returns DWT2_OK, or DWT2_ERR_ARG for a dir above 2, a level outside
  * 1..DWT2_MAX_LEVELS or a null event. */
 int dwt2_set_probe(int32_t dir, int32_t level, void* ev_begin, void* ev_end);
@@ -325,6 +325,17 @@ int dwt2_set_job_wait(int32_t max_polls, int32_t unreachable);
  * by the next transform call on the device (dwt2_fwd ... dwt2_bwd_batched),
  * which then returns DWT2_ERR_HIP without running. */
 int dwt2_synchronize(void* stream);
+
+/* Measurement aid: the launches a plain call of this geometry makes on the
+ * current path (dwt2_set_path), in execution order.  dir: 0 dwt2_fwd,
+ * 1 dwt2_inv, 2 dwt2_bwd.  Launch i covers levels first[i] .. last[i]
+ * (1 = finest); a probe (dwt2_set_probe) on any of those levels times that
+ * launch.  first / last are HOST arrays of `cap` entries (may be NULL with
+ * cap 0).  Returns the number of launches (>= 1), or DWT2_ERR_ARG /
+ * DWT2_ERR_SIZE for an invalid geometry, batch or dir. */
+int32_t dwt2_launch_levels(int32_t width, int32_t height, int32_t batch,
+                           int32_t levels, int32_t dir, int32_t* first,
+                           int32_t* last, int32_t cap);
 
 /* Static description of a status code. */
 const char* dwt2_status_string(int status);

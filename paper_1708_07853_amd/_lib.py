@@ -27,7 +27,7 @@ EXPORTS = [
     "dwt2_status_string", "dwt2_last_error", "dwt2_clear_plan_cache", "dwt2_set_tiling", "dwt2_set_path",
     "dwt2_set_probe", "dwt2_separable_workspace_size", "dwt2_fwd_separable", "dwt2_fwd_lds",
     "dwt2_fwd_cdf97", "dwt2_inv_cdf97", "dwt2_fwd_cdf97_separable", "dwt2_set_job_wait", "dwt2_synchronize",
-    "dwt2_plan_cache_size",
+    "dwt2_plan_cache_size", "dwt2_launch_levels",
 ]
 
 
@@ -97,6 +97,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dwt2_plan_cache_size.restype = i32
     lib.dwt2_set_job_wait.argtypes = [i32, i32]
     lib.dwt2_set_job_wait.restype = ctypes.c_int
+    lib.dwt2_launch_levels.argtypes = [i32, i32, i32, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), i32]
+    lib.dwt2_launch_levels.restype = i32
     lib.dwt2_synchronize.argtypes = [vp]
     lib.dwt2_synchronize.restype = ctypes.c_int
     _lib = lib

@@ -19,7 +19,7 @@ from ._lib import DWT2_EXT_SYMMETRIC, DWT2_F32, DWT2_I32_REV
 __all__ = ["fwd", "inv", "bwd", "fwd_batched", "inv_batched", "bwd_batched", "DWT2Function", "workspace_size",
            "batched_workspace_size", "level_sizes", "set_tiling", "set_path", "set_probe", "fwd_separable",
            "separable_workspace_size", "fwd_lds", "fwd_cdf97", "inv_cdf97", "fwd_cdf97_separable",
-           "synchronize", "set_job_wait", "plan_cache_size", "clear_plan_cache", "DWT2_F32", "DWT2_I32_REV"]
+           "synchronize", "set_job_wait", "plan_cache_size", "launch_levels", "clear_plan_cache", "DWT2_F32", "DWT2_I32_REV"]
 
 
 def level_sizes(w: int, h: int, levels: int):
@@ -97,6 +97,16 @@ def set_probe(direction: str | None, level: int = 1, begin: "torch.cuda.Event | 
         if not ev.cuda_event:  # torch creates the HIP event on its first record
             ev.record()
     _lib.check(lib.dwt2_set_probe(_PROBE_DIRS[direction], level, begin.cuda_event, end.cuda_event))
+
+
+def launch_levels(w: int, h: int, levels: int, direction: str = "fwd", batch: int = 1):
+    """[(first, last), ...]: the launches of a plain call on the current path,
+    in execution order, each with the levels it computes (dwt2_launch_levels)."""
+    lib = _lib.load()
+    first, last = (ctypes.c_int32 * 16)(), (ctypes.c_int32 * 16)()
+    n = lib.dwt2_launch_levels(w, h, batch, levels, _PROBE_DIRS[direction], first, last, 16)
+    _lib.check(min(n, 0))
+    return [(first[i], last[i]) for i in range(n)]
 
 
 def workspace_size(w: int, h: int, levels: int, batch: int = 1, mode: int = DWT2_F32) -> int:

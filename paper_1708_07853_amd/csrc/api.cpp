@@ -323,43 +323,49 @@ static int launch_tail_levels(int dir, const Call& c, const Geo& g, int k0, void
   return launch_tail(dir, c.mode, t, stream);
 }
 
+// The launches of a plain call on the per-level path, in execution order:
+// each covers levels [first, last] (one level, or the fused tail).
+int plan_launches(int dir, const Geo& g, int batch, bool tail, Launch* out) {
+  const int k0 = tail ? tail_first_level(dir, g, batch) : 0;
+  const int last_single = k0 ? k0 - 1 : g.L;  // levels 1 .. last_single run one per launch
+  int n = 0;
+  if (dir == kFwd) {
+    for (int k = 1; k <= last_single; ++k) out[n++] = Launch{k, k};
+    if (k0) out[n++] = Launch{k0, g.L};
+  } else {
+    if (k0) out[n++] = Launch{k0, g.L};
+    for (int k = last_single; k >= 1; --k) out[n++] = Launch{k, k};
+  }
+  return n;
+}
+
 int run_levels(int dir, const Call& c, const Geo& g, void* stream, bool tail) {
-  const int k0 = tail ? tail_first_level(dir, g, c.batch) : 0;
-  // forward: levels 1 .. k0-1, then the tail; inverse: the tail, then k0-1 .. 1
-  const int order_begin = dir == kFwd ? 1 : (k0 ? k0 - 1 : g.L), order_end = dir == kFwd ? (k0 ? k0 : g.L + 1) : 0;
-  const int step = dir == kFwd ? 1 : -1;
+  Launch plan[DWT2_MAX_LEVELS];
+  const int nl = plan_launches(dir, g, c.batch, tail, plan);
   Probe pr;
   {
     std::lock_guard<std::mutex> lock(g_probe_mu);
     pr = g_probe;
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
-  auto run_tail = [&]() -> int {
-    // the tail levels share one launch; a probe on any of them times it
-    const bool probed = pr.dir == dir && pr.level >= k0;
+  for (int i = 0; i < nl; ++i) {
+    const Launch& l = plan[i];
+    // a probe on any level of a launch times that launch
+    const bool probed = pr.dir == dir && pr.level >= l.first && pr.level <= l.last;
     if (probed && hipEventRecord(pr.begin, s) != hipSuccess) return fail(DWT2_ERR_HIP, "probe event record failed");
-    const int err = launch_tail_levels(dir, c, g, k0, stream);
+    int err;
+    if (l.first == l.last) {  // a fused tail always covers at least two levels
+      LevelLaunch a;
+      int ch;
+      level_launch(dir, c, g, l.first, 0, a, ch);
+      err = launch_level(dir, c.mode, ch, a, stream);
+    } else {
+      err = launch_tail_levels(dir, c, g, l.first, stream);
+    }
     if (err != hipSuccess)
-      return fail(DWT2_ERR_HIP, "tail levels %d..%d launch failed: %s", k0, g.L, hipGetErrorString((hipError_t)err));
-    if (probed && hipEventRecord(pr.end, s) != hipSuccess) return fail(DWT2_ERR_HIP, "probe event record failed");
-    return DWT2_OK;
-  };
-  if (k0 && dir != kFwd) {
-    const int st = run_tail();
-    if (st) return st;
-  }
-  for (int k = order_begin; k != order_end; k += step) {
-    LevelLaunch a;
-    int ch;
-    level_launch(dir, c, g, k, 0, a, ch);
-    const bool probed = pr.dir == dir && pr.level == k;
-    if (probed && hipEventRecord(pr.begin, s) != hipSuccess) return fail(DWT2_ERR_HIP, "probe event record failed");
-    const int err = launch_level(dir, c.mode, ch, a, stream);
-    if (err != hipSuccess)
-      return fail(DWT2_ERR_HIP, "level %d launch failed: %s", k, hipGetErrorString((hipError_t)err));
+      return fail(DWT2_ERR_HIP, "levels %d..%d launch failed: %s", l.first, l.last, hipGetErrorString((hipError_t)err));
     if (probed && hipEventRecord(pr.end, s) != hipSuccess) return fail(DWT2_ERR_HIP, "probe event record failed");
   }
-  if (k0 && dir == kFwd) return run_tail();
   return DWT2_OK;
 }
 
@@ -746,6 +752,30 @@ int dwt2_set_path(int32_t path) {
   if (path < 0 || path > 2) return fail(DWT2_ERR_ARG, "path must be 0, 1 or 2");
   g_persistent.store(path);
   return DWT2_OK;
+}
+
+int32_t dwt2_launch_levels(int32_t width, int32_t height, int32_t batch, int32_t levels, int32_t dir,
+                           int32_t* first, int32_t* last, int32_t cap) {
+  clear_error();
+  Geo g;
+  if (batch < 1 || dir < 0 || dir > 2) return fail(DWT2_ERR_ARG, "batch must be >= 1 and dir 0..2");
+  if (int st = check_geometry(width, height, levels, g)) return st;
+  if (g_persistent.load() < 0) g_persistent.store(env_int("DWT2_PERSISTENT") == 1 ? 1 : 0);
+  const int path = g_persistent.load();
+  if (path == 1 && g.L <= kInlineDescs) {  // one cooperative launch covers every level
+    if (cap >= 1 && first && last) {
+      first[0] = 1;
+      last[0] = g.L;
+    }
+    return 1;
+  }
+  Launch plan[DWT2_MAX_LEVELS];
+  const int n = plan_launches(dir, g, batch, path != 2, plan);
+  for (int i = 0; i < n && i < cap && first && last; ++i) {
+    first[i] = plan[i].first;
+    last[i] = plan[i].last;
+  }
+  return n;
 }
 
 int dwt2_set_job_wait(int32_t max_polls, int32_t unreachable) {
