@@ -288,8 +288,11 @@ int dwt2_set_tiling(int32_t seg, int32_t chunk);
  * the adjoint's first ones; the inverse also needs the coarsest input at
  * least 4 x 4); 1 = every level of a call in one cooperative persistent
  * launch whose work items wait only for the rows they read; 2 = one launch
- * per level throughout.  Results are bit-identical.  Returns DWT2_OK or
- * DWT2_ERR_ARG. */
+ * per level throughout; 3 = like 0, with the levels before the fused ones
+ * in pairs (levels k, k+1 in one launch that keeps LL_k on chip, from the
+ * finest level, where the level-k input is at least 8 x 8); 4 = pairs as
+ * in 3 and single levels, without the fused coarsest levels.  Results are
+ * bit-identical.  Returns DWT2_OK or DWT2_ERR_ARG. */
 int dwt2_set_path(int32_t path);
 
 /* Process-wide timing probe, a measurement aid: while set, every

@@ -63,14 +63,16 @@ def set_tiling(seg: int = 0, chunk: int = 0) -> None:
     _lib.check(_lib.load().dwt2_set_tiling(seg, chunk))
 
 
-PATHS = {"levels": 0, "persistent": 1, "levels-only": 2}
+PATHS = {"levels": 0, "persistent": 1, "levels-only": 2, "pairs": 3, "pairs-only": 4}
 
 
 def set_path(path="levels") -> None:
     """How levels are chained (see dwt2_set_path): "levels" (default: one
-    launch per level, the forward's small last levels fused into one),
+    launch per level, the small coarsest levels fused into one),
     "persistent" (one cooperative launch), "levels-only" (one launch per
-    level throughout).  True / False select "persistent" / "levels".
+    level throughout), "pairs" (like "levels" with pairs of levels in one
+    launch before the fused ones), "pairs-only" (pairs and single levels, no
+    fused coarsest levels).  True / False select "persistent" / "levels".
     Results are bit-identical."""
     if isinstance(path, bool):
         path = "persistent" if path else "levels"

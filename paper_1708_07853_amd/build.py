@@ -18,6 +18,7 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libdwt2.so")
 OBJDIR = os.path.join(HERE, "_build")
 SOURCES = ["strip_fwd.hip", "strip_inv.hip", "strip_bwd.hip", "job_fwd.hip", "job_inv.hip", "job_bwd.hip",
+           "fused_fwd.hip", "fused_inv.hip", "fused_bwd.hip",
            "tail_kernels.hip", "lds_kernels.hip", "separable.hip", "cdf97.hip", "api.cpp", "batched.cpp"]
 ARCH = os.environ.get("DWT2_ARCH", "gfx950")
 

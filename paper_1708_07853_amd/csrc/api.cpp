@@ -262,6 +262,48 @@ static void level_launch(int dir, const Call& c, const Geo& g, int k, int64_t sl
   a.items = (int64_t)a.items_per_image * c.batch;
 }
 
+// Levels k and k+1 in one pair launch: level k's pixels (input of the
+// forward, output of the inverse and adjoint), LL_{k+1} (output of the
+// forward, input of the others), and the packed array's bands of both.
+static void pair_launch(int dir, const Call& c, const Geo& g, int k, LevelLaunch& a, int& ch) {
+  memset(&a, 0, sizeof a);
+  const int W = g.w[k - 1], H = g.h[k - 1];
+  const int ns_w = ceil_half(W), ns_h1 = ceil_half(ceil_half(H));
+  const int strips = (ns_w + pair_strip_q(dir) - 1) / pair_strip_q(dir);
+  const Tiling t = choose_tiling(ns_h1, (int64_t)strips * c.batch);
+  ch = t.ch;
+  a.d.W = W;
+  a.d.H = H;
+  a.d.seg = t.seg;
+  a.d.nstrips = strips;
+  a.d.nsegs = (ns_h1 + t.seg - 1) / t.seg;
+  LevelDesc dk, dk1;
+  int64_t pix_bs, ll_bs, band_bs, u0, u1, u2;
+  memset(&dk, 0, sizeof dk);
+  memset(&dk1, 0, sizeof dk1);
+  level_pointers(dir, c, g, k, dk, pix_bs, u0, band_bs);
+  level_pointers(dir, c, g, k + 1, dk1, u1, ll_bs, u2);
+  a.d.pix_in = dk.pix_in;
+  a.d.pix_out = dk.pix_out;
+  a.d.pix_stride = dk.pix_stride;
+  a.d.band_in = dk.band_in;
+  a.d.band_out = dk.band_out;
+  a.d.band_stride = dk.band_stride;
+  a.d.ll_in = dk1.ll_in;
+  a.d.ll_out = dk1.ll_out;
+  a.d.ll_stride = dk1.ll_stride;
+  a.pix_bstride = pix_bs;
+  a.ll_bstride = ll_bs;
+  a.band_bstride = band_bs;
+  // the output a later launch reads: LL_{k+1} (forward, k+1 < L), LL_{k-1}
+  // (inverse / adjoint, k > 1)
+  const int ko = dir == kFwd ? k + 1 : k - 1;
+  const bool feeds = dir == kFwd ? (k + 1 < g.L) : (k > 1);
+  a.d.keep_out = feeds && (int64_t)g.w[ko] * g.h[ko] * 4 * c.batch <= kKeepBytes;
+  a.items_per_image = a.d.nstrips * a.d.nsegs;
+  a.items = (int64_t)a.items_per_image * c.batch;
+}
+
 // One kernel launch per level (levels meet at kernel boundaries).
 // Timing probe (dwt2_set_probe): events recorded around one level's launch.
 struct Probe {
@@ -324,24 +366,33 @@ static int launch_tail_levels(int dir, const Call& c, const Geo& g, int k0, void
 }
 
 // The launches of a plain call on the per-level path, in execution order:
-// each covers levels [first, last] (one level, or the fused tail).
-int plan_launches(int dir, const Geo& g, int batch, bool tail, Launch* out) {
+// each covers levels [first, last] -- one level, a pair of levels, or the
+// fused tail.  Levels before the tail go in pairs from the finest one where
+// the pair kernels apply (a level-k input of at least kPairMin x kPairMin,
+// see fused.h), else one by one.
+constexpr int kPairMin = 8;
+int plan_launches(int dir, const Geo& g, int batch, bool tail, bool pairs, Launch* out) {
   const int k0 = tail ? tail_first_level(dir, g, batch) : 0;
-  const int last_single = k0 ? k0 - 1 : g.L;  // levels 1 .. last_single run one per launch
+  const int last_single = k0 ? k0 - 1 : g.L;  // levels 1 .. last_single precede the tail
+  Launch fwd[DWT2_MAX_LEVELS];
   int n = 0;
-  if (dir == kFwd) {
-    for (int k = 1; k <= last_single; ++k) out[n++] = Launch{k, k};
-    if (k0) out[n++] = Launch{k0, g.L};
-  } else {
-    if (k0) out[n++] = Launch{k0, g.L};
-    for (int k = last_single; k >= 1; --k) out[n++] = Launch{k, k};
+  for (int k = 1; k <= last_single;) {
+    if (pairs && k + 1 <= last_single && g.w[k - 1] >= kPairMin && g.h[k - 1] >= kPairMin) {
+      fwd[n++] = Launch{k, k + 1, kLaunchPair};
+      k += 2;
+    } else {
+      fwd[n++] = Launch{k, k, kLaunchLevel};
+      k += 1;
+    }
   }
+  if (k0) fwd[n++] = Launch{k0, g.L, kLaunchTail};
+  for (int i = 0; i < n; ++i) out[i] = dir == kFwd ? fwd[i] : fwd[n - 1 - i];  // the inverses run coarsest first
   return n;
 }
 
-int run_levels(int dir, const Call& c, const Geo& g, void* stream, bool tail) {
+int run_levels(int dir, const Call& c, const Geo& g, void* stream, bool tail, bool pairs) {
   Launch plan[DWT2_MAX_LEVELS];
-  const int nl = plan_launches(dir, g, c.batch, tail, plan);
+  const int nl = plan_launches(dir, g, c.batch, tail, pairs, plan);
   Probe pr;
   {
     std::lock_guard<std::mutex> lock(g_probe_mu);
@@ -354,11 +405,16 @@ int run_levels(int dir, const Call& c, const Geo& g, void* stream, bool tail) {
     const bool probed = pr.dir == dir && pr.level >= l.first && pr.level <= l.last;
     if (probed && hipEventRecord(pr.begin, s) != hipSuccess) return fail(DWT2_ERR_HIP, "probe event record failed");
     int err;
-    if (l.first == l.last) {  // a fused tail always covers at least two levels
+    if (l.kind == kLaunchLevel) {
       LevelLaunch a;
       int ch;
       level_launch(dir, c, g, l.first, 0, a, ch);
       err = launch_level(dir, c.mode, ch, a, stream);
+    } else if (l.kind == kLaunchPair) {
+      LevelLaunch a;
+      int ch;
+      pair_launch(dir, c, g, l.first, a, ch);
+      err = launch_pair(dir, c.mode, ch >= 4 ? 2 : 1, a, stream);
     } else {
       err = launch_tail_levels(dir, c, g, l.first, stream);
     }
@@ -628,8 +684,9 @@ static int transform(int dir, const void* src, int64_t src_stride, int64_t src_b
   if (g_persistent.load() < 0) g_persistent.store(env_int("DWT2_PERSISTENT") == 1 ? 1 : 0);
   const int path = g_persistent.load();
   if (path == 1 && g.L <= kInlineDescs) return run_job(dir, c, g, stream);
-  if (path == 2) return run_levels(dir, c, g, stream, false);
-  return run_levels(dir, c, g, stream, true);
+  if (path == 2) return run_levels(dir, c, g, stream, false, false);
+  if (path == 4) return run_levels(dir, c, g, stream, false, true);
+  return run_levels(dir, c, g, stream, true, path == 3);
 }
 
 }  // namespace dwt2
@@ -749,7 +806,7 @@ int dwt2_set_probe(int32_t dir, int32_t level, void* ev_begin, void* ev_end) {
 
 int dwt2_set_path(int32_t path) {
   clear_error();
-  if (path < 0 || path > 2) return fail(DWT2_ERR_ARG, "path must be 0, 1 or 2");
+  if (path < 0 || path > 4) return fail(DWT2_ERR_ARG, "path must be 0 .. 4");
   g_persistent.store(path);
   return DWT2_OK;
 }
@@ -770,7 +827,7 @@ int32_t dwt2_launch_levels(int32_t width, int32_t height, int32_t batch, int32_t
     return 1;
   }
   Launch plan[DWT2_MAX_LEVELS];
-  const int n = plan_launches(dir, g, batch, path != 2, plan);
+  const int n = plan_launches(dir, g, batch, path != 2 && path != 4, path == 3 || path == 4, plan);
   for (int i = 0; i < n && i < cap && first && last; ++i) {
     first[i] = plan[i].first;
     last[i] = plan[i].last;

@@ -208,6 +208,18 @@ inline int launch_table(int dir, int mode, const TableArgs& a, void* stream) {
   if (dir == kInv) return launch_table_dir<kInv>(mode, a, stream);
   return launch_table_dir<kBwd>(mode, a, stream);
 }
+// Two levels in one pass (fused_fwd.hip, fused_inv.hip, fused_bwd.hip):
+// the descriptor's W, H are the finer level's input, seg counts rows of
+// quadruples of the coarser level, ll is the coarser level's LL, nstrips
+// counts strips of pair_strip_q(dir) owned quadruple columns of the finer
+// level.
+constexpr int pair_strip_q(int dir) { return dir == kBwd ? 120 : 122; }
+template <int DIR> int launch_pair_dir(int mode, int chunk, const LevelLaunch& a, void* stream);
+inline int launch_pair(int dir, int mode, int chunk, const LevelLaunch& a, void* stream) {
+  if (dir == kFwd) return launch_pair_dir<kFwd>(mode, chunk, a, stream);
+  if (dir == kInv) return launch_pair_dir<kInv>(mode, chunk, a, stream);
+  return launch_pair_dir<kBwd>(mode, chunk, a, stream);
+}
 // Clears n synchronisation words with a fill kernel (tail_kernels.hip).
 int launch_zero(uint32_t* p, int64_t n, void* stream);
 

@@ -1,0 +1,6 @@
+// Pair kernels (two levels per pass) of the forward (float32 and int32).
+#include "fused.h"
+
+namespace dwt2 {
+DWT2_INSTANTIATE_PAIR(kFwd)
+}  // namespace dwt2

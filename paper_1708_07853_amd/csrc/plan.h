@@ -53,12 +53,14 @@ Tiling choose_tiling(int ns_h, int64_t strips_times_batch, int64_t slots_hint = 
 void fill_level(LevelDesc& d, int W, int H, int seg);
 void level_pointers(int dir, const Call& c, const Geo& g, int k, LevelDesc& d, int64_t& pix_bs, int64_t& ll_bs,
                     int64_t& band_bs);
-// One launch of a plain call: levels [first, last].
+// One launch of a plain call: levels [first, last], by the single-level,
+// pair or fused-tail kernels.
+enum { kLaunchLevel = 0, kLaunchPair = 1, kLaunchTail = 2 };
 struct Launch {
-  int first, last;
+  int first, last, kind;
 };
-int plan_launches(int dir, const Geo& g, int batch, bool tail, Launch* out);
-int run_levels(int dir, const Call& c, const Geo& g, void* stream, bool tail);
+int plan_launches(int dir, const Geo& g, int batch, bool tail, bool pairs, Launch* out);
+int run_levels(int dir, const Call& c, const Geo& g, void* stream, bool tail, bool pairs);
 int run_job(int dir, const Call& c, const Geo& g, void* stream);
 // DWT2_ERR_HIP (once) if a persistent launch gave up a wait since the last report.
 int report_async_error();

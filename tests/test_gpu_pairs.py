@@ -1,0 +1,135 @@
+"""GPU parity of the pair kernels (two levels per launch, LL_k kept on
+chip): on a sweep of sizes that covers odd and even level inputs, strip and
+segment boundaries and the smallest inputs the pairs take, the paths with
+pairs are bit-identical to one launch per level in every direction and
+mode, and match the oracle; forced tilings and batched / strided views
+change nothing."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import INT
+from paper_1708_07853_amd import synth
+
+pytestmark = pytest.mark.gpu
+TOL = 2e-4
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def D():
+    import paper_1708_07853_amd as d
+    return d
+
+
+def _img(h, w, seed, dt):
+    return torch.from_numpy(np.random.default_rng(seed).integers(0, 256, size=(h, w)).astype(dt)).cuda()
+
+
+# level-1 inputs: the smallest sizes a pair takes (8), odd and even sizes,
+# and widths around the 244-pixel strip pitch of the pair kernels
+SIZES_H = [8, 9, 10, 11, 13, 16, 17, 31, 34, 65, 130]
+SIZES_W = [8, 9, 12, 15, 33, 64, 239, 240, 241, 242, 243, 244, 245, 246, 250, 479, 481, 487, 489, 490, 731, 1030]
+SHAPES = [(h, 245) for h in SIZES_H] + [(37, w) for w in SIZES_W] + [(8, 8), (9, 9), (300, 1031), (1030, 300)]
+
+
+def _max_levels(w, h):
+    lv = 1
+    while lv < 6 and -(-w // (1 << lv)) >= 2 and -(-h // (1 << lv)) >= 2:
+        lv += 1
+    return lv
+
+
+@pytest.mark.parametrize("mode", ["f32", "int"])
+def test_pairs_equal_single_levels(mode):
+    d = D()
+    dt = np.float32 if mode == "f32" else np.int32
+    try:
+        for idx, (h, w) in enumerate(SHAPES):
+            x = _img(h, w, idx, dt)
+            g = (_img(h, w, 1000 + idx, np.float32) - 128) / 8
+            for levels in sorted({2, 3, _max_levels(w, h)}):
+                if levels > _max_levels(w, h):
+                    continue
+                print(f"pairs: {mode} {h}x{w} L={levels}", flush=True)
+                d.set_path("levels-only")
+                ref_f = d.fwd(x, levels)
+                ref_i = d.inv(ref_f, levels)
+                ref_b = d.bwd(g, levels) if mode == "f32" else None
+                for path in ("pairs", "pairs-only"):
+                    d.set_path(path)
+                    assert torch.equal(d.fwd(x, levels), ref_f), (h, w, levels, path)
+                    assert torch.equal(d.inv(ref_f, levels), ref_i), (h, w, levels, path)
+                    if ref_b is not None:
+                        assert torch.equal(d.bwd(g, levels), ref_b), (h, w, levels, path)
+    finally:
+        d.set_path("levels")
+
+
+@pytest.mark.parametrize("mode", ["f32", "int"])
+def test_pairs_match_oracle(mode):
+    d = D()
+    d.set_path("pairs-only")
+    for idx, (h, w) in enumerate([(17, 489), (130, 245), (300, 1031), (65, 8), (8, 9)]):
+        levels = min(3, _max_levels(w, h))
+        if mode == "f32":
+            x = synth.image(w, h, 60 + idx)
+            c = d.fwd(torch.from_numpy(x).cuda(), levels)
+            assert float(np.abs(c.cpu().numpy() - oracle.fwd(x.astype(np.float64), levels)).max()) <= TOL
+            r = d.inv(c, levels).cpu().numpy()
+            assert float(np.abs(r - oracle.inv(c.cpu().numpy().astype(np.float64), levels)).max()) <= TOL
+            g = np.random.default_rng(idx).normal(size=(h, w)).astype(np.float32) * 16
+            a = d.bwd(torch.from_numpy(g).cuda(), levels).cpu().numpy()
+            assert float(np.abs(a - oracle.adj(g.astype(np.float64), levels)).max()) <= TOL
+        else:
+            x = synth.image(w, h, 60 + idx, np.int32)
+            c = d.fwd(torch.from_numpy(x).cuda(), levels)
+            assert np.array_equal(c.cpu().numpy(), oracle.fwd(x.astype(np.int64), levels, INT))
+            assert np.array_equal(d.inv(c, levels).cpu().numpy(), x)
+    d.set_path("levels")
+
+
+@pytest.mark.parametrize("mode", ["f32", "int"])
+def test_pairs_every_tiling(mode):
+    d = D()
+    dt = np.float32 if mode == "f32" else np.int32
+    x = _img(203, 1001, 5, dt)
+    g = (_img(203, 1001, 6, np.float32) - 128) / 8
+    try:
+        d.set_path("levels-only")
+        ref = d.fwd(x, 4), None
+        ref_i = d.inv(ref[0], 4)
+        ref_b = d.bwd(g, 4) if mode == "f32" else None
+        d.set_path("pairs-only")
+        for seg, ch in [(1, 1), (2, 2), (3, 1), (5, 4), (8, 4), (64, 2), (1000, 4)]:
+            print(f"pairs tiling: {mode} seg {seg} chunk {ch}", flush=True)
+            d.set_tiling(seg, ch)
+            assert torch.equal(d.fwd(x, 4), ref[0]), (seg, ch)
+            assert torch.equal(d.inv(ref[0], 4), ref_i), (seg, ch)
+            if ref_b is not None:
+                assert torch.equal(d.bwd(g, 4), ref_b), (seg, ch)
+    finally:
+        d.set_tiling(0, 0)
+        d.set_path("levels")
+
+
+def test_pairs_batch_and_strided_views():
+    d = D()
+    xb = _img(3 * 150, 700, 9, np.float32).reshape(3, 150, 700)
+    view = xb[:, 3:140, 5:650]          # strided, misaligned rows
+    try:
+        d.set_path("levels-only")
+        ref = d.fwd(view, 3)
+        ref_i = d.inv(ref, 3)
+        ref_b = d.bwd(view, 3)
+        d.set_path("pairs-only")
+        assert torch.equal(d.fwd(view, 3), ref)
+        assert torch.equal(d.inv(ref, 3), ref_i)
+        assert torch.equal(d.bwd(view, 3), ref_b)
+    finally:
+        d.set_path("levels")
