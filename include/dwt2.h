@@ -273,6 +273,22 @@ int dwt2_bwd_batched(const dwt2_image_t* images, int32_t n, int32_t levels,
                      int32_t mode, int32_t boundary, void* workspace,
                      size_t workspace_bytes, void* stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): dwt2_fwd with the
+ * workspace taken from a device array the library holds (96 MiB per GPU it
+ * runs on, kept until the process ends; enough for one 8192 x 8192 image at
+ * six levels) instead of a caller's buffer.  Arguments other than the
+ * workspace, layout, ownership, results and errors are those of dwt2_fwd;
+ * a call whose dwt2_workspace_size exceeds 96 MiB returns
+ * DWT2_ERR_WORKSPACE.  It always runs the per-level path (path 0 of
+ * dwt2_set_path), allocates nothing and issues no memset.  Every call on a
+ * GPU shares that GPU's array: calls that overlap in time on one GPU (two
+ * streams, two threads) race and must be serialised by the caller. */
+int dwt2_fwd_noalloc(const void* src, int64_t src_stride, int64_t src_batch_stride,
+                     void* dst, int64_t dst_stride, int64_t dst_batch_stride,
+                     int32_t width, int32_t height, int32_t batch, int32_t levels,
+                     int32_t mode, int32_t boundary, void* stream);
+
 /* Process-wide tiling override, for tuning sweeps and tests: seg = quadruple
  * rows per work item (0 = automatic), chunk = quadruple rows per prefetch
  * chunk (1, 2 or 4; 0 = automatic).  Results are bit-identical for every

@@ -19,7 +19,8 @@ LIB = os.path.join(HERE, "libdwt2.so")
 OBJDIR = os.path.join(HERE, "_build")
 SOURCES = ["strip_fwd.hip", "strip_inv.hip", "strip_bwd.hip", "job_fwd.hip", "job_inv.hip", "job_bwd.hip",
            "fused_fwd.hip", "fused_inv.hip", "fused_bwd.hip",
-           "tail_kernels.hip", "lds_kernels.hip", "separable.hip", "cdf97.hip", "api.cpp", "batched.cpp"]
+           "tail_kernels.hip", "lds_kernels.hip", "separable.hip", "cdf97.hip", "noalloc.hip", "api.cpp",
+           "batched.cpp"]
 ARCH = os.environ.get("DWT2_ARCH", "gfx950")
 
 FLAGS = [

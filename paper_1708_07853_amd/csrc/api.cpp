@@ -637,7 +637,8 @@ static int run_cdf97(int dir, bool separable, const Call& c, const Geo& g, void*
 // Which kernels compute a call: the product path, one of the comparison
 // baselines (separable passes, LDS-tiled separable, LDS-tiled non-separable),
 // or the CDF 9/7 kernels.
-enum { kProduct = 0, kSepPasses = 1, kLdsSep = 2, kLdsNonSep = 3, kCdf97 = 4, kLdsAdapted = 5, kCdf97Sep = 6 };
+enum { kProduct = 0, kSepPasses = 1, kLdsSep = 2, kLdsNonSep = 3, kCdf97 = 4, kLdsAdapted = 5, kCdf97Sep = 6,
+       kProductLevels = 7 };
 
 static int transform(int dir, const void* src, int64_t src_stride, int64_t src_bs, void* dst, int64_t dst_stride,
                      int64_t dst_bs, int32_t width, int32_t height, int32_t batch, int32_t levels, int32_t mode,
@@ -681,12 +682,23 @@ static int transform(int dir, const void* src, int64_t src_stride, int64_t src_b
   if (variant == kLdsNonSep) return run_lds(DWT2_SCHEME_NONSEPARABLE, c, g, stream);
   if (variant == kLdsAdapted) return run_lds(DWT2_SCHEME_ADAPTED, c, g, stream);
   if (variant == kCdf97 || variant == kCdf97Sep) return run_cdf97(dir, variant == kCdf97Sep, c, g, stream);
+  // the per-level path whatever the process-wide setting (the entry point
+  // without a workspace: it must not reach the persistent path, whose
+  // host-visible error word is allocated on first use)
+  if (variant == kProductLevels) return run_levels(dir, c, g, stream, true, false);
   if (g_persistent.load() < 0) g_persistent.store(env_int("DWT2_PERSISTENT") == 1 ? 1 : 0);
   const int path = g_persistent.load();
   if (path == 1 && g.L <= kInlineDescs) return run_job(dir, c, g, stream);
   if (path == 2) return run_levels(dir, c, g, stream, false, false);
   if (path == 4) return run_levels(dir, c, g, stream, false, true);
   return run_levels(dir, c, g, stream, true, path == 3);
+}
+
+int fwd_levels_path(const void* src, int64_t src_stride, int64_t src_bs, void* dst, int64_t dst_stride,
+                    int64_t dst_bs, int32_t width, int32_t height, int32_t batch, int32_t levels, int32_t mode,
+                    int32_t boundary, void* workspace, size_t workspace_bytes, void* stream) {
+  return transform(kFwd, src, src_stride, src_bs, dst, dst_stride, dst_bs, width, height, batch, levels, mode,
+                   boundary, workspace, workspace_bytes, stream, kProductLevels);
 }
 
 }  // namespace dwt2

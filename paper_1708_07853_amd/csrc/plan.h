@@ -62,6 +62,11 @@ struct Launch {
 int plan_launches(int dir, const Geo& g, int batch, bool tail, bool pairs, Launch* out);
 int run_levels(int dir, const Call& c, const Geo& g, void* stream, bool tail, bool pairs);
 int run_job(int dir, const Call& c, const Geo& g, void* stream);
+// dwt2_fwd on the per-level path whatever the process-wide path setting
+// (validation, errors and results as dwt2_fwd).
+int fwd_levels_path(const void* src, int64_t src_stride, int64_t src_bs, void* dst, int64_t dst_stride,
+                    int64_t dst_bs, int32_t width, int32_t height, int32_t batch, int32_t levels, int32_t mode,
+                    int32_t boundary, void* workspace, size_t workspace_bytes, void* stream);
 // DWT2_ERR_HIP (once) if a persistent launch gave up a wait since the last report.
 int report_async_error();
 

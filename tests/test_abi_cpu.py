@@ -269,3 +269,12 @@ def test_set_job_wait_validation(lib):
 def test_plan_cache_starts_empty_and_clears(lib):
     lib.dwt2_clear_plan_cache()
     assert lib.dwt2_plan_cache_size() == 0
+
+
+def test_noalloc_validation(lib):
+    # sizes beyond the 96 MiB scratch array are rejected before any HIP call
+    st = lib.dwt2_fwd_noalloc(FAKE_A, 16384, 0, FAKE_B, 16384, 0, 16384, 16384, 1, 6, 0, 0, None)
+    assert st == -4 and b"scratch" in lib.dwt2_last_error()
+    assert lib.dwt2_fwd_noalloc(FAKE_A, 64, 0, FAKE_B, 64, 0, 1, 64, 1, 1, 0, 0, None) == -1
+    assert lib.dwt2_fwd_noalloc(FAKE_A, 64, 0, FAKE_B, 64, 0, 64, 64, 1, 9, 0, 0, None) == -2
+    assert lib.dwt2_fwd_noalloc(FAKE_A, 64, 0, FAKE_B, 64, 0, 64, 64, 1, 2, 7, 0, None) == -3
