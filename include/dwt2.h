@@ -297,18 +297,23 @@ int dwt2_fwd_noalloc(const void* src, int64_t src_stride, int64_t src_batch_stri
 int dwt2_set_tiling(int32_t seg, int32_t chunk);
 
 /* Process-wide choice of how levels are chained, for tests and
- * measurements: 0 (default) = one kernel launch per level, except that the
- * 2-3 coarsest levels, when their inputs hold at most 1024 x 1024 pixels
- * over the batch, share one launch (each workgroup runs them in LDS on its
- * tile plus a recompute halo; the forward's last levels, the inverse's and
- * the adjoint's first ones; the inverse also needs the coarsest input at
- * least 4 x 4); 1 = every level of a call in one cooperative persistent
- * launch whose work items wait only for the rows they read; 2 = one launch
- * per level throughout; 3 = like 0, with the levels before the fused ones
- * in pairs (levels k, k+1 in one launch that keeps LL_k on chip, from the
- * finest level, where the level-k input is at least 8 x 8); 4 = pairs as
- * in 3 and single levels, without the fused coarsest levels.  Results are
- * bit-identical.  Returns DWT2_OK or DWT2_ERR_ARG. */
+ * measurements.  The building blocks: single-level launches; pair launches
+ * (levels k and k+1 in one launch that keeps LL_k on chip, from the finest
+ * level, where the level-k input is at least 8 x 8); and the fused coarsest
+ * levels (the 2-3 coarsest levels, when their inputs hold at most
+ * 1024 x 1024 pixels over the batch, in one launch in which each workgroup
+ * runs them in LDS on its tile plus a recompute halo; the inverse also
+ * needs the coarsest input at least 4 x 4).
+ *   0 (default): pairs for dwt2_inv and dwt2_bwd, single levels for dwt2_fwd
+ *     (what measured fastest on MI355X), then the fused coarsest levels;
+ *   1: every level of a call in one cooperative persistent launch whose
+ *     work items wait only for the rows they read;
+ *   2: one launch per level throughout;
+ *   3: pairs in every direction, then the fused coarsest levels;
+ *   4: pairs in every direction, single levels where no pair applies, no
+ *     fused coarsest levels;
+ *   5: single levels in every direction, then the fused coarsest levels.
+ * Results are bit-identical.  Returns DWT2_OK or DWT2_ERR_ARG. */
 int dwt2_set_path(int32_t path);
 
 /* Process-wide timing probe, a measurement aid: while set, every

@@ -63,17 +63,18 @@ def set_tiling(seg: int = 0, chunk: int = 0) -> None:
     _lib.check(_lib.load().dwt2_set_tiling(seg, chunk))
 
 
-PATHS = {"levels": 0, "persistent": 1, "levels-only": 2, "pairs": 3, "pairs-only": 4}
+PATHS = {"levels": 0, "persistent": 1, "levels-only": 2, "pairs": 3, "pairs-only": 4, "no-pairs": 5}
 
 
 def set_path(path="levels") -> None:
-    """How levels are chained (see dwt2_set_path): "levels" (default: one
-    launch per level, the small coarsest levels fused into one),
+    """How levels are chained (see dwt2_set_path): "levels" (default: pairs
+    of levels in one launch for the inverse and adjoint, single levels for
+    the forward, the small coarsest levels fused into one launch),
     "persistent" (one cooperative launch), "levels-only" (one launch per
-    level throughout), "pairs" (like "levels" with pairs of levels in one
-    launch before the fused ones), "pairs-only" (pairs and single levels, no
-    fused coarsest levels).  True / False select "persistent" / "levels".
-    Results are bit-identical."""
+    level throughout), "pairs" (pairs in every direction), "pairs-only"
+    (pairs and single levels, no fused coarsest levels), "no-pairs" (single
+    levels and the fused coarsest levels).  True / False select
+    "persistent" / "levels".  Results are bit-identical."""
     if isinstance(path, bool):
         path = "persistent" if path else "levels"
     if path not in PATHS:

@@ -369,7 +369,9 @@ static int launch_tail_levels(int dir, const Call& c, const Geo& g, int k0, void
 // each covers levels [first, last] -- one level, a pair of levels, or the
 // fused tail.  Levels before the tail go in pairs from the finest one where
 // the pair kernels apply (a level-k input of at least kPairMin x kPairMin,
-// see fused.h), else one by one.
+// see fused.h), else one by one.  (Shortening a three-level tail so that a
+// pair takes its finest level, 8192^2 at six levels as pairs 1-2, 3-4 and
+// tail 5-6, measured no faster than pair 1-2, level 3 and tail 4-6.)
 constexpr int kPairMin = 8;
 int plan_launches(int dir, const Geo& g, int batch, bool tail, bool pairs, Launch* out) {
   const int k0 = tail ? tail_first_level(dir, g, batch) : 0;
@@ -389,6 +391,13 @@ int plan_launches(int dir, const Geo& g, int batch, bool tail, bool pairs, Launc
   for (int i = 0; i < n; ++i) out[i] = dir == kFwd ? fwd[i] : fwd[n - 1 - i];  // the inverses run coarsest first
   return n;
 }
+
+// Whether the default path uses pairs: measured on MI355X, the inverse and
+// adjoint pairs beat two single-level launches (8192^2 float, six levels:
+// 137 vs 148 us and 141 vs 150 us; 16384^2 int32 inverse: 518 vs 559 us),
+// the forward pair does not reliably (137 vs 140 us float, 581 vs 550 us
+// int32), so the forward keeps single levels by default.
+static bool default_pairs(int dir) { return dir != kFwd; }
 
 int run_levels(int dir, const Call& c, const Geo& g, void* stream, bool tail, bool pairs) {
   Launch plan[DWT2_MAX_LEVELS];
@@ -691,7 +700,7 @@ static int transform(int dir, const void* src, int64_t src_stride, int64_t src_b
   if (path == 1 && g.L <= kInlineDescs) return run_job(dir, c, g, stream);
   if (path == 2) return run_levels(dir, c, g, stream, false, false);
   if (path == 4) return run_levels(dir, c, g, stream, false, true);
-  return run_levels(dir, c, g, stream, true, path == 3);
+  return run_levels(dir, c, g, stream, true, path == 3 || (path == 0 && default_pairs(dir)));
 }
 
 int fwd_levels_path(const void* src, int64_t src_stride, int64_t src_bs, void* dst, int64_t dst_stride,
@@ -818,7 +827,7 @@ int dwt2_set_probe(int32_t dir, int32_t level, void* ev_begin, void* ev_end) {
 
 int dwt2_set_path(int32_t path) {
   clear_error();
-  if (path < 0 || path > 4) return fail(DWT2_ERR_ARG, "path must be 0 .. 4");
+  if (path < 0 || path > 5) return fail(DWT2_ERR_ARG, "path must be 0 .. 5");
   g_persistent.store(path);
   return DWT2_OK;
 }
@@ -839,7 +848,8 @@ int32_t dwt2_launch_levels(int32_t width, int32_t height, int32_t batch, int32_t
     return 1;
   }
   Launch plan[DWT2_MAX_LEVELS];
-  const int n = plan_launches(dir, g, batch, path != 2 && path != 4, path == 3 || path == 4, plan);
+  const bool pairs = path == 3 || path == 4 || (path == 0 && default_pairs(dir));
+  const int n = plan_launches(dir, g, batch, path != 2 && path != 4, pairs, plan);
   for (int i = 0; i < n && i < cap && first && last; ++i) {
     first[i] = plan[i].first;
     last[i] = plan[i].last;

@@ -184,6 +184,18 @@ template <int DIR> int launch_job_dir(int mode, const JobArgs& a, int blocks, vo
 template <int DIR> int job_blocks_per_cu_dir(int mode, bool table);
 template <int DIR> int launch_table_dir(int mode, const TableArgs& a, void* stream);
 
+// Each direction's instantiation lives in its own translation unit; the
+// others only refer to it.
+#define DWT2_EXTERN_STRIP(DIR)                                                        \
+  extern template int launch_level_dir<DIR>(int, int, const LevelLaunch&, void*);     \
+  extern template int launch_job_dir<DIR>(int, const JobArgs&, int, void*);           \
+  extern template int job_blocks_per_cu_dir<DIR>(int, bool);                          \
+  extern template int launch_table_dir<DIR>(int, const TableArgs&, void*);
+DWT2_EXTERN_STRIP(kFwd)
+DWT2_EXTERN_STRIP(kInv)
+DWT2_EXTERN_STRIP(kBwd)
+#undef DWT2_EXTERN_STRIP
+
 // One level of a plain call; `chunk`: prefetch chunk (1, 2 or 4 quadruple rows).
 inline int launch_level(int dir, int mode, int chunk, const LevelLaunch& a, void* stream) {
   if (dir == kFwd) return launch_level_dir<kFwd>(mode, chunk, a, stream);
@@ -213,8 +225,11 @@ inline int launch_table(int dir, int mode, const TableArgs& a, void* stream) {
 // quadruples of the coarser level, ll is the coarser level's LL, nstrips
 // counts strips of pair_strip_q(dir) owned quadruple columns of the finer
 // level.
-constexpr int pair_strip_q(int dir) { return dir == kBwd ? 120 : 122; }
+constexpr int pair_strip_q(int) { return 112; }
 template <int DIR> int launch_pair_dir(int mode, int chunk, const LevelLaunch& a, void* stream);
+extern template int launch_pair_dir<kFwd>(int, int, const LevelLaunch&, void*);
+extern template int launch_pair_dir<kInv>(int, int, const LevelLaunch&, void*);
+extern template int launch_pair_dir<kBwd>(int, int, const LevelLaunch&, void*);
 inline int launch_pair(int dir, int mode, int chunk, const LevelLaunch& a, void* stream) {
   if (dir == kFwd) return launch_pair_dir<kFwd>(mode, chunk, a, stream);
   if (dir == kInv) return launch_pair_dir<kInv>(mode, chunk, a, stream);

@@ -185,9 +185,9 @@ def test_batched_validation(lib, fn):
 
 
 def test_set_path_validation(lib):
-    assert lib.dwt2_set_path(5) == -1
+    assert lib.dwt2_set_path(6) == -1
     assert lib.dwt2_set_path(-1) == -1
-    for path in (1, 2, 3, 4, 0):
+    for path in (1, 2, 3, 4, 5, 0):
         assert lib.dwt2_set_path(path) == 0
 
 
