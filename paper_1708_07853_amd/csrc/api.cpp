@@ -275,7 +275,14 @@ static void pair_launch(int dir, const Call& c, const Geo& g, int k, LevelLaunch
   a.d.W = W;
   a.d.H = H;
   a.d.seg = t.seg;
-  a.d.nstrips = strips;
+  // the forward pair stages its level-(k+1) rows through LDS per workgroup
+  // of four adjacent strips when they would not stay in the caches (their
+  // bytes over the batch above kPairStageBytes): then pad the strips to a
+  // multiple of four (the extra strips lie past the image and store nothing)
+  const char* stage_env = getenv("DWT2_PAIR_STAGE_MB");  // read per call: tests switch it
+  const int64_t stage_bytes = stage_env ? (int64_t)atoi(stage_env) << 20 : kKeepBytes;
+  a.d.stage = dir == kFwd && (int64_t)ceil_half(W) * ceil_half(H) * 4 * c.batch > stage_bytes;
+  a.d.nstrips = a.d.stage ? (strips + kWavesPerBlock - 1) / kWavesPerBlock * kWavesPerBlock : strips;
   a.d.nsegs = (ns_h1 + t.seg - 1) / t.seg;
   LevelDesc dk, dk1;
   int64_t pix_bs, ll_bs, band_bs, u0, u1, u2;
@@ -365,6 +372,20 @@ static int launch_tail_levels(int dir, const Call& c, const Geo& g, int k0, void
   return launch_tail(dir, c.mode, t, stream);
 }
 
+// Which pairs the default path uses, from measurements on MI355X (six-level
+// calls; pair path against single levels):
+//   inverse, adjoint: faster everywhere (8192^2 float 138 vs 148 us and 141
+//     vs 150 us; 16384^2 float 521 vs 564 and 539 vs 573 us; 16384^2 int32
+//     inverse 519 vs 556 us; 32 x 3 x 1024^2 at four levels 208 vs 225 and
+//     206 vs 226 us);
+//   forward: faster for wide images (8192^2 float 137.5 vs 141 us, 16384^2
+//     float 527 vs 556 us, int32 525 vs 550 us), even at 4096^2, slower for
+//     the batch of narrow 1024^2 images (231 vs 221 us), whose few strips
+//     leave much of the overlapped and padded lanes idle: pairs from level-k
+//     inputs of at least kFwdPairMinW columns.
+constexpr int kFwdPairMinW = 4096;
+static bool default_pair(int dir, const Geo& g, int k) { return dir != kFwd || g.w[k - 1] >= kFwdPairMinW; }
+
 // The launches of a plain call on the per-level path, in execution order:
 // each covers levels [first, last] -- one level, a pair of levels, or the
 // fused tail.  Levels before the tail go in pairs from the finest one where
@@ -373,13 +394,14 @@ static int launch_tail_levels(int dir, const Call& c, const Geo& g, int k0, void
 // pair takes its finest level, 8192^2 at six levels as pairs 1-2, 3-4 and
 // tail 5-6, measured no faster than pair 1-2, level 3 and tail 4-6.)
 constexpr int kPairMin = 8;
-int plan_launches(int dir, const Geo& g, int batch, bool tail, bool pairs, Launch* out) {
+int plan_launches(int dir, const Geo& g, int batch, bool tail, int pairs, Launch* out) {
   const int k0 = tail ? tail_first_level(dir, g, batch) : 0;
   const int last_single = k0 ? k0 - 1 : g.L;  // levels 1 .. last_single precede the tail
   Launch fwd[DWT2_MAX_LEVELS];
   int n = 0;
   for (int k = 1; k <= last_single;) {
-    if (pairs && k + 1 <= last_single && g.w[k - 1] >= kPairMin && g.h[k - 1] >= kPairMin) {
+    const bool want = pairs == kPairsAll || (pairs == kPairsDefault && default_pair(dir, g, k));
+    if (want && k + 1 <= last_single && g.w[k - 1] >= kPairMin && g.h[k - 1] >= kPairMin) {
       fwd[n++] = Launch{k, k + 1, kLaunchPair};
       k += 2;
     } else {
@@ -392,14 +414,8 @@ int plan_launches(int dir, const Geo& g, int batch, bool tail, bool pairs, Launc
   return n;
 }
 
-// Whether the default path uses pairs: measured on MI355X, the inverse and
-// adjoint pairs beat two single-level launches (8192^2 float, six levels:
-// 137 vs 148 us and 141 vs 150 us; 16384^2 int32 inverse: 518 vs 559 us),
-// the forward pair does not reliably (137 vs 140 us float, 581 vs 550 us
-// int32), so the forward keeps single levels by default.
-static bool default_pairs(int dir) { return dir != kFwd; }
 
-int run_levels(int dir, const Call& c, const Geo& g, void* stream, bool tail, bool pairs) {
+int run_levels(int dir, const Call& c, const Geo& g, void* stream, bool tail, int pairs) {
   Launch plan[DWT2_MAX_LEVELS];
   const int nl = plan_launches(dir, g, c.batch, tail, pairs, plan);
   Probe pr;
@@ -694,13 +710,13 @@ static int transform(int dir, const void* src, int64_t src_stride, int64_t src_b
   // the per-level path whatever the process-wide setting (the entry point
   // without a workspace: it must not reach the persistent path, whose
   // host-visible error word is allocated on first use)
-  if (variant == kProductLevels) return run_levels(dir, c, g, stream, true, false);
+  if (variant == kProductLevels) return run_levels(dir, c, g, stream, true, kPairsNone);
   if (g_persistent.load() < 0) g_persistent.store(env_int("DWT2_PERSISTENT") == 1 ? 1 : 0);
   const int path = g_persistent.load();
   if (path == 1 && g.L <= kInlineDescs) return run_job(dir, c, g, stream);
-  if (path == 2) return run_levels(dir, c, g, stream, false, false);
-  if (path == 4) return run_levels(dir, c, g, stream, false, true);
-  return run_levels(dir, c, g, stream, true, path == 3 || (path == 0 && default_pairs(dir)));
+  if (path == 2) return run_levels(dir, c, g, stream, false, kPairsNone);
+  if (path == 4) return run_levels(dir, c, g, stream, false, kPairsAll);
+  return run_levels(dir, c, g, stream, true, path == 3 ? kPairsAll : (path == 5 ? kPairsNone : kPairsDefault));
 }
 
 int fwd_levels_path(const void* src, int64_t src_stride, int64_t src_bs, void* dst, int64_t dst_stride,
@@ -848,7 +864,7 @@ int32_t dwt2_launch_levels(int32_t width, int32_t height, int32_t batch, int32_t
     return 1;
   }
   Launch plan[DWT2_MAX_LEVELS];
-  const bool pairs = path == 3 || path == 4 || (path == 0 && default_pairs(dir));
+  const int pairs = path == 3 || path == 4 ? kPairsAll : (path == 0 ? kPairsDefault : kPairsNone);
   const int n = plan_launches(dir, g, batch, path != 2 && path != 4, pairs, plan);
   for (int i = 0; i < n && i < cap && first && last; ++i) {
     first[i] = plan[i].first;

@@ -42,6 +42,8 @@ struct LevelDesc {
   int32_t nstrips;
   int32_t nsegs;
   int32_t keep_out;     // a later launch reads this level's LL output (cache it)
+  int32_t stage;        // forward pair: stage the coarser level's rows through LDS
+  int32_t pad_;
 };
 
 // Plain (uniform-geometry) launch of one level over a batch of images.

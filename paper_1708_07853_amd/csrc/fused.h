@@ -187,9 +187,14 @@ __device__ __forceinline__ void bst1(T v, Rsrc r, int e) {
 // ---------------------------------------------------------------------------
 // Forward pair: levels k and k+1.
 // ---------------------------------------------------------------------------
-template <typename T, int CP, bool EDGE>
+// Level-(k+1) columns a workgroup of the forward pair stages through LDS.
+constexpr int kPairGroupQ = kWavesPerBlock * PairLanes<kFwd>::count;
+
+// stage_lds: the workgroup's staging array, 2 x 4 x kPairGroupQ elements
+// (one array for every wave of the workgroup, whichever variant it runs).
+template <typename T, int CP, bool EDGE, bool STAGED>
 __device__ void fwd_pair(const LevelDesc& d, const T* __restrict__ px, T* __restrict__ ll2, T* __restrict__ band,
-                         const PairItem& it) {
+                         const PairItem& it, T* stage_lds) {
   using O = Ops<T>;
   PairPx<T, EDGE> L;
   L.base = px; L.stride = d.pix_stride; L.W = it.W; L.H = it.H; L.c0 = 2 * it.qL;
@@ -208,22 +213,67 @@ __device__ void fwd_pair(const LevelDesc& d, const T* __restrict__ px, T* __rest
     bst2<kNT>(lhL, lhR, rlh, qst);
     bst2<kNT>(hhL, hhR, rhh, qst);
   };
-  // level-(k+1) stores (LL_{k+1} and the three bands): one element per lane
+  // level-(k+1) stores (LL_{k+1} and the three bands), one element per lane.
+  // STAGED: through LDS.  The four waves of a workgroup hold four adjacent
+  // strips of one segment (the host pads the strip count to a multiple of
+  // four), so together they own 224 adjacent level-(k+1) columns -- 896
+  // bytes of each band row, from a 128-byte boundary on.  Each wave puts its
+  // 56 values of the four bands into LDS, and after a barrier wave w writes
+  // band w's run with one 16-byte store per lane.  Otherwise each lane
+  // stores its 4-byte values directly with the write-back policy, which
+  // leaves partial cache lines at every strip edge for L2 to merge with the
+  // neighbouring strips' stores: cheap while the output stays in the caches
+  // (8192^2: 117 us for the pair, 123 staged), costly beyond them (16384^2:
+  // 533 us, 482 staged; streaming the 4-byte stores instead is no better).
+  T (*stage)[4][kPairGroupQ] = reinterpret_cast<T (*)[4][kPairGroupQ]>(stage_lds);
+  constexpr int kGroupQ = kPairGroupQ;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int lane = threadIdx.x & (kWave - 1);
+  const int slot = w * PairLanes<kFwd>::count + lane - PairLanes<kFwd>::base;  // this lane's column in the group
+  const int Q0 = it.Q - slot;                // the group's first level-(k+1) column
+  const int qs = 4 * lane;                   // the columns this lane stores: Q0 + qs .. Q0 + qs + 3
+  const bool st_lane = qs < kGroupQ;
+  int buf = 0;
   const int Qst = it.own ? it.Q : kOff;
   auto store_k1 = [&](int j, T ll, T hl, T lh, T hh) {
+    if constexpr (!STAGED) {
+      const bool real = j >= it.J0 && j < it.J1, real2 = real && j < it.nd_h1;
+      const Rsrc rl = row_rsrc(ll2 + (int64_t)j * ls, real ? it.ns_w1 * 4 : 0);
+      const Rsrc rh = row_rsrc(band + (int64_t)j * bs + it.ns_w1, real ? it.nd_w1 * 4 : 0);
+      T* row2 = band + (int64_t)(it.ns_h1 + j) * bs;
+      const Rsrc rlh = row_rsrc(row2, real2 ? it.ns_w1 * 4 : 0);
+      const Rsrc rhh = row_rsrc(row2 + it.ns_w1, real2 ? it.nd_w1 * 4 : 0);
+      bst1<0>(ll, rl, Qst);
+      bst1<0>(hl, rh, Qst);
+      bst1<0>(lh, rlh, Qst);
+      bst1<0>(hh, rhh, Qst);
+      return;
+    }
+    if (it.own) {
+      stage[buf][0][slot] = ll;
+      stage[buf][1][slot] = hl;
+      stage[buf][2][slot] = lh;
+      stage[buf][3][slot] = hh;
+    }
+    __syncthreads();
+    // wave w stores band w (0 LL_{k+1}, 1 HL, 2 LH, 3 HH) of row j
     const bool real = j >= it.J0 && j < it.J1, real2 = real && j < it.nd_h1;
-    const Rsrc rl = row_rsrc(ll2 + (int64_t)j * ls, real ? it.ns_w1 * 4 : 0);
-    const Rsrc rh = row_rsrc(band + (int64_t)j * bs + it.ns_w1, real ? it.nd_w1 * 4 : 0);
-    T* row2 = band + (int64_t)(it.ns_h1 + j) * bs;
-    const Rsrc rlh = row_rsrc(row2, real2 ? it.ns_w1 * 4 : 0);
-    const Rsrc rhh = row_rsrc(row2 + it.ns_w1, real2 ? it.nd_w1 * 4 : 0);
-    // one element per lane: these 4-byte stores leave partial cache lines,
-    // which the write-back policy merges in L2 with the neighbouring
-    // strips' stores (streaming them measured 20 % slower for the pair)
-    bst1<0>(ll, rl, Qst);
-    bst1<0>(hl, rh, Qst);
-    bst1<0>(lh, rlh, Qst);
-    bst1<0>(hh, rhh, Qst);
+    const bool hpar = w == 1 || w == 3;
+    const bool ok = w < 2 ? real : real2;
+    T* row = w == 0 ? ll2 + (int64_t)j * ls
+                    : band + (int64_t)(w < 2 ? j : it.ns_h1 + j) * bs + (hpar ? it.ns_w1 : 0);
+    const Rsrc rs = row_rsrc(row, ok ? (hpar ? it.nd_w1 : it.ns_w1) * 4 : 0);
+    V4<T> v;
+    v.x = stage[buf][w][st_lane ? qs : 0];
+    v.y = stage[buf][w][st_lane ? qs + 1 : 0];
+    v.z = stage[buf][w][st_lane ? qs + 2 : 0];
+    v.w = stage[buf][w][st_lane ? qs + 3 : 0];
+    // the group's columns before 0 (strip 0's left lanes) are not stored:
+    // Q0 >= 0 always, since the first group starts at column 0
+    // LL_{k+1} keeps the caching policy when a later launch reads it
+    if (w == 0 && d.keep_out) bst4<0>(v, rs, st_lane ? Q0 + qs : kOff);
+    else bst4<kNT>(v, rs, st_lane ? Q0 + qs : kOff);
+    buf ^= 1;
   };
 
   // ---- level k: one quadruple row from pixel rows E (2i), O (2i+1), E1 (2i+2)
@@ -695,8 +745,14 @@ __global__ __launch_bounds__(kBlock) void pair_kernel(LevelLaunch a) {
     const T* px = static_cast<const T*>(d.pix_in) + img * a.pix_bstride;
     T* ll2 = static_cast<T*>(d.ll_out) + img * a.ll_bstride;
     T* band = static_cast<T*>(d.band_out) + img * a.band_bstride;
-    if (edge) fwd_pair<T, CP, true>(d, px, ll2, band, it);
-    else fwd_pair<T, CP, false>(d, px, ll2, band, it);
+    __shared__ T stage[2 * 4 * kPairGroupQ];
+    if (d.stage) {
+      if (edge) fwd_pair<T, CP, true, true>(d, px, ll2, band, it, stage);
+      else fwd_pair<T, CP, false, true>(d, px, ll2, band, it, stage);
+    } else {
+      if (edge) fwd_pair<T, CP, true, false>(d, px, ll2, band, it, stage);
+      else fwd_pair<T, CP, false, false>(d, px, ll2, band, it, stage);
+    }
   } else {
     const T* ll2 = static_cast<const T*>(d.ll_in) + img * a.ll_bstride;
     const T* band = static_cast<const T*>(d.band_in) + img * a.band_bstride;

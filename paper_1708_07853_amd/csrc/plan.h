@@ -59,8 +59,11 @@ enum { kLaunchLevel = 0, kLaunchPair = 1, kLaunchTail = 2 };
 struct Launch {
   int first, last, kind;
 };
-int plan_launches(int dir, const Geo& g, int batch, bool tail, bool pairs, Launch* out);
-int run_levels(int dir, const Call& c, const Geo& g, void* stream, bool tail, bool pairs);
+// Which levels go in pairs: none, every pair that applies, or the pairs the
+// default path picks (see default_pair in api.cpp).
+enum { kPairsNone = 0, kPairsAll = 1, kPairsDefault = 2 };
+int plan_launches(int dir, const Geo& g, int batch, bool tail, int pairs, Launch* out);
+int run_levels(int dir, const Call& c, const Geo& g, void* stream, bool tail, int pairs);
 int run_job(int dir, const Call& c, const Geo& g, void* stream);
 // dwt2_fwd on the per-level path whatever the process-wide path setting
 // (validation, errors and results as dwt2_fwd).

@@ -45,8 +45,17 @@ def _max_levels(w, h):
     return lv
 
 
+@pytest.fixture(params=["direct", "staged"])
+def fwd_stores(request, monkeypatch):
+    """The forward pair's two ways of storing the coarser level: direct
+    4-byte stores (small outputs) or staged through LDS (large outputs),
+    forced here by the size threshold."""
+    monkeypatch.setenv("DWT2_PAIR_STAGE_MB", "0" if request.param == "staged" else "100000")
+    return request.param
+
+
 @pytest.mark.parametrize("mode", ["f32", "int"])
-def test_pairs_equal_single_levels(mode):
+def test_pairs_equal_single_levels(mode, fwd_stores):
     d = D()
     dt = np.float32 if mode == "f32" else np.int32
     try:
@@ -56,7 +65,7 @@ def test_pairs_equal_single_levels(mode):
             for levels in sorted({2, 3, _max_levels(w, h)}):
                 if levels > _max_levels(w, h):
                     continue
-                print(f"pairs: {mode} {h}x{w} L={levels}", flush=True)
+                print(f"pairs: {mode} {fwd_stores} {h}x{w} L={levels}", flush=True)
                 d.set_path("levels-only")
                 ref_f = d.fwd(x, levels)
                 ref_i = d.inv(ref_f, levels)
@@ -95,7 +104,7 @@ def test_pairs_match_oracle(mode):
 
 
 @pytest.mark.parametrize("mode", ["f32", "int"])
-def test_pairs_every_tiling(mode):
+def test_pairs_every_tiling(mode, fwd_stores):
     d = D()
     dt = np.float32 if mode == "f32" else np.int32
     x = _img(203, 1001, 5, dt)
@@ -118,7 +127,7 @@ def test_pairs_every_tiling(mode):
         d.set_path("levels")
 
 
-def test_pairs_batch_and_strided_views():
+def test_pairs_batch_and_strided_views(fwd_stores):
     d = D()
     xb = _img(3 * 150, 700, 9, np.float32).reshape(3, 150, 700)
     view = xb[:, 3:140, 5:650]          # strided, misaligned rows
