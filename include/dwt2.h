@@ -305,9 +305,10 @@ int dwt2_set_tiling(int32_t seg, int32_t chunk);
  * runs them in LDS on its tile plus a recompute halo; the inverse also
  * needs the coarsest input at least 4 x 4).
  *   0 (default): pairs for dwt2_inv and dwt2_bwd, and for dwt2_fwd where
- *     the level-k input is at least 4096 columns wide, single levels
- *     elsewhere (what measured fastest on MI355X), then the fused coarsest
- *     levels;
+ *     the pair's strips (112 quadruple columns each) would be at least 80 %
+ *     filled by the level-k input's ceil(w/2) quadruple columns, single
+ *     levels elsewhere (what measured fastest on MI355X), then the fused
+ *     coarsest levels;
  *   1: every level of a call in one cooperative persistent launch whose
  *     work items wait only for the rows they read;
  *   2: one launch per level throughout;

@@ -372,19 +372,24 @@ static int launch_tail_levels(int dir, const Call& c, const Geo& g, int k0, void
   return launch_tail(dir, c.mode, t, stream);
 }
 
-// Which pairs the default path uses, from measurements on MI355X (six-level
-// calls; pair path against single levels):
-//   inverse, adjoint: faster everywhere (8192^2 float 138 vs 148 us and 141
-//     vs 150 us; 16384^2 float 521 vs 564 and 539 vs 573 us; 16384^2 int32
-//     inverse 519 vs 556 us; 32 x 3 x 1024^2 at four levels 208 vs 225 and
-//     206 vs 226 us);
-//   forward: faster for wide images (8192^2 float 137.5 vs 141 us, 16384^2
-//     float 527 vs 556 us, int32 525 vs 550 us), even at 4096^2, slower for
-//     the batch of narrow 1024^2 images (231 vs 221 us), whose few strips
-//     leave much of the overlapped and padded lanes idle: pairs from level-k
-//     inputs of at least kFwdPairMinW columns.
-constexpr int kFwdPairMinW = 4096;
-static bool default_pair(int dir, const Geo& g, int k) { return dir != kFwd || g.w[k - 1] >= kFwdPairMinW; }
+// Which pairs the default path uses, from measurements on MI355X (whole
+// calls, default path against single levels, same tail):
+//   inverse, adjoint: faster everywhere (8192^2 float six levels 127 vs 144
+//     us and 132 vs 147 us; 16384^2 int32 inverse 472 vs 554 us;
+//     32 x 3 x 1024^2 at four levels 186 vs 219 and 192 vs 219 us; 96 x 512^2
+//     at four levels 51 vs 71 and 60 vs 69 us);
+//   forward: faster where the strips' owned lanes are mostly busy (8192^2
+//     131.5 vs 140.9 us, 16384^2 int32 486 vs 552 us, 32 x 3 x 1024^2 207 vs
+//     224 us, 24 x 2048^2 at five levels 206 vs 229 us), slower for the batch
+//     of 512^2 images (74 vs 66 us), whose level-1 strips own 256 quadruple
+//     columns in 336 lanes' worth: the forward pairs a level only when at
+//     least 80 % of its strips' owned lanes hold quadruples.
+static bool default_pair(int dir, const Geo& g, int k) {
+  if (dir != kFwd) return true;
+  const int ns_w = ceil_half(g.w[k - 1]), q = pair_strip_q(dir);
+  const int strips = (ns_w + q - 1) / q;
+  return 5 * ns_w >= 4 * strips * q;
+}
 
 // The launches of a plain call on the per-level path, in execution order:
 // each covers levels [first, last] -- one level, a pair of levels, or the

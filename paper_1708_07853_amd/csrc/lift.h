@@ -652,7 +652,12 @@ struct BandLoader {
   // per-dword range check already yields the zeros past a band's end.
   __device__ __forceinline__ void part(const T* rl, const T* rh, bool valid, bool ll_row, T& lL, T& lR, T& hL, T& hR,
                                        V4<T>& pt, T& h0, T& h1) const {
-    constexpr int P = Pol<COH>::ld, PH = Pol<COH>::halo, PB = kNT;
+    // LL rows outside a persistent job take the caching policy: the two
+    // halo values of the strip's edge lanes usually come from LL rows, and
+    // with the rows streamed they missed in L2 (8192^2 float, one level:
+    // inverse 97.6 -> 94.0 us, adjoint 99.8 -> 96.4 us; caching the H-band
+    // rows as well measured slower than either).
+    constexpr int P = COH == kCoh ? Pol<COH>::ld : 0, PH = Pol<COH>::halo, PB = kNT;
     const Rsrc bl = row_rsrc(rl, (MIRROR || valid) ? ns_w * 4 : 0);
     const Rsrc bh = row_rsrc(rh, (MIRROR || valid) ? nd_w * 4 : 0);
     if (ll_row) bld2<P>(bl, qL, lL, lR);
