@@ -296,6 +296,36 @@ int dwt2_fwd_noalloc(const void* src, int64_t src_stride, int64_t src_batch_stri
  * Returns DWT2_OK, or DWT2_ERR_ARG for values outside those ranges. */
 int dwt2_set_tiling(int32_t seg, int32_t chunk);
 
+/* Per-shape tuning of the work-item height of the per-level path (a
+ * performance aid; results never change).  Runs the call that dwt2_fwd
+ * (dir 0), dwt2_inv (dir 1) or dwt2_bwd (dir 2) would run with these
+ * arguments -- same meaning, layout, validation and errors -- several
+ * times: for each single-level or pair launch of the current path, in
+ * execution order, it times that launch (events on `stream`) at a few
+ * candidate heights and records the fastest for the launch's shape
+ * (launch kind, direction, mode, level input size, batch) when it beats
+ * the automatic choice by more than 2 %.  Later calls of any entry point
+ * on the per-level path that launch the same shape use the recorded
+ * height, unless dwt2_set_tiling forces one.  dst and the workspace are
+ * overwritten (dst ends holding the call's result); src is only read.
+ * Blocks the host until the timed calls finish; not capturable into a
+ * graph; must not race with other calls.  Does nothing more than one call
+ * when a tiling is forced or the persistent path is selected.  Returns
+ * DWT2_OK or the status of the first failing call (DWT2_ERR_ARG also for
+ * dir outside 0..2, DWT2_ERR_HIP for event failures). */
+int dwt2_tune(int32_t dir, const void* src, int64_t src_stride, int64_t src_batch_stride,
+              void* dst, int64_t dst_stride, int64_t dst_batch_stride,
+              int32_t width, int32_t height, int32_t batch, int32_t levels,
+              int32_t mode, int32_t boundary, void* workspace, size_t workspace_bytes,
+              void* stream);
+
+/* Number of launch shapes with a recorded height (dwt2_tune). */
+int32_t dwt2_tune_entries(void);
+
+/* Forgets every recorded height; always DWT2_OK.  Must not race with
+ * running calls. */
+int dwt2_tune_clear(void);
+
 /* Process-wide choice of how levels are chained, for tests and
  * measurements.  The building blocks: single-level launches; pair launches
  * (levels k and k+1 in one launch that keeps LL_k on chip, from the finest

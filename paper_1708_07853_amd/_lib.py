@@ -27,7 +27,8 @@ EXPORTS = [
     "dwt2_status_string", "dwt2_last_error", "dwt2_clear_plan_cache", "dwt2_set_tiling", "dwt2_set_path",
     "dwt2_set_probe", "dwt2_separable_workspace_size", "dwt2_fwd_separable", "dwt2_fwd_lds",
     "dwt2_fwd_cdf97", "dwt2_inv_cdf97", "dwt2_fwd_cdf97_separable", "dwt2_set_job_wait", "dwt2_synchronize",
-    "dwt2_plan_cache_size", "dwt2_launch_levels", "dwt2_fwd_noalloc",
+    "dwt2_plan_cache_size", "dwt2_launch_levels", "dwt2_fwd_noalloc", "dwt2_tune", "dwt2_tune_entries",
+    "dwt2_tune_clear",
 ]
 
 
@@ -75,6 +76,12 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         fn.restype = ctypes.c_int
     lib.dwt2_fwd_noalloc.argtypes = [vp, i64, i64, vp, i64, i64, i32, i32, i32, i32, i32, i32, vp]
     lib.dwt2_fwd_noalloc.restype = ctypes.c_int
+    lib.dwt2_tune.argtypes = [i32, vp, i64, i64, vp, i64, i64, i32, i32, i32, i32, i32, i32, vp, sz, vp]
+    lib.dwt2_tune.restype = ctypes.c_int
+    lib.dwt2_tune_entries.argtypes = []
+    lib.dwt2_tune_entries.restype = i32
+    lib.dwt2_tune_clear.argtypes = []
+    lib.dwt2_tune_clear.restype = ctypes.c_int
     lib.dwt2_fwd_lds.argtypes = [vp, i64, i64, vp, i64, i64, i32, i32, i32, i32, i32, i32, i32, vp, sz, vp]
     lib.dwt2_fwd_lds.restype = ctypes.c_int
     lib.dwt2_batched_workspace_size.argtypes = [ctypes.POINTER(Dwt2Image), i32, i32, i32]

@@ -167,7 +167,7 @@ def separable_workspace_size(w: int, h: int, levels: int, batch: int = 1, mode: 
 
 
 def _run(name: str, x: torch.Tensor, levels: int, mode, out: torch.Tensor | None,
-         workspace: torch.Tensor | None = None, extra: tuple = ()) -> torch.Tensor:
+         workspace: torch.Tensor | None = None, extra: tuple = (), lead: tuple = ()) -> torch.Tensor:
     lib = _lib.load()
     mode = _mode_of(x, mode)
     xb = _as_batch(x)
@@ -189,7 +189,7 @@ def _run(name: str, x: torch.Tensor, levels: int, mode, out: torch.Tensor | None
             ws = torch.empty(nbytes, dtype=torch.uint8, device=x.device)
     with torch.cuda.device(x.device):
         status = getattr(lib, name)(
-            xb.data_ptr(), xb.stride(1), xb.stride(0) if batch > 1 else 0,
+            *lead, xb.data_ptr(), xb.stride(1), xb.stride(0) if batch > 1 else 0,
             ob.data_ptr(), ob.stride(1), ob.stride(0) if batch > 1 else 0,
             w, h, batch, levels, mode, DWT2_EXT_SYMMETRIC, *extra,
             ws.data_ptr() if ws is not None else None, nbytes, _stream())
@@ -212,6 +212,27 @@ def inv(c: torch.Tensor, levels: int, mode=None, out=None, workspace=None) -> to
 def bwd(g: torch.Tensor, levels: int, out=None, workspace=None) -> torch.Tensor:
     """Adjoint of the float forward transform: W^T g."""
     return _run("dwt2_bwd", g, levels, DWT2_F32, out, workspace)
+
+
+def tune(direction: str, x: torch.Tensor, levels: int, mode=None, out=None, workspace=None) -> torch.Tensor:
+    """Tune the work-item heights of the launches of `direction` ("fwd",
+    "inv" or "bwd") on inputs shaped like x (see dwt2_tune): later calls of
+    the same shapes use the fastest heights.  Returns the call's result."""
+    if direction not in _PROBE_DIRS:
+        raise ValueError("direction must be 'fwd', 'inv' or 'bwd'")
+    if direction == "bwd":
+        mode = DWT2_F32
+    return _run("dwt2_tune", x, levels, mode, out, workspace, lead=(_PROBE_DIRS[direction],))
+
+
+def tune_entries() -> int:
+    """Launch shapes with a tuned height."""
+    return int(_lib.load().dwt2_tune_entries())
+
+
+def tune_clear() -> None:
+    """Forget every tuned height."""
+    _lib.check(_lib.load().dwt2_tune_clear())
 
 
 def _image_table(srcs: Sequence[torch.Tensor], dsts: Sequence[torch.Tensor]):

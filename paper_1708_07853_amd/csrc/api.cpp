@@ -7,8 +7,11 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <algorithm>
+#include <map>
 #include <mutex>
 #include <string>
+#include <tuple>
 
 #include "dwt2_internal.h"
 #include "plan.h"
@@ -203,6 +206,48 @@ Tiling choose_tiling(int ns_h, int64_t strips_times_batch, int64_t slots_hint) {
   return t;
 }
 
+// Segment heights picked by dwt2_tune, per launch shape (launch kind,
+// direction, mode, level-k input size, batch).  While dwt2_tune times one
+// launch, g_trial holds the height under test for that shape.  The table is
+// never destroyed, so process exit runs no teardown code for it.
+struct TuneKey {
+  int kind, dir, mode, w, h, batch;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(kind, dir, mode, w, h, batch) < std::tie(o.kind, o.dir, o.mode, o.w, o.h, o.batch);
+  }
+  bool operator==(const TuneKey& o) const { return !(*this < o) && !(o < *this); }
+};
+struct Trial {
+  bool on = false;
+  TuneKey key{};
+  int seg = 0;
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, int>& g_tuned_seg = *new std::map<TuneKey, int>;
+Trial g_trial;
+
+// The tiling of a per-level-path launch: the model's (choose_tiling), or
+// the tuned height for its shape; a forced tiling (dwt2_set_tiling) wins.
+static Tiling tuned_tiling(Tiling t, int kind, int dir, int mode, const Geo& g, int k, int batch) {
+  if (g_forced_seg.load() > 0) return t;
+  const TuneKey key{kind, dir, mode, g.w[k - 1], g.h[k - 1], batch};
+  int seg = 0;
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    if (g_trial.on && g_trial.key == key) {
+      seg = g_trial.seg;
+    } else {
+      auto it = g_tuned_seg.find(key);
+      if (it != g_tuned_seg.end()) seg = it->second;
+    }
+  }
+  if (seg > 0) {
+    t.seg = seg;
+    if (g_forced_ch.load() <= 0) t.ch = seg < 4 ? 1 : 2;  // choose_tiling's chunk rule
+  }
+  return t;
+}
+
 void fill_level(LevelDesc& d, int W, int H, int seg) {
   d.W = W;
   d.H = H;
@@ -249,7 +294,8 @@ static void level_launch(int dir, const Call& c, const Geo& g, int k, int64_t sl
   memset(&a, 0, sizeof a);
   const int W = g.w[k - 1], H = g.h[k - 1];
   const int64_t strips_batch = (int64_t)num_strips(W) * c.batch;
-  const Tiling t = choose_tiling(ceil_half(H), strips_batch, slots_hint);
+  Tiling t = choose_tiling(ceil_half(H), strips_batch, slots_hint);
+  if (slots_hint == 0) t = tuned_tiling(t, kLaunchLevel, dir, c.mode, g, k, c.batch);
   ch = t.ch;
   fill_level(a.d, W, H, t.seg);
   level_pointers(dir, c, g, k, a.d, a.pix_bstride, a.ll_bstride, a.band_bstride);
@@ -270,7 +316,7 @@ static void pair_launch(int dir, const Call& c, const Geo& g, int k, LevelLaunch
   const int W = g.w[k - 1], H = g.h[k - 1];
   const int ns_w = ceil_half(W), ns_h1 = ceil_half(ceil_half(H));
   const int strips = (ns_w + pair_strip_q(dir) - 1) / pair_strip_q(dir);
-  const Tiling t = choose_tiling(ns_h1, (int64_t)strips * c.batch);
+  const Tiling t = tuned_tiling(choose_tiling(ns_h1, (int64_t)strips * c.batch), kLaunchPair, dir, c.mode, g, k, c.batch);
   ch = t.ch;
   a.d.W = W;
   a.d.H = H;
@@ -731,6 +777,122 @@ int fwd_levels_path(const void* src, int64_t src_stride, int64_t src_bs, void* d
                    boundary, workspace, workspace_bytes, stream, kProductLevels);
 }
 
+// The launches a plain call runs on the current per-level path setting
+// (0 when the persistent path takes the call).
+static int current_plan(int dir, const Geo& g, int batch, Launch* plan) {
+  if (g_persistent.load() < 0) g_persistent.store(env_int("DWT2_PERSISTENT") == 1 ? 1 : 0);
+  const int path = g_persistent.load();
+  if (path == 1 && g.L <= kInlineDescs) return 0;
+  const int pairs = path == 3 || path == 4 ? kPairsAll : (path == 0 ? kPairsDefault : kPairsNone);
+  return plan_launches(dir, g, batch, path != 2 && path != 4, pairs, plan);
+}
+
+// dwt2_tune: for each single-level or pair launch of the call, in
+// execution order, times the whole call once per candidate segment height
+// with events around that launch (the median of kTuneReps calls after two
+// untimed ones) and keeps the fastest height if it beats the model's by
+// more than kTuneGain; later calls of the same shapes use it.
+constexpr int kTuneReps = 5;
+constexpr float kTuneGain = 0.02f;
+static int tune(int dir, const void* src, int64_t src_stride, int64_t src_bs, void* dst, int64_t dst_stride,
+                int64_t dst_bs, int32_t width, int32_t height, int32_t batch, int32_t levels, int32_t mode,
+                int32_t boundary, void* workspace, size_t workspace_bytes, void* stream) {
+  auto call = [&]() {
+    return transform(dir, src, src_stride, src_bs, dst, dst_stride, dst_bs, width, height, batch, levels, mode,
+                     boundary, workspace, workspace_bytes, stream);
+  };
+  if (int st = call()) return st;  // validates every argument
+  Geo g;
+  check_geometry(width, height, levels, g);
+  Launch plan[DWT2_MAX_LEVELS];
+  const int n = g_forced_seg.load() > 0 ? 0 : current_plan(dir, g, batch, plan);
+  if (n == 0) return DWT2_OK;  // a forced tiling or the persistent path: nothing to tune
+  hipEvent_t ev[2 * kTuneReps] = {};
+  for (hipEvent_t& e : ev)
+    if (hipEventCreate(&e) != hipSuccess) {
+      for (hipEvent_t& f : ev)
+        if (f) (void)hipEventDestroy(f);
+      return fail(DWT2_ERR_HIP, "tuning event creation failed");
+    }
+  Probe saved;
+  {
+    std::lock_guard<std::mutex> lock(g_probe_mu);
+    saved = g_probe;
+  }
+  static const int kPairSegs[] = {0, 4, 6, 8, 10, 12, 16, 20, 24, 32};
+  static const int kLevelSegs[] = {0, 2, 4, 6, 8, 12, 16, 24, 32, 48, 64};
+  int st = DWT2_OK;
+  for (int i = 0; i < n && st == DWT2_OK; ++i) {
+    const Launch& l = plan[i];
+    if (l.kind == kLaunchTail) continue;
+    const int k = l.first;
+    const bool pair = l.kind == kLaunchPair;
+    const int rows = pair ? ceil_half(ceil_half(g.h[k - 1])) : ceil_half(g.h[k - 1]);
+    const TuneKey key{l.kind, dir, mode, g.w[k - 1], g.h[k - 1], batch};
+    {
+      std::lock_guard<std::mutex> lock(g_tune_mu);
+      g_tuned_seg.erase(key);  // candidate 0 is the model's height
+    }
+    const int* cand = pair ? kPairSegs : kLevelSegs;
+    const int ncand = pair ? (int)(sizeof kPairSegs / sizeof *kPairSegs) : (int)(sizeof kLevelSegs / sizeof *kLevelSegs);
+    float model_ms = 0.f, best_ms = 0.f;
+    int best = 0;
+    for (int j = 0; j < ncand && st == DWT2_OK; ++j) {
+      const int seg = cand[j];
+      if (seg > rows) continue;
+      {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        g_trial.on = seg > 0;
+        g_trial.key = key;
+        g_trial.seg = seg;
+      }
+      float t[kTuneReps];
+      for (int r = -2; r < kTuneReps && st == DWT2_OK; ++r) {
+        {
+          std::lock_guard<std::mutex> lock(g_probe_mu);
+          g_probe = Probe();
+          if (r >= 0) {
+            g_probe.dir = dir;
+            g_probe.level = k;
+            g_probe.begin = ev[2 * r];
+            g_probe.end = ev[2 * r + 1];
+          }
+        }
+        st = call();
+      }
+      if (st) break;
+      if (hipEventSynchronize(ev[2 * kTuneReps - 1]) != hipSuccess) {
+        st = fail(DWT2_ERR_HIP, "tuning event wait failed");
+        break;
+      }
+      for (int r = 0; r < kTuneReps && st == DWT2_OK; ++r)
+        if (hipEventElapsedTime(&t[r], ev[2 * r], ev[2 * r + 1]) != hipSuccess)
+          st = fail(DWT2_ERR_HIP, "tuning event time failed");
+      if (st) break;
+      std::sort(t, t + kTuneReps);
+      const float med = t[kTuneReps / 2];
+      if (seg == 0) model_ms = med;
+      if (j == 0 || med < best_ms) {
+        best_ms = med;
+        best = seg;
+      }
+    }
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_trial = Trial();
+    if (st == DWT2_OK && best > 0 && best_ms < (1.f - kTuneGain) * model_ms) g_tuned_seg[key] = best;
+  }
+  {
+    std::lock_guard<std::mutex> lock(g_probe_mu);
+    g_probe = saved;
+  }
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_trial = Trial();
+  }
+  for (hipEvent_t& e : ev) (void)hipEventDestroy(e);
+  return st;
+}
+
 }  // namespace dwt2
 
 using namespace dwt2;
@@ -850,6 +1012,27 @@ int dwt2_set_path(int32_t path) {
   clear_error();
   if (path < 0 || path > 5) return fail(DWT2_ERR_ARG, "path must be 0 .. 5");
   g_persistent.store(path);
+  return DWT2_OK;
+}
+
+int dwt2_tune(int32_t dir, const void* src, int64_t src_stride, int64_t src_batch_stride, void* dst,
+              int64_t dst_stride, int64_t dst_batch_stride, int32_t width, int32_t height, int32_t batch,
+              int32_t levels, int32_t mode, int32_t boundary, void* workspace, size_t workspace_bytes, void* stream) {
+  clear_error();
+  if (dir < 0 || dir > 2) return fail(DWT2_ERR_ARG, "dir must be 0 (forward), 1 (inverse) or 2 (adjoint)");
+  return tune(dir, src, src_stride, src_batch_stride, dst, dst_stride, dst_batch_stride, width, height, batch, levels,
+              mode, boundary, workspace, workspace_bytes, stream);
+}
+
+int32_t dwt2_tune_entries(void) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  return (int32_t)g_tuned_seg.size();
+}
+
+int dwt2_tune_clear(void) {
+  clear_error();
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  g_tuned_seg.clear();
   return DWT2_OK;
 }
 

@@ -278,3 +278,27 @@ def test_noalloc_validation(lib):
     assert lib.dwt2_fwd_noalloc(FAKE_A, 64, 0, FAKE_B, 64, 0, 1, 64, 1, 1, 0, 0, None) == -1
     assert lib.dwt2_fwd_noalloc(FAKE_A, 64, 0, FAKE_B, 64, 0, 64, 64, 1, 9, 0, 0, None) == -2
     assert lib.dwt2_fwd_noalloc(FAKE_A, 64, 0, FAKE_B, 64, 0, 64, 64, 1, 2, 7, 0, None) == -3
+
+
+def call_tune(lib, d=0, **kw):
+    a = dict(src=FAKE_A, ss=64, sb=0, dst=FAKE_B, ds=64, db=0, w=64, h=64, batch=1, levels=2,
+             mode=0, boundary=0, ws=FAKE_WS, wsb=1 << 30, stream=None)
+    a.update(kw)
+    return lib.dwt2_tune(d, a["src"], a["ss"], a["sb"], a["dst"], a["ds"], a["db"], a["w"], a["h"], a["batch"],
+                         a["levels"], a["mode"], a["boundary"], a["ws"], a["wsb"], a["stream"])
+
+
+@pytest.mark.parametrize("d", [0, 1, 2])
+@pytest.mark.parametrize("kw,code", BAD, ids=[str(b[0]) for b in BAD])
+def test_tune_validation_errors(lib, d, kw, code):
+    """dwt2_tune validates as the call it tunes, before any HIP call."""
+    assert call_tune(lib, d, **kw) == code
+    assert lib.dwt2_last_error().decode() != ""
+
+
+def test_tune_direction_and_table(lib):
+    assert call_tune(lib, 3) == -1
+    assert call_tune(lib, -1) == -1
+    assert call_tune(lib, 2, mode=1) == -3      # the adjoint is float only
+    assert lib.dwt2_tune_clear() == 0
+    assert lib.dwt2_tune_entries() == 0

@@ -32,9 +32,11 @@ def _img(h, w, seed, dt):
 
 
 # level-1 inputs: the smallest sizes a pair takes (8), odd and even sizes,
-# and widths around the 244-pixel strip pitch of the pair kernels
+# and widths around multiples of the 224-pixel strip pitch of the pair
+# kernels (112 owned quadruple columns per strip)
 SIZES_H = [8, 9, 10, 11, 13, 16, 17, 31, 34, 65, 130]
-SIZES_W = [8, 9, 12, 15, 33, 64, 239, 240, 241, 242, 243, 244, 245, 246, 250, 479, 481, 487, 489, 490, 731, 1030]
+SIZES_W = [8, 9, 12, 15, 33, 64, 221, 222, 223, 224, 225, 226, 227, 239, 244, 250, 446, 447, 448, 449, 450, 479,
+           489, 671, 672, 673, 731, 1030]
 SHAPES = [(h, 245) for h in SIZES_H] + [(37, w) for w in SIZES_W] + [(8, 8), (9, 9), (300, 1031), (1030, 300)]
 
 
