@@ -311,6 +311,7 @@ static void level_launch(int dir, const Call& c, const Geo& g, int k, int64_t sl
 // Levels k and k+1 in one pair launch: level k's pixels (input of the
 // forward, output of the inverse and adjoint), LL_{k+1} (output of the
 // forward, input of the others), and the packed array's bands of both.
+constexpr int kPairStageStrips = 24;
 static void pair_launch(int dir, const Call& c, const Geo& g, int k, LevelLaunch& a, int& ch) {
   memset(&a, 0, sizeof a);
   const int W = g.w[k - 1], H = g.h[k - 1];
@@ -321,13 +322,19 @@ static void pair_launch(int dir, const Call& c, const Geo& g, int k, LevelLaunch
   a.d.W = W;
   a.d.H = H;
   a.d.seg = t.seg;
-  // the forward pair stages its level-(k+1) rows through LDS per workgroup
-  // of four adjacent strips when they would not stay in the caches (their
-  // bytes over the batch above kPairStageBytes): then pad the strips to a
-  // multiple of four (the extra strips lie past the image and store nothing)
-  const char* stage_env = getenv("DWT2_PAIR_STAGE_MB");  // read per call: tests switch it
-  const int64_t stage_bytes = stage_env ? (int64_t)atoi(stage_env) << 20 : kKeepBytes;
-  a.d.stage = dir == kFwd && (int64_t)ceil_half(W) * ceil_half(H) * 4 * c.batch > stage_bytes;
+  // the forward pair stages its stores through LDS per workgroup of four
+  // adjacent strips (whole 128-byte lines instead of runs that split lines
+  // at strip edges) when the image has at least kPairStageStrips strips:
+  // then the strips are padded to a multiple of four (the extra strips lie
+  // past the image and store nothing), which costs more than it saves on
+  // narrower images.  Measured on MI355X, forward, default path: 8192^2
+  // six levels 129.8 staged vs 133.1 us, 16384^2 483 vs 508, 6144^2 83.0
+  // vs 86.7, 12000^2 287 vs 293; 4096^2 45.5 vs 44.0, 3000^2 five levels
+  // 33.2 vs 29.0, 32 x 3 x 1024^2 four levels 246 vs 204 (5 strips -> 8).
+  // DWT2_PAIR_STAGE=1 / 0 forces either form (read per call: tests switch it).
+  const char* stage_env = getenv("DWT2_PAIR_STAGE");
+  const bool staged = stage_env && *stage_env ? atoi(stage_env) != 0 : strips >= kPairStageStrips;
+  a.d.stage = dir == kFwd && staged;
   a.d.nstrips = a.d.stage ? (strips + kWavesPerBlock - 1) / kWavesPerBlock * kWavesPerBlock : strips;
   a.d.nsegs = (ns_h1 + t.seg - 1) / t.seg;
   LevelDesc dk, dk1;

@@ -196,10 +196,15 @@ __device__ __forceinline__ void bst1(T v, Rsrc r, int e) {
 // ---------------------------------------------------------------------------
 // Forward pair: levels k and k+1.
 // ---------------------------------------------------------------------------
-// Level-(k+1) columns a workgroup of the forward pair stages through LDS.
+// Level-(k+1) columns a workgroup of the forward pair stages through LDS,
+// and the staging array's layout: per buffer, the workgroup's run of each
+// of the three level-k bands on two level-k rows (kPairStageK elements
+// each), then its run of each of the four level-(k+1) bands (kPairGroupQ).
 constexpr int kPairGroupQ = kWavesPerBlock * PairLanes<kFwd>::count;
+constexpr int kPairStageK = 2 * kPairGroupQ;
+constexpr int kPairStageBuf = 6 * kPairStageK + 4 * kPairGroupQ;
 
-// stage_lds: the workgroup's staging array, 2 x 4 x kPairGroupQ elements
+// stage_lds: the workgroup's staging array, 2 x kPairStageBuf elements
 // (one array for every wave of the workgroup, whichever variant it runs).
 template <typename T, int CP, bool EDGE, bool STAGED>
 __device__ void fwd_pair(const LevelDesc& d, const T* __restrict__ px, T* __restrict__ ll2, T* __restrict__ band,
@@ -209,40 +214,56 @@ __device__ void fwd_pair(const LevelDesc& d, const T* __restrict__ px, T* __rest
   L.base = px; L.stride = d.pix_stride; L.W = it.W; L.H = it.H; L.c0 = 2 * it.qL;
   for (int k = 0; k < 4; ++k) L.pc[k] = fold_idx(L.c0 + k, it.W);
   const int64_t bs = d.band_stride, ls = d.ll_stride;
-  // level-k band stores: owned lanes only, rows [2 J0, min(2 J1, ns_h))
-  const int qst = it.own ? it.qL : kOff;
-  const int krow_lo = 2 * it.J0, krow_hi = min(2 * it.J1, it.ns_h);
-  auto store_k = [&](int i, T hlL, T hlR, T lhL, T lhR, T hhL, T hhR) {
-    const bool real = i >= krow_lo && i < krow_hi, real2 = real && i < it.nd_h;
-    const Rsrc rh = row_rsrc(band + (int64_t)i * bs + it.ns_w, real ? it.nd_w * 4 : 0);
-    T* row2 = band + (int64_t)(it.ns_h + i) * bs;
-    const Rsrc rlh = row_rsrc(row2, real2 ? it.ns_w * 4 : 0);
-    const Rsrc rhh = row_rsrc(row2 + it.ns_w, real2 ? it.nd_w * 4 : 0);
-    bst2<kNT>(hlL, hlR, rh, qst);
-    bst2<kNT>(lhL, lhR, rlh, qst);
-    bst2<kNT>(hhL, hhR, rhh, qst);
-  };
-  // level-(k+1) stores (LL_{k+1} and the three bands), one element per lane.
+  // Stores.  Direct: each lane writes its own values -- its two level-k
+  // quadruples' band values (8 bytes per band row, owned lanes only) with
+  // the streaming policy, its level-(k+1) values (4 bytes) with the
+  // write-back policy.  A strip's level-k runs are 448 bytes long, so every
+  // other strip starts in the middle of a 128-byte line, and the level-(k+1)
+  // runs (224 bytes) split lines at most strip edges.
   // STAGED: through LDS.  The four waves of a workgroup hold four adjacent
   // strips of one segment (the host pads the strip count to a multiple of
-  // four), so together they own 224 adjacent level-(k+1) columns -- 896
-  // bytes of each band row, from a 128-byte boundary on.  Each wave puts its
-  // 56 values of the four bands into LDS, and after a barrier wave w writes
-  // band w's run with one 16-byte store per lane.  Otherwise each lane
-  // stores its 4-byte values directly with the write-back policy, which
-  // leaves partial cache lines at every strip edge for L2 to merge with the
-  // neighbouring strips' stores: cheap while the output stays in the caches
-  // (8192^2: 117 us for the pair, 123 staged), costly beyond them (16384^2:
-  // 533 us, 482 staged; streaming the 4-byte stores instead is no better).
-  T (*stage)[4][kPairGroupQ] = reinterpret_cast<T (*)[4][kPairGroupQ]>(stage_lds);
-  constexpr int kGroupQ = kPairGroupQ;
+  // four), so together they own 448 adjacent level-k and 224 level-(k+1)
+  // columns: 1792 and 896 bytes of each band row, from a 128-byte boundary
+  // on.  Each wave puts its values of the two level-k rows and the
+  // level-(k+1) row of a step into LDS, and after one barrier the waves
+  // write whole runs with 16-byte stores: wave w the halves (w & 1) of the
+  // level-k band rows w >> 1, 2 + (w >> 1), 4 + (w >> 1) of the six, and
+  // level-(k+1) band w.  The prologue's level-k row goes out directly.
+  // Split lines cost: the staged pair takes 107.8 us on 8192^2 float, the
+  // direct one 110.8 us.
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int lane = threadIdx.x & (kWave - 1);
   const int slot = w * PairLanes<kFwd>::count + lane - PairLanes<kFwd>::base;  // this lane's column in the group
   const int Q0 = it.Q - slot;                // the group's first level-(k+1) column
-  const int qs = 4 * lane;                   // the columns this lane stores: Q0 + qs .. Q0 + qs + 3
-  const bool st_lane = qs < kGroupQ;
   int buf = 0;
+  bool direct_k = true;                      // level-k rows of the prologue
+  // level-k band stores: owned lanes only, rows [2 J0, min(2 J1, ns_h))
+  const int qst = it.own ? it.qL : kOff;
+  const int krow_lo = 2 * it.J0, krow_hi = min(2 * it.J1, it.ns_h);
+  // level-k band row `bnd` (0 HL, 1 LH, 2 HH) of row i, and whether it is stored
+  auto krow_rsrc = [&](int i, int bnd) {
+    const bool real = i >= krow_lo && i < krow_hi, real2 = real && i < it.nd_h;
+    T* row = bnd == 0 ? band + (int64_t)i * bs + it.ns_w
+                      : band + (int64_t)(it.ns_h + i) * bs + (bnd == 2 ? it.ns_w : 0);
+    const bool ok = bnd == 0 ? real : real2;
+    return row_rsrc(row, ok ? (bnd == 1 ? it.ns_w : it.nd_w) * 4 : 0);
+  };
+  auto store_k = [&](int i, T hlL, T hlR, T lhL, T lhR, T hhL, T hhR) {
+    if constexpr (STAGED) {
+      if (!direct_k) {
+        if (it.own) {  // row 2j+1 -> slot 0, row 2j+2 -> slot 1
+          T* sk = stage_lds + buf * kPairStageBuf + ((i + 1) & 1) * 3 * kPairStageK + 2 * slot;
+          sk[0] = hlL; sk[1] = hlR;
+          sk[kPairStageK] = lhL; sk[kPairStageK + 1] = lhR;
+          sk[2 * kPairStageK] = hhL; sk[2 * kPairStageK + 1] = hhR;
+        }
+        return;
+      }
+    }
+    bst2<kNT>(hlL, hlR, krow_rsrc(i, 0), qst);
+    bst2<kNT>(lhL, lhR, krow_rsrc(i, 1), qst);
+    bst2<kNT>(hhL, hhR, krow_rsrc(i, 2), qst);
+  };
   const int Qst = it.own ? it.Q : kOff;
   auto store_k1 = [&](int j, T ll, T hl, T lh, T hh) {
     if constexpr (!STAGED) {
@@ -258,25 +279,39 @@ __device__ void fwd_pair(const LevelDesc& d, const T* __restrict__ px, T* __rest
       bst1<0>(hh, rhh, Qst);
       return;
     }
+    T* sb = stage_lds + buf * kPairStageBuf;
     if (it.own) {
-      stage[buf][0][slot] = ll;
-      stage[buf][1][slot] = hl;
-      stage[buf][2][slot] = lh;
-      stage[buf][3][slot] = hh;
+      T* s1 = sb + 6 * kPairStageK + slot;
+      s1[0] = ll;
+      s1[kPairGroupQ] = hl;
+      s1[2 * kPairGroupQ] = lh;
+      s1[3 * kPairGroupQ] = hh;
     }
     __syncthreads();
-    // wave w stores band w (0 LL_{k+1}, 1 HL, 2 LH, 3 HH) of row j
+    // level-k rows 2j+1 (band rows 0..2) and 2j+2 (3..5)
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      const int rb = 2 * t + (w >> 1), half = w & 1;
+      const int r = rb >= 3 ? 1 : 0;
+      const int e = half * 4 * kWave + 4 * lane;  // element of the group's run
+      const bool st = e < kPairStageK;
+      const T* src = sb + rb * kPairStageK + (st ? e : 0);
+      V4<T> v;
+      v.x = src[0]; v.y = src[1]; v.z = src[2]; v.w = src[3];
+      bst4<kNT>(v, krow_rsrc(2 * j + 1 + r, rb - 3 * r), st ? 2 * Q0 + e : kOff);
+    }
+    // level k+1: wave w stores band w (0 LL_{k+1}, 1 HL, 2 LH, 3 HH) of row j
     const bool real = j >= it.J0 && j < it.J1, real2 = real && j < it.nd_h1;
     const bool hpar = w == 1 || w == 3;
     const bool ok = w < 2 ? real : real2;
     T* row = w == 0 ? ll2 + (int64_t)j * ls
                     : band + (int64_t)(w < 2 ? j : it.ns_h1 + j) * bs + (hpar ? it.ns_w1 : 0);
     const Rsrc rs = row_rsrc(row, ok ? (hpar ? it.nd_w1 : it.ns_w1) * 4 : 0);
+    const int qs = 4 * lane;                 // the columns this lane stores: Q0 + qs .. Q0 + qs + 3
+    const bool st_lane = qs < kPairGroupQ;
+    const T* src = sb + 6 * kPairStageK + w * kPairGroupQ + (st_lane ? qs : 0);
     V4<T> v;
-    v.x = stage[buf][w][st_lane ? qs : 0];
-    v.y = stage[buf][w][st_lane ? qs + 1 : 0];
-    v.z = stage[buf][w][st_lane ? qs + 2 : 0];
-    v.w = stage[buf][w][st_lane ? qs + 3 : 0];
+    v.x = src[0]; v.y = src[1]; v.z = src[2]; v.w = src[3];
     // the group's columns before 0 (strip 0's left lanes) are not stored:
     // Q0 >= 0 always, since the first group starts at column 0
     // LL_{k+1} keeps the caching policy when a later launch reads it
@@ -356,6 +391,7 @@ __device__ void fwd_pair(const LevelDesc& d, const T* __restrict__ px, T* __rest
     ea = l2; eb = r2;
     oc = l1; od = r1;  // replaced before use
   }
+  direct_k = false;
 
   // ---- pairs p = J0 .. J1-1: level-k rows 2p+1, 2p+2; level-(k+1) row p
   struct Buf {
@@ -754,7 +790,7 @@ __global__ __launch_bounds__(kBlock) void pair_kernel(LevelLaunch a) {
     const T* px = static_cast<const T*>(d.pix_in) + img * a.pix_bstride;
     T* ll2 = static_cast<T*>(d.ll_out) + img * a.ll_bstride;
     T* band = static_cast<T*>(d.band_out) + img * a.band_bstride;
-    __shared__ T stage[2 * 4 * kPairGroupQ];
+    __shared__ T stage[2 * kPairStageBuf];
     if (d.stage) {
       if (edge) fwd_pair<T, CP, true, true>(d, px, ll2, band, it, stage);
       else fwd_pair<T, CP, false, true>(d, px, ll2, band, it, stage);

@@ -49,10 +49,10 @@ def _max_levels(w, h):
 
 @pytest.fixture(params=["direct", "staged"])
 def fwd_stores(request, monkeypatch):
-    """The forward pair's two ways of storing the coarser level: direct
-    4-byte stores (small outputs) or staged through LDS (large outputs),
-    forced here by the size threshold."""
-    monkeypatch.setenv("DWT2_PAIR_STAGE_MB", "0" if request.param == "staged" else "100000")
+    """The forward pair's two ways of storing: each lane's values directly
+    (narrow images) or whole lines staged through LDS per workgroup of four
+    strips (wide images), forced here either way."""
+    monkeypatch.setenv("DWT2_PAIR_STAGE", "1" if request.param == "staged" else "0")
     return request.param
 
 
