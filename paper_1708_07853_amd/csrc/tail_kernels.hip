@@ -37,7 +37,8 @@ constexpr int kTailLoads = ((kTailS + 2 * 14) * (kTailS + 2 * 14) + kTailBlock -
 template <typename T>
 __global__ __launch_bounds__(kTailBlock) void tail_fwd(TailArgs a) {
   __shared__ T lds[kTailLds];
-  const int lx = threadIdx.x & (kTailRowT - 1), ly = threadIdx.x / kTailRowT;
+  const int lx = threadIdx.x & (kTailRowT - 1);
+  const int ly = __builtin_amdgcn_readfirstlane(threadIdx.x / kTailRowT);  // one wave per row: uniform
   const int tx = blockIdx.x % a.tiles_x, ty = blockIdx.x / a.tiles_x;
   const int n = a.n;
   // region arrays, one per level, then the three predict arrays
@@ -187,7 +188,8 @@ __global__ __launch_bounds__(kTailBlock) void tail_inv(TailArgs a) {
   T* U1 = U0 + EE;
   T* U2 = U1 + EE;
   T* XB[2] = {U2 + EE, U2 + 2 * EE};  // LL input of a level / its output
-  const int lx = threadIdx.x & (kTailRowT - 1), ly = threadIdx.x / kTailRowT;
+  const int lx = threadIdx.x & (kTailRowT - 1);
+  const int ly = __builtin_amdgcn_readfirstlane(threadIdx.x / kTailRowT);  // one wave per row: uniform
   const int tx = blockIdx.x % a.tiles_x, ty = blockIdx.x / a.tiles_x;
   const int n = a.n;
   // ranges per level (x, y): output pixels [d0, d1), quadruples [q0, q1]
@@ -332,7 +334,8 @@ __global__ __launch_bounds__(kTailBlock) void tail_bwd(TailArgs a) {
   float* GC = GB + EE;
   float* GD = GC + EE;
   float* XO = GD + EE;       // a level's output pixels (the finer level's LL)
-  const int lx = threadIdx.x & (kTailRowT - 1), ly = threadIdx.x / kTailRowT;
+  const int lx = threadIdx.x & (kTailRowT - 1);
+  const int ly = __builtin_amdgcn_readfirstlane(threadIdx.x / kTailRowT);  // one wave per row: uniform
   const int tx = blockIdx.x % a.tiles_x, ty = blockIdx.x / a.tiles_x;
   const int n = a.n;
   int d0x[kTailMaxLevels + 1], d1x[kTailMaxLevels + 1], d0y[kTailMaxLevels + 1], d1y[kTailMaxLevels + 1];
