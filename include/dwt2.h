@@ -330,7 +330,8 @@ int dwt2_tune_clear(void);
  * measurements.  The building blocks: single-level launches; pair launches
  * (levels k and k+1 in one launch that keeps LL_k on chip, from the finest
  * level, where the level-k input is at least 8 x 8); and the fused coarsest
- * levels (the 2-3 coarsest levels, when their inputs hold at most
+ * levels (the 2-3 coarsest levels -- at most 2 for dwt2_inv -- when their
+ * inputs hold at most
  * 1024 x 1024 pixels over the batch, in one launch in which each workgroup
  * runs them in LDS on its tile plus a recompute halo; the inverse also
  * needs the coarsest input at least 4 x 4).

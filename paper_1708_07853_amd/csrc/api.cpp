@@ -374,13 +374,18 @@ std::mutex g_probe_mu;
 Probe g_probe;
 
 // First level of the fused tail (0: none): the last 2..kTailMaxLevels
-// levels whose inputs hold at most kTailArea pixels over the whole batch.
-// Larger levels are bandwidth-bound and run faster in the strip kernels
-// than with the tail's recomputed halos; the tail wins only where launch
-// latency dominates.
+// levels whose inputs hold at most kTailArea pixels over the whole batch
+// (inverse: at most two levels).  Larger levels are bandwidth-bound and run
+// faster in the strip kernels than with the tail's recomputed halos; the
+// tail wins only where launch latency dominates.  The inverse tail's
+// coarse-to-fine walk leaves half its lanes idle, so a pair launch takes
+// its finest level: 8192^2 float at six levels inside the benchmark step,
+// tail 5-6 + pair 3-4 + pair 1-2 129.0 us against tail 4-6 + level 3 +
+// pair 1-2 132.0 us (forward and adjoint measured no faster that way).
 static int tail_first_level(int dir, const Geo& g, int batch) {
   int k = g.L, n = 0;
-  while (k >= 1 && n < kTailMaxLevels && (int64_t)g.w[k - 1] * g.h[k - 1] * batch <= kTailArea) {
+  const int nmax = dir == kInv ? 2 : kTailMaxLevels;
+  while (k >= 1 && n < nmax && (int64_t)g.w[k - 1] * g.h[k - 1] * batch <= kTailArea) {
     --k;
     ++n;
   }
