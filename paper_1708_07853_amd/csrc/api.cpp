@@ -668,6 +668,7 @@ static int run_cdf97(int dir, bool separable, const Call& c, const Geo& g, void*
     a.W = g.w[k - 1];
     a.H = g.h[k - 1];
     a.batch = c.batch;
+    a.final_out = dir == kFwd ? k == g.L : k == 1;  // no later level reads them
     int tx, ty;
     if (!cdf97_tiles(a.W, a.H, tx, ty)) return fail(DWT2_ERR_SIZE, "level %d needs more tiles than a launch holds", k);
     if (dir == kFwd) {

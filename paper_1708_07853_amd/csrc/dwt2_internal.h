@@ -172,7 +172,8 @@ struct Level97 {
   int64_t ll_stride, ll_bstride;
   void* out;           // forward: the packed array (H bands); inverse: the pixels
   int64_t out_stride, out_bstride;
-  int32_t W, H, batch, pad_;
+  int32_t W, H, batch;
+  int32_t final_out;   // 1: LL_k (forward) or the pixels (inverse) are final results
 };
 int cdf97_tiles(int W, int H, int& tiles_x, int& tiles_y);
 // separable: the comparison kernel with the eight separable steps (forward only)
