@@ -716,7 +716,20 @@ static int run_cdf97(int dir, bool separable, const Call& c, const Geo& g, void*
         a.out_bstride = ws_bs;
       }
     }
-    const int err = launch_cdf97_level(dir, separable, a, stream);
+    // the forward's levels of at least 16 x 16 run in the strip kernel
+    // (bit-identical to the tiled one; DWT2_CDF97_TILED=1, read per call,
+    // forces the tiled kernel for tests and comparisons)
+    int nstrips = 0;
+    const char* tiled_env = getenv("DWT2_CDF97_TILED");
+    const bool strip = dir == kFwd && !separable && cdf97_strip_geometry(a.W, a.H, nstrips) &&
+                       !(tiled_env && atoi(tiled_env) == 1);
+    int err;
+    if (strip) {
+      const Tiling t = choose_tiling(ceil_half(a.H), (int64_t)nstrips * c.batch);
+      err = launch_cdf97_strip(a, t.seg, t.ch, stream);
+    } else {
+      err = launch_cdf97_level(dir, separable, a, stream);
+    }
     if (err != hipSuccess)
       return fail(DWT2_ERR_HIP, "CDF 9/7 level %d launch failed: %s", k, hipGetErrorString((hipError_t)err));
   }

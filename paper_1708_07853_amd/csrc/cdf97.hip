@@ -21,7 +21,7 @@
 // quadruple.  Six planes (32640 bytes) leave room for five workgroups per CU.
 #include <hip/hip_runtime.h>
 
-#include "dwt2_internal.h"
+#include "fused.h"
 
 namespace dwt2 {
 namespace {
@@ -326,6 +326,143 @@ __global__ __launch_bounds__(kBlk, 5) void inv97(Level97 a, int tiles_x) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Forward level as a register-resident strip kernel (the default for level
+// inputs of at least kStrip97Min pixels on each axis).  The mapping is the
+// 5/3 pair kernels': a wave covers 128 quadruple columns, lane l holding two
+// adjacent quadruples (one 16-byte vector per pixel row), and owns the 112
+// columns of lanes 4..59.  The four spatial steps run in registers, row by
+// row: the first pair (alpha, beta) on quadruple row r, then the second
+// (gamma, delta) on row r - 1, which by then has its lower neighbour.  Each
+// step reaches one quadruple to one side, the predicts to the right and the
+// updates to the left, so after the four steps lanes 1..62 hold exact
+// values and every neighbour crosses lanes by DPP; the edge lanes of a strip
+// recompute its neighbours' columns instead of exchanging them.  Reads go
+// through the symmetric fold of the pixels, which commutes with the lifting
+// (it keeps every index's parity), exactly as in the tiled kernel, and each
+// output comes from the same step functions on the same operands: results
+// are bit-identical to fwd97.
+// ---------------------------------------------------------------------------
+constexpr int kStrip97Min = 16;
+
+template <bool EDGE, int CP>
+__device__ void fwd97_strip_item(const Level97& a, const float* __restrict__ px, float* __restrict__ ll,
+                                 float* __restrict__ band, int strip, int seg, int segh, int lane) {
+  using PL = PairLanes<kFwd>;
+  const int W = a.W, H = a.H;
+  const int ns_w = (W + 1) >> 1, ns_h = (H + 1) >> 1, nd_w = W >> 1, nd_h = H >> 1;
+  const int Q = PL::count * strip + lane - PL::base;  // the lane's quadruple pair
+  const int qL = 2 * Q;                                 // its first quadruple column
+  const bool own = lane >= PL::base && lane < PL::base + PL::count;
+  const int I0 = seg * segh, I1 = min(I0 + segh, ns_h);  // quadruple rows written
+  PairPx<float, EDGE> L;
+  L.base = px; L.stride = a.in_stride; L.W = W; L.H = H; L.c0 = 2 * qL;
+  for (int k = 0; k < 4; ++k) L.pc[k] = fold_idx(L.c0 + k, W);
+  const int qst = own ? qL : kOff;
+  const int64_t bs = a.out_stride, ls = a.ll_stride;
+  const bool keep_ll = !a.final_out;
+  // output row r: LL, HL, LH, HH of the lane's two quadruples
+  auto store = [&](int r, float llL, float llR, float hlL, float hlR, float lhL, float lhR, float hhL, float hhR) {
+    const bool real = r >= I0 && r < I1, real2 = real && r < nd_h;
+    const Rsrc rl = row_rsrc(ll + (int64_t)r * ls, real ? ns_w * 4 : 0);
+    const Rsrc rh = row_rsrc(band + (int64_t)r * bs + ns_w, real ? nd_w * 4 : 0);
+    float* row2 = band + (int64_t)(ns_h + r) * bs;
+    const Rsrc rlh = row_rsrc(row2, real2 ? ns_w * 4 : 0);
+    const Rsrc rhh = row_rsrc(row2 + ns_w, real2 ? nd_w * 4 : 0);
+    if (keep_ll) bst2<0>(llL * kLLScale, llR * kLLScale, rl, qst);
+    else bst2<kNT>(llL * kLLScale, llR * kLLScale, rl, qst);
+    bst2<kNT>(hlL, hlR, rh, qst);
+    bst2<kNT>(lhL, lhR, rlh, qst);
+    bst2<kNT>(hhL * kHHScale, hhR * kHHScale, rhh, qst);
+  };
+
+  V4<float> E;                                  // pixel row 2r of the row being computed
+  float p1U_L, p1U_R, p2U_L, p2U_R, p2U_P;      // first predict (c', d') of the row above
+  float a1L = 0.f, b1L = 0.f, c1L = 0.f, d1L = 0.f, a1R = 0.f, b1R = 0.f, c1R = 0.f, d1R = 0.f;  // first pair, row r-1
+  float q1U_L = 0.f, q1U_R = 0.f, q2U_L = 0.f, q2U_R = 0.f, q2U_P = 0.f;  // second predict of row r-2
+  // first pair (alpha, beta) on row r from pixel rows 2r (E), 2r+1 (O), 2r+2 (E1)
+  auto pair1 = [&](const V4<float>& O, const V4<float>& E1, float& aL, float& bL, float& cL, float& dL, float& aR,
+                   float& bR, float& cR, float& dR) {
+    float p0L, p1L, p2L, p0R, p1R, p2R;
+    sp_pred(kAlpha, kAlpha2, E.x, E.z, E1.x, E1.z, E.y, E1.y, O.x, O.z, O.y, p0L, p1L, p2L);
+    sp_pred(kAlpha, kAlpha2, E.z, from_next(E.x), E1.z, from_next(E1.x), E.w, E1.w, O.z, from_next(O.x), O.w, p0R,
+            p1R, p2R);
+    const float p0P = from_prev(p0R), p2P = from_prev(p2R);
+    sp_upd(kBeta, kBeta2, E.x, p0P, p0L, p1U_L, p1L, p2U_P, p2U_L, p2P, p2L, aL, bL, cL);
+    sp_upd(kBeta, kBeta2, E.z, p0L, p0R, p1U_R, p1R, p2U_L, p2U_R, p2L, p2R, aR, bR, cR);
+    dL = p2L;
+    dR = p2R;
+    p1U_L = p1L; p1U_R = p1R; p2U_L = p2L; p2U_R = p2R; p2U_P = p2P;
+    E = E1;
+  };
+  // prologue: pixel rows 2 I0 - 4 .. 2 I0; the first predict of row I0 - 2
+  // and the first pair of row I0 - 1
+  {
+    V4<float> v[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) L.load(2 * I0 - 4 + k, v[k]);
+    E = v[0];
+    float p0L, p0R;
+    sp_pred(kAlpha, kAlpha2, E.x, E.z, v[2].x, v[2].z, E.y, v[2].y, v[1].x, v[1].z, v[1].y, p0L, p1U_L, p2U_L);
+    sp_pred(kAlpha, kAlpha2, E.z, from_next(E.x), v[2].z, from_next(v[2].x), E.w, v[2].w, v[1].z, from_next(v[1].x),
+            v[1].w, p0R, p1U_R, p2U_R);
+    p2U_P = from_prev(p2U_R);
+    E = v[2];
+    pair1(v[3], v[4], a1L, b1L, c1L, d1L, a1R, b1R, c1R, d1R);
+  }
+  struct Buf {
+    V4<float> v[CP][2];
+  };
+  auto load_chunk = [&](Buf& b, int r0) {
+#pragma unroll
+    for (int m = 0; m < CP; ++m) {
+      L.load(2 * (r0 + m) + 1, b.v[m][0]);
+      L.load(2 * (r0 + m) + 2, b.v[m][1]);
+    }
+  };
+  // row r: the first pair of row r, then the second pair of row r - 1
+  auto row = [&](const Buf& b, int m, int r) {
+    float aL, bL, cL, dL, aR, bR, cR, dR;
+    pair1(b.v[m][0], b.v[m][1], aL, bL, cL, dL, aR, bR, cR, dR);
+    float q0L, q1L, q2L, q0R, q1R, q2R;
+    sp_pred(kGamma, kGamma2, a1L, a1R, aL, aR, b1L, bL, c1L, c1R, d1L, q0L, q1L, q2L);
+    sp_pred(kGamma, kGamma2, a1R, from_next(a1L), aR, from_next(aL), b1R, bR, c1R, from_next(c1L), d1R, q0R, q1R,
+            q2R);
+    const float q0P = from_prev(q0R), q2P = from_prev(q2R);
+    float llL, hlL, lhL, llR, hlR, lhR;
+    sp_upd(kDelta, kDelta2, a1L, q0P, q0L, q1U_L, q1L, q2U_P, q2U_L, q2P, q2L, llL, hlL, lhL);
+    sp_upd(kDelta, kDelta2, a1R, q0L, q0R, q1U_R, q1R, q2U_L, q2U_R, q2L, q2R, llR, hlR, lhR);
+    store(r - 1, llL, llR, hlL, hlR, lhL, lhR, q2L, q2R);
+    q1U_L = q1L; q1U_R = q1R; q2U_L = q2L; q2U_R = q2R; q2U_P = q2P;
+    a1L = aL; b1L = bL; c1L = cL; d1L = dL; a1R = aR; b1R = bR; c1R = cR; d1R = dR;
+  };
+  Buf A, B;
+  load_chunk(A, I0);
+  run_rows<CP>(I0, I1 + 1, A, B, load_chunk, row);
+}
+
+// One wave per (image, segment, strip) item; items past the grid's last
+// full workgroup return at once (no barrier in this kernel).
+template <int CP>
+__global__ __launch_bounds__(kBlock) void fwd97_strip(Level97 a, int nstrips, int nsegs, int segh, int64_t items) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t item = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock +
+                       __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  if (item >= items) return;
+  const int per_img = nstrips * nsegs;
+  const int img = (int)(item / per_img);
+  const int rem = (int)(item - (int64_t)img * per_img);
+  const int seg = rem / nstrips;
+  const int strip = rem - seg * nstrips;
+  const float* px = static_cast<const float*>(a.in) + img * a.in_bstride;
+  float* ll = static_cast<float*>(a.ll) + img * a.ll_bstride;
+  float* band = static_cast<float*>(a.out) + img * a.out_bstride;
+  // the wave's pixel columns 4 (112 strip - 4) .. + 255, all inside the image?
+  const int c_first = 4 * (PairLanes<kFwd>::count * strip - PairLanes<kFwd>::base);
+  if (c_first < 0 || c_first + 4 * kWave > a.W) fwd97_strip_item<true, CP>(a, px, ll, band, strip, seg, segh, lane);
+  else fwd97_strip_item<false, CP>(a, px, ll, band, strip, seg, segh, lane);
+}
+
 // Separable comparison kernel on the same tiles: per level and per pair,
 // horizontal predict, vertical predict, horizontal update, vertical update
 // (eq. (3)), eight steps with a workgroup barrier between steps, then the
@@ -417,6 +554,23 @@ int cdf97_tiles(int W, int H, int& tiles_x, int& tiles_y) {
   tiles_x = (((W + 1) >> 1) + kQX - 1) / kQX;
   tiles_y = (((H + 1) >> 1) + kQY - 1) / kQY;
   return (int64_t)tiles_x * tiles_y <= 0x7fffffff;
+}
+
+int cdf97_strip_geometry(int W, int H, int& nstrips) {
+  nstrips = (((W + 1) >> 1) + 2 * PairLanes<kFwd>::count - 1) / (2 * PairLanes<kFwd>::count);
+  return W >= kStrip97Min && H >= kStrip97Min;
+}
+
+int launch_cdf97_strip(const Level97& a, int segh, int chunk, void* stream) {
+  int nstrips;
+  if (!cdf97_strip_geometry(a.W, a.H, nstrips) || segh < 1) return hipErrorInvalidValue;
+  const int nsegs = (((a.H + 1) >> 1) + segh - 1) / segh;
+  const int64_t items = (int64_t)nstrips * nsegs * a.batch;
+  const dim3 grid((unsigned)((items + kWavesPerBlock - 1) / kWavesPerBlock));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (chunk >= 2) hipLaunchKernelGGL(fwd97_strip<2>, grid, dim3(kBlock), 0, s, a, nstrips, nsegs, segh, items);
+  else hipLaunchKernelGGL(fwd97_strip<1>, grid, dim3(kBlock), 0, s, a, nstrips, nsegs, segh, items);
+  return hipGetLastError();
 }
 
 int launch_cdf97_level(int dir, bool separable, const Level97& a, void* stream) {

@@ -67,6 +67,42 @@ def test_cdf97_forward_matches_oracle():
     print(f"worst forward error {worst:.3g}")
 
 
+# the forward's strip kernel (level inputs of at least 16 x 16): widths
+# around multiples of its 224-pixel strip pitch and of the 256-pixel wave,
+# heights across segment boundaries
+STRIP_SHAPES = [(16, 16), (17, 23), (16, 221), (33, 224), (40, 225), (19, 226), (64, 446), (65, 448), (31, 449),
+                (100, 479), (130, 672), (129, 673), (37, 1030), (300, 517), (260, 131), (16, 256), (23, 257)]
+
+
+def test_cdf97_strip_kernel_equals_tiled(monkeypatch):
+    """The register-resident forward (default from 16 x 16) is bit-identical
+    to the LDS-tiled kernel at every size, level count and work-item shape,
+    and matches the oracle."""
+    d = D()
+    for idx, (h, w) in enumerate(STRIP_SHAPES):
+        xn = _img(h, w, 9900 + idx)
+        x = to_gpu(xn)
+        for levels in sorted({1, 2, max_levels(w, h)}):
+            print(f"cdf97 strip: {h}x{w} levels {levels}", flush=True)
+            monkeypatch.setenv("DWT2_CDF97_TILED", "1")
+            ref = d.fwd_cdf97(x, levels)
+            monkeypatch.delenv("DWT2_CDF97_TILED")
+            got = d.fwd_cdf97(x, levels)
+            assert torch.equal(got, ref), (h, w, levels, float((got - ref).abs().max()))
+            assert maxdiff(got.cpu().numpy(), dwt97.fwd(xn, levels)) <= TOL97, (h, w, levels)
+    x = to_gpu(_img(300, 517, 9999))
+    monkeypatch.setenv("DWT2_CDF97_TILED", "1")
+    ref = d.fwd_cdf97(x, 3)
+    monkeypatch.delenv("DWT2_CDF97_TILED")
+    try:
+        for seg, ch in [(1, 1), (2, 2), (3, 1), (5, 2), (64, 2), (1000, 1)]:
+            print(f"cdf97 strip tiling: seg {seg} chunk {ch}", flush=True)
+            d.set_tiling(seg, ch)
+            assert torch.equal(d.fwd_cdf97(x, 3), ref), (seg, ch)
+    finally:
+        d.set_tiling(0, 0)
+
+
 def test_cdf97_inverse_matches_oracle_and_round_trips():
     d = D()
     for idx, (h, w) in enumerate(SHAPES):
