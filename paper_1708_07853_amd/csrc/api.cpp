@@ -716,17 +716,16 @@ static int run_cdf97(int dir, bool separable, const Call& c, const Geo& g, void*
         a.out_bstride = ws_bs;
       }
     }
-    // the forward's levels of at least 16 x 16 run in the strip kernel
-    // (bit-identical to the tiled one; DWT2_CDF97_TILED=1, read per call,
-    // forces the tiled kernel for tests and comparisons)
+    // levels of at least 16 x 16 run in the strip kernels (bit-identical to
+    // the tiled ones; DWT2_CDF97_TILED=1, read per call, forces the tiled
+    // kernels for tests and comparisons)
     int nstrips = 0;
     const char* tiled_env = getenv("DWT2_CDF97_TILED");
-    const bool strip = dir == kFwd && !separable && cdf97_strip_geometry(a.W, a.H, nstrips) &&
-                       !(tiled_env && atoi(tiled_env) == 1);
+    const bool strip = !separable && cdf97_strip_geometry(a.W, a.H, nstrips) && !(tiled_env && atoi(tiled_env) == 1);
     int err;
     if (strip) {
       const Tiling t = choose_tiling(ceil_half(a.H), (int64_t)nstrips * c.batch);
-      err = launch_cdf97_strip(a, t.seg, t.ch, stream);
+      err = launch_cdf97_strip(dir, a, t.seg, t.ch, stream);
     } else {
       err = launch_cdf97_level(dir, separable, a, stream);
     }

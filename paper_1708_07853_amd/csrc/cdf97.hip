@@ -441,6 +441,126 @@ __device__ void fwd97_strip_item(const Level97& a, const float* __restrict__ px,
   run_rows<CP>(I0, I1 + 1, A, B, load_chunk, row);
 }
 
+// Inverse level as a strip kernel, the same mapping: per quadruple row r it
+// undoes the second update (delta) on row r, the second predict (gamma) on
+// row r - 1, the first update (beta) on row r - 1 and the first predict
+// (alpha) on row r - 2, whose pixels it then writes.  The undone updates
+// reach up and left, the undone predicts down and right, so lanes 1..62 end
+// exact.  Coefficients are read through the symmetric extension of the
+// interleaved array (PairBands), as the tiled kernel reads them, and the
+// results are bit-identical to inv97.
+template <bool EDGE, int CP>
+__device__ void inv97_strip_item(const Level97& a, const float* __restrict__ lls, const float* __restrict__ bands,
+                                 float* __restrict__ px, int strip, int seg, int segh, int lane) {
+  using PL = PairLanes<kInv>;
+  const int W = a.W, H = a.H;
+  const int ns_h = (H + 1) >> 1;
+  const int qL = 2 * (PL::count * strip + lane - PL::base);
+  const bool own = lane >= PL::base && lane < PL::base + PL::count;
+  const int I0 = seg * segh, I1 = min(I0 + segh, ns_h);
+  const PairBands<float, true, EDGE, 2> B =
+      pair_bands<float, true, EDGE, 2>(bands, a.bands_stride, lls, a.in_stride, W, H, qL);
+  const int c0 = own ? 2 * qL : kOff;
+  const int lo = 2 * I0, hi = min(2 * I1, H);
+  auto store = [&](int r, const V4<float>& v) {  // pixel row r
+    const Rsrc rs = row_rsrc(px + (int64_t)r * a.out_stride, (r >= lo && r < hi) ? W * 4 : 0);
+    if (a.final_out) bst4<kNT>(v, rs, c0);
+    else bst4<0>(v, rs, c0);
+  };
+  // carried state: the scaled LH, HH of coefficient row r-1; the first
+  // undone step (U1) of row r-1; the second (P1, its c and d) of row r-2;
+  // the third (U2) of row r-2 with its d
+  float lhU_L, lhU_R, hhU_L, hhU_R, hhU_P;
+  float A1L, A1R, B1L, B1R, C1L, C1R, D1L, D1R;
+  float pcU_L = 0.f, pcU_R = 0.f, pdU_L = 0.f, pdU_R = 0.f, pdU_P = 0.f;
+  float A2L = 0.f, A2R = 0.f, B2L = 0.f, B2R = 0.f, C2L = 0.f, C2R = 0.f, D2L = 0.f, D2R = 0.f;
+  // U1 (undo delta) of a coefficient row
+  auto undo1 = [&](const float* ll, const float* hl, const float* lh, const float* hh, float& aL, float& bL, float& cL,
+                   float& dL, float& aR, float& bR, float& cR, float& dR) {
+    const float llL = ll[0] * kHHScale, llR = ll[1] * kHHScale;
+    const float hhL = hh[0] * kLLScale, hhR = hh[1] * kLLScale;
+    const float hlP = from_prev(hl[1]), hhP = from_prev(hhR);
+    sp_inv_upd(kDelta, kDelta2, llL, hlP, hl[0], lhU_L, lh[0], hhU_P, hhU_L, hhP, hhL, aL, bL, cL);
+    sp_inv_upd(kDelta, kDelta2, llR, hl[0], hl[1], lhU_R, lh[1], hhU_L, hhU_R, hhL, hhR, aR, bR, cR);
+    dL = hhL;
+    dR = hhR;
+    lhU_L = lh[0]; lhU_R = lh[1]; hhU_L = hhL; hhU_R = hhR; hhU_P = hhP;
+  };
+  // prologue: coefficient rows I0 - 2 (the up neighbours) and I0 - 1 (U1)
+  {
+    float ll0[2], hl0[2], lh0[2], hh0[2], ll1[2], hl1[2], lh1[2], hh1[2];
+    B.even(I0 - 2, ll0, hl0);
+    B.odd(I0 - 2, lh0, hh0);
+    B.even(I0 - 1, ll1, hl1);
+    B.odd(I0 - 1, lh1, hh1);
+    lhU_L = lh0[0]; lhU_R = lh0[1];
+    hhU_L = hh0[0] * kLLScale; hhU_R = hh0[1] * kLLScale;
+    hhU_P = from_prev(hhU_R);
+    undo1(ll1, hl1, lh1, hh1, A1L, B1L, C1L, D1L, A1R, B1R, C1R, D1R);
+  }
+  struct Buf {
+    float ll[CP][2], hl[CP][2], lh[CP][2], hh[CP][2];
+  };
+  auto load_chunk = [&](Buf& b, int r0) {
+#pragma unroll
+    for (int m = 0; m < CP; ++m) {
+      B.even(r0 + m, b.ll[m], b.hl[m]);
+      B.odd(r0 + m, b.lh[m], b.hh[m]);
+    }
+  };
+  auto row = [&](const Buf& b, int m, int r) {
+    float a1L, b1L, c1L, d1L, a1R, b1R, c1R, d1R;
+    undo1(b.ll[m], b.hl[m], b.lh[m], b.hh[m], a1L, b1L, c1L, d1L, a1R, b1R, c1R, d1R);
+    // P1 (undo gamma) of row r-1
+    float pbL, pcL, pdL, pbR, pcR, pdR;
+    sp_inv_pred(kGamma, kGamma2, A1L, A1R, a1L, a1R, B1L, b1L, C1L, C1R, D1L, pbL, pcL, pdL);
+    sp_inv_pred(kGamma, kGamma2, A1R, from_next(A1L), a1R, from_next(a1L), B1R, b1R, C1R, from_next(C1L), D1R, pbR,
+                pcR, pdR);
+    // U2 (undo beta) of row r-1
+    const float pbP = from_prev(pbR), pdP = from_prev(pdR);
+    float a2L, b2L, c2L, a2R, b2R, c2R;
+    sp_inv_upd(kBeta, kBeta2, A1L, pbP, pbL, pcU_L, pcL, pdU_P, pdU_L, pdP, pdL, a2L, b2L, c2L);
+    sp_inv_upd(kBeta, kBeta2, A1R, pbL, pbR, pcU_R, pcR, pdU_L, pdU_R, pdL, pdR, a2R, b2R, c2R);
+    pcU_L = pcL; pcU_R = pcR; pdU_L = pdL; pdU_R = pdR; pdU_P = pdP;
+    // P2 (undo alpha) of row r-2: its pixels
+    float xbL, xcL, xdL, xbR, xcR, xdR;
+    sp_inv_pred(kAlpha, kAlpha2, A2L, A2R, a2L, a2R, B2L, b2L, C2L, C2R, D2L, xbL, xcL, xdL);
+    sp_inv_pred(kAlpha, kAlpha2, A2R, from_next(A2L), a2R, from_next(a2L), B2R, b2R, C2R, from_next(C2L), D2R, xbR,
+                xcR, xdR);
+    V4<float> e, o;
+    e.x = A2L; e.y = xbL; e.z = A2R; e.w = xbR;
+    o.x = xcL; o.y = xdL; o.z = xcR; o.w = xdR;
+    store(2 * (r - 2), e);
+    store(2 * (r - 2) + 1, o);
+    A1L = a1L; B1L = b1L; C1L = c1L; D1L = d1L; A1R = a1R; B1R = b1R; C1R = c1R; D1R = d1R;
+    A2L = a2L; B2L = b2L; C2L = c2L; D2L = pdL; A2R = a2R; B2R = b2R; C2R = c2R; D2R = pdR;
+  };
+  Buf A, Bb;
+  load_chunk(A, I0);
+  run_rows<CP>(I0, I1 + 2, A, Bb, load_chunk, row);
+}
+
+template <int CP>
+__global__ __launch_bounds__(kBlock) void inv97_strip(Level97 a, int nstrips, int nsegs, int segh, int64_t items) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t item = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock +
+                       __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  if (item >= items) return;
+  const int per_img = nstrips * nsegs;
+  const int img = (int)(item / per_img);
+  const int rem = (int)(item - (int64_t)img * per_img);
+  const int seg = rem / nstrips;
+  const int strip = rem - seg * nstrips;
+  const float* lls = static_cast<const float*>(a.in) + img * a.in_bstride;
+  const float* bands = static_cast<const float*>(a.bands) + img * a.bands_bstride;
+  float* px = static_cast<float*>(a.out) + img * a.out_bstride;
+  // the wave's quadruple columns 2 (56 strip - 4) .. + 127: all with both
+  // band parities inside the bands?
+  const int q_first = 2 * (PairLanes<kInv>::count * strip - PairLanes<kInv>::base);
+  if (q_first < 0 || q_first + 2 * kWave > (a.W >> 1)) inv97_strip_item<true, CP>(a, lls, bands, px, strip, seg, segh, lane);
+  else inv97_strip_item<false, CP>(a, lls, bands, px, strip, seg, segh, lane);
+}
+
 // One wave per (image, segment, strip) item; items past the grid's last
 // full workgroup return at once (no barrier in this kernel).
 template <int CP>
@@ -561,15 +681,22 @@ int cdf97_strip_geometry(int W, int H, int& nstrips) {
   return W >= kStrip97Min && H >= kStrip97Min;
 }
 
-int launch_cdf97_strip(const Level97& a, int segh, int chunk, void* stream) {
+int launch_cdf97_strip(int dir, const Level97& a, int segh, int chunk, void* stream) {
   int nstrips;
   if (!cdf97_strip_geometry(a.W, a.H, nstrips) || segh < 1) return hipErrorInvalidValue;
   const int nsegs = (((a.H + 1) >> 1) + segh - 1) / segh;
   const int64_t items = (int64_t)nstrips * nsegs * a.batch;
   const dim3 grid((unsigned)((items + kWavesPerBlock - 1) / kWavesPerBlock));
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (chunk >= 2) hipLaunchKernelGGL(fwd97_strip<2>, grid, dim3(kBlock), 0, s, a, nstrips, nsegs, segh, items);
-  else hipLaunchKernelGGL(fwd97_strip<1>, grid, dim3(kBlock), 0, s, a, nstrips, nsegs, segh, items);
+  if (dir == kFwd) {
+    if (chunk >= 2) hipLaunchKernelGGL(fwd97_strip<2>, grid, dim3(kBlock), 0, s, a, nstrips, nsegs, segh, items);
+    else hipLaunchKernelGGL(fwd97_strip<1>, grid, dim3(kBlock), 0, s, a, nstrips, nsegs, segh, items);
+  } else if (dir == kInv) {
+    if (chunk >= 2) hipLaunchKernelGGL(inv97_strip<2>, grid, dim3(kBlock), 0, s, a, nstrips, nsegs, segh, items);
+    else hipLaunchKernelGGL(inv97_strip<1>, grid, dim3(kBlock), 0, s, a, nstrips, nsegs, segh, items);
+  } else {
+    return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

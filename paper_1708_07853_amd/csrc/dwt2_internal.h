@@ -178,11 +178,11 @@ struct Level97 {
 int cdf97_tiles(int W, int H, int& tiles_x, int& tiles_y);
 // separable: the comparison kernel with the eight separable steps (forward only)
 int launch_cdf97_level(int dir, bool separable, const Level97& a, void* stream);
-// The forward level as a register-resident strip kernel: nstrips for width
-// W, and whether the level takes it (inputs of at least 16 x 16).  segh =
-// quadruple rows per work item, chunk = prefetch rows (1 or 2).
+// A forward or inverse level as a register-resident strip kernel: nstrips
+// for width W, and whether the level takes it (inputs of at least 16 x 16).
+// segh = quadruple rows per work item, chunk = prefetch rows (1 or 2).
 int cdf97_strip_geometry(int W, int H, int& nstrips);
-int launch_cdf97_strip(const Level97& a, int segh, int chunk, void* stream);
+int launch_cdf97_strip(int dir, const Level97& a, int segh, int chunk, void* stream);
 
 // Strip-kernel launchers, instantiated per direction (level kernels in
 // strip_fwd.hip, strip_inv.hip, strip_bwd.hip; job and table kernels in

@@ -75,9 +75,9 @@ STRIP_SHAPES = [(16, 16), (17, 23), (16, 221), (33, 224), (40, 225), (19, 226), 
 
 
 def test_cdf97_strip_kernel_equals_tiled(monkeypatch):
-    """The register-resident forward (default from 16 x 16) is bit-identical
-    to the LDS-tiled kernel at every size, level count and work-item shape,
-    and matches the oracle."""
+    """The register-resident forward and inverse (default from 16 x 16) are
+    bit-identical to the LDS-tiled kernels at every size, level count and
+    work-item shape, and match the oracle."""
     d = D()
     for idx, (h, w) in enumerate(STRIP_SHAPES):
         xn = _img(h, w, 9900 + idx)
@@ -86,19 +86,25 @@ def test_cdf97_strip_kernel_equals_tiled(monkeypatch):
             print(f"cdf97 strip: {h}x{w} levels {levels}", flush=True)
             monkeypatch.setenv("DWT2_CDF97_TILED", "1")
             ref = d.fwd_cdf97(x, levels)
+            ref_i = d.inv_cdf97(ref, levels)
             monkeypatch.delenv("DWT2_CDF97_TILED")
             got = d.fwd_cdf97(x, levels)
             assert torch.equal(got, ref), (h, w, levels, float((got - ref).abs().max()))
             assert maxdiff(got.cpu().numpy(), dwt97.fwd(xn, levels)) <= TOL97, (h, w, levels)
+            got_i = d.inv_cdf97(ref, levels)
+            assert torch.equal(got_i, ref_i), (h, w, levels, float((got_i - ref_i).abs().max()))
+            assert float((got_i - x).abs().max()) <= TOL97, (h, w, levels)
     x = to_gpu(_img(300, 517, 9999))
     monkeypatch.setenv("DWT2_CDF97_TILED", "1")
     ref = d.fwd_cdf97(x, 3)
+    ref_i = d.inv_cdf97(ref, 3)
     monkeypatch.delenv("DWT2_CDF97_TILED")
     try:
         for seg, ch in [(1, 1), (2, 2), (3, 1), (5, 2), (64, 2), (1000, 1)]:
             print(f"cdf97 strip tiling: seg {seg} chunk {ch}", flush=True)
             d.set_tiling(seg, ch)
             assert torch.equal(d.fwd_cdf97(x, 3), ref), (seg, ch)
+            assert torch.equal(d.inv_cdf97(ref, 3), ref_i), (seg, ch)
     finally:
         d.set_tiling(0, 0)
 
