@@ -783,10 +783,10 @@ static int transform(int dir, const void* src, int64_t src_stride, int64_t src_b
   if (variant == kLdsNonSep) return run_lds(DWT2_SCHEME_NONSEPARABLE, c, g, stream);
   if (variant == kLdsAdapted) return run_lds(DWT2_SCHEME_ADAPTED, c, g, stream);
   if (variant == kCdf97 || variant == kCdf97Sep) return run_cdf97(dir, variant == kCdf97Sep, c, g, stream);
-  // the per-level path whatever the process-wide setting (the entry point
-  // without a workspace: it must not reach the persistent path, whose
-  // host-visible error word is allocated on first use)
-  if (variant == kProductLevels) return run_levels(dir, c, g, stream, true, kPairsNone);
+  // the default per-level path (path 0) whatever the process-wide setting
+  // (the entry point without a workspace: it must not reach the persistent
+  // path, whose host-visible error word is allocated on first use)
+  if (variant == kProductLevels) return run_levels(dir, c, g, stream, true, kPairsDefault);
   if (g_persistent.load() < 0) g_persistent.store(env_int("DWT2_PERSISTENT") == 1 ? 1 : 0);
   const int path = g_persistent.load();
   if (path == 1 && g.L <= kInlineDescs) return run_job(dir, c, g, stream);
