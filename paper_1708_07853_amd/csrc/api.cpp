@@ -312,12 +312,14 @@ static void level_launch(int dir, const Call& c, const Geo& g, int k, int64_t sl
 // forward, output of the inverse and adjoint), LL_{k+1} (output of the
 // forward, input of the others), and the packed array's bands of both.
 constexpr int kPairStageStrips = 24;
-static void pair_launch(int dir, const Call& c, const Geo& g, int k, LevelLaunch& a, int& ch) {
+void pair_launch(int dir, const Call& c, const Geo& g, int k, LevelLaunch& a, int& ch, int seg_override,
+                 bool allow_stage) {
   memset(&a, 0, sizeof a);
   const int W = g.w[k - 1], H = g.h[k - 1];
   const int ns_w = ceil_half(W), ns_h1 = ceil_half(ceil_half(H));
   const int strips = (ns_w + pair_strip_q(dir) - 1) / pair_strip_q(dir);
-  const Tiling t = tuned_tiling(choose_tiling(ns_h1, (int64_t)strips * c.batch), kLaunchPair, dir, c.mode, g, k, c.batch);
+  Tiling t = tuned_tiling(choose_tiling(ns_h1, (int64_t)strips * c.batch), kLaunchPair, dir, c.mode, g, k, c.batch);
+  if (seg_override > 0) t.seg = seg_override;
   ch = t.ch;
   a.d.W = W;
   a.d.H = H;
@@ -333,7 +335,7 @@ static void pair_launch(int dir, const Call& c, const Geo& g, int k, LevelLaunch
   // 33.2 vs 29.0, 32 x 3 x 1024^2 four levels 246 vs 204 (5 strips -> 8).
   // DWT2_PAIR_STAGE=1 / 0 forces either form (read per call: tests switch it).
   const char* stage_env = getenv("DWT2_PAIR_STAGE");
-  const bool staged = stage_env && *stage_env ? atoi(stage_env) != 0 : strips >= kPairStageStrips;
+  const bool staged = allow_stage && (stage_env && *stage_env ? atoi(stage_env) != 0 : strips >= kPairStageStrips);
   a.d.stage = dir == kFwd && staged;
   a.d.nstrips = a.d.stage ? (strips + kWavesPerBlock - 1) / kWavesPerBlock * kWavesPerBlock : strips;
   a.d.nsegs = (ns_h1 + t.seg - 1) / t.seg;

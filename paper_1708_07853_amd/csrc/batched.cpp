@@ -29,11 +29,14 @@ namespace {
 constexpr int kBatchCh = 2;     // prefetch chunk of the batched job kernel
 constexpr int kMinSeg = 2 * kBatchCh;
 // Schedules: one cooperative persistent launch whose items wait for the rows
-// of the previous level of the same image (kChained), or one launch per
-// level over every image's items (kLevelSync; levels meet at kernel
-// boundaries, nothing waits).  A policy is a schedule plus the level-1
-// segment height, coded as kind * kPolicyKind + base.
-constexpr int kChained = 0, kLevelSync = 1, kPolicyKind = 10000;
+// of the previous level of the same image (kChained); one launch per level
+// over every image's items (kLevelSync; levels meet at kernel boundaries,
+// nothing waits); or the same with levels 1 and 2 of every image in one
+// launch of the pair kernels (kPairSync; when every image's level-1 input is
+// at least kPairMinEdge on each side).  A policy is a schedule plus the
+// level-1 segment height, coded as kind * kPolicyKind + base.
+constexpr int kChained = 0, kLevelSync = 1, kPairSync = 2, kPolicyKind = 10000;
+constexpr int kPairMinEdge = 8;
 
 // `pointers`: also check pointers, strides and aliasing (a size query reads
 // only the geometry).
@@ -123,6 +126,18 @@ Layout layout(const std::vector<Geo>& geos) {
     L.ll_off[i] = ll;
     ll += ws_per_image(g);
   }
+  // a pair-schedule plan: levels 1-2 in the pair kernels' strips, level-2
+  // rows per item at least kMinSeg; then the single levels 3..L
+  int64_t pair_items = 0;
+  for (int i = 0; i < n; ++i) {
+    const Geo& g = geos[i];
+    if (g.L < 2) continue;
+    const int q = pair_strip_q(kFwd);
+    pair_items += (int64_t)((ceil_half(g.w[0]) + q - 1) / q) * ((ceil_half(ceil_half(g.h[0])) + kMinSeg - 1) / kMinSeg);
+    for (int k = 3; k <= g.L; ++k)
+      pair_items += (int64_t)num_strips(g.w[k - 1]) * ((ceil_half(g.h[k - 1]) + kMinSeg - 1) / kMinSeg);
+  }
+  if (pair_items > items) items = pair_items;
   L.max_items = items;
   L.max_counters = counters;
   L.sync = 0;
@@ -146,7 +161,7 @@ int seg_for(int base, int k, int ns_h) {
 struct Plan {
   int n = 0, levels = 0, mode = 0;
   int dir = kFwd;               // kFwd, kInv or kBwd
-  int kind = 0;                 // kChained or kLevelSync
+  int kind = 0;                 // kChained, kLevelSync or kPairSync
   int base_seg = 32;
   std::vector<Geo> geos;
   std::vector<int> order;       // images by decreasing pixel count
@@ -154,8 +169,11 @@ struct Plan {
   int32_t ndesc = 0, total_items = 0, counters = 0;
   std::vector<uint32_t> item_desc;
   std::vector<int> desc_seg;    // segment height per desc
-  std::vector<int32_t> step_begin;   // first item of each level, plus the total
-  std::vector<int64_t> step_ll_bytes;  // LL output bytes of each level over all images
+  int nsteps = 0;               // launches (level-synchronous kinds) or levels (chained)
+  std::vector<int> step_level;  // per step: its (finer) level
+  std::vector<char> step_pair;  // per step: levels k and k+1 in the pair kernels
+  std::vector<int32_t> step_begin;   // first item of each step, plus the total
+  std::vector<int64_t> step_ll_bytes;  // LL output bytes of each step over all images
   // device side
   char* ws = nullptr;
   void* staging = nullptr;      // pinned: descs then items
@@ -197,7 +215,7 @@ constexpr int kMaxSeg = 4096;
 bool valid_policy(int policy) {
   if (policy < 0) return false;
   const int kind = policy / kPolicyKind, base = policy % kPolicyKind;
-  return (kind == kChained || kind == kLevelSync) && base >= kMinSeg && base <= kMaxSeg;
+  return (kind == kChained || kind == kLevelSync || kind == kPairSync) && base >= kMinSeg && base <= kMaxSeg;
 }
 
 std::string shape_key(int dir, const dwt2_image_t* images, int n, int levels, int mode) {
@@ -244,46 +262,77 @@ void save_tune(const std::string& hk, int base) {
 }
 
 // Item table and segment heights for a policy.
+// Whether every image can run levels 1 and 2 in the pair kernels.
+bool pairs_apply(const Plan& p) {
+  if (p.levels < 2) return false;
+  for (const Geo& g : p.geos)
+    if (g.w[0] < kPairMinEdge || g.h[0] < kPairMinEdge) return false;
+  return true;
+}
+
 void build_schedule(Plan& p, int policy) {
   const int base = policy % kPolicyKind;
   p.kind = policy / kPolicyKind;
   p.base_seg = base;
-  p.ndesc = p.n * p.levels;
+  // steps in execution order: the forward runs finest first, the inverse
+  // and adjoint coarsest first; kPairSync joins levels 1 and 2
+  p.step_level.clear();
+  p.step_pair.clear();
+  const bool pair = p.kind == kPairSync;
+  for (int t = 0; t < p.levels; ++t) {
+    const int k = p.dir == kFwd ? t + 1 : p.levels - t;
+    if (pair && k == 2) continue;  // inside the pair step of level 1
+    p.step_level.push_back(k);
+    p.step_pair.push_back(pair && k == 1);
+  }
+  p.nsteps = (int)p.step_level.size();
+  p.ndesc = p.n * p.nsteps;
   p.desc_seg.assign(p.ndesc, 0);
-  p.step_begin.assign(p.levels + 1, 0);
-  p.step_ll_bytes.assign(p.levels, 0);
+  p.step_begin.assign(p.nsteps + 1, 0);
+  p.step_ll_bytes.assign(p.nsteps, 0);
   p.item_desc.clear();
   p.counters = 0;
-  for (int t = 0; t < p.levels; ++t) {
+  for (int t = 0; t < p.nsteps; ++t) {
     p.step_begin[t] = (int32_t)p.item_desc.size();
+    const int k = p.step_level[t];
     for (int oi = 0; oi < p.n; ++oi) {
       const int i = p.order[oi];
       const Geo& g = p.geos[i];
-      const int k = p.dir == kFwd ? t + 1 : p.levels - t;  // level of step t
-      const int ns_h = ceil_half(g.h[k - 1]);
-      const int seg = seg_for(base, k, ns_h);
       const int j = t * p.n + oi;
+      int seg, nsegs, items;
+      if (p.step_pair[t]) {  // segments of level-2 quadruple rows
+        const int ns_h1 = ceil_half(ceil_half(g.h[0]));
+        seg = seg_for(base, 2, ns_h1);
+        nsegs = (ns_h1 + seg - 1) / seg;
+        const int q = pair_strip_q(p.dir);
+        items = nsegs * ((ceil_half(g.w[0]) + q - 1) / q);
+        // LL_2 (forward) or the image (inverse, adjoint)
+        p.step_ll_bytes[t] += p.dir == kFwd ? (int64_t)g.w[2] * g.h[2] * 4 : (int64_t)g.w[0] * g.h[0] * 4;
+      } else {
+        const int ns_h = ceil_half(g.h[k - 1]);
+        seg = seg_for(base, k, ns_h);
+        nsegs = (ns_h + seg - 1) / seg;
+        items = nsegs * num_strips(g.w[k - 1]);
+        const int ko = p.dir == kFwd ? k : k - 1;  // the step's LL output
+        p.step_ll_bytes[t] += (int64_t)g.w[ko] * g.h[ko] * 4;
+      }
       p.desc_seg[j] = seg;
-      const int nsegs = (ns_h + seg - 1) / seg;
-      const int items = nsegs * num_strips(g.w[k - 1]);
       p.item_desc.insert(p.item_desc.end(), items, (uint32_t)j);
       p.counters += nsegs;
-      const int ko = p.dir == kFwd ? k : k - 1;  // the step's LL output
-      p.step_ll_bytes[t] += (int64_t)g.w[ko] * g.h[ko] * 4;
     }
   }
   p.total_items = (int32_t)p.item_desc.size();
-  p.step_begin[p.levels] = p.total_items;
+  p.step_begin[p.nsteps] = p.total_items;
 }
 
 // Step descriptors for the current pointers, written to the staging buffer.
 void fill_descs(Plan& p, const dwt2_image_t* images, JobDesc* out) {
   int32_t start = 0, cbase = 0;
-  for (int t = 0; t < p.levels; ++t) {
+  for (int t = 0; t < p.nsteps; ++t) {
+    const int k = p.step_level[t];
     for (int oi = 0; oi < p.n; ++oi) {
       const int i = p.order[oi];
       const Geo& g = p.geos[i];
-      const int k = p.dir == kFwd ? t + 1 : p.levels - t;
       const int j = t * p.n + oi;
       const dwt2_image_t& im = images[i];
       Call c{static_cast<const char*>(im.src), im.src_stride, 0, static_cast<char*>(im.dst), im.dst_stride, 0, 1,
@@ -291,16 +340,25 @@ void fill_descs(Plan& p, const dwt2_image_t* images, JobDesc* out) {
       JobDesc& jd = out[j];
       memset(&jd, 0, sizeof jd);
       LevelDesc& d = jd.d;
-      const int W = g.w[k - 1], H = g.h[k - 1];
-      fill_level(d, W, H, p.desc_seg[j]);
-      level_pointers(p.dir, c, g, k, d, jd.pix_bstride, jd.ll_bstride, jd.band_bstride);
+      if (p.step_pair[t]) {
+        LevelLaunch la;
+        int ch;
+        pair_launch(p.dir, c, g, 1, la, ch, p.desc_seg[j], false);
+        d = la.d;
+        jd.pix_bstride = la.pix_bstride;
+        jd.ll_bstride = la.ll_bstride;
+        jd.band_bstride = la.band_bstride;
+      } else {
+        fill_level(d, g.w[k - 1], g.h[k - 1], p.desc_seg[j]);
+        level_pointers(p.dir, c, g, k, d, jd.pix_bstride, jd.ll_bstride, jd.band_bstride);
+      }
       jd.nimg = 1;
       jd.item_start = start;
       jd.items = d.nsegs * d.nstrips;
       jd.cbase = cbase;
       jd.prev = t > 0 ? (t - 1) * p.n + oi : -1;
-      jd.coh = p.kind != kLevelSync ? ((t > 0 ? 1 : 0) | (t + 1 < p.levels ? 2 : 0)) : 0;
-      d.keep_out = p.kind == kLevelSync && t + 1 < p.levels && p.step_ll_bytes[t] <= kKeepBytes;
+      jd.coh = p.kind == kChained ? ((t > 0 ? 1 : 0) | (t + 1 < p.nsteps ? 2 : 0)) : 0;
+      d.keep_out = p.kind != kChained && t + 1 < p.nsteps && p.step_ll_bytes[t] <= kKeepBytes;
       start += jd.items;
       cbase += d.nsegs;
     }
@@ -330,14 +388,14 @@ hipError_t enqueue(const Plan& p, hipStream_t s) {
   e = hipMemcpyAsync(p.ws + p.lay.items, static_cast<char*>(p.staging) + round256(dbytes),
                      (size_t)p.total_items * 4, hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return e;
-  if (p.kind == kLevelSync) {
-    for (int t = 0; t < p.levels; ++t) {
+  if (p.kind != kChained) {
+    for (int t = 0; t < p.nsteps; ++t) {
       TableArgs a;
       a.descs = reinterpret_cast<const JobDesc*>(p.ws + p.lay.descs);
       a.item_desc = reinterpret_cast<const uint32_t*>(p.ws + p.lay.items);
       a.item_begin = p.step_begin[t];
       a.items = p.step_begin[t + 1] - p.step_begin[t];
-      const int err = launch_table(p.dir, p.mode, a, s);
+      const int err = p.step_pair[t] ? launch_pair_table(p.dir, p.mode, a, s) : launch_table(p.dir, p.mode, a, s);
       if (err != hipSuccess) return (hipError_t)err;
     }
     return hipSuccess;
@@ -372,20 +430,25 @@ int autotune(Plan& p, const dwt2_image_t* images, hipStream_t s, const std::stri
                                    kChained * kPolicyKind + 32,   kChained * kPolicyKind + 64,
                                    kLevelSync * kPolicyKind + 8,  kLevelSync * kPolicyKind + 16,
                                    kLevelSync * kPolicyKind + 32, kLevelSync * kPolicyKind + 64,
-                                   kLevelSync * kPolicyKind + 128};
+                                   kLevelSync * kPolicyKind + 128, kPairSync * kPolicyKind + 8,
+                                   kPairSync * kPolicyKind + 16,  kPairSync * kPolicyKind + 32,
+                                   kPairSync * kPolicyKind + 64};
   const char* fk = getenv("DWT2_BATCH_SCHEDULE");
   const char* fs = getenv("DWT2_BATCH_SEG");
   const int forced_kind = fk ? atoi(fk) : -1;
   const int forced_seg = fs ? atoi(fs) : 0;
-  if (forced_kind == kChained || forced_kind == kLevelSync) {
+  if (forced_kind == kChained || forced_kind == kLevelSync || forced_kind == kPairSync) {
     const int policy = forced_kind * kPolicyKind + (forced_seg > 0 ? forced_seg : 32);
     if (!valid_policy(policy))
       return fail(DWT2_ERR_ARG, "DWT2_BATCH_SEG must lie in [%d, %d] (got %d)", kMinSeg, kMaxSeg, forced_seg);
+    if (forced_kind == kPairSync && !pairs_apply(p))
+      return fail(DWT2_ERR_ARG, "the pair schedule needs two levels and images of at least %d x %d", kPairMinEdge,
+                  kPairMinEdge);
     build_schedule(p, policy);
     return DWT2_OK;
   }
   auto it = g_tuned.find(hk);
-  if (it != g_tuned.end()) {
+  if (it != g_tuned.end() && (it->second / kPolicyKind != kPairSync || pairs_apply(p))) {
     build_schedule(p, it->second);
     return DWT2_OK;
   }
@@ -395,6 +458,7 @@ int autotune(Plan& p, const dwt2_image_t* images, hipStream_t s, const std::stri
   float best = 1e30f;
   int best_policy = kLevelSync * kPolicyKind + 32;
   for (int policy : candidates) {
+    if (policy / kPolicyKind == kPairSync && !pairs_apply(p)) continue;
     build_schedule(p, policy);
     if (p.total_items > p.lay.max_items || p.counters > p.lay.max_counters) continue;
     int st = ensure_staging(p);
@@ -417,7 +481,8 @@ int autotune(Plan& p, const dwt2_image_t* images, hipStream_t s, const std::stri
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         return fail(DWT2_ERR_HIP, "autotune %s of %s schedule, segment %d failed: %s", what,
-                    p.kind == kLevelSync ? "level-synchronous" : "chained", p.base_seg, hipGetErrorString(e));
+                    p.kind == kChained ? "chained" : (p.kind == kLevelSync ? "level-synchronous" : "pair"),
+                    p.base_seg, hipGetErrorString(e));
       }
       (void)hipEventElapsedTime(&t, e0, e1);
     }
@@ -488,7 +553,8 @@ int build_plan(Plan& p, int dir, const dwt2_image_t* images, int n, int levels, 
   if (verbose && atoi(verbose) > 0)
     fprintf(stderr, "dwt2 batched %s plan: %d images, %d levels, %s schedule, level-1 segment %d, %d items, %s\n",
             dir == kFwd ? "forward" : (dir == kInv ? "inverse" : "adjoint"), n, levels,
-            p.kind == kLevelSync ? "level-synchronous" : "chained persistent", p.base_seg, p.total_items,
+            p.kind == kChained ? "chained persistent" : (p.kind == kLevelSync ? "level-synchronous" : "pair"),
+            p.base_seg, p.total_items,
             p.exec ? "graph replay" : "direct launches");
   return DWT2_OK;
 }

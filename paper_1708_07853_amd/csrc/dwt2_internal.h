@@ -243,6 +243,17 @@ inline int launch_pair(int dir, int mode, int chunk, const LevelLaunch& a, void*
   if (dir == kInv) return launch_pair_dir<kInv>(mode, chunk, a, stream);
   return launch_pair_dir<kBwd>(mode, chunk, a, stream);
 }
+// One pair step of a ragged batch over the items [item_begin, item_begin +
+// items) of a table (level-synchronous schedule; descriptors never stage).
+template <int DIR> int launch_pair_table_dir(int mode, const TableArgs& a, void* stream);
+extern template int launch_pair_table_dir<kFwd>(int, const TableArgs&, void*);
+extern template int launch_pair_table_dir<kInv>(int, const TableArgs&, void*);
+extern template int launch_pair_table_dir<kBwd>(int, const TableArgs&, void*);
+inline int launch_pair_table(int dir, int mode, const TableArgs& a, void* stream) {
+  if (dir == kFwd) return launch_pair_table_dir<kFwd>(mode, a, stream);
+  if (dir == kInv) return launch_pair_table_dir<kInv>(mode, a, stream);
+  return launch_pair_table_dir<kBwd>(mode, a, stream);
+}
 // Clears n synchronisation words with a fill kernel (tail_kernels.hip).
 int launch_zero(uint32_t* p, int64_t n, void* stream);
 

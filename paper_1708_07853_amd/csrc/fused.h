@@ -773,35 +773,32 @@ __device__ void bwd_pair(const LevelDesc& d, const float* __restrict__ ll2, cons
 // quadruple rows, ll is LL_{k+1} (output of the forward, input of the
 // inverse and adjoint).
 // ---------------------------------------------------------------------------
-template <int DIR, typename T, int CP>
-__global__ __launch_bounds__(kBlock) void pair_kernel(LevelLaunch a) {
-  const int lane = threadIdx.x & (kWave - 1);
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  const int64_t item = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + wave;
-  if (item >= a.items) return;
-  const int img = (int)(item / a.items_per_image);
-  const int rem = (int)(item - (int64_t)img * a.items_per_image);
-  const int seg = rem / a.d.nstrips;
-  const int strip = rem - seg * a.d.nstrips;
-  const PairItem it = make_pair_item<DIR>(a.d, strip, seg, lane);
+// One work item of a pair launch: strip `strip` of segment `seg`, with the
+// image's element offsets from the descriptor's pointers.  STAGE_OK: the
+// launch may stage the forward's stores (d.stage; four adjacent strips per
+// workgroup, `stage` the workgroup's LDS array); otherwise d.stage is 0.
+template <int DIR, typename T, int CP, bool STAGE_OK>
+__device__ __forceinline__ void pair_run(const LevelDesc& d, int64_t pix_off, int64_t ll_off, int64_t band_off,
+                                         int strip, int seg, int lane, T* stage) {
+  const PairItem it = make_pair_item<DIR>(d, strip, seg, lane);
   const bool edge = pair_edge<DIR>(it, strip);
-  const LevelDesc& d = a.d;
   if constexpr (DIR == kFwd) {
-    const T* px = static_cast<const T*>(d.pix_in) + img * a.pix_bstride;
-    T* ll2 = static_cast<T*>(d.ll_out) + img * a.ll_bstride;
-    T* band = static_cast<T*>(d.band_out) + img * a.band_bstride;
-    __shared__ T stage[2 * kPairStageBuf];
-    if (d.stage) {
-      if (edge) fwd_pair<T, CP, true, true>(d, px, ll2, band, it, stage);
-      else fwd_pair<T, CP, false, true>(d, px, ll2, band, it, stage);
-    } else {
-      if (edge) fwd_pair<T, CP, true, false>(d, px, ll2, band, it, stage);
-      else fwd_pair<T, CP, false, false>(d, px, ll2, band, it, stage);
+    const T* px = static_cast<const T*>(d.pix_in) + pix_off;
+    T* ll2 = static_cast<T*>(d.ll_out) + ll_off;
+    T* band = static_cast<T*>(d.band_out) + band_off;
+    if constexpr (STAGE_OK) {
+      if (d.stage) {
+        if (edge) fwd_pair<T, CP, true, true>(d, px, ll2, band, it, stage);
+        else fwd_pair<T, CP, false, true>(d, px, ll2, band, it, stage);
+        return;
+      }
     }
+    if (edge) fwd_pair<T, CP, true, false>(d, px, ll2, band, it, stage);
+    else fwd_pair<T, CP, false, false>(d, px, ll2, band, it, stage);
   } else {
-    const T* ll2 = static_cast<const T*>(d.ll_in) + img * a.ll_bstride;
-    const T* band = static_cast<const T*>(d.band_in) + img * a.band_bstride;
-    T* px = static_cast<T*>(d.pix_out) + img * a.pix_bstride;
+    const T* ll2 = static_cast<const T*>(d.ll_in) + ll_off;
+    const T* band = static_cast<const T*>(d.band_in) + band_off;
+    T* px = static_cast<T*>(d.pix_out) + pix_off;
     if constexpr (DIR == kInv) {
       if (d.keep_out) {
         if (edge) inv_pair<T, CP, true, 0>(d, ll2, band, px, it);
@@ -815,6 +812,47 @@ __global__ __launch_bounds__(kBlock) void pair_kernel(LevelLaunch a) {
       else bwd_pair<CP, false, kNT>(d, ll2, band, px, it);
     }
   }
+}
+
+template <int DIR, typename T, int CP>
+__global__ __launch_bounds__(kBlock) void pair_kernel(LevelLaunch a) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int64_t item = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + wave;
+  if (item >= a.items) return;
+  const int img = (int)(item / a.items_per_image);
+  const int rem = (int)(item - (int64_t)img * a.items_per_image);
+  const int seg = rem / a.d.nstrips;
+  const int strip = rem - seg * a.d.nstrips;
+  T* stage = nullptr;
+  if constexpr (DIR == kFwd) {
+    __shared__ T stage_lds[2 * kPairStageBuf];
+    stage = stage_lds;
+  }
+  pair_run<DIR, T, CP, true>(a.d, img * a.pix_bstride, img * a.ll_bstride, img * a.band_bstride, strip, seg, lane,
+                             stage);
+}
+
+// One pair step of a ragged batch (level-synchronous schedule): one wave per
+// work item, the item's image descriptor found through the device item ->
+// descriptor table, as in table_kernel.  The descriptors never stage.
+template <int DIR, typename T, int CP>
+__global__ __launch_bounds__(kBlock) void pair_table_kernel(TableArgs a) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int64_t w = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + wave;
+  if (w >= a.items) return;
+  const int q = a.item_begin + (int)w;
+  const int j = __builtin_amdgcn_readfirstlane(((const uint32_t* __restrict__)a.item_desc)[q]);
+  const JobDesc jd = ((const JobDesc* __restrict__)a.descs)[j];
+  const int item = q - jd.item_start;
+  const int per_img = jd.d.nsegs * jd.d.nstrips;
+  const int img = item / per_img;
+  const int rem = item - img * per_img;
+  const int seg = rem / jd.d.nstrips;
+  const int strip = rem - seg * jd.d.nstrips;
+  pair_run<DIR, T, CP, false>(jd.d, img * jd.pix_bstride, img * jd.ll_bstride, img * jd.band_bstride, strip, seg,
+                              lane, (T*)nullptr);
 }
 
 template <int DIR, typename T>
@@ -838,6 +876,24 @@ int launch_pair_dir(int mode, int chunk, const LevelLaunch& a, void* stream) {
   return hipErrorInvalidValue;
 }
 
-#define DWT2_INSTANTIATE_PAIR(DIR) template int launch_pair_dir<DIR>(int, int, const LevelLaunch&, void*);
+template <int DIR, typename T>
+hipError_t launch_pair_table_t(const TableArgs& a, hipStream_t s) {
+  const dim3 grid((unsigned)((a.items + kWavesPerBlock - 1) / kWavesPerBlock));
+  hipLaunchKernelGGL((pair_table_kernel<DIR, T, 1>), grid, dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+template <int DIR>
+int launch_pair_table_dir(int mode, const TableArgs& a, void* stream) {
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (a.items <= 0) return hipSuccess;
+  if (mode == DWT2_F32) return launch_pair_table_t<DIR, float>(a, s);
+  if constexpr (DIR != kBwd) return launch_pair_table_t<DIR, int>(a, s);
+  return hipErrorInvalidValue;
+}
+
+#define DWT2_INSTANTIATE_PAIR(DIR)                                                 \
+  template int launch_pair_dir<DIR>(int, int, const LevelLaunch&, void*);         \
+  template int launch_pair_table_dir<DIR>(int, const TableArgs&, void*);
 
 }  // namespace dwt2

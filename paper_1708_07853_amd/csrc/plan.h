@@ -63,6 +63,13 @@ struct Launch {
 // default path picks (see default_pair in api.cpp).
 enum { kPairsNone = 0, kPairsAll = 1, kPairsDefault = 2 };
 int plan_launches(int dir, const Geo& g, int batch, bool tail, int pairs, Launch* out);
+// The launch of levels k and k+1 by the pair kernels for a call: geometry,
+// pointers, tiling (seg_override > 0: that segment height in level-(k+1)
+// quadruple rows) and whether the forward stages its stores (only if
+// allow_stage: staging needs four adjacent strips of one image and segment
+// per workgroup).
+void pair_launch(int dir, const Call& c, const Geo& g, int k, LevelLaunch& a, int& ch, int seg_override = 0,
+                 bool allow_stage = true);
 int run_levels(int dir, const Call& c, const Geo& g, void* stream, bool tail, int pairs);
 int run_job(int dir, const Call& c, const Geo& g, void* stream);
 // dwt2_fwd on the per-level path whatever the process-wide path setting

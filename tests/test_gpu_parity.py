@@ -388,9 +388,11 @@ def test_batched_equals_plain_on_ragged_set():
 
 
 def test_batched_every_schedule_equals_plain():
-    """Both batched schedules (chained persistent, level-synchronous), each
-    at several level-1 segment heights, reproduce per-image calls bit for
-    bit (float and integer), including replays with new pointers."""
+    """The three batched schedules (chained persistent, level-synchronous,
+    level-synchronous with levels 1-2 in the pair kernels), each at several
+    level-1 segment heights, reproduce per-image calls bit for bit (float
+    and integer), including replays with new pointers; the pair schedule is
+    refused for images below 8 x 8."""
     import os
     from paper_1708_07853_amd import _lib
     d = D()
@@ -401,7 +403,7 @@ def test_batched_every_schedule_equals_plain():
         for dt in (np.float32, np.int32):
             imgs = [to_gpu(synth.image(w, h, 500 + i, dt)) for i, (w, h) in enumerate(sizes)]
             refs = [d.fwd(im, 3) for im in imgs]
-            for kind in ("0", "1"):
+            for kind in ("0", "1", "2"):
                 for seg in ("4", "8", "32", "128"):
                     os.environ["DWT2_BATCH_SCHEDULE"], os.environ["DWT2_BATCH_SEG"] = kind, seg
                     lib.dwt2_clear_plan_cache()
@@ -409,6 +411,11 @@ def test_batched_every_schedule_equals_plain():
                         outs = d.fwd_batched(imgs, 3)
                         for i, (o, r) in enumerate(zip(outs, refs)):
                             assert torch.equal(o, r), (dt, kind, seg, rep, i, sizes[i])
+        os.environ["DWT2_BATCH_SCHEDULE"], os.environ["DWT2_BATCH_SEG"] = "2", "32"
+        lib.dwt2_clear_plan_cache()
+        small = [to_gpu(synth.image(w, h, 900 + i)) for i, (w, h) in enumerate([(64, 40), (7, 30), (33, 9)])]
+        with pytest.raises(ValueError, match="pair schedule"):
+            d.fwd_batched(small, 2)
     finally:
         for k, v in saved.items():
             if v is None:
@@ -582,7 +589,7 @@ def test_lds_tiled_batch_strides_and_full_size():
 
 def test_batched_inverse_and_adjoint_every_schedule():
     """dwt2_inv_batched and dwt2_bwd_batched reproduce per-image dwt2_inv /
-    dwt2_bwd bit for bit under both schedules, and the integer batched round
+    dwt2_bwd bit for bit under every schedule, and the integer batched round
     trip is exact."""
     import os
     from paper_1708_07853_amd import _lib
@@ -596,7 +603,7 @@ def test_batched_inverse_and_adjoint_every_schedule():
             coefs = [d.fwd(im, 3) for im in imgs]
             ref_inv = [d.inv(c, 3) for c in coefs]
             ref_bwd = [d.bwd(c, 3) for c in coefs] if dt == np.float32 else None
-            for kind in ("0", "1"):
+            for kind in ("0", "1", "2"):
                 for seg in ("4", "32"):
                     os.environ["DWT2_BATCH_SCHEDULE"], os.environ["DWT2_BATCH_SEG"] = kind, seg
                     lib.dwt2_clear_plan_cache()
