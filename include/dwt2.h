@@ -241,12 +241,15 @@ size_t dwt2_batched_workspace_size(const dwt2_image_t* images, int32_t n,
  *   images  HOST array of n descriptors; every image is validated like a
  *           dwt2_fwd call (the detail string names the failing image).
  * The work items (image, level, strip, segment) of all images run under one
- * of two schedules, picked per shape set by timing both on the first call:
+ * of three schedules, picked per shape set by timing them on the first call:
  * one cooperative persistent launch in which an item waits only for the
- * rows of the previous level of its own image, or one launch per level over
- * every image.  The environment variables DWT2_BATCH_SCHEDULE (0 persistent,
- * 1 per level) and DWT2_BATCH_SEG (level-1 segment height) force a policy,
- * and DWT2_TUNE_CACHE names a file that keeps tuning results.
+ * rows of the previous level of its own image; one launch per level over
+ * every image; or the same with levels 1 and 2 of every image in one launch
+ * of the two-level kernels (when levels >= 2 and every image is at least
+ * 8 x 8).  The environment variables DWT2_BATCH_SCHEDULE (0 persistent,
+ * 1 per level, 2 with the two-level launch; DWT2_ERR_ARG when it does not
+ * apply) and DWT2_BATCH_SEG (level-1 segment height) force a policy, and
+ * DWT2_TUNE_CACHE names a file that keeps tuning results.
  * Results are bit-identical to n separate dwt2_fwd calls under every
  * policy.  The first call for a new shape set builds the plan (tuning,
  * schedule, graph); later calls with the same shapes and workspace only

@@ -1,13 +1,17 @@
-// dwt2_fwd_batched: a ragged list of images in one persistent launch.
+// dwt2_fwd_batched (and the inverse and adjoint): a ragged list of images.
 //
-// Plan (cached per shape set and workspace, at most 16): every (level, image) becomes one
-// step of a persistent job; the queue holds level 1 of all images (largest
-// first), then level 2, and so on, so an image's next level starts as soon
-// as the rows it reads exist while other images are still at the previous
-// level.  The segment heights come from a small autotuner that times a few
-// policies on the first call.  Each call refreshes the step descriptors
-// (image pointers) in pinned staging and replays a HIP graph:
-//   copy staging -> workspace tables, clear the sync words, persistent job.
+// Plan (cached per shape set and workspace, at most 16): every (step, image)
+// becomes one descriptor, and the work items of a step are numbered over all
+// images (largest first).  Three schedules: one persistent job whose queue
+// holds level 1 of all images, then level 2, and so on, so an image's next
+// level starts as soon as the rows it reads exist while other images are
+// still at the previous level; one table-driven launch per level; or one per
+// step with levels 1 and 2 in the pair kernels.  The schedule and segment
+// heights come from a small autotuner that times the policies on the first
+// call.  Each call refreshes the step descriptors (image pointers) in pinned
+// staging and replays a HIP graph:
+//   copy staging -> workspace tables, then the persistent job (after clearing
+//   its sync words) or the per-step launches.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
