@@ -42,7 +42,7 @@ struct LevelDesc {
   int32_t nstrips;
   int32_t nsegs;
   int32_t keep_out;     // a later launch reads this level's LL output (cache it)
-  int32_t stage;        // forward pair: stage the coarser level's rows through LDS
+  int32_t stage;        // forward pair: stage its stores through LDS (whole 128-byte lines)
   int32_t pad_;
 };
 
