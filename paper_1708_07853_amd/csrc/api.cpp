@@ -727,7 +727,11 @@ static int run_cdf97(int dir, bool separable, const Call& c, const Geo& g, void*
     int err;
     if (strip) {
       const Tiling t = choose_tiling(ceil_half(a.H), (int64_t)nstrips * c.batch);
-      err = launch_cdf97_strip(dir, a, t.seg, t.ch, stream);
+      // the forward stages its stores from kPairStageStrips strips, as the pairs
+      // do (DWT2_PAIR_STAGE=1 / 0 forces either form, read per call)
+      const char* stage_env = getenv("DWT2_PAIR_STAGE");
+      const bool staged = stage_env && *stage_env ? atoi(stage_env) != 0 : nstrips >= kPairStageStrips;
+      err = launch_cdf97_strip(dir, a, t.seg, t.ch, staged, stream);
     } else {
       err = launch_cdf97_level(dir, separable, a, stream);
     }

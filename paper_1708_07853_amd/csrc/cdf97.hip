@@ -344,10 +344,17 @@ __global__ __launch_bounds__(kBlk, 5) void inv97(Level97 a, int tiles_x) {
 // are bit-identical to fwd97.
 // ---------------------------------------------------------------------------
 constexpr int kStrip97Min = 16;
+// STAGED stores: the four waves of a workgroup hold four adjacent strips of
+// one segment (the host pads the strip count to a multiple of four); per
+// output row each wave puts its 112 values of each band into LDS and, after
+// one barrier, wave w writes band w's 448-value run (1792 bytes from a
+// 128-byte boundary) with 16-byte stores, instead of four 448-byte runs
+// that split a line at every other strip edge.
+constexpr int kStage97 = kWavesPerBlock * 2 * 56;  // one band row of a workgroup
 
-template <bool EDGE, int CP>
+template <bool EDGE, int CP, bool STAGED>
 __device__ void fwd97_strip_item(const Level97& a, const float* __restrict__ px, float* __restrict__ ll,
-                                 float* __restrict__ band, int strip, int seg, int segh, int lane) {
+                                 float* __restrict__ band, int strip, int seg, int segh, int lane, float* stage) {
   using PL = PairLanes<kFwd>;
   const int W = a.W, H = a.H;
   const int ns_w = (W + 1) >> 1, ns_h = (H + 1) >> 1, nd_w = W >> 1, nd_h = H >> 1;
@@ -361,19 +368,51 @@ __device__ void fwd97_strip_item(const Level97& a, const float* __restrict__ px,
   const int qst = own ? qL : kOff;
   const int64_t bs = a.out_stride, ls = a.ll_stride;
   const bool keep_ll = !a.final_out;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int slot = w * PL::count + lane - PL::base;  // the lane's quadruple pair in the workgroup's run
+  const int q0 = qL - 2 * slot;                        // the run's first quadruple column
+  int buf = 0;
   // output row r: LL, HL, LH, HH of the lane's two quadruples
   auto store = [&](int r, float llL, float llR, float hlL, float hlR, float lhL, float lhR, float hhL, float hhR) {
     const bool real = r >= I0 && r < I1, real2 = real && r < nd_h;
-    const Rsrc rl = row_rsrc(ll + (int64_t)r * ls, real ? ns_w * 4 : 0);
-    const Rsrc rh = row_rsrc(band + (int64_t)r * bs + ns_w, real ? nd_w * 4 : 0);
-    float* row2 = band + (int64_t)(ns_h + r) * bs;
-    const Rsrc rlh = row_rsrc(row2, real2 ? ns_w * 4 : 0);
-    const Rsrc rhh = row_rsrc(row2 + ns_w, real2 ? nd_w * 4 : 0);
-    if (keep_ll) bst2<0>(llL * kLLScale, llR * kLLScale, rl, qst);
-    else bst2<kNT>(llL * kLLScale, llR * kLLScale, rl, qst);
-    bst2<kNT>(hlL, hlR, rh, qst);
-    bst2<kNT>(lhL, lhR, rlh, qst);
-    bst2<kNT>(hhL * kHHScale, hhR * kHHScale, rhh, qst);
+    if constexpr (STAGED) {
+      float* sb = stage + buf * 4 * kStage97;
+      if (own) {
+        sb[2 * slot] = llL * kLLScale; sb[2 * slot + 1] = llR * kLLScale;
+        sb[kStage97 + 2 * slot] = hlL; sb[kStage97 + 2 * slot + 1] = hlR;
+        sb[2 * kStage97 + 2 * slot] = lhL; sb[2 * kStage97 + 2 * slot + 1] = lhR;
+        sb[3 * kStage97 + 2 * slot] = hhL * kHHScale; sb[3 * kStage97 + 2 * slot + 1] = hhR * kHHScale;
+      }
+      __syncthreads();
+      // wave w: band w (0 LL, 1 HL, 2 LH, 3 HH) of row r
+      const bool hpar = w == 1 || w == 3;
+      const bool ok = w < 2 ? real : real2;
+      float* row = w == 0 ? ll + (int64_t)r * ls : band + (int64_t)(w < 2 ? r : ns_h + r) * bs + (hpar ? ns_w : 0);
+      const Rsrc rs = row_rsrc(row, ok ? (hpar ? nd_w : ns_w) * 4 : 0);
+      const float* src = sb + w * kStage97;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int e = h * 4 * kWave + 4 * lane;  // element of the run
+        const bool st = e < kStage97;
+        const float* v = src + (st ? e : 0);
+        V4<float> o;
+        o.x = v[0]; o.y = v[1]; o.z = v[2]; o.w = v[3];
+        if (w == 0 && keep_ll) bst4<0>(o, rs, st ? q0 + e : kOff);
+        else bst4<kNT>(o, rs, st ? q0 + e : kOff);
+      }
+      buf ^= 1;
+    } else {
+      const Rsrc rl = row_rsrc(ll + (int64_t)r * ls, real ? ns_w * 4 : 0);
+      const Rsrc rh = row_rsrc(band + (int64_t)r * bs + ns_w, real ? nd_w * 4 : 0);
+      float* row2 = band + (int64_t)(ns_h + r) * bs;
+      const Rsrc rlh = row_rsrc(row2, real2 ? ns_w * 4 : 0);
+      const Rsrc rhh = row_rsrc(row2 + ns_w, real2 ? nd_w * 4 : 0);
+      if (keep_ll) bst2<0>(llL * kLLScale, llR * kLLScale, rl, qst);
+      else bst2<kNT>(llL * kLLScale, llR * kLLScale, rl, qst);
+      bst2<kNT>(hlL, hlR, rh, qst);
+      bst2<kNT>(lhL, lhR, rlh, qst);
+      bst2<kNT>(hhL * kHHScale, hhR * kHHScale, rhh, qst);
+    }
   };
 
   V4<float> E;                                  // pixel row 2r of the row being computed
@@ -563,7 +602,7 @@ __global__ __launch_bounds__(kBlock) void inv97_strip(Level97 a, int nstrips, in
 
 // One wave per (image, segment, strip) item; items past the grid's last
 // full workgroup return at once (no barrier in this kernel).
-template <int CP>
+template <int CP, bool STAGED>
 __global__ __launch_bounds__(kBlock) void fwd97_strip(Level97 a, int nstrips, int nsegs, int segh, int64_t items) {
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t item = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock +
@@ -579,8 +618,15 @@ __global__ __launch_bounds__(kBlock) void fwd97_strip(Level97 a, int nstrips, in
   float* band = static_cast<float*>(a.out) + img * a.out_bstride;
   // the wave's pixel columns 4 (112 strip - 4) .. + 255, all inside the image?
   const int c_first = 4 * (PairLanes<kFwd>::count * strip - PairLanes<kFwd>::base);
-  if (c_first < 0 || c_first + 4 * kWave > a.W) fwd97_strip_item<true, CP>(a, px, ll, band, strip, seg, segh, lane);
-  else fwd97_strip_item<false, CP>(a, px, ll, band, strip, seg, segh, lane);
+  float* stage = nullptr;
+  if constexpr (STAGED) {
+    __shared__ float stage_lds[2 * 4 * kStage97];
+    stage = stage_lds;
+  }
+  if (c_first < 0 || c_first + 4 * kWave > a.W)
+    fwd97_strip_item<true, CP, STAGED>(a, px, ll, band, strip, seg, segh, lane, stage);
+  else
+    fwd97_strip_item<false, CP, STAGED>(a, px, ll, band, strip, seg, segh, lane, stage);
 }
 
 // Separable comparison kernel on the same tiles: per level and per pair,
@@ -681,16 +727,24 @@ int cdf97_strip_geometry(int W, int H, int& nstrips) {
   return W >= kStrip97Min && H >= kStrip97Min;
 }
 
-int launch_cdf97_strip(int dir, const Level97& a, int segh, int chunk, void* stream) {
+int launch_cdf97_strip(int dir, const Level97& a, int segh, int chunk, bool staged, void* stream) {
   int nstrips;
   if (!cdf97_strip_geometry(a.W, a.H, nstrips) || segh < 1) return hipErrorInvalidValue;
+  staged = staged && dir == kFwd;
+  if (staged) nstrips = (nstrips + kWavesPerBlock - 1) / kWavesPerBlock * kWavesPerBlock;  // whole workgroups
   const int nsegs = (((a.H + 1) >> 1) + segh - 1) / segh;
   const int64_t items = (int64_t)nstrips * nsegs * a.batch;
   const dim3 grid((unsigned)((items + kWavesPerBlock - 1) / kWavesPerBlock));
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (dir == kFwd) {
-    if (chunk >= 2) hipLaunchKernelGGL(fwd97_strip<2>, grid, dim3(kBlock), 0, s, a, nstrips, nsegs, segh, items);
-    else hipLaunchKernelGGL(fwd97_strip<1>, grid, dim3(kBlock), 0, s, a, nstrips, nsegs, segh, items);
+    if (staged && chunk >= 2)
+      hipLaunchKernelGGL((fwd97_strip<2, true>), grid, dim3(kBlock), 0, s, a, nstrips, nsegs, segh, items);
+    else if (staged)
+      hipLaunchKernelGGL((fwd97_strip<1, true>), grid, dim3(kBlock), 0, s, a, nstrips, nsegs, segh, items);
+    else if (chunk >= 2)
+      hipLaunchKernelGGL((fwd97_strip<2, false>), grid, dim3(kBlock), 0, s, a, nstrips, nsegs, segh, items);
+    else
+      hipLaunchKernelGGL((fwd97_strip<1, false>), grid, dim3(kBlock), 0, s, a, nstrips, nsegs, segh, items);
   } else if (dir == kInv) {
     if (chunk >= 2) hipLaunchKernelGGL(inv97_strip<2>, grid, dim3(kBlock), 0, s, a, nstrips, nsegs, segh, items);
     else hipLaunchKernelGGL(inv97_strip<1>, grid, dim3(kBlock), 0, s, a, nstrips, nsegs, segh, items);

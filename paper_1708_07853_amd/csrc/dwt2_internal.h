@@ -180,9 +180,10 @@ int cdf97_tiles(int W, int H, int& tiles_x, int& tiles_y);
 int launch_cdf97_level(int dir, bool separable, const Level97& a, void* stream);
 // A forward or inverse level as a register-resident strip kernel: nstrips
 // for width W, and whether the level takes it (inputs of at least 16 x 16).
-// segh = quadruple rows per work item, chunk = prefetch rows (1 or 2).
+// segh = quadruple rows per work item, chunk = prefetch rows (1 or 2),
+// staged = the forward writes whole lines through LDS.
 int cdf97_strip_geometry(int W, int H, int& nstrips);
-int launch_cdf97_strip(int dir, const Level97& a, int segh, int chunk, void* stream);
+int launch_cdf97_strip(int dir, const Level97& a, int segh, int chunk, bool staged, void* stream);
 
 // Strip-kernel launchers, instantiated per direction (level kernels in
 // strip_fwd.hip, strip_inv.hip, strip_bwd.hip; job and table kernels in

@@ -74,16 +74,20 @@ STRIP_SHAPES = [(16, 16), (17, 23), (16, 221), (33, 224), (40, 225), (19, 226), 
                 (100, 479), (130, 672), (129, 673), (37, 1030), (300, 517), (260, 131), (16, 256), (23, 257)]
 
 
-def test_cdf97_strip_kernel_equals_tiled(monkeypatch):
+@pytest.mark.parametrize("stores", ["auto", "direct", "staged"])
+def test_cdf97_strip_kernel_equals_tiled(monkeypatch, stores):
     """The register-resident forward and inverse (default from 16 x 16) are
     bit-identical to the LDS-tiled kernels at every size, level count and
-    work-item shape, and match the oracle."""
+    work-item shape, and match the oracle; the forward's stores either go
+    out directly or are staged through LDS (forced here both ways)."""
     d = D()
+    if stores != "auto":
+        monkeypatch.setenv("DWT2_PAIR_STAGE", "1" if stores == "staged" else "0")
     for idx, (h, w) in enumerate(STRIP_SHAPES):
         xn = _img(h, w, 9900 + idx)
         x = to_gpu(xn)
         for levels in sorted({1, 2, max_levels(w, h)}):
-            print(f"cdf97 strip: {h}x{w} levels {levels}", flush=True)
+            print(f"cdf97 strip ({stores}): {h}x{w} levels {levels}", flush=True)
             monkeypatch.setenv("DWT2_CDF97_TILED", "1")
             ref = d.fwd_cdf97(x, levels)
             ref_i = d.inv_cdf97(ref, levels)
