@@ -340,9 +340,11 @@ int dwt2_tune_clear(void);
  * needs the coarsest input at least 4 x 4).
  *   0 (default): pairs for dwt2_inv and dwt2_bwd, and for dwt2_fwd where
  *     the pair's strips (112 quadruple columns each) would be at least 80 %
- *     filled by the level-k input's ceil(w/2) quadruple columns, single
- *     levels elsewhere (what measured fastest on MI355X), then the fused
- *     coarsest levels;
+ *     filled by the level-k input's ceil(w/2) quadruple columns or the
+ *     level-k input holds at most 1024 x 1024 pixels over the batch, single
+ *     levels elsewhere, and the fused coarsest levels only where they take
+ *     fewer launches than pairs and single levels (what measured fastest
+ *     on MI355X);
  *   1: every level of a call in one cooperative persistent launch whose
  *     work items wait only for the rows they read;
  *   2: one launch per level throughout;

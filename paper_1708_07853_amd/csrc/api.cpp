@@ -442,40 +442,61 @@ static int launch_tail_levels(int dir, const Call& c, const Geo& g, int k0, void
 //     131.5 vs 140.9 us, 16384^2 int32 486 vs 552 us, 32 x 3 x 1024^2 207 vs
 //     224 us, 24 x 2048^2 at five levels 206 vs 229 us), slower for the batch
 //     of 512^2 images (74 vs 66 us), whose level-1 strips own 256 quadruple
-//     columns in 336 lanes' worth: the forward pairs a level only when at
-//     least 80 % of its strips' owned lanes hold quadruples.
-static bool default_pair(int dir, const Geo& g, int k) {
+//     columns in 336 lanes' worth: the forward pairs a level when at least
+//     80 % of its strips' owned lanes hold quadruples, or when the level is
+//     small (at most kTailArea input pixels over the batch), where launch
+//     latency, not lane use, decides.
+constexpr int kPairMin = 8;
+static bool default_pair(int dir, const Geo& g, int k, int batch) {
   if (dir != kFwd) return true;
   const int ns_w = ceil_half(g.w[k - 1]), q = pair_strip_q(dir);
   const int strips = (ns_w + q - 1) / q;
-  return 5 * ns_w >= 4 * strips * q;
+  return 5 * ns_w >= 4 * strips * q || (int64_t)g.w[k - 1] * g.h[k - 1] * batch <= kTailArea;
+}
+
+// The launches of levels 1..L before the fused tail at level k0 (0: none),
+// in pairs where `pairs` asks for them and they apply, finest first.
+static int plan_levels(int dir, const Geo& g, int batch, int k0, int pairs, Launch* out) {
+  const int last_single = k0 ? k0 - 1 : g.L;  // levels 1 .. last_single precede the tail
+  int n = 0;
+  for (int k = 1; k <= last_single;) {
+    const bool want = pairs == kPairsAll || (pairs == kPairsDefault && default_pair(dir, g, k, batch));
+    if (want && k + 1 <= last_single && g.w[k - 1] >= kPairMin && g.h[k - 1] >= kPairMin) {
+      out[n++] = Launch{k, k + 1, kLaunchPair};
+      k += 2;
+    } else {
+      out[n++] = Launch{k, k, kLaunchLevel};
+      k += 1;
+    }
+  }
+  if (k0) out[n++] = Launch{k0, g.L, kLaunchTail};
+  return n;
 }
 
 // The launches of a plain call on the per-level path, in execution order:
 // each covers levels [first, last] -- one level, a pair of levels, or the
 // fused tail.  Levels before the tail go in pairs from the finest one where
 // the pair kernels apply (a level-k input of at least kPairMin x kPairMin,
-// see fused.h), else one by one.  (Shortening a three-level tail so that a
-// pair takes its finest level, 8192^2 at six levels as pairs 1-2, 3-4 and
-// tail 5-6, measured no faster than pair 1-2, level 3 and tail 4-6.)
-constexpr int kPairMin = 8;
+// see fused.h), else one by one.  The default path keeps the fused tail
+// only where it saves a launch: a pair launch now runs small levels faster
+// than the tail (8192^2 float six levels, pairs 1-2, 3-4, 5-6 against pairs
+// 1-2, level 3, tail 4-6: forward 124.9 vs 128.8 us, inverse 124.5 vs 127.5,
+// adjoint 132.7 vs 133.3; 2048^2: 26.4 / 25.3 / 32.1 vs 26.8 / 29.1 / 34.1
+// us), while a tail that replaces two launches with one still wins on tiny
+// images (256^2 at five levels: forward 19.3 vs 21.4 us).
 int plan_launches(int dir, const Geo& g, int batch, bool tail, int pairs, Launch* out) {
+  Launch a[DWT2_MAX_LEVELS + 1], b[DWT2_MAX_LEVELS + 1];
   const int k0 = tail ? tail_first_level(dir, g, batch) : 0;
-  const int last_single = k0 ? k0 - 1 : g.L;  // levels 1 .. last_single precede the tail
-  Launch fwd[DWT2_MAX_LEVELS];
-  int n = 0;
-  for (int k = 1; k <= last_single;) {
-    const bool want = pairs == kPairsAll || (pairs == kPairsDefault && default_pair(dir, g, k));
-    if (want && k + 1 <= last_single && g.w[k - 1] >= kPairMin && g.h[k - 1] >= kPairMin) {
-      fwd[n++] = Launch{k, k + 1, kLaunchPair};
-      k += 2;
-    } else {
-      fwd[n++] = Launch{k, k, kLaunchLevel};
-      k += 1;
+  int n = plan_levels(dir, g, batch, k0, pairs, a);
+  const Launch* p = a;
+  if (pairs == kPairsDefault && k0) {
+    const int nb = plan_levels(dir, g, batch, 0, pairs, b);
+    if (nb <= n) {
+      n = nb;
+      p = b;
     }
   }
-  if (k0) fwd[n++] = Launch{k0, g.L, kLaunchTail};
-  for (int i = 0; i < n; ++i) out[i] = dir == kFwd ? fwd[i] : fwd[n - 1 - i];  // the inverses run coarsest first
+  for (int i = 0; i < n; ++i) out[i] = dir == kFwd ? p[i] : p[n - 1 - i];  // the inverses run coarsest first
   return n;
 }
 
