@@ -339,7 +339,7 @@ int dwt2_tune_clear(void);
  * runs them in LDS on its tile plus a recompute halo; the inverse also
  * needs the coarsest input at least 4 x 4).
  *   0 (default): pairs for dwt2_inv and dwt2_bwd, and for dwt2_fwd where
- *     the pair's strips (112 quadruple columns each) would be at least 80 %
+ *     the pair's strips (112 quadruple columns each) would be at least 60 %
  *     filled by the level-k input's ceil(w/2) quadruple columns or the
  *     level-k input holds at most 1024 x 1024 pixels over the batch, single
  *     levels elsewhere, and the fused coarsest levels only where they take

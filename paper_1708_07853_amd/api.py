@@ -69,7 +69,7 @@ PATHS = {"levels": 0, "persistent": 1, "levels-only": 2, "pairs": 3, "pairs-only
 def set_path(path="levels") -> None:
     """How levels are chained (see dwt2_set_path): "levels" (default: pairs
     of levels in one launch for the inverse and adjoint, and for the forward
-    where the pair's strips are at least 80 % filled or the level is small;
+    where the pair's strips are at least 60 % filled or the level is small;
     the small coarsest levels fused into one launch where that saves a
     launch),
     "persistent" (one cooperative launch), "levels-only" (one launch per

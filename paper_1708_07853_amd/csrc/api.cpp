@@ -438,20 +438,22 @@ static int launch_tail_levels(int dir, const Call& c, const Geo& g, int k0, void
 //     us and 132 vs 147 us; 16384^2 int32 inverse 472 vs 554 us;
 //     32 x 3 x 1024^2 at four levels 186 vs 219 and 192 vs 219 us; 96 x 512^2
 //     at four levels 51 vs 71 and 60 vs 69 us);
-//   forward: faster where the strips' owned lanes are mostly busy (8192^2
-//     131.5 vs 140.9 us, 16384^2 int32 486 vs 552 us, 32 x 3 x 1024^2 207 vs
-//     224 us, 24 x 2048^2 at five levels 206 vs 229 us), slower for the batch
-//     of 512^2 images (74 vs 66 us), whose level-1 strips own 256 quadruple
-//     columns in 336 lanes' worth: the forward pairs a level when at least
-//     80 % of its strips' owned lanes hold quadruples, or when the level is
-//     small (at most kTailArea input pixels over the batch), where launch
-//     latency, not lane use, decides.
+//   forward: faster unless most of the strips' owned lanes are idle.  With
+//     tuned heights: 8192^2 131.5 vs 140.9 us, 16384^2 int32 486 vs 552 us,
+//     24 x 2048^2 at five levels 206 vs 229 us; 96 x 512^2 at four levels
+//     49 vs 66 us (256 quadruple columns in 3 strips: 76 % of the owned
+//     lanes), 24 x 700^2 30 vs 44 us (78 %), 96 x 300^2 at three levels 30
+//     vs 42 us (67 %); but 96 x 256^2 at three levels 28.2 vs 26.5 us (128
+//     columns in 2 strips: 57 %).  So the forward pairs a level when at
+//     least 60 % of its strips' owned lanes hold quadruples, or when the
+//     level is small (at most kTailArea input pixels over the batch), where
+//     launch latency, not lane use, decides.
 constexpr int kPairMin = 8;
 static bool default_pair(int dir, const Geo& g, int k, int batch) {
   if (dir != kFwd) return true;
   const int ns_w = ceil_half(g.w[k - 1]), q = pair_strip_q(dir);
   const int strips = (ns_w + q - 1) / q;
-  return 5 * ns_w >= 4 * strips * q || (int64_t)g.w[k - 1] * g.h[k - 1] * batch <= kTailArea;
+  return 5 * ns_w >= 3 * strips * q || (int64_t)g.w[k - 1] * g.h[k - 1] * batch <= kTailArea;
 }
 
 // The launches of levels 1..L before the fused tail at level k0 (0: none),
