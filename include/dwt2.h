@@ -341,7 +341,7 @@ int dwt2_tune_clear(void);
  *   0 (default): pairs for dwt2_inv and dwt2_bwd, and for dwt2_fwd where
  *     the pair's strips (112 quadruple columns each) would be at least 60 %
  *     filled by the level-k input's ceil(w/2) quadruple columns or the
- *     level-k input holds at most 1024 x 1024 pixels over the batch, single
+ *     level-k input holds at most 2 x 1024 x 1024 pixels over the batch, single
  *     levels elsewhere, and the fused coarsest levels only where they take
  *     fewer launches than pairs and single levels (what measured fastest
  *     on MI355X);

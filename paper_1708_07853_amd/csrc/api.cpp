@@ -446,14 +446,18 @@ static int launch_tail_levels(int dir, const Call& c, const Geo& g, int k0, void
 //     vs 42 us (67 %); but 96 x 256^2 at three levels 28.2 vs 26.5 us (128
 //     columns in 2 strips: 57 %).  So the forward pairs a level when at
 //     least 60 % of its strips' owned lanes hold quadruples, or when the
-//     level is small (at most kTailArea input pixels over the batch), where
-//     launch latency, not lane use, decides.
+//     level is small (at most kPairSmallArea input pixels over the batch),
+//     where launch latency, not lane use, decides: levels 2-3 of 96 x 256^2
+//     (1.6 Mpx) 21.4 vs 26.1 us, levels 3-4 of 96 x 512^2 49.2 vs 56.3 us
+//     for the whole call; but levels 3-4 of 32 x 3 x 1024^2 (6.3 Mpx) 193.1
+//     vs 190.4 us.
 constexpr int kPairMin = 8;
+constexpr int64_t kPairSmallArea = 2 * kTailArea;
 static bool default_pair(int dir, const Geo& g, int k, int batch) {
   if (dir != kFwd) return true;
   const int ns_w = ceil_half(g.w[k - 1]), q = pair_strip_q(dir);
   const int strips = (ns_w + q - 1) / q;
-  return 5 * ns_w >= 3 * strips * q || (int64_t)g.w[k - 1] * g.h[k - 1] * batch <= kTailArea;
+  return 5 * ns_w >= 3 * strips * q || (int64_t)g.w[k - 1] * g.h[k - 1] * batch <= kPairSmallArea;
 }
 
 // The launches of levels 1..L before the fused tail at level k0 (0: none),

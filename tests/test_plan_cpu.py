@@ -53,7 +53,7 @@ def test_launches_cover_every_level_once(path, w, h, b, L, d):
 
 def test_default_forward_pairs_follow_strip_fill():
     """A forward pair needs its strips (112 quadruple columns each) at least
-    60 % filled, or a small level (at most 1024^2 input pixels over the
+    60 % filled, or a small level (at most 2 x 1024^2 input pixels over the
     batch); the inverse and adjoint pair wherever a pair applies.  The fused
     tail stays only where it saves a launch."""
     api.set_path("levels")
@@ -67,12 +67,13 @@ def test_default_forward_pairs_follow_strip_fill():
     # save no launch
     assert api.launch_levels(2048, 2048, 6, "fwd", batch=8) == [(1, 2), (3, 4), (5, 6)]
     # 512 wide: 256 quadruple columns in 3 strips (336, 76 %) -> pair; level 3
-    # (128 wide, 1.6 Mpx): 64 columns in one strip (57 %) -> single
-    assert api.launch_levels(512, 512, 4, "fwd", batch=96) == [(1, 2), (3, 3), (4, 4)]
+    # (128 wide): 64 columns in one strip (57 %), but 1.6 Mpx -> pair
+    assert api.launch_levels(512, 512, 4, "fwd", batch=96) == [(1, 2), (3, 4)]
     # 300 wide: 150 columns in 2 strips (67 %) -> pair
     assert api.launch_levels(300, 300, 3, "fwd", batch=96) == [(1, 2), (3, 3)]
-    # 256 wide: 128 columns in 2 strips (57 %) -> single levels
-    assert api.launch_levels(256, 256, 3, "fwd", batch=96) == [(1, 1), (2, 2), (3, 3)]
+    # 256 wide: 128 columns in 2 strips (57 %, 6.3 Mpx) -> single; level 2
+    # (1.6 Mpx) -> pair
+    assert api.launch_levels(256, 256, 3, "fwd", batch=96) == [(1, 1), (2, 3)]
     assert api.launch_levels(512, 512, 4, "inv", batch=96) == [(3, 4), (1, 2)]
     # 1024 wide: 512 in 5 strips (560) -> pair; level 3 (256 wide): 128 in 2 strips (224) -> single
     assert api.launch_levels(1024, 1024, 4, "fwd", batch=96) == [(1, 2), (3, 3), (4, 4)]
