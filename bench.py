@@ -202,8 +202,9 @@ def cpu_baseline(w=4096, h=4096, levels=6, runs=3):
 
 
 def _tiled97(f):
-    """Run f with the CDF 9/7 on its LDS-tiled kernels (the same tiles as the
-    separable 9/7 comparison kernel) instead of the strip kernels."""
+    """Run f with the CDF 9/7 on its LDS-tiled kernels at every level (the same
+    tiles as the separable 9/7 comparison kernel) instead of the default
+    choice, which takes the strip kernels for most levels."""
     os.environ["DWT2_CDF97_TILED"] = "1"
     try:
         return f()

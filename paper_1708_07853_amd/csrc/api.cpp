@@ -688,6 +688,9 @@ static int run_lds(int scheme, const Call& c, const Geo& g, void* stream) {
 }
 
 // CDF 9/7: one launch per level, LL through the plain workspace's buffers.
+constexpr int64_t kTiled97Area = 512 * 512;
+constexpr int kTiled97Strips = 10;
+constexpr int kTile97Px = 128;  // a tiled-kernel tile's width in pixels (64 quadruples)
 static int run_cdf97(int dir, bool separable, const Call& c, const Geo& g, void* stream) {
   const int64_t ws_bs = (int64_t)(ws_per_image(g) / 4);
   for (int s = 0; s < g.L; ++s) {
@@ -745,12 +748,28 @@ static int run_cdf97(int dir, bool separable, const Call& c, const Geo& g, void*
         a.out_bstride = ws_bs;
       }
     }
-    // levels of at least 16 x 16 run in the strip kernels (bit-identical to
-    // the tiled ones; DWT2_CDF97_TILED=1, read per call, forces the tiled
-    // kernels for tests and comparisons)
+    // Levels of at least 16 x 16 run in the strip kernels, bit-identical to
+    // the tiled ones, except the forward's levels of at most kTiled97Strips
+    // strips per image (at least a fifth of them edge strips, whose folded
+    // single-element loads are slow), whose width is a whole number of
+    // tiles (kTile97Px) and that hold more than kTiled97Area pixels over
+    // the batch (below that, launch latency decides).  Forward, whole calls,
+    // strips only against this choice: 16 x 1024^2 four levels 58.6 vs
+    // 53.4 us, 96 x 256^2 three levels 44.8 vs 30.3, 4 x 2048^2 five levels
+    // 61.5 vs 58.8, 8192^2 six levels 167.3 vs 165.1.  The tiled kernel lost
+    // on 1500-pixel-wide levels (1500^2 at four levels 26.0 against 28.2
+    // us; 3000^2 at five, whose level 2 is 1500 wide, 44.0 against 46.0)
+    // and on a level of 14 strips (3000^2 with level 1 tiled too: 44.5
+    // against 47.7).  The inverse's strip kernels were faster everywhere.
+    // DWT2_CDF97_TILED=1 / 0, read per call, forces the tiled / strip
+    // kernels for tests and comparisons.
     int nstrips = 0;
     const char* tiled_env = getenv("DWT2_CDF97_TILED");
-    const bool strip = !separable && cdf97_strip_geometry(a.W, a.H, nstrips) && !(tiled_env && atoi(tiled_env) == 1);
+    const int force = tiled_env && *tiled_env ? atoi(tiled_env) : -1;
+    bool strip = !separable && cdf97_strip_geometry(a.W, a.H, nstrips) && force != 1;
+    if (strip && force != 0 && dir == kFwd && nstrips <= kTiled97Strips && a.W % kTile97Px == 0 &&
+        (int64_t)a.W * a.H * c.batch > kTiled97Area)
+      strip = false;
     int err;
     if (strip) {
       const Tiling t = choose_tiling(ceil_half(a.H), (int64_t)nstrips * c.batch);
