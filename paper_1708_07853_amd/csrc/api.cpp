@@ -691,10 +691,39 @@ static int run_lds(int scheme, const Call& c, const Geo& g, void* stream) {
 constexpr int64_t kTiled97Area = 512 * 512;
 constexpr int kTiled97Strips = 10;
 constexpr int kTile97Px = 128;  // a tiled-kernel tile's width in pixels (64 quadruples)
+// First level of the 9/7 forward's fused tail (0: none): the last
+// 2..kTailMaxLevels levels whose inputs hold at most kTailArea pixels over
+// the batch, each at least kTail97Min on a side.  Off unless
+// DWT2_CDF97_TAIL=1 (read per call; either DWT2_CDF97_TILED setting turns
+// it off again): measured on MI355X it is slower than the per-level
+// launches it replaces, whose strip kernels keep their state in registers,
+// while the tail runs a dozen barrier-separated LDS phases in one
+// workgroup per CU (96 KiB of LDS each).  Whole forward calls, tail
+// against per-level: 8192^2 six levels 169 vs 165 us, 16 x 1024^2 four
+// levels 56.9 vs 53.2, 1500^2 four levels 30.9 vs 26.4; with at most two
+// tail levels 169.5 vs 164.4 and 57 vs 53; with 32-pixel tiles and 512
+// threads 184 vs 165 and 67 vs 54 (only a lone 1024^2 image at four
+// levels gained, 24.0 vs 26.6).
+constexpr int kTail97Min = 8;
+static int cdf97_tail_first(const Call& c, const Geo& g) {
+  const char* tail_env = getenv("DWT2_CDF97_TAIL");
+  const char* tiled_env = getenv("DWT2_CDF97_TILED");
+  if (!(tail_env && *tail_env && atoi(tail_env) == 1) || (tiled_env && *tiled_env)) return 0;
+  int k = g.L, n = 0;
+  while (k >= 1 && n < kTailMaxLevels && (int64_t)g.w[k - 1] * g.h[k - 1] * c.batch <= kTailArea &&
+         g.w[k - 1] >= kTail97Min && g.h[k - 1] >= kTail97Min) {
+    --k;
+    ++n;
+  }
+  return n >= 2 ? k + 1 : 0;
+}
+
 static int run_cdf97(int dir, bool separable, const Call& c, const Geo& g, void* stream) {
   const int64_t ws_bs = (int64_t)(ws_per_image(g) / 4);
+  const int k0 = dir == kFwd && !separable ? cdf97_tail_first(c, g) : 0;
   for (int s = 0; s < g.L; ++s) {
     const int k = dir == kFwd ? s + 1 : g.L - s;  // the inverse runs coarsest first
+    if (k0 && k >= k0) break;  // the forward's last levels: the fused tail below
     Level97 a;
     memset(&a, 0, sizeof a);
     a.W = g.w[k - 1];
@@ -783,6 +812,32 @@ static int run_cdf97(int dir, bool separable, const Call& c, const Geo& g, void*
     }
     if (err != hipSuccess)
       return fail(DWT2_ERR_HIP, "CDF 9/7 level %d launch failed: %s", k, hipGetErrorString((hipError_t)err));
+  }
+  if (k0) {
+    TailArgs t;
+    memset(&t, 0, sizeof t);
+    t.n = g.L - k0 + 1;
+    t.batch = c.batch;
+    for (int m = 0; m <= t.n; ++m) {
+      t.W[m] = g.w[k0 - 1 + m];
+      t.H[m] = g.h[k0 - 1 + m];
+    }
+    if (k0 == 1) {
+      t.in = c.src;
+      t.in_stride = c.src_stride;
+      t.in_bstride = c.src_bs;
+    } else {
+      t.in = ll_buf(c, g, k0 - 1);
+      t.in_stride = ll_pitch(g.w[k0 - 1]);
+      t.in_bstride = ws_bs;
+    }
+    t.out = c.dst;
+    t.out_stride = c.dst_stride;
+    t.out_bstride = c.dst_bs;
+    cdf97_tail_tiles(t.W[0], t.H[0], t.tiles_x, t.tiles_y);
+    const int err = launch_cdf97_tail(t, stream);
+    if (err != hipSuccess)
+      return fail(DWT2_ERR_HIP, "CDF 9/7 levels %d..%d launch failed: %s", k0, g.L, hipGetErrorString((hipError_t)err));
   }
   return DWT2_OK;
 }

@@ -714,7 +714,154 @@ __global__ __launch_bounds__(kBlk) void fwd97_sep(Level97 a, int tiles_x) {
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// Fused forward tail: the last n (2 or 3) levels, whose inputs are small,
+// in one launch.  Each workgroup owns a kT97 x kT97 tile of the first tail
+// level's input and runs every level on that tile plus a recompute halo in
+// LDS.  A level reaches two quadruples (four pixels) to each side, so level
+// m of the tail needs 4 (2^(n-m) - 1) pixels of halo and its region, minus
+// two quadruples on each side, is the next level's region.  Each region is
+// filled through the symmetric fold of its own level (the first from
+// memory, the others from the LL the level before left in LDS), so every
+// value past an edge is the one the per-level kernels read, and far-out
+// positions that no in-image output reaches take any in-region value.  The
+// four steps are the tiled kernel's on the same operands: the results are
+// bit-identical to the per-level launches.
+// ---------------------------------------------------------------------------
+constexpr int kT97 = 64;
+__host__ __device__ constexpr int tail97_halo(int n, int m) { return 4 * ((1 << (n - m)) - 1); }
+constexpr int kTail97Q = (kT97 + 2 * tail97_halo(kTailMaxLevels, 0)) / 2;  // largest region, quadruples per side
+constexpr int kTail97N = kT97 / 2 + 2 * tail97_halo(kTailMaxLevels, 1);    // largest LL hand-off, pixels per side
+constexpr int kTail97Lds = 6 * kTail97Q * kTail97Q + kTail97N * kTail97N;   // floats (96.6 KiB)
+constexpr int kTail97Block = 1024;
+static_assert(kTail97Q - 4 == kTail97N, "level 1's region is level 0's, less two quadruples per side");
+
+// f(i, q) for i in [i0, i1), q in [q0, q1): consecutive threads take
+// consecutive columns.
+template <typename F>
+__device__ __forceinline__ void tail97_walk(int i0, int i1, int q0, int q1, F&& f) {
+  const int cols = q1 - q0, cnt = (i1 - i0) * cols;
+  for (int e = (int)threadIdx.x; e < cnt; e += kTail97Block) {
+    const int r = e / cols;
+    f(i0 + r, q0 + e - r * cols);
+  }
+}
+
+__global__ __launch_bounds__(kTail97Block) void tail97_fwd(TailArgs a) {
+  __shared__ float S[kTail97Lds];
+  float* N = S + 6 * kTail97Q * kTail97Q;  // LL of the level just done, over the next region
+  const int t = threadIdx.x;
+  const int ty = blockIdx.x / a.tiles_x, tx = blockIdx.x - ty * a.tiles_x;
+  const int n = a.n;
+  // level-0 loads per thread: all issued before the first LDS store
+  constexpr int kLoads = (4 * kTail97Q * kTail97Q + kTail97Block - 1) / kTail97Block;
+  for (int img = blockIdx.y; img < a.batch; img += gridDim.y) {
+    const float* src = static_cast<const float*>(a.in) + img * a.in_bstride;
+    float* dst = static_cast<float*>(a.out) + img * a.out_bstride;
+    for (int m = 0; m < n; ++m) {
+      const int T = kT97 >> m, h = tail97_halo(n, m);
+      const int R = T + 2 * h, Q = R / 2, P = Q * Q;
+      const int W = a.W[m], H = a.H[m];
+      const int ox = tx * T - h, oy = ty * T - h;  // level-m pixel of the region's local (0, 0)
+      float* A = S;
+      float* B = S + P;
+      float* C = S + 2 * P;
+      float* D = S + 3 * P;
+      float* B1 = S + 4 * P;
+      float* C1 = S + 5 * P;
+      __syncthreads();  // the previous level's LL is in N; S is free
+      if (m == 0) {
+        float v[kLoads];
+#pragma unroll
+        for (int k = 0; k < kLoads; ++k) {
+          const int e = t + k * kTail97Block < R * R ? t + k * kTail97Block : 0;
+          const int r = e / R, c = e - r * R;
+          v[k] = src[(int64_t)fold97(oy + r, H) * a.in_stride + fold97(ox + c, W)];
+        }
+#pragma unroll
+        for (int k = 0; k < kLoads; ++k) {
+          const int e = t + k * kTail97Block;
+          if (e < R * R) {
+            const int r = e / R, c = e - r * R;
+            S[((r & 1) * 2 + (c & 1)) * P + (r >> 1) * Q + (c >> 1)] = v[k];
+          }
+        }
+      } else {
+        for (int e = t; e < R * R; e += kTail97Block) {
+          const int r = e / R, c = e - r * R;
+          const int fr = min(max(fold97(oy + r, H) - oy, 0), R - 1);
+          const int fc = min(max(fold97(ox + c, W) - ox, 0), R - 1);
+          S[((r & 1) * 2 + (c & 1)) * P + (r >> 1) * Q + (c >> 1)] = N[fr * R + fc];
+        }
+      }
+      __syncthreads();
+      // pair 1 predict (alpha), update (beta); pair 2 predict (gamma)
+      tail97_walk(0, Q - 1, 0, Q - 1, [&](int i, int q) {
+        const int o = i * Q + q;
+        sp_pred(kAlpha, kAlpha2, A[o], A[o + 1], A[o + Q], A[o + Q + 1], B[o], B[o + Q], C[o], C[o + 1], D[o], B1[o],
+                C1[o], D[o]);
+      });
+      __syncthreads();
+      tail97_walk(1, Q - 1, 1, Q - 1, [&](int i, int q) {
+        const int o = i * Q + q;
+        sp_upd(kBeta, kBeta2, A[o], B1[o - 1], B1[o], C1[o - Q], C1[o], D[o - Q - 1], D[o - Q], D[o - 1], D[o], A[o],
+               B[o], C[o]);
+      });
+      __syncthreads();
+      tail97_walk(1, Q - 2, 1, Q - 2, [&](int i, int q) {
+        const int o = i * Q + q;
+        sp_pred(kGamma, kGamma2, A[o], A[o + 1], A[o + Q], A[o + Q + 1], B[o], B[o + Q], C[o], C[o + 1], D[o], B1[o],
+                C1[o], D[o]);
+      });
+      __syncthreads();
+      // pair 2 update (delta) and the scaling over the next region; the
+      // tile's own quadruples go out (their H bands, and the last level's LL)
+      const bool last = m == n - 1;
+      const int ns_w = (W + 1) >> 1, ns_h = (H + 1) >> 1, nd_w = W >> 1, nd_h = H >> 1;
+      const int own0 = h / 2, Tq = T / 2, Rn = Q - 4;
+      tail97_walk(2, Q - 2, 2, Q - 2, [&](int i, int q) {
+        const int o = i * Q + q;
+        float vll, vhl, vlh;
+        sp_upd(kDelta, kDelta2, A[o], B1[o - 1], B1[o], C1[o - Q], C1[o], D[o - Q - 1], D[o - Q], D[o - 1], D[o], vll,
+               vhl, vlh);
+        const float vhh = D[o] * kHHScale;
+        vll *= kLLScale;
+        if (!last) N[(i - 2) * Rn + (q - 2)] = vll;
+        const int li = i - own0, lq = q - own0;
+        const int gqy = ty * Tq + li, gqx = tx * Tq + lq;
+        if (li >= 0 && li < Tq && lq >= 0 && lq < Tq && gqx < ns_w && gqy < ns_h) {
+          if (last) __builtin_nontemporal_store(vll, dst + (int64_t)gqy * a.out_stride + gqx);
+          if (gqx < nd_w) __builtin_nontemporal_store(vhl, dst + (int64_t)gqy * a.out_stride + ns_w + gqx);
+          if (gqy < nd_h) {
+            __builtin_nontemporal_store(vlh, dst + (int64_t)(ns_h + gqy) * a.out_stride + gqx);
+            if (gqx < nd_w) __builtin_nontemporal_store(vhh, dst + (int64_t)(ns_h + gqy) * a.out_stride + ns_w + gqx);
+          }
+        }
+      });
+    }
+  }
+}
+
 }  // namespace
+
+int cdf97_tail_tiles(int W, int H, int& tiles_x, int& tiles_y) {
+  tiles_x = (W + kT97 - 1) / kT97;
+  tiles_y = (H + kT97 - 1) / kT97;
+  return (int64_t)tiles_x * tiles_y <= 0x7fffffff;
+}
+
+int launch_cdf97_tail(const TailArgs& a, void* stream) {
+  int tx, ty;
+  if (a.n < 2 || a.n > kTailMaxLevels || !cdf97_tail_tiles(a.W[0], a.H[0], tx, ty) || tx != a.tiles_x ||
+      ty != a.tiles_y)
+    return hipErrorInvalidValue;
+  for (int m = 0; m < a.n; ++m)
+    if (a.W[m] < 2 || a.H[m] < 2) return hipErrorInvalidValue;  // the fold needs two samples
+  const dim3 grid((unsigned)(tx * ty), (unsigned)(a.batch < 65535 ? a.batch : 65535));
+  hipLaunchKernelGGL(tail97_fwd, grid, dim3(kTail97Block), 0, static_cast<hipStream_t>(stream), a);
+  return hipGetLastError();
+}
 
 int cdf97_tiles(int W, int H, int& tiles_x, int& tiles_y) {
   tiles_x = (((W + 1) >> 1) + kQX - 1) / kQX;

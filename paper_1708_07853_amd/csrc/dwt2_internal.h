@@ -184,6 +184,12 @@ int launch_cdf97_level(int dir, bool separable, const Level97& a, void* stream);
 // staged = the forward writes whole lines through LDS.
 int cdf97_strip_geometry(int W, int H, int& nstrips);
 int launch_cdf97_strip(int dir, const Level97& a, int segh, int chunk, bool staged, void* stream);
+// The last a.n (2..kTailMaxLevels) levels of a CDF 9/7 forward in one
+// launch (a.in: the first tail level's input; a.out: the packed array,
+// which takes every tail level's bands and the last LL); tiles of 64 x 64
+// pixels of the first tail level's input; every tail level at least 2 x 2.
+int cdf97_tail_tiles(int W, int H, int& tiles_x, int& tiles_y);
+int launch_cdf97_tail(const TailArgs& a, void* stream);
 
 // Strip-kernel launchers, instantiated per direction (level kernels in
 // strip_fwd.hip, strip_inv.hip, strip_bwd.hip; job and table kernels in

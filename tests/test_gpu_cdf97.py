@@ -164,6 +164,31 @@ def test_cdf97_batch_strides():
     assert torch.all(obase[:, 0] == -5) and torch.all(obase[:, 334:] == -5)
 
 
+# the forward's fused tail (DWT2_CDF97_TAIL=1: its last 2-3 levels of at most
+# 1024^2 pixels over the batch, each at least 8 x 8, in one launch on 64 x 64
+# pixel tiles): ragged and odd sizes, tiles past the edge, two or three
+# levels in the tail, whole transforms in it, batches; bit-identical to the
+# per-level kernels
+TAIL_CASES = [((64, 64), 3), ((300, 517), 4), ((97, 131), 3), ((1000, 1000), 2), ((33, 70), 2), ((256, 256), 5),
+              ((130, 65), 3), ((9, 200), 1)]
+
+
+def test_cdf97_tail_equals_per_level(monkeypatch):
+    d = D()
+    for idx, ((h, w), levels) in enumerate(TAIL_CASES):
+        for batch in (1, 3):
+            xn = np.stack([_img(h, w, 9600 + 10 * idx + b) for b in range(batch)])
+            x = to_gpu(xn if batch > 1 else xn[0])
+            print(f"cdf97 tail: {batch} x {h}x{w} levels {levels}", flush=True)
+            monkeypatch.delenv("DWT2_CDF97_TAIL", raising=False)
+            ref = d.fwd_cdf97(x, levels)
+            monkeypatch.setenv("DWT2_CDF97_TAIL", "1")
+            got = d.fwd_cdf97(x, levels)
+            assert torch.equal(got, ref), (batch, h, w, levels, float((got - ref).abs().max()))
+            g0 = got[0] if batch > 1 else got
+            assert maxdiff(g0.cpu().numpy(), dwt97.fwd(xn[0], levels)) <= TOL97, (batch, h, w, levels)
+
+
 def test_cdf97_full_size():
     """The 8192^2 6-level workload: the forward against the oracle element
     by element, the inverse through the round trip."""
