@@ -434,21 +434,7 @@ __device__ void fwd97_strip_item(const Level97& a, const float* __restrict__ px,
     p1U_L = p1L; p1U_R = p1R; p2U_L = p2L; p2U_R = p2R; p2U_P = p2P;
     E = E1;
   };
-  // prologue: pixel rows 2 I0 - 4 .. 2 I0; the first predict of row I0 - 2
-  // and the first pair of row I0 - 1
-  {
-    V4<float> v[5];
-#pragma unroll
-    for (int k = 0; k < 5; ++k) L.load(2 * I0 - 4 + k, v[k]);
-    E = v[0];
-    float p0L, p0R;
-    sp_pred(kAlpha, kAlpha2, E.x, E.z, v[2].x, v[2].z, E.y, v[2].y, v[1].x, v[1].z, v[1].y, p0L, p1U_L, p2U_L);
-    sp_pred(kAlpha, kAlpha2, E.z, from_next(E.x), v[2].z, from_next(v[2].x), E.w, v[2].w, v[1].z, from_next(v[1].x),
-            v[1].w, p0R, p1U_R, p2U_R);
-    p2U_P = from_prev(p2U_R);
-    E = v[2];
-    pair1(v[3], v[4], a1L, b1L, c1L, d1L, a1R, b1R, c1R, d1R);
-  }
+  // chunks of the row loop (below)
   struct Buf {
     V4<float> v[CP][2];
   };
@@ -459,6 +445,24 @@ __device__ void fwd97_strip_item(const Level97& a, const float* __restrict__ px,
       L.load(2 * (r0 + m) + 2, b.v[m][1]);
     }
   };
+  Buf A, B;
+  // prologue: pixel rows 2 I0 - 4 .. 2 I0; the first predict of row I0 - 2
+  // and the first pair of row I0 - 1; the first chunk's loads go out right
+  // after these, before the arithmetic
+  {
+    V4<float> v[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) L.load(2 * I0 - 4 + k, v[k]);
+    load_chunk(A, I0);
+    E = v[0];
+    float p0L, p0R;
+    sp_pred(kAlpha, kAlpha2, E.x, E.z, v[2].x, v[2].z, E.y, v[2].y, v[1].x, v[1].z, v[1].y, p0L, p1U_L, p2U_L);
+    sp_pred(kAlpha, kAlpha2, E.z, from_next(E.x), v[2].z, from_next(v[2].x), E.w, v[2].w, v[1].z, from_next(v[1].x),
+            v[1].w, p0R, p1U_R, p2U_R);
+    p2U_P = from_prev(p2U_R);
+    E = v[2];
+    pair1(v[3], v[4], a1L, b1L, c1L, d1L, a1R, b1R, c1R, d1R);
+  }
   // row r: the first pair of row r, then the second pair of row r - 1
   auto row = [&](const Buf& b, int m, int r) {
     float aL, bL, cL, dL, aR, bR, cR, dR;
@@ -475,8 +479,6 @@ __device__ void fwd97_strip_item(const Level97& a, const float* __restrict__ px,
     q1U_L = q1L; q1U_R = q1R; q2U_L = q2L; q2U_R = q2R; q2U_P = q2P;
     a1L = aL; b1L = bL; c1L = cL; d1L = dL; a1R = aR; b1R = bR; c1R = cR; d1R = dR;
   };
-  Buf A, B;
-  load_chunk(A, I0);
   run_rows<CP>(I0, I1 + 1, A, B, load_chunk, row);
 }
 
@@ -525,18 +527,7 @@ __device__ void inv97_strip_item(const Level97& a, const float* __restrict__ lls
     dR = hhR;
     lhU_L = lh[0]; lhU_R = lh[1]; hhU_L = hhL; hhU_R = hhR; hhU_P = hhP;
   };
-  // prologue: coefficient rows I0 - 2 (the up neighbours) and I0 - 1 (U1)
-  {
-    float ll0[2], hl0[2], lh0[2], hh0[2], ll1[2], hl1[2], lh1[2], hh1[2];
-    B.even(I0 - 2, ll0, hl0);
-    B.odd(I0 - 2, lh0, hh0);
-    B.even(I0 - 1, ll1, hl1);
-    B.odd(I0 - 1, lh1, hh1);
-    lhU_L = lh0[0]; lhU_R = lh0[1];
-    hhU_L = hh0[0] * kLLScale; hhU_R = hh0[1] * kLLScale;
-    hhU_P = from_prev(hhU_R);
-    undo1(ll1, hl1, lh1, hh1, A1L, B1L, C1L, D1L, A1R, B1R, C1R, D1R);
-  }
+  // chunks of the row loop (below)
   struct Buf {
     float ll[CP][2], hl[CP][2], lh[CP][2], hh[CP][2];
   };
@@ -547,6 +538,21 @@ __device__ void inv97_strip_item(const Level97& a, const float* __restrict__ lls
       B.odd(r0 + m, b.lh[m], b.hh[m]);
     }
   };
+  Buf A, Bb;
+  // prologue: coefficient rows I0 - 2 (the up neighbours) and I0 - 1 (U1);
+  // the first chunk's loads go out right after these, before the arithmetic
+  {
+    float ll0[2], hl0[2], lh0[2], hh0[2], ll1[2], hl1[2], lh1[2], hh1[2];
+    B.even(I0 - 2, ll0, hl0);
+    B.odd(I0 - 2, lh0, hh0);
+    B.even(I0 - 1, ll1, hl1);
+    B.odd(I0 - 1, lh1, hh1);
+    load_chunk(A, I0);
+    lhU_L = lh0[0]; lhU_R = lh0[1];
+    hhU_L = hh0[0] * kLLScale; hhU_R = hh0[1] * kLLScale;
+    hhU_P = from_prev(hhU_R);
+    undo1(ll1, hl1, lh1, hh1, A1L, B1L, C1L, D1L, A1R, B1R, C1R, D1R);
+  }
   auto row = [&](const Buf& b, int m, int r) {
     float a1L, b1L, c1L, d1L, a1R, b1R, c1R, d1R;
     undo1(b.ll[m], b.hl[m], b.lh[m], b.hh[m], a1L, b1L, c1L, d1L, a1R, b1R, c1R, d1R);
@@ -574,8 +580,6 @@ __device__ void inv97_strip_item(const Level97& a, const float* __restrict__ lls
     A1L = a1L; B1L = b1L; C1L = c1L; D1L = d1L; A1R = a1R; B1R = b1R; C1R = c1R; D1R = d1R;
     A2L = a2L; B2L = b2L; C2L = c2L; D2L = pdL; A2R = a2R; B2R = b2R; C2R = c2R; D2R = pdR;
   };
-  Buf A, Bb;
-  load_chunk(A, I0);
   run_rows<CP>(I0, I1 + 2, A, Bb, load_chunk, row);
 }
 

@@ -371,13 +371,27 @@ __device__ void fwd_pair(const LevelDesc& d, const T* __restrict__ px, T* __rest
   // the pair before (pea, peb, poc, pod) for the bottom fold of odd H1
   T ea, eb, oc, od, pea, peb, poc, pod;
 
+  struct Buf {
+    V4<T> v[CP][4];
+  };
+  auto load_chunk = [&](Buf& b, int p0) {
+#pragma unroll
+    for (int m = 0; m < CP; ++m)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) L.load(4 * (p0 + m) + 3 + k, b.v[m][k]);
+  };
+  Buf A, B;
+
   // ---- prologue: level-k rows 2 J0 - 3 (predicted only) .. 2 J0, level-(k+1)
-  // predicted row J0 - 1
+  // predicted row J0 - 1.  The first chunk's loads go out right after the
+  // prologue's, before its arithmetic: a work item waits for memory once
+  // before its first pair, not twice.
   const int r0 = 4 * it.J0 - 6;  // first pixel row read
   {
     V4<T> v[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) L.load(r0 + k, v[k]);
+    load_chunk(A, it.J0);
     E = v[0];
     kpredict(v[1], v[2]);
     T l0, r0_, l1, r1, l2, r2;
@@ -394,15 +408,6 @@ __device__ void fwd_pair(const LevelDesc& d, const T* __restrict__ px, T* __rest
   direct_k = false;
 
   // ---- pairs p = J0 .. J1-1: level-k rows 2p+1, 2p+2; level-(k+1) row p
-  struct Buf {
-    V4<T> v[CP][4];
-  };
-  auto load_chunk = [&](Buf& b, int p0) {
-#pragma unroll
-    for (int m = 0; m < CP; ++m)
-#pragma unroll
-      for (int k = 0; k < 4; ++k) L.load(4 * (p0 + m) + 3 + k, b.v[m][k]);
-  };
   auto pair = [&](const Buf& b, int m, int p) {
     T xc, xd, xaD, xbD;
     krow(2 * p + 1, b.v[m][0], b.v[m][1], xc, xd);
@@ -422,8 +427,6 @@ __device__ void fwd_pair(const LevelDesc& d, const T* __restrict__ px, T* __rest
     pea = ea; peb = eb; poc = xc; pod = xd;
     ea = xaD; eb = xbD;
   };
-  Buf A, B;
-  load_chunk(A, it.J0);
   run_rows<CP>(it.J0, it.J1, A, B, load_chunk, pair);
 }
 
@@ -564,27 +567,7 @@ __device__ void inv_pair(const LevelDesc& d, const T* __restrict__ ll2, const T*
   // row H1 (virtual) as row H1 - 1 (H even) or H1 - 2 (H odd)
   T xa_p, xb_p, xc_p, xd_p;  // LL_k rows 2p - 2 (xa, xb) and 2p - 1 (xc, xd)
 
-  // ---- prologue: level-(k+1) odd part of row J0 - 1 and undone update of
-  // row J0; level-k odd part of row 2 J0 - 1
-  {
-    T lh0, hh0, ll1, hl1, lh1, hh1_;
-    B1.odd(it.J0 - 1, &lh0, &hh0);
-    B1.even(it.J0, &ll1, &hl1);
-    B1.odd(it.J0, &lh1, &hh1_);
-    T lh[2], hh[2];
-    B0.odd(2 * it.J0 - 1, lh, hh);
-    lhU1 = lh0;
-    hhU1 = hh0;
-    k1undo(ll1, hl1, lh1, hh1_, v0, v1, v2);
-    hh1 = hh1_;
-    lhU_L = lh[0]; lhU_R = lh[1]; hhU_L = hh[0]; hhU_R = hh[1];
-    a_L = a_R = b_L = b_R = c_L = c_R = hh_L = hh_R = T(0);  // row 2 J0 - 1: not stored
-    xa_p = xb_p = xc_p = xd_p = T(0);
-  }
-
-  // ---- pairs p = J0 .. J1: level-(k+1) row p+1 undone, row p reconstructed
-  // (LL_k rows 2p, 2p+1); level-k rows 2p and 2p+1 undone, rows 2p-1 and 2p
-  // reconstructed (pixel rows 4p-2 .. 4p+1)
+  // chunks of the pair loop (below)
   struct Buf {
     T ll1[CP], hl1[CP], lh1[CP], hh1[CP];
     T hl[CP][2][2], lh[CP][2][2], hh[CP][2][2];
@@ -602,6 +585,31 @@ __device__ void inv_pair(const LevelDesc& d, const T* __restrict__ ll2, const T*
       }
     }
   };
+  Buf A, Bb;
+
+  // ---- prologue: level-(k+1) odd part of row J0 - 1 and undone update of
+  // row J0; level-k odd part of row 2 J0 - 1.  The first chunk's loads go
+  // out right after the prologue's, before its arithmetic.
+  {
+    T lh0, hh0, ll1, hl1, lh1, hh1_;
+    B1.odd(it.J0 - 1, &lh0, &hh0);
+    B1.even(it.J0, &ll1, &hl1);
+    B1.odd(it.J0, &lh1, &hh1_);
+    T lh[2], hh[2];
+    B0.odd(2 * it.J0 - 1, lh, hh);
+    load_chunk(A, it.J0);
+    lhU1 = lh0;
+    hhU1 = hh0;
+    k1undo(ll1, hl1, lh1, hh1_, v0, v1, v2);
+    hh1 = hh1_;
+    lhU_L = lh[0]; lhU_R = lh[1]; hhU_L = hh[0]; hhU_R = hh[1];
+    a_L = a_R = b_L = b_R = c_L = c_R = hh_L = hh_R = T(0);  // row 2 J0 - 1: not stored
+    xa_p = xb_p = xc_p = xd_p = T(0);
+  }
+
+  // ---- pairs p = J0 .. J1: level-(k+1) row p+1 undone, row p reconstructed
+  // (LL_k rows 2p, 2p+1); level-k rows 2p and 2p+1 undone, rows 2p-1 and 2p
+  // reconstructed (pixel rows 4p-2 .. 4p+1)
   auto pair = [&](const Buf& b, int m, int p) {
     T n0, n1, n2;
     k1undo(b.ll1[m], b.hl1[m], b.lh1[m], b.hh1[m], n0, n1, n2);
@@ -619,8 +627,6 @@ __device__ void inv_pair(const LevelDesc& d, const T* __restrict__ ll2, const T*
     krow(2 * p + 1, oc, od, b.hl[m][1], b.lh[m][1], b.hh[m][1]);
     xa_p = ea; xb_p = eb; xc_p = oc; xd_p = od;
   };
-  Buf A, Bb;
-  load_chunk(A, it.J0);
   run_rows<CP>(it.J0, it.J1 + 1, A, Bb, load_chunk, pair);
 }
 
@@ -707,36 +713,7 @@ __device__ void bwd_pair(const LevelDesc& d, const float* __restrict__ ll2, cons
     ka_L = naL; ka_R = naR; kb_L = nb[0]; kb_R = nb[1]; kc_L = nc[0]; kc_R = nc[1]; kd_L = nd[0]; kd_R = nd[1];
   };
 
-  // ---- prologue: level-(k+1) rows J0 - 2 .. J0 loaded, step A of J0 - 2
-  // and J0 - 1, step B of J0 - 1 (LL_k-gradient rows 2 J0 - 2, 2 J0 - 1);
-  // level-k row 2 J0 - 1 current, its step A needs LL_k-gradient row 2 J0
-  {
-    float a0, b0, c0, d0, a1, b1_, c1, d1, a2, b2, c2, d2;
-    B1.even(it.J0 - 2, &a0, &b0);
-    B1.odd(it.J0 - 2, &c0, &d0);
-    B1.even(it.J0 - 1, &a1, &b1_);
-    B1.odd(it.J0 - 1, &c1, &d1);
-    B1.even(it.J0, &a2, &b2);
-    B1.odd(it.J0, &c2, &d2);
-    float hb[2], hc[2], hd[2];
-    B0.even(2 * it.J0 - 1, nullptr, hb);
-    B0.odd(2 * it.J0 - 1, hc, hd);
-    ga1 = a0; gb1 = b0; gc1 = c0; gd1 = d0;
-    k1stepA(it.J0 - 2, a1, b1_);
-    sc1U = sc1; sd1U = sd1; sd1UP = from_prev(sd1);
-    ga1 = a1; gb1 = b1_; gc1 = c1; gd1 = d1;
-    k1stepA(it.J0 - 1, a2, b2);
-    float xa, xb, xc, xd;
-    k1stepB(it.J0 - 1, xa, xb, xc, xd);
-    ga1 = a2; gb1 = b2; gc1 = c2; gd1 = d2;
-    // level k: row 2 J0 - 1 (LL_k gradient xc, xd) is the current row
-    ka_L = xc; ka_R = xd; kb_L = hb[0]; kb_R = hb[1]; kc_L = hc[0]; kc_R = hc[1]; kd_L = hd[0]; kd_R = hd[1];
-    tc_UL = tc_UR = td_UL = td_UR = td_UP = 0.f;  // row 2 J0 - 2: its outputs are not stored
-  }
-
-  // ---- pairs p = J0 .. J1: level-(k+1) step A of row p (needs row p+1),
-  // step B of row p (LL_k-gradient rows 2p, 2p+1); level-k rows 2p - 1 and
-  // 2p (pixel rows 4p - 2 .. 4p + 1)
+  // chunks of the pair loop (below)
   struct Buf {
     float a1[CP], b1[CP], c1[CP], d1[CP];
     float hb[CP][2][2], hc[CP][2][2], hd[CP][2][2];
@@ -754,6 +731,41 @@ __device__ void bwd_pair(const LevelDesc& d, const float* __restrict__ ll2, cons
       }
     }
   };
+  Buf A, Bb;
+
+  // ---- prologue: level-(k+1) rows J0 - 2 .. J0 loaded, step A of J0 - 2
+  // and J0 - 1, step B of J0 - 1 (LL_k-gradient rows 2 J0 - 2, 2 J0 - 1);
+  // level-k row 2 J0 - 1 current, its step A needs LL_k-gradient row 2 J0.
+  // The first chunk's loads go out right after the prologue's, before its
+  // arithmetic.
+  {
+    float a0, b0, c0, d0, a1, b1_, c1, d1, a2, b2, c2, d2;
+    B1.even(it.J0 - 2, &a0, &b0);
+    B1.odd(it.J0 - 2, &c0, &d0);
+    B1.even(it.J0 - 1, &a1, &b1_);
+    B1.odd(it.J0 - 1, &c1, &d1);
+    B1.even(it.J0, &a2, &b2);
+    B1.odd(it.J0, &c2, &d2);
+    float hb[2], hc[2], hd[2];
+    B0.even(2 * it.J0 - 1, nullptr, hb);
+    B0.odd(2 * it.J0 - 1, hc, hd);
+    load_chunk(A, it.J0);
+    ga1 = a0; gb1 = b0; gc1 = c0; gd1 = d0;
+    k1stepA(it.J0 - 2, a1, b1_);
+    sc1U = sc1; sd1U = sd1; sd1UP = from_prev(sd1);
+    ga1 = a1; gb1 = b1_; gc1 = c1; gd1 = d1;
+    k1stepA(it.J0 - 1, a2, b2);
+    float xa, xb, xc, xd;
+    k1stepB(it.J0 - 1, xa, xb, xc, xd);
+    ga1 = a2; gb1 = b2; gc1 = c2; gd1 = d2;
+    // level k: row 2 J0 - 1 (LL_k gradient xc, xd) is the current row
+    ka_L = xc; ka_R = xd; kb_L = hb[0]; kb_R = hb[1]; kc_L = hc[0]; kc_R = hc[1]; kd_L = hd[0]; kd_R = hd[1];
+    tc_UL = tc_UR = td_UL = td_UR = td_UP = 0.f;  // row 2 J0 - 2: its outputs are not stored
+  }
+
+  // ---- pairs p = J0 .. J1: level-(k+1) step A of row p (needs row p+1),
+  // step B of row p (LL_k-gradient rows 2p, 2p+1); level-k rows 2p - 1 and
+  // 2p (pixel rows 4p - 2 .. 4p + 1)
   auto pair = [&](const Buf& b, int m, int p) {
     k1stepA(p, b.a1[m], b.b1[m]);
     float xa, xb, xc, xd;
@@ -762,8 +774,6 @@ __device__ void bwd_pair(const LevelDesc& d, const float* __restrict__ ll2, cons
     krow(2 * p - 1, xa, xb, b.hb[m][0], b.hc[m][0], b.hd[m][0]);
     krow(2 * p, xc, xd, b.hb[m][1], b.hc[m][1], b.hd[m][1]);
   };
-  Buf A, Bb;
-  load_chunk(A, it.J0);
   run_rows<CP>(it.J0, it.J1 + 1, A, Bb, load_chunk, pair);
 }
 
