@@ -951,8 +951,8 @@ static int tune(int dir, const void* src, int64_t src_stride, int64_t src_bs, vo
     std::lock_guard<std::mutex> lock(g_probe_mu);
     saved = g_probe;
   }
-  static const int kPairSegs[] = {0, 4, 6, 8, 10, 12, 16, 20, 24, 32};
-  static const int kLevelSegs[] = {0, 2, 4, 6, 8, 12, 16, 24, 32, 48, 64};
+  static const int kPairSegs[] = {0, 1, 2, 3, 4, 6, 8, 10, 12, 16, 20, 24, 32};
+  static const int kLevelSegs[] = {0, 1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64};
   int st = DWT2_OK;
   for (int i = 0; i < n && st == DWT2_OK; ++i) {
     const Launch& l = plan[i];
