@@ -292,6 +292,9 @@ def main():
     fwd(s0)  # the inverse's tuning input
     tune_passes(dwt, [("fwd", s0["x"], s0["c"], ws), ("inv", s0["c"], s0["r"], ws), ("bwd", s0["g"], s0["gx"], ws)], L)
 
+    if args.only in ("fwd97", "inv97"):
+        dwt.fwd_cdf97(s0["x"], L, out=s0["c"], workspace=ws)
+        tune_passes(dwt, [("fwd_cdf97", s0["x"], s0["c"], ws), ("inv_cdf97", s0["c"], s0["r"], ws)], L)
     if args.only:
         reps = max(1, args.steps)
         for i in range(reps):
@@ -466,6 +469,9 @@ def side_measurements(detail, sets, ws, fwd, W, H, L, npx, torch, dwt, synth, de
         "lds_tiled_speedup_of_two_steps_over_four": round(lds["separable"] / lds["nonseparable"], 3)}
     del wss
     # CDF 9/7 (float32), the same image and levels: forward and inverse
+    s0 = sets[0]
+    dwt.fwd_cdf97(s0["x"], L, out=s0["c"], workspace=ws)  # the inverse's tuning input
+    tune_passes(dwt, [("fwd_cdf97", s0["x"], s0["c"], ws), ("inv_cdf97", s0["c"], s0["r"], ws)], L)
     t97 = {}
     for name, f in (("fwd", lambda s_: dwt.fwd_cdf97(s_["x"], L, out=s_["c"], workspace=ws)),
                     ("inv", lambda s_: dwt.inv_cdf97(s_["c"], L, out=s_["r"], workspace=ws)),

@@ -301,13 +301,14 @@ int dwt2_set_tiling(int32_t seg, int32_t chunk);
 
 /* Per-shape tuning of the work-item height of the per-level path (a
  * performance aid; results never change).  Runs the call that dwt2_fwd
- * (dir 0), dwt2_inv (dir 1) or dwt2_bwd (dir 2) would run with these
- * arguments -- same meaning, layout, validation and errors -- several
- * times: for each single-level or pair launch of the current path, in
- * execution order, it times that launch (events on `stream`) at a few
- * candidate heights and records the fastest for the launch's shape
- * (launch kind, direction, mode, level input size, batch) when it beats
- * the automatic choice by more than 2 %.  Later calls of any entry point
+ * (dir 0), dwt2_inv (dir 1), dwt2_bwd (dir 2), dwt2_fwd_cdf97 (dir 3) or
+ * dwt2_inv_cdf97 (dir 4) would run with these arguments -- same meaning,
+ * layout, validation and errors -- several times: for each single-level or
+ * pair launch of the current path (for the CDF 9/7: each level that runs in
+ * a strip kernel), in execution order, it times that launch (events on
+ * `stream`) at a few candidate heights and records the fastest for the
+ * launch's shape (launch kind, direction, mode, level input size, batch)
+ * when it beats the automatic choice by more than 2 %.  Later calls of any entry point
  * on the per-level path that launch the same shape use the recorded
  * height, unless dwt2_set_tiling forces one.  dst and the workspace are
  * overwritten (dst ends holding the call's result); src is only read.
@@ -315,7 +316,7 @@ int dwt2_set_tiling(int32_t seg, int32_t chunk);
  * graph; must not race with other calls.  Does nothing more than one call
  * when a tiling is forced or the persistent path is selected.  Returns
  * DWT2_OK or the status of the first failing call (DWT2_ERR_ARG also for
- * dir outside 0..2, DWT2_ERR_HIP for event failures). */
+ * dir outside 0..4, DWT2_ERR_HIP for event failures). */
 int dwt2_tune(int32_t dir, const void* src, int64_t src_stride, int64_t src_batch_stride,
               void* dst, int64_t dst_stride, int64_t dst_batch_stride,
               int32_t width, int32_t height, int32_t batch, int32_t levels,

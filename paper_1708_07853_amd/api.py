@@ -235,15 +235,19 @@ def bwd(g: torch.Tensor, levels: int, out=None, workspace=None) -> torch.Tensor:
     return _run("dwt2_bwd", g, levels, DWT2_F32, out, workspace)
 
 
+_TUNE_DIRS = {"fwd": 0, "inv": 1, "bwd": 2, "fwd_cdf97": 3, "inv_cdf97": 4}
+
+
 def tune(direction: str, x: torch.Tensor, levels: int, mode=None, out=None, workspace=None) -> torch.Tensor:
     """Tune the work-item heights of the launches of `direction` ("fwd",
-    "inv" or "bwd") on inputs shaped like x (see dwt2_tune): later calls of
-    the same shapes use the fastest heights.  Returns the call's result."""
-    if direction not in _PROBE_DIRS:
-        raise ValueError("direction must be 'fwd', 'inv' or 'bwd'")
-    if direction == "bwd":
+    "inv", "bwd", or the CDF 9/7's "fwd_cdf97" / "inv_cdf97") on inputs
+    shaped like x (see dwt2_tune): later calls of the same shapes use the
+    fastest heights.  Returns the call's result."""
+    if direction not in _TUNE_DIRS:
+        raise ValueError("direction must be 'fwd', 'inv', 'bwd', 'fwd_cdf97' or 'inv_cdf97'")
+    if direction in ("bwd", "fwd_cdf97", "inv_cdf97"):
         mode = DWT2_F32
-    return _run("dwt2_tune", x, levels, mode, out, workspace, lead=(_PROBE_DIRS[direction],))
+    return _run("dwt2_tune", x, levels, mode, out, workspace, lead=(_TUNE_DIRS[direction],))
 
 
 def tune_entries() -> int:

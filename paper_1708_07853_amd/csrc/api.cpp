@@ -691,6 +691,33 @@ static int run_lds(int scheme, const Call& c, const Geo& g, void* stream) {
 constexpr int64_t kTiled97Area = 512 * 512;
 constexpr int kTiled97Strips = 10;
 constexpr int kTile97Px = 128;  // a tiled-kernel tile's width in pixels (64 quadruples)
+
+// Whether a CDF 9/7 level with input W x H runs in a strip kernel (else the
+// tiled one); nstrips: the strips per image.  Levels of at least 16 x 16 run
+// in the strip kernels, bit-identical to the tiled ones, except the
+// forward's levels of at most kTiled97Strips strips per image (at least a
+// fifth of them edge strips, whose folded single-element loads are slow),
+// whose width is a whole number of tiles (kTile97Px) and that hold more
+// than kTiled97Area pixels over the batch (below that, launch latency
+// decides).  Forward, whole calls, strips only against this choice:
+// 16 x 1024^2 four levels 58.6 vs 53.4 us, 96 x 256^2 three levels 44.8 vs
+// 30.3, 4 x 2048^2 five levels 61.5 vs 58.8, 8192^2 six levels 167.3 vs
+// 165.1.  The tiled kernel lost on 1500-pixel-wide levels (1500^2 at four
+// levels 26.0 against 28.2 us; 3000^2 at five, whose level 2 is 1500 wide,
+// 44.0 against 46.0) and on a level of 14 strips (3000^2 with level 1 tiled
+// too: 44.5 against 47.7).  The inverse's strip kernels were faster
+// everywhere.  DWT2_CDF97_TILED=1 / 0, read per call, forces the tiled /
+// strip kernels for tests and comparisons.
+static bool cdf97_strip_level(int dir, bool separable, int W, int H, int batch, int& nstrips) {
+  nstrips = 0;
+  const char* tiled_env = getenv("DWT2_CDF97_TILED");
+  const int force = tiled_env && *tiled_env ? atoi(tiled_env) : -1;
+  bool strip = !separable && cdf97_strip_geometry(W, H, nstrips) && force != 1;
+  if (strip && force != 0 && dir == kFwd && nstrips <= kTiled97Strips && W % kTile97Px == 0 &&
+      (int64_t)W * H * batch > kTiled97Area)
+    strip = false;
+  return strip;
+}
 // First level of the 9/7 forward's fused tail (0: none): the last
 // 2..kTailMaxLevels levels whose inputs hold at most kTailArea pixels over
 // the batch, each at least kTail97Min on a side.  Off unless
@@ -718,9 +745,19 @@ static int cdf97_tail_first(const Call& c, const Geo& g) {
   return n >= 2 ? k + 1 : 0;
 }
 
+// dwt2_tune's direction codes for the CDF 9/7 forward and inverse (the
+// probe of a 9/7 level carries them, so that it never matches a 5/3 call).
+constexpr int kTune97 = 3;
+
 static int run_cdf97(int dir, bool separable, const Call& c, const Geo& g, void* stream) {
   const int64_t ws_bs = (int64_t)(ws_per_image(g) / 4);
   const int k0 = dir == kFwd && !separable ? cdf97_tail_first(c, g) : 0;
+  Probe pr;
+  {
+    std::lock_guard<std::mutex> lock(g_probe_mu);
+    pr = g_probe;
+  }
+  hipStream_t hs = static_cast<hipStream_t>(stream);
   for (int s = 0; s < g.L; ++s) {
     const int k = dir == kFwd ? s + 1 : g.L - s;  // the inverse runs coarsest first
     if (k0 && k >= k0) break;  // the forward's last levels: the fused tail below
@@ -777,31 +814,17 @@ static int run_cdf97(int dir, bool separable, const Call& c, const Geo& g, void*
         a.out_bstride = ws_bs;
       }
     }
-    // Levels of at least 16 x 16 run in the strip kernels, bit-identical to
-    // the tiled ones, except the forward's levels of at most kTiled97Strips
-    // strips per image (at least a fifth of them edge strips, whose folded
-    // single-element loads are slow), whose width is a whole number of
-    // tiles (kTile97Px) and that hold more than kTiled97Area pixels over
-    // the batch (below that, launch latency decides).  Forward, whole calls,
-    // strips only against this choice: 16 x 1024^2 four levels 58.6 vs
-    // 53.4 us, 96 x 256^2 three levels 44.8 vs 30.3, 4 x 2048^2 five levels
-    // 61.5 vs 58.8, 8192^2 six levels 167.3 vs 165.1.  The tiled kernel lost
-    // on 1500-pixel-wide levels (1500^2 at four levels 26.0 against 28.2
-    // us; 3000^2 at five, whose level 2 is 1500 wide, 44.0 against 46.0)
-    // and on a level of 14 strips (3000^2 with level 1 tiled too: 44.5
-    // against 47.7).  The inverse's strip kernels were faster everywhere.
-    // DWT2_CDF97_TILED=1 / 0, read per call, forces the tiled / strip
-    // kernels for tests and comparisons.
+    // Levels of at least 16 x 16 run in the strip kernels (cdf97_strip_level).
     int nstrips = 0;
-    const char* tiled_env = getenv("DWT2_CDF97_TILED");
-    const int force = tiled_env && *tiled_env ? atoi(tiled_env) : -1;
-    bool strip = !separable && cdf97_strip_geometry(a.W, a.H, nstrips) && force != 1;
-    if (strip && force != 0 && dir == kFwd && nstrips <= kTiled97Strips && a.W % kTile97Px == 0 &&
-        (int64_t)a.W * a.H * c.batch > kTiled97Area)
-      strip = false;
+    const bool strip = cdf97_strip_level(dir, separable, a.W, a.H, c.batch, nstrips);
+    // a probe on this level (dwt2_tune) times its launch
+    const bool probed = !separable && pr.dir == kTune97 + dir && pr.level == k;
+    if (probed && hipEventRecord(pr.begin, hs) != hipSuccess) return fail(DWT2_ERR_HIP, "probe event record failed");
     int err;
     if (strip) {
-      const Tiling t = choose_tiling(ceil_half(a.H), (int64_t)nstrips * c.batch);
+      // the model's segment height, or the one dwt2_tune recorded for the shape
+      const Tiling t = tuned_tiling(choose_tiling(ceil_half(a.H), (int64_t)nstrips * c.batch), kLaunch97, dir, c.mode,
+                                    g, k, c.batch);
       // the forward stages its stores from kPairStageStrips strips, as the pairs
       // do (DWT2_PAIR_STAGE=1 / 0 forces either form, read per call)
       const char* stage_env = getenv("DWT2_PAIR_STAGE");
@@ -812,6 +835,7 @@ static int run_cdf97(int dir, bool separable, const Call& c, const Geo& g, void*
     }
     if (err != hipSuccess)
       return fail(DWT2_ERR_HIP, "CDF 9/7 level %d launch failed: %s", k, hipGetErrorString((hipError_t)err));
+    if (probed && hipEventRecord(pr.end, hs) != hipSuccess) return fail(DWT2_ERR_HIP, "probe event record failed");
   }
   if (k0) {
     TailArgs t;
@@ -919,7 +943,8 @@ static int current_plan(int dir, const Geo& g, int batch, Launch* plan) {
   return plan_launches(dir, g, batch, path != 2 && path != 4, pairs, plan);
 }
 
-// dwt2_tune: for each single-level or pair launch of the call, in
+// dwt2_tune: for each single-level or pair launch of the call (dir 0..2),
+// or each strip-kernel level of a CDF 9/7 call (dir kTune97 + 0 / 1), in
 // execution order, times the whole call once per candidate segment height
 // with events around that launch (the median of kTuneReps calls after two
 // untimed ones) and keeps the fastest height if it beats the model's by
@@ -929,15 +954,32 @@ constexpr float kTuneGain = 0.02f;
 static int tune(int dir, const void* src, int64_t src_stride, int64_t src_bs, void* dst, int64_t dst_stride,
                 int64_t dst_bs, int32_t width, int32_t height, int32_t batch, int32_t levels, int32_t mode,
                 int32_t boundary, void* workspace, size_t workspace_bytes, void* stream) {
+  const bool is97 = dir >= kTune97;
+  const int tdir = is97 ? dir - kTune97 : dir;  // the transform's direction
   auto call = [&]() {
-    return transform(dir, src, src_stride, src_bs, dst, dst_stride, dst_bs, width, height, batch, levels, mode,
-                     boundary, workspace, workspace_bytes, stream);
+    return transform(tdir, src, src_stride, src_bs, dst, dst_stride, dst_bs, width, height, batch, levels, mode,
+                     boundary, workspace, workspace_bytes, stream, is97 ? kCdf97 : kProduct);
   };
   if (int st = call()) return st;  // validates every argument
   Geo g;
   check_geometry(width, height, levels, g);
   Launch plan[DWT2_MAX_LEVELS];
-  const int n = g_forced_seg.load() > 0 ? 0 : current_plan(dir, g, batch, plan);
+  int n = 0;
+  if (g_forced_seg.load() > 0) {
+    n = 0;  // a forced tiling: nothing to tune
+  } else if (is97) {
+    Call cc{};
+    cc.batch = batch;
+    const int k0 = tdir == kFwd ? cdf97_tail_first(cc, g) : 0;
+    for (int s = 0; s < g.L; ++s) {
+      const int k = tdir == kFwd ? s + 1 : g.L - s;
+      int ns;
+      if (k0 && k >= k0) break;
+      if (cdf97_strip_level(tdir, false, g.w[k - 1], g.h[k - 1], batch, ns)) plan[n++] = Launch{k, k, kLaunch97};
+    }
+  } else {
+    n = current_plan(dir, g, batch, plan);
+  }
   if (n == 0) return DWT2_OK;  // a forced tiling or the persistent path: nothing to tune
   hipEvent_t ev[2 * kTuneReps] = {};
   for (hipEvent_t& e : ev)
@@ -960,7 +1002,7 @@ static int tune(int dir, const void* src, int64_t src_stride, int64_t src_bs, vo
     const int k = l.first;
     const bool pair = l.kind == kLaunchPair;
     const int rows = pair ? ceil_half(ceil_half(g.h[k - 1])) : ceil_half(g.h[k - 1]);
-    const TuneKey key{l.kind, dir, mode, g.w[k - 1], g.h[k - 1], batch};
+    const TuneKey key{l.kind, tdir, mode, g.w[k - 1], g.h[k - 1], batch};
     {
       std::lock_guard<std::mutex> lock(g_tune_mu);
       g_tuned_seg.erase(key);  // candidate 0 is the model's height
@@ -1151,7 +1193,8 @@ int dwt2_tune(int32_t dir, const void* src, int64_t src_stride, int64_t src_batc
               int64_t dst_stride, int64_t dst_batch_stride, int32_t width, int32_t height, int32_t batch,
               int32_t levels, int32_t mode, int32_t boundary, void* workspace, size_t workspace_bytes, void* stream) {
   clear_error();
-  if (dir < 0 || dir > 2) return fail(DWT2_ERR_ARG, "dir must be 0 (forward), 1 (inverse) or 2 (adjoint)");
+  if (dir < 0 || dir > kTune97 + 1)
+    return fail(DWT2_ERR_ARG, "dir must be 0 (forward), 1 (inverse), 2 (adjoint), 3 (CDF 9/7 forward) or 4 (CDF 9/7 inverse)");
   return tune(dir, src, src_stride, src_batch_stride, dst, dst_stride, dst_batch_stride, width, height, batch, levels,
               mode, boundary, workspace, workspace_bytes, stream);
 }

@@ -54,8 +54,9 @@ void fill_level(LevelDesc& d, int W, int H, int seg);
 void level_pointers(int dir, const Call& c, const Geo& g, int k, LevelDesc& d, int64_t& pix_bs, int64_t& ll_bs,
                     int64_t& band_bs);
 // One launch of a plain call: levels [first, last], by the single-level,
-// pair or fused-tail kernels.
-enum { kLaunchLevel = 0, kLaunchPair = 1, kLaunchTail = 2 };
+// pair or fused-tail kernels (kLaunch97: a CDF 9/7 strip-kernel level, for
+// the tuning table).
+enum { kLaunchLevel = 0, kLaunchPair = 1, kLaunchTail = 2, kLaunch97 = 3 };
 struct Launch {
   int first, last, kind;
 };

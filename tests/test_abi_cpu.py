@@ -288,7 +288,7 @@ def call_tune(lib, d=0, **kw):
                          a["levels"], a["mode"], a["boundary"], a["ws"], a["wsb"], a["stream"])
 
 
-@pytest.mark.parametrize("d", [0, 1, 2])
+@pytest.mark.parametrize("d", [0, 1, 2, 3, 4])
 @pytest.mark.parametrize("kw,code", BAD, ids=[str(b[0]) for b in BAD])
 def test_tune_validation_errors(lib, d, kw, code):
     """dwt2_tune validates as the call it tunes, before any HIP call."""
@@ -297,8 +297,10 @@ def test_tune_validation_errors(lib, d, kw, code):
 
 
 def test_tune_direction_and_table(lib):
-    assert call_tune(lib, 3) == -1
+    assert call_tune(lib, 5) == -1
     assert call_tune(lib, -1) == -1
     assert call_tune(lib, 2, mode=1) == -3      # the adjoint is float only
+    assert call_tune(lib, 3, mode=1) == -3      # so is the CDF 9/7
+    assert call_tune(lib, 4, mode=1) == -3
     assert lib.dwt2_tune_clear() == 0
     assert lib.dwt2_tune_entries() == 0

@@ -55,6 +55,24 @@ def test_tuned_results_are_unchanged(w, h, b, L, dt):
         assert torch.equal(ref_i, x)
 
 
+@pytest.mark.parametrize("w,h,b,L", [(4096, 4096, 1, 6), (1500, 900, 3, 5), (600, 2000, 2, 4)])
+def test_tuned_cdf97_results_are_unchanged(w, h, b, L):
+    """The CDF 9/7 strip levels (dwt2_tune directions 3 and 4): the tuning
+    calls and later calls give the untuned bits."""
+    d = D()
+    print(f"tune cdf97 case {w}x{h} batch {b} levels {L}", flush=True)
+    x = torch.stack([synth.image_device(w, h, 61 + i) for i in range(b)])
+    d.tune_clear()
+    ref_f = d.fwd_cdf97(x, L)
+    ref_i = d.inv_cdf97(ref_f, L)
+    assert torch.equal(d.tune("fwd_cdf97", x, L), ref_f)
+    assert torch.equal(d.tune("inv_cdf97", ref_f, L), ref_i)
+    print(f"tuned launch shapes: {d.tune_entries()}", flush=True)
+    for _ in range(2):
+        assert torch.equal(d.fwd_cdf97(x, L), ref_f)
+        assert torch.equal(d.inv_cdf97(ref_f, L), ref_i)
+
+
 def test_tune_restores_probe_and_respects_forced_tiling():
     d = D()
     x = synth.image_device(2048, 2048, 3)
