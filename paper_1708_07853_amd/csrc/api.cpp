@@ -207,9 +207,11 @@ Tiling choose_tiling(int ns_h, int64_t strips_times_batch, int64_t slots_hint) {
 }
 
 // Segment heights picked by dwt2_tune, per launch shape (launch kind,
-// direction, mode, level-k input size, batch).  While dwt2_tune times one
-// launch, g_trial holds the height under test for that shape.  The table is
-// never destroyed, so process exit runs no teardown code for it.
+// direction, mode, level-k input size, batch), each with the prefetch chunk
+// it was timed with (value seg | ch << 16; ch 0: choose_tiling's rule for
+// that height).  While dwt2_tune times one launch, g_trial holds the height
+// and chunk under test for that shape.  The table is never destroyed, so
+// process exit runs no teardown code for it.
 struct TuneKey {
   int kind, dir, mode, w, h, batch;
   bool operator<(const TuneKey& o) const {
@@ -220,7 +222,7 @@ struct TuneKey {
 struct Trial {
   bool on = false;
   TuneKey key{};
-  int seg = 0;
+  int seg = 0, ch = 0;
 };
 std::mutex g_tune_mu;
 std::map<TuneKey, int>& g_tuned_seg = *new std::map<TuneKey, int>;
@@ -231,19 +233,23 @@ Trial g_trial;
 static Tiling tuned_tiling(Tiling t, int kind, int dir, int mode, const Geo& g, int k, int batch) {
   if (g_forced_seg.load() > 0) return t;
   const TuneKey key{kind, dir, mode, g.w[k - 1], g.h[k - 1], batch};
-  int seg = 0;
+  int seg = 0, ch = 0;
   {
     std::lock_guard<std::mutex> lock(g_tune_mu);
     if (g_trial.on && g_trial.key == key) {
       seg = g_trial.seg;
+      ch = g_trial.ch;
     } else {
       auto it = g_tuned_seg.find(key);
-      if (it != g_tuned_seg.end()) seg = it->second;
+      if (it != g_tuned_seg.end()) {
+        seg = it->second & 0xffff;
+        ch = it->second >> 16;
+      }
     }
   }
   if (seg > 0) {
     t.seg = seg;
-    if (g_forced_ch.load() <= 0) t.ch = seg < 4 ? 1 : 2;  // choose_tiling's chunk rule
+    if (g_forced_ch.load() <= 0) t.ch = ch > 0 ? ch : (seg < 4 ? 1 : 2);  // else choose_tiling's chunk rule
   }
   return t;
 }
@@ -1007,18 +1013,35 @@ static int tune(int dir, const void* src, int64_t src_stride, int64_t src_bs, vo
       std::lock_guard<std::mutex> lock(g_tune_mu);
       g_tuned_seg.erase(key);  // candidate 0 is the model's height
     }
-    const int* cand = pair ? kPairSegs : kLevelSegs;
-    const int ncand = pair ? (int)(sizeof kPairSegs / sizeof *kPairSegs) : (int)(sizeof kLevelSegs / sizeof *kLevelSegs);
+    // candidates: (height, chunk), chunk 0 taking the rule's; the 9/7 strip
+    // levels also try the other chunk at the heights where the rule switches
+    // (forced on every level, 3 rows with a two-row chunk took level 2 of
+    // the 8192^2 forward from 33.7 to 24.4 us)
+    int cseg[32], cch[32], ncand = 0;
+    const int* base = pair ? kPairSegs : kLevelSegs;
+    const int nbase = pair ? (int)(sizeof kPairSegs / sizeof *kPairSegs) : (int)(sizeof kLevelSegs / sizeof *kLevelSegs);
+    for (int j = 0; j < nbase; ++j) {
+      cseg[ncand] = base[j];
+      cch[ncand++] = 0;
+    }
+    if (l.kind == kLaunch97) {
+      static const int kExtra97[][2] = {{2, 2}, {3, 2}, {4, 1}, {6, 1}};
+      for (const auto& e : kExtra97) {
+        cseg[ncand] = e[0];
+        cch[ncand++] = e[1];
+      }
+    }
     float model_ms = 0.f, best_ms = 0.f;
     int best = 0;
     for (int j = 0; j < ncand && st == DWT2_OK; ++j) {
-      const int seg = cand[j];
+      const int seg = cseg[j];
       if (seg > rows) continue;
       {
         std::lock_guard<std::mutex> lock(g_tune_mu);
         g_trial.on = seg > 0;
         g_trial.key = key;
         g_trial.seg = seg;
+        g_trial.ch = cch[j];
       }
       float t[kTuneReps];
       for (int r = -2; r < kTuneReps && st == DWT2_OK; ++r) {
@@ -1048,7 +1071,7 @@ static int tune(int dir, const void* src, int64_t src_stride, int64_t src_bs, vo
       if (seg == 0) model_ms = med;
       if (j == 0 || med < best_ms) {
         best_ms = med;
-        best = seg;
+        best = seg | cch[j] << 16;
       }
     }
     std::lock_guard<std::mutex> lock(g_tune_mu);
